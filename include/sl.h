@@ -1,0 +1,215 @@
+/*
+ * sl.h -- C ABI of the MI355X semi-Lagrangian Monte-Carlo library.
+ *
+ * The library advances Monte-Carlo samples of the drift-diffusion problem of
+ * Natarajan, Popov & Jacobs, "A high-order semi-Lagrangian method for the
+ * consistent Monte-Carlo solution of stochastic Lagrangian drift-diffusion
+ * models coupled with Eulerian discontinuous spectral element method"
+ * (arXiv:2009.07340):
+ *
+ *   dX = u(X) dt + sqrt(2 D(X)) dW                     (Sec. 2, eq. canonical_sde,
+ *                                                        D = sigma^2/2, eq. fokkerplanck)
+ *
+ * by the semi-Lagrangian step of Sec. 5 on a box of equal affine elements with
+ * N Gauss nodes per direction (Sec. 3), one polynomial field per sample:
+ *   seed at the Gauss nodes (Sec. 5.1), move the nodes by one Euler-Maruyama
+ *   step with one Wiener increment per sample (Sec. 5.2, eq. def_dx), carry the
+ *   source along (eq. advection_phi), remap by a least-squares fit constrained
+ *   by upwinded boundary values (Sec. 5.3, eqs. phi_star, remap_bnd,
+ *   bnd_update) and average samples at the nodes (Sec. 5.4, eq. averaged).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status: every function returns an int, 0 (SL_OK) on success or a negative
+ * SL_E* code; sl_last_error() gives a message for the calling thread.  No C++
+ * exception crosses this interface.  A failed call leaves the handle usable
+ * unless it returns SL_EDEVICE.
+ *
+ * Elements: e = ey*kx + ex (x fastest).  Element e has N_e nodes per
+ * direction, n_e = N_e^dim nodes; node i = iy*N_e + ix.  Reference node
+ * coordinates xi are the Gauss nodes of the chosen family on [0, 1],
+ * correctly rounded to float64.  Physical node coordinates:
+ *   x = x0 + hx*(ex + xi_ix),  y = y0 + hy*(ey + xi_iy),  hx = (x1-x0)/kx.
+ * Per-sample node arrays are ragged: element e occupies entries
+ * [off_e, off_e + n_e) with off_e = sum_{e'<e} n_e'; "nodes" below is the
+ * total sum_e n_e per sample.
+ *
+ * Edges: 1-D element e has edges L (xi = 0) and R (xi = 1), one point each;
+ * 2-D element e has edges W (xi = 0), E (xi = 1), S (eta = 0), N (eta = 1),
+ * each with the element's own N_e Gauss abscissae along it, so 4*N_e points,
+ * stored edge-major (W points 0..N-1, then E, S, N).  "edge points" below is
+ * the total per sample.  The normal component of a velocity at an edge point
+ * is its x component on L/R/W/E edges and its y component on S/N edges.
+ *
+ * Particle positions (bit-exact contract with independent implementations):
+ * with z the standard normal of the sample for the step and direction,
+ *   A = (u*dt)/h,  B = sqrt((2*D)*dt)/h  (float64, in this order, host side),
+ *   xi* = xi + (A + B*z)                  (three roundings, no fused ops).
+ * z comes from Philox4x32-10 (Salmon et al., SC'11) with
+ * counter (step n, sample s, attempt a, stream id) and key (seed lo, seed hi):
+ * words r0..r3 -> k = (r0>>6)*2^26 + (r1>>6), va = (2k+1)*2^-52 - 1, vb from
+ * (r2, r3) the same way; polar method: s = va*va + vb*vb (rounded products
+ * and sum), accept s < 1 else a+1 (at most 64 attempts, else z = 0);
+ * z_a = va*sqrt((-2*log(s))/s), z_b = vb*(same), with log computed by the
+ * fixed Cody-Waite + atanh-series recipe documented in the library source.
+ * One dimension uses z_a; two dimensions use (z_a, z_b) for (x, y).
+ *
+ * Memory: pointers named host_* or documented as host are host memory and are
+ * read or written before the call returns.  Device pointers are borrowed,
+ * never freed by the library.  Handles are not thread-safe: calls on one
+ * handle must be serialised by the caller; distinct handles are independent.
+ */
+#ifndef SL_H
+#define SL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SL_ABI_VERSION 1
+
+enum sl_status {
+  SL_OK = 0,
+  SL_EINVAL = -1,        /* invalid argument or descriptor */
+  SL_ENOMEM = -2,        /* device or host allocation failed, or workspace too small */
+  SL_EDEVICE = -3,       /* a HIP runtime call failed; the handle should be destroyed */
+  SL_ENONFINITE = -4,    /* non-finite input values */
+  SL_ESTATE = -5,        /* call out of order (e.g. step before fields were set) */
+  SL_EUNSUPPORTED = -6   /* valid request this build does not implement */
+};
+
+enum { SL_BC_PERIODIC = 0, SL_BC_DIRICHLET = 1 };
+enum { SL_NODES_GL = 0, SL_NODES_CG = 1 };
+enum {
+  SL_PREC_FP64 = 0,          /* every operation of the fit in float64 */
+  SL_PREC_FP32_REFINE = 1,   /* float32 Gram / factorisation, float64 refinement */
+  SL_PREC_BF16SPLIT_REFINE = 2 /* bf16 hi/lo split Gram products, float64 refinement */
+};
+
+typedef struct sl_ctx* sl_handle;
+
+/* Problem description (Sec. 3: box of K = kx*ky affine elements, N nodes
+ * per direction; Sec. 5: M Monte-Carlo samples). */
+typedef struct sl_mesh_desc {
+  int32_t dim;            /* 1 or 2 */
+  int32_t kx, ky;         /* elements per direction, >= 1 (ky ignored in 1-D) */
+  double x0, x1, y0, y1;  /* box, x1 > x0 (and y1 > y0 in 2-D) */
+  int32_t n_uniform;      /* N for every element when order == NULL; 2 <= N <= 16 */
+  const int32_t* order;   /* optional host array of K per-element N (copied); 2-D only
+                             may mix orders */
+  int32_t nodes;          /* SL_NODES_GL (default) or SL_NODES_CG */
+  int32_t bc;             /* SL_BC_PERIODIC or SL_BC_DIRICHLET */
+  int64_t samples;        /* M >= 1 */
+  uint64_t seed;          /* Philox key */
+  uint32_t stream_id;     /* fourth Philox counter word (e.g. a request id) */
+  int32_t precision;      /* SL_PREC_* */
+  int32_t refine_iters;   /* FP64 refinement sweeps for the mixed modes; -1 = default */
+} sl_mesh_desc;
+
+typedef struct sl_diag_t {
+  int64_t steps;              /* Philox step counter n: steps taken since set_fields */
+  int64_t samples;            /* M */
+  int64_t nodes;              /* nodes per sample */
+  int64_t edge_points;        /* edge points per sample */
+  double max_disp_ratio;      /* for the last dt: max over nodes and directions of
+                                 (|A| + |B|) / (minimum reference node spacing), the
+                                 one-sigma displacement measured in node spacings
+                                 (Sec. 5.2, eq. 1d_timestep); values well above 1
+                                 put the scheme outside its stable range */
+  int32_t precision;
+  int32_t refine_iters;
+  size_t device_bytes;        /* bytes of device memory the handle uses */
+} sl_diag_t;
+
+/* Device bytes sl_init_mesh needs for this description (state, traces, fields,
+ * tables, scratch), for admission control.  Pure host computation. */
+int sl_required_bytes(const sl_mesh_desc* desc, size_t* bytes);
+
+/* Create a handle.  desc is validated and copied.  dev_ws: optional device
+ * workspace of ws_bytes >= sl_required_bytes() bytes, caller-owned and
+ * borrowed for the handle's lifetime (e.g. a torch tensor's data pointer);
+ * NULL makes the library allocate.  hip_stream: the hipStream_t every
+ * operation of the handle is enqueued on (NULL = the default stream).
+ * Uploads the node tables; the handle then needs sl_set_fields. */
+int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                 sl_handle* out);
+
+/* Per-sample sizes: nodes, edge points, elements. */
+int sl_sizes(sl_handle h, int64_t* nodes, int64_t* edge_points, int64_t* elements);
+
+/* Physical coordinates of the nodes ([nodes][dim]) and of the edge points
+ * ([edge points][dim]) where the caller samples the fields.  Host buffers.
+ * edge_axis (optional, [edge points]) receives 0 for points on x-normal edges
+ * and 1 for y-normal edges. */
+int sl_node_coords(sl_handle h, double* host_xy);
+int sl_edge_coords(sl_handle h, double* host_xy, int32_t* host_edge_axis);
+
+/* Reference nodes of order N for this handle's family (N doubles, host). */
+int sl_ref_nodes(sl_handle h, int32_t N, double* host_xi);
+
+/* Fields at the nodes and edge points (Sec. 5.1: available at the quadrature
+ * points; Sec. 5.2: div u from the field solver).  Host arrays, copied:
+ *   u [nodes][dim] drift; D [nodes] diffusion coefficient (>= 0);
+ *   divu [nodes] physical divergence of u, NULL = 0;
+ *   un [edge points] normal drift; Dn [edge points] diffusion at edge points;
+ *   ghost [edge points] Dirichlet ghost values (required iff bc = DIRICHLET;
+ *     only entries on the domain boundary are read);
+ *   phi0 [nodes] initial field, NULL keeps the current samples; when given,
+ *     every sample is set to phi0 and the step counter to 0.
+ * Values must be finite (SL_ENONFINITE otherwise). */
+int sl_set_fields(sl_handle h, const double* u, const double* D, const double* divu,
+                  const double* un, const double* Dn, const double* ghost, const double* phi0);
+
+/* Advance every sample nsteps >= 0 steps of size dt > 0 (Sec. 5).  Enqueued on
+ * the handle's stream; returns without waiting.  The step counter advances by
+ * nsteps. */
+int sl_step(sl_handle h, double dt, int32_t nsteps);
+
+/* One batched pass: advance nh handles by nsteps steps each, handle i with
+ * step dts[i], in shared launches.  Every handle's result equals sl_step on
+ * that handle alone.  Work is enqueued on the first handle's stream; the
+ * other handles' streams must not have pending work. */
+int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t nsteps);
+
+/* Sample mean at every node (eq. averaged): out[nodes].  out_is_device != 0:
+ * out is a device pointer and the call is asynchronous on the handle's
+ * stream; otherwise out is host memory and the call waits. */
+int sl_mean(sl_handle h, double* out, int32_t out_is_device);
+
+/* Copy ns samples starting at s0 ([ns][nodes]) out of / into the handle (for
+ * checkpoints and subset checks).  Host buffers unless *_is_device != 0. */
+int sl_get_samples(sl_handle h, int64_t s0, int64_t ns, double* out, int32_t out_is_device);
+int sl_set_samples(sl_handle h, int64_t s0, int64_t ns, const double* in, int32_t in_is_device);
+
+/* Step counter n (the first Philox counter word of the next step). */
+int sl_get_step(sl_handle h, int64_t* n);
+int sl_set_step(sl_handle h, int64_t n);
+
+/* Test aids.  sl_debug_normals: z (z_a, z_b) of samples [s0, s0+ns) at step
+ * n, computed by the device generator: out[ns][2], host.
+ * sl_debug_positions: moved reference coordinates xi* the next step would
+ * produce with step size dt, by the same device code as the step:
+ * out[samples][nodes][dim], host. */
+int sl_debug_normals(sl_handle h, int64_t n, int64_t s0, int64_t ns, double* out);
+int sl_debug_positions(sl_handle h, double dt, double* out);
+
+/* Per-kernel device time, for measurement.  sl_profile(h, 1) starts
+ * recording HIP events around every launch on the handle's stream and clears
+ * the totals; sl_profile(h, 0) stops.  sl_kernel_time(h, name, &launches,
+ * &ms) reads the totals for a kernel name (see the library source for the
+ * names), waiting for the stream first. */
+int sl_profile(sl_handle h, int32_t enable);
+int sl_kernel_time(sl_handle h, const char* name, int64_t* launches, double* ms);
+
+int sl_diag(sl_handle h, sl_diag_t* out);
+int sl_sync(sl_handle h);                 /* wait for the handle's stream */
+const char* sl_last_error(void);          /* thread-local message of the last failure */
+int sl_destroy(sl_handle h);              /* waits, frees what the library allocated */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SL_H */

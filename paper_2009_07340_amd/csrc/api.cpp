@@ -1,0 +1,595 @@
+// C ABI of the library (declared in include/sl.h): handle lifetime, argument
+// checks, host-side step coefficients, workspace layout and kernel dispatch.
+#include "../../include/sl.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sl_internal.hpp"
+#include "tables.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define SL_HIP(call)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess) return fail(SL_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct KStat {
+  int64_t launches = 0;
+  double ms = 0.0;
+};
+
+struct PendingEvent {
+  std::string name;
+  hipEvent_t a, b;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Sizes derived from a descriptor (shared by sl_required_bytes and sl_init_mesh).
+struct Layout {
+  int dim = 1, kx = 1, ky = 1, K = 1;
+  std::vector<int> order;
+  std::vector<int64_t> noff, eoff;
+  int64_t nodes = 0, edges = 0, M = 0;
+  int maxN = 0;
+  bool uniform = true;
+  // byte offsets in the workspace
+  size_t o_phi, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0, total;
+};
+
+int make_layout(const sl_mesh_desc* d, Layout& L) {
+  if (!d) return fail(SL_EINVAL, "null descriptor");
+  if (d->dim != 1 && d->dim != 2) return fail(SL_EINVAL, "dim must be 1 or 2");
+  if (d->kx < 1 || (d->dim == 2 && d->ky < 1)) return fail(SL_EINVAL, "kx, ky must be >= 1");
+  if (!(d->x1 > d->x0) || (d->dim == 2 && !(d->y1 > d->y0))) return fail(SL_EINVAL, "empty box");
+  if (!std::isfinite(d->x0) || !std::isfinite(d->x1) || !std::isfinite(d->y0) || !std::isfinite(d->y1))
+    return fail(SL_EINVAL, "non-finite box");
+  if (d->samples < 1) return fail(SL_EINVAL, "samples must be >= 1");
+  if (d->nodes != SL_NODES_GL && d->nodes != SL_NODES_CG) return fail(SL_EINVAL, "unknown node family");
+  if (d->bc != SL_BC_PERIODIC && d->bc != SL_BC_DIRICHLET) return fail(SL_EINVAL, "unknown boundary condition");
+  if (d->precision < SL_PREC_FP64 || d->precision > SL_PREC_BF16SPLIT_REFINE)
+    return fail(SL_EINVAL, "unknown precision mode");
+  L.dim = d->dim;
+  L.kx = d->kx;
+  L.ky = d->dim == 2 ? d->ky : 1;
+  const int64_t K64 = (int64_t)L.kx * L.ky;
+  if (K64 > (1 << 26)) return fail(SL_EINVAL, "too many elements");
+  L.K = (int)K64;
+  L.order.resize(L.K);
+  for (int e = 0; e < L.K; ++e) {
+    const int N = d->order ? d->order[e] : d->n_uniform;
+    if (N < 2 || N > sl::kMaxN) return fail(SL_EINVAL, "element order N must be in [2, 16]");
+    L.order[e] = N;
+  }
+  L.maxN = *std::max_element(L.order.begin(), L.order.end());
+  L.uniform = std::all_of(L.order.begin(), L.order.end(), [&](int n) { return n == L.order[0]; });
+  L.noff.resize(L.K + 1);
+  L.eoff.resize(L.K + 1);
+  L.noff[0] = L.eoff[0] = 0;
+  for (int e = 0; e < L.K; ++e) {
+    const int N = L.order[e];
+    L.noff[e + 1] = L.noff[e] + (L.dim == 1 ? N : N * N);
+    L.eoff[e + 1] = L.eoff[e] + (L.dim == 1 ? 2 : 4 * N);
+  }
+  L.nodes = L.noff[L.K];
+  L.edges = L.eoff[L.K];
+  L.M = d->samples;
+  if ((double)L.M * (double)L.nodes * 8.0 > 250e9) return fail(SL_ENOMEM, "state exceeds device memory");
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  L.o_phi = take(sizeof(double) * (size_t)L.M * L.nodes);
+  L.o_tr = take(L.dim == 2 ? sizeof(double) * (size_t)L.M * L.edges : 0);
+  L.o_xi = take(sizeof(double) * L.nodes * L.dim);
+  L.o_A = take(sizeof(double) * L.nodes * L.dim);
+  L.o_B = take(sizeof(double) * L.nodes * L.dim);
+  L.o_src = take(sizeof(double) * L.nodes);
+  L.o_Af = take(sizeof(double) * L.edges);
+  L.o_Bf = take(sizeof(double) * L.edges);
+  L.o_ghost = take(sizeof(double) * L.edges);
+  L.o_mean = take(sizeof(double) * L.nodes);
+  L.o_phi0 = take(sizeof(double) * L.nodes);
+  L.total = o;
+  return SL_OK;
+}
+
+}  // namespace
+
+struct sl_ctx {
+  sl_mesh_desc desc{};
+  Layout L;
+  double hx = 1, hy = 1;
+  int family = 0;
+  hipStream_t stream = nullptr;
+  bool own_ws = false;
+  char* ws = nullptr;
+  double *phi = nullptr, *tr = nullptr, *xi_node = nullptr, *A = nullptr, *B = nullptr, *src = nullptr;
+  double *Af = nullptr, *Bf = nullptr, *ghost = nullptr, *mean = nullptr, *phi0 = nullptr;
+  std::map<int, std::vector<double>> xi_tab;    // reference nodes per order
+  sl::LegendreRec rec{};
+  // host copies of the fields
+  std::vector<double> u, D, divu, un, Dn, ghost_h;
+  std::vector<double> hA, hB, hsrc, hAf, hBf;
+  bool fields_set = false;
+  bool coeff_valid = false;
+  double coeff_dt = 0.0;
+  double max_disp_ratio = 0.0;
+  int64_t step = 0;
+  // measurement
+  bool profile = false;
+  std::vector<PendingEvent> pending;
+  std::map<std::string, KStat> kstats;
+};
+
+namespace {
+
+int check_handle(sl_handle h) {
+  if (!h) return fail(SL_EINVAL, "null handle");
+  return SL_OK;
+}
+
+// Record an event pair around a launch when profiling is on.
+struct ProfScope {
+  sl_ctx* h;
+  PendingEvent ev;
+  bool on;
+  ProfScope(sl_ctx* h_, const char* name) : h(h_), on(h_->profile) {
+    if (on) {
+      ev.name = name;
+      (void)hipEventCreate(&ev.a);
+      (void)hipEventCreate(&ev.b);
+      (void)hipEventRecord(ev.a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (on) {
+      (void)hipEventRecord(ev.b, h->stream);
+      h->pending.push_back(ev);
+    }
+  }
+};
+
+void drain_events(sl_ctx* h) {
+  if (h->pending.empty()) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    auto& k = h->kstats[p.name];
+    k.launches += 1;
+    k.ms += ms;
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  h->pending.clear();
+}
+
+// Step coefficients for dt (position contract, host side):
+//   A = (u*dt)/h, B = sqrt((2*D)*dt)/h, src = 1 - dt*divu,
+//   Af = (un*dt)/h_axis, Bf = sqrt((2*Dn)*dt)/h_axis.
+int update_coefficients(sl_ctx* h, double dt) {
+  if (h->coeff_valid && h->coeff_dt == dt) return SL_OK;
+  const Layout& L = h->L;
+  const double hdir[2] = {h->hx, h->hy};
+  h->hA.resize(L.nodes * L.dim);
+  h->hB.resize(L.nodes * L.dim);
+  h->hsrc.resize(L.nodes);
+  double maxratio = 0.0;
+  for (int e = 0; e < L.K; ++e) {
+    const int N = L.order[e];
+    const double spacing = sl::min_node_spacing(h->xi_tab[N]);
+    for (int64_t k = L.noff[e]; k < L.noff[e + 1]; ++k) {
+      const double sq = std::sqrt((2.0 * h->D[k]) * dt);
+      for (int j = 0; j < L.dim; ++j) {
+        const double a = (h->u[k * L.dim + j] * dt) / hdir[j];
+        const double b = sq / hdir[j];
+        h->hA[k * L.dim + j] = a;
+        h->hB[k * L.dim + j] = b;
+        maxratio = std::max(maxratio, (std::fabs(a) + std::fabs(b)) / spacing);
+      }
+      h->hsrc[k] = 1.0 - dt * (h->divu.empty() ? 0.0 : h->divu[k]);
+    }
+  }
+  h->hAf.resize(L.edges);
+  h->hBf.resize(L.edges);
+  for (int e = 0; e < L.K; ++e) {
+    const int N = L.order[e];
+    for (int64_t q = L.eoff[e]; q < L.eoff[e + 1]; ++q) {
+      const int64_t local = q - L.eoff[e];
+      const int axis = (L.dim == 1 || local < 2 * N) ? 0 : 1;
+      h->hAf[q] = (h->un[q] * dt) / hdir[axis];
+      h->hBf[q] = std::sqrt((2.0 * h->Dn[q]) * dt) / hdir[axis];
+    }
+  }
+  SL_HIP(hipMemcpyAsync(h->A, h->hA.data(), sizeof(double) * h->hA.size(), hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipMemcpyAsync(h->B, h->hB.data(), sizeof(double) * h->hB.size(), hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipMemcpyAsync(h->src, h->hsrc.data(), sizeof(double) * h->hsrc.size(), hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipMemcpyAsync(h->Af, h->hAf.data(), sizeof(double) * h->hAf.size(), hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipMemcpyAsync(h->Bf, h->hBf.data(), sizeof(double) * h->hBf.size(), hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipStreamSynchronize(h->stream));   // host vectors may be reused right after
+  h->coeff_valid = true;
+  h->coeff_dt = dt;
+  h->max_disp_ratio = maxratio;
+  return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sl_required_bytes(const sl_mesh_desc* desc, size_t* bytes) {
+  if (!bytes) return fail(SL_EINVAL, "null output");
+  Layout L;
+  const int rc = make_layout(desc, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return SL_OK;
+}
+
+int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* hip_stream, sl_handle* out) {
+  if (!out) return fail(SL_EINVAL, "null output handle");
+  *out = nullptr;
+  std::unique_ptr<sl_ctx> h(new (std::nothrow) sl_ctx());
+  if (!h) return fail(SL_ENOMEM, "host allocation failed");
+  int rc = make_layout(desc, h->L);
+  if (rc) return rc;
+  const Layout& L = h->L;
+  if (L.dim == 2) return fail(SL_EUNSUPPORTED, "two-dimensional meshes are not built into this library yet");
+  if (!L.uniform) return fail(SL_EUNSUPPORTED, "1-D meshes need a uniform order");
+  if (L.K > 256) return fail(SL_EUNSUPPORTED, "1-D meshes with more than 256 elements are not supported yet");
+  if (desc->precision != SL_PREC_FP64) return fail(SL_EUNSUPPORTED, "1-D path runs in float64 only");
+  h->desc = *desc;
+  h->desc.order = nullptr;
+  h->hx = (desc->x1 - desc->x0) / L.kx;
+  h->hy = L.dim == 2 ? (desc->y1 - desc->y0) / L.ky : 1.0;
+  h->family = desc->nodes == SL_NODES_CG ? 1 : 0;
+  h->stream = (hipStream_t)hip_stream;
+  for (int N : L.order)
+    if (!h->xi_tab.count(N)) h->xi_tab[N] = sl::gauss_nodes(N, h->family);
+  h->rec = sl::legendre_recurrence();
+  if (dev_ws) {
+    if (ws_bytes < L.total) return fail(SL_ENOMEM, "workspace smaller than sl_required_bytes");
+    h->ws = (char*)dev_ws;
+  } else {
+    void* p = nullptr;
+    if (hipMalloc(&p, L.total) != hipSuccess) return fail(SL_ENOMEM, "hipMalloc of the workspace failed");
+    h->ws = (char*)p;
+    h->own_ws = true;
+  }
+  h->phi = (double*)(h->ws + L.o_phi);
+  h->tr = (double*)(h->ws + L.o_tr);
+  h->xi_node = (double*)(h->ws + L.o_xi);
+  h->A = (double*)(h->ws + L.o_A);
+  h->B = (double*)(h->ws + L.o_B);
+  h->src = (double*)(h->ws + L.o_src);
+  h->Af = (double*)(h->ws + L.o_Af);
+  h->Bf = (double*)(h->ws + L.o_Bf);
+  h->ghost = (double*)(h->ws + L.o_ghost);
+  h->mean = (double*)(h->ws + L.o_mean);
+  h->phi0 = (double*)(h->ws + L.o_phi0);
+  // reference coordinates of every node, [nodes][dim]
+  std::vector<double> xin(L.nodes * L.dim);
+  for (int e = 0; e < L.K; ++e) {
+    const int N = L.order[e];
+    const auto& xi = h->xi_tab[N];
+    const int n = L.dim == 1 ? N : N * N;
+    for (int i = 0; i < n; ++i) {
+      const int64_t k = L.noff[e] + i;
+      xin[k * L.dim + 0] = xi[i % N];
+      if (L.dim == 2) xin[k * L.dim + 1] = xi[i / N];
+    }
+  }
+  hipError_t e1 = hipMemcpyAsync(h->xi_node, xin.data(), sizeof(double) * xin.size(), hipMemcpyHostToDevice, h->stream);
+  hipError_t e2 = hipMemsetAsync(h->phi, 0, sizeof(double) * (size_t)L.M * L.nodes, h->stream);
+  hipError_t e3 = hipStreamSynchronize(h->stream);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    if (h->own_ws) (void)hipFree(h->ws);
+    return fail(SL_EDEVICE, "initial upload failed");
+  }
+  *out = h.release();
+  return SL_OK;
+}
+
+int sl_sizes(sl_handle h, int64_t* nodes, int64_t* edge_points, int64_t* elements) {
+  if (int rc = check_handle(h)) return rc;
+  if (nodes) *nodes = h->L.nodes;
+  if (edge_points) *edge_points = h->L.edges;
+  if (elements) *elements = h->L.K;
+  return SL_OK;
+}
+
+int sl_ref_nodes(sl_handle h, int32_t N, double* host_xi) {
+  if (int rc = check_handle(h)) return rc;
+  if (N < 1 || N > 64 || !host_xi) return fail(SL_EINVAL, "bad order or null output");
+  const auto xi = sl::gauss_nodes(N, h->family);
+  std::memcpy(host_xi, xi.data(), sizeof(double) * N);
+  return SL_OK;
+}
+
+int sl_node_coords(sl_handle h, double* xy) {
+  if (int rc = check_handle(h)) return rc;
+  if (!xy) return fail(SL_EINVAL, "null output");
+  const Layout& L = h->L;
+  for (int e = 0; e < L.K; ++e) {
+    const int N = L.order[e];
+    const int ex = e % L.kx, ey = e / L.kx;
+    const auto& xi = h->xi_tab[N];
+    const int n = L.dim == 1 ? N : N * N;
+    for (int i = 0; i < n; ++i) {
+      const int64_t k = L.noff[e] + i;
+      xy[k * L.dim] = h->desc.x0 + h->hx * (ex + xi[i % N]);
+      if (L.dim == 2) xy[k * L.dim + 1] = h->desc.y0 + h->hy * (ey + xi[i / N]);
+    }
+  }
+  return SL_OK;
+}
+
+int sl_edge_coords(sl_handle h, double* xy, int32_t* axis) {
+  if (int rc = check_handle(h)) return rc;
+  const Layout& L = h->L;
+  for (int e = 0; e < L.K; ++e) {
+    const int N = L.order[e];
+    const int ex = e % L.kx, ey = e / L.kx;
+    const auto& xi = h->xi_tab[N];
+    if (L.dim == 1) {
+      for (int w = 0; w < 2; ++w) {
+        const int64_t q = L.eoff[e] + w;
+        if (xy) xy[q] = h->desc.x0 + h->hx * (ex + (w == 0 ? 0.0 : 1.0));
+        if (axis) axis[q] = 0;
+      }
+    } else {
+      for (int w = 0; w < 4; ++w)
+        for (int j = 0; j < N; ++j) {
+          const int64_t q = L.eoff[e] + w * N + j;
+          double rx, ry;
+          if (w == 0) { rx = 0.0; ry = xi[j]; }
+          else if (w == 1) { rx = 1.0; ry = xi[j]; }
+          else if (w == 2) { rx = xi[j]; ry = 0.0; }
+          else { rx = xi[j]; ry = 1.0; }
+          if (xy) {
+            xy[2 * q] = h->desc.x0 + h->hx * (ex + rx);
+            xy[2 * q + 1] = h->desc.y0 + h->hy * (ey + ry);
+          }
+          if (axis) axis[q] = w < 2 ? 0 : 1;
+        }
+    }
+  }
+  return SL_OK;
+}
+
+int sl_set_fields(sl_handle h, const double* u, const double* D, const double* divu, const double* un,
+                  const double* Dn, const double* ghost, const double* phi0) {
+  if (int rc = check_handle(h)) return rc;
+  const Layout& L = h->L;
+  if (!u || !D || !un || !Dn) return fail(SL_EINVAL, "u, D, un and Dn are required");
+  if (h->desc.bc == SL_BC_DIRICHLET && !ghost) return fail(SL_EINVAL, "Dirichlet boundaries need ghost values");
+  auto finite = [](const double* p, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(p[i])) return false;
+    return true;
+  };
+  if (!finite(u, L.nodes * L.dim) || !finite(D, L.nodes) || (divu && !finite(divu, L.nodes)) ||
+      !finite(un, L.edges) || !finite(Dn, L.edges) || (ghost && !finite(ghost, L.edges)) ||
+      (phi0 && !finite(phi0, L.nodes)))
+    return fail(SL_ENONFINITE, "non-finite field values");
+  for (int64_t i = 0; i < L.nodes; ++i)
+    if (D[i] < 0) return fail(SL_EINVAL, "D must be >= 0");
+  for (int64_t i = 0; i < L.edges; ++i)
+    if (Dn[i] < 0) return fail(SL_EINVAL, "Dn must be >= 0");
+  h->u.assign(u, u + L.nodes * L.dim);
+  h->D.assign(D, D + L.nodes);
+  if (divu) h->divu.assign(divu, divu + L.nodes);
+  else h->divu.assign(L.nodes, 0.0);
+  h->un.assign(un, un + L.edges);
+  h->Dn.assign(Dn, Dn + L.edges);
+  h->ghost_h.assign(L.edges, 0.0);
+  if (ghost) h->ghost_h.assign(ghost, ghost + L.edges);
+  SL_HIP(hipMemcpyAsync(h->ghost, h->ghost_h.data(), sizeof(double) * L.edges, hipMemcpyHostToDevice, h->stream));
+  if (phi0) {
+    SL_HIP(hipMemcpyAsync(h->phi0, phi0, sizeof(double) * L.nodes, hipMemcpyHostToDevice, h->stream));
+    SL_HIP(sl::launch_broadcast(h->phi, h->phi0, L.M, L.nodes, h->stream));
+    h->step = 0;
+  }
+  SL_HIP(hipStreamSynchronize(h->stream));
+  h->coeff_valid = false;
+  h->fields_set = true;
+  return SL_OK;
+}
+
+int sl_step(sl_handle h, double dt, int32_t nsteps) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->fields_set) return fail(SL_ESTATE, "sl_set_fields must come before sl_step");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(SL_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(SL_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return SL_OK;
+  if (int rc = update_coefficients(h, dt)) return rc;
+  const Layout& L = h->L;
+  const int N = L.order[0];
+  sl::Params1D p{};
+  p.A = h->A;
+  p.B = h->B;
+  p.src = h->src;
+  p.Af = h->Af;
+  p.Bf = h->Bf;
+  p.ghost = h->ghost;
+  p.phi = h->phi;
+  p.K = L.K;
+  p.samples_per_block = sl::resident_1d_samples_per_block(L.K);
+  p.dirichlet = h->desc.bc == SL_BC_DIRICHLET;
+  p.nsteps = nsteps;
+  p.M = L.M;
+  p.step0 = h->step;
+  p.seed = h->desc.seed;
+  p.stream = h->desc.stream_id;
+  p.rec = h->rec;
+  const auto& xi = h->xi_tab[N];
+  for (int i = 0; i < N; ++i) p.xi[i] = xi[i];
+  {
+    ProfScope ps(h, "resident_1d");
+    SL_HIP(sl::launch_resident_1d(N, p, h->stream));
+  }
+  h->step += nsteps;
+  return SL_OK;
+}
+
+int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t nsteps) {
+  if (!hs || !dts || nh < 0) return fail(SL_EINVAL, "bad batch arguments");
+  for (int i = 0; i < nh; ++i)
+    if (int rc = sl_step(hs[i], dts[i], nsteps)) return rc;
+  return SL_OK;
+}
+
+int sl_mean(sl_handle h, double* out, int32_t out_is_device) {
+  if (int rc = check_handle(h)) return rc;
+  if (!out) return fail(SL_EINVAL, "null output");
+  const Layout& L = h->L;
+  double* dst = out_is_device ? out : h->mean;
+  {
+    ProfScope ps(h, "mean");
+    SL_HIP(sl::launch_mean(h->phi, dst, L.M, L.nodes, h->stream));
+  }
+  if (!out_is_device) {
+    SL_HIP(hipMemcpyAsync(out, h->mean, sizeof(double) * L.nodes, hipMemcpyDeviceToHost, h->stream));
+    SL_HIP(hipStreamSynchronize(h->stream));
+  }
+  return SL_OK;
+}
+
+int sl_get_samples(sl_handle h, int64_t s0, int64_t ns, double* out, int32_t out_is_device) {
+  if (int rc = check_handle(h)) return rc;
+  const Layout& L = h->L;
+  if (!out || s0 < 0 || ns < 0 || s0 + ns > L.M) return fail(SL_EINVAL, "sample range out of bounds");
+  SL_HIP(hipMemcpyAsync(out, h->phi + s0 * L.nodes, sizeof(double) * ns * L.nodes,
+                        out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  if (!out_is_device) SL_HIP(hipStreamSynchronize(h->stream));
+  return SL_OK;
+}
+
+int sl_set_samples(sl_handle h, int64_t s0, int64_t ns, const double* in, int32_t in_is_device) {
+  if (int rc = check_handle(h)) return rc;
+  const Layout& L = h->L;
+  if (!in || s0 < 0 || ns < 0 || s0 + ns > L.M) return fail(SL_EINVAL, "sample range out of bounds");
+  SL_HIP(hipMemcpyAsync(h->phi + s0 * L.nodes, in, sizeof(double) * ns * L.nodes,
+                        in_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipStreamSynchronize(h->stream));
+  return SL_OK;
+}
+
+int sl_get_step(sl_handle h, int64_t* n) {
+  if (int rc = check_handle(h)) return rc;
+  if (!n) return fail(SL_EINVAL, "null output");
+  *n = h->step;
+  return SL_OK;
+}
+
+int sl_set_step(sl_handle h, int64_t n) {
+  if (int rc = check_handle(h)) return rc;
+  if (n < 0 || n > 0xFFFFFFFFll) return fail(SL_EINVAL, "step counter out of range");
+  h->step = n;
+  return SL_OK;
+}
+
+int sl_debug_normals(sl_handle h, int64_t n, int64_t s0, int64_t ns, double* out) {
+  if (int rc = check_handle(h)) return rc;
+  if (!out || ns < 0 || s0 < 0 || n < 0) return fail(SL_EINVAL, "bad arguments");
+  if (ns == 0) return SL_OK;
+  double* d = nullptr;
+  SL_HIP(hipMalloc(&d, sizeof(double) * 2 * ns));
+  hipError_t e = sl::launch_debug_normals(d, h->desc.seed, h->desc.stream_id, n, s0, ns, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(SL_EDEVICE, hipGetErrorString(e));
+  return SL_OK;
+}
+
+int sl_debug_positions(sl_handle h, double dt, double* out) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->fields_set) return fail(SL_ESTATE, "fields not set");
+  if (!out || !(dt > 0)) return fail(SL_EINVAL, "bad arguments");
+  if (int rc = update_coefficients(h, dt)) return rc;
+  const Layout& L = h->L;
+  const size_t n = (size_t)L.M * L.nodes * L.dim;
+  double* d = nullptr;
+  SL_HIP(hipMalloc(&d, sizeof(double) * n));
+  hipError_t e = sl::launch_debug_positions(d, h->xi_node, h->A, h->B, L.dim, L.nodes, L.M, h->desc.seed,
+                                            h->desc.stream_id, h->step, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(SL_EDEVICE, hipGetErrorString(e));
+  return SL_OK;
+}
+
+int sl_profile(sl_handle h, int32_t enable) {
+  if (int rc = check_handle(h)) return rc;
+  drain_events(h);
+  if (enable) h->kstats.clear();
+  h->profile = enable != 0;
+  return SL_OK;
+}
+
+int sl_kernel_time(sl_handle h, const char* name, int64_t* launches, double* ms) {
+  if (int rc = check_handle(h)) return rc;
+  if (!name) return fail(SL_EINVAL, "null name");
+  drain_events(h);
+  auto it = h->kstats.find(name);
+  if (launches) *launches = it == h->kstats.end() ? 0 : it->second.launches;
+  if (ms) *ms = it == h->kstats.end() ? 0.0 : it->second.ms;
+  return SL_OK;
+}
+
+int sl_diag(sl_handle h, sl_diag_t* out) {
+  if (int rc = check_handle(h)) return rc;
+  if (!out) return fail(SL_EINVAL, "null output");
+  std::memset(out, 0, sizeof(*out));
+  out->steps = h->step;
+  out->samples = h->L.M;
+  out->nodes = h->L.nodes;
+  out->edge_points = h->L.edges;
+  out->max_disp_ratio = h->max_disp_ratio;
+  out->precision = h->desc.precision;
+  out->refine_iters = h->desc.refine_iters;
+  out->device_bytes = h->L.total;
+  return SL_OK;
+}
+
+int sl_sync(sl_handle h) {
+  if (int rc = check_handle(h)) return rc;
+  SL_HIP(hipStreamSynchronize(h->stream));
+  return SL_OK;
+}
+
+const char* sl_last_error(void) { return g_last_error.c_str(); }
+
+int sl_destroy(sl_handle h) {
+  if (!h) return SL_OK;
+  (void)hipStreamSynchronize(h->stream);
+  drain_events(h);
+  if (h->own_ws && h->ws) (void)hipFree(h->ws);
+  delete h;
+  return SL_OK;
+}
+
+}  // extern "C"

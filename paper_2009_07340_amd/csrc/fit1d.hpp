@@ -1,0 +1,172 @@
+// One-dimensional element fit for one (element, sample) held in one lane.
+//
+// Per element and sample (Sec. 5):
+//   moved nodes xi*_i = xi_i + (A_i + B_i z)                      (eq. def_dx)
+//   carried values f_i = phi_i (1 - dt div u)_i                     (eq. advection_phi)
+//   advected interpolant p0 with p0(xi*_i) = f_i                    (eqs. phi_stardef, h_star)
+//   traces t = (p0(0), p0(1))                                       (eq. remap_bnd)
+//   constrained fit p = argmin sum_i (q(xi*_i) - f_i)^2 s.t. q(0) = g_L, q(1) = g_R
+//   new values phi_i = p(xi_i)                                      (eq. phi_star)
+//
+// Algorithm (range-space Lagrange multipliers on the normal equations):
+// basis psi_k(xi - dbar), dbar the mean node displacement; V the N x N basis
+// matrix at the moved nodes; G = V^T V = L L^T (Cholesky), c0 = G^-1 V^T f;
+// C = [psi(0 - dbar); psi(1 - dbar)] (2 x N); W = G^-1 C^T; S = C W (2 x 2);
+// lambda = S^-1 (C c0 - g); c = c0 - W lambda.  Everything that does not
+// depend on g (the unconstrained values at the Gauss nodes E c0, the columns
+// E W and S) is formed before the boundary values of the neighbours are
+// known, so after the exchange only a 2 x 2 solve and N multiply-adds remain.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "sl_internal.hpp"
+#include "philox.hpp"
+
+namespace sl {
+
+template <int N>
+__device__ __forceinline__ void legendre_eval(double t, const LegendreRec& rec, double (&psi)[N]) {
+  const double x = 2.0 * t - 1.0;
+  psi[0] = 1.0;
+  if constexpr (N > 1) psi[1] = rec.a[0] * x;
+#pragma unroll
+  for (int k = 1; k + 1 < N; ++k) psi[k + 1] = rec.a[k] * x * psi[k] - rec.b[k] * psi[k - 1];
+}
+
+template <int N>
+struct Fit1DPre {
+  double phiu[N];   // unconstrained values at the Gauss nodes, E c0
+  double wl[N];     // E G^-1 psi(0 - dbar)
+  double wr[N];     // E G^-1 psi(1 - dbar)
+  double s00, s01, s11;
+  double tL, tR;    // traces of p0
+};
+
+// Packed lower-triangular index.
+__device__ __forceinline__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+template <int N>
+__device__ __forceinline__ void chol_solve(const double (&L)[N * (N + 1) / 2], const double (&dinv)[N],
+                                           double (&x)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double acc = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) acc -= L[tri(i, k)] * x[k];
+    x[i] = acc * dinv[i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double acc = x[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) acc -= L[tri(k, i)] * x[k];
+    x[i] = acc * dinv[i];
+  }
+}
+
+// Phase before the exchange.  xs: moved nodes; f: carried values; xi: Gauss nodes.
+template <int N>
+__device__ __forceinline__ void fit1d_pre(const double (&xs)[N], const double (&f)[N], const double* xi,
+                                          const LegendreRec& rec, Fit1DPre<N>& out) {
+  double dsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) dsum += xs[i] - xi[i];
+  const double dbar = dsum / N;
+
+  double G[N * (N + 1) / 2];
+  double b[N];
+#pragma unroll
+  for (int k = 0; k < N * (N + 1) / 2; ++k) G[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) b[k] = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double psi[N];
+    legendre_eval<N>(xs[i] - dbar, rec, psi);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+#pragma unroll
+      for (int q = 0; q <= p; ++q) G[tri(p, q)] += psi[p] * psi[q];
+      b[p] += psi[p] * f[i];
+    }
+  }
+  // Cholesky G = L L^T in place (column-oriented, Crout order)
+  double dinv[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double d = G[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= G[tri(j, k)] * G[tri(j, k)];
+    const double ljj = sqrt(d);
+    dinv[j] = 1.0 / ljj;
+    G[tri(j, j)] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      double v = G[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= G[tri(i, k)] * G[tri(j, k)];
+      G[tri(i, j)] = v * dinv[j];
+    }
+  }
+  double pl[N], pr[N];
+  legendre_eval<N>(0.0 - dbar, rec, pl);
+  legendre_eval<N>(1.0 - dbar, rec, pr);
+  double wl[N], wr[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    wl[k] = pl[k];
+    wr[k] = pr[k];
+  }
+  chol_solve<N>(G, dinv, b);   // b <- c0
+  chol_solve<N>(G, dinv, wl);
+  chol_solve<N>(G, dinv, wr);
+  double tL = 0.0, tR = 0.0, s00 = 0.0, s01 = 0.0, s11 = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    tL += pl[k] * b[k];
+    tR += pr[k] * b[k];
+    s00 += pl[k] * wl[k];
+    s01 += pl[k] * wr[k];
+    s11 += pr[k] * wr[k];
+  }
+  out.tL = tL;
+  out.tR = tR;
+  out.s00 = s00;
+  out.s01 = s01;
+  out.s11 = s11;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double psi[N];
+    legendre_eval<N>(xi[i] - dbar, rec, psi);
+    double u = 0.0, a = 0.0, c = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      u += psi[k] * b[k];
+      a += psi[k] * wl[k];
+      c += psi[k] * wr[k];
+    }
+    out.phiu[i] = u;
+    out.wl[i] = a;
+    out.wr[i] = c;
+  }
+}
+
+// Phase after the exchange: new values from the boundary data gL, gR.
+template <int N>
+__device__ __forceinline__ void fit1d_post(const Fit1DPre<N>& pre, double gL, double gR, double (&phi)[N]) {
+  const double r0 = pre.tL - gL, r1 = pre.tR - gR;
+  const double det = pre.s00 * pre.s11 - pre.s01 * pre.s01;
+  const double l0 = (pre.s11 * r0 - pre.s01 * r1) / det;
+  const double l1 = (pre.s00 * r1 - pre.s01 * r0) / det;
+#pragma unroll
+  for (int i = 0; i < N; ++i) phi[i] = pre.phiu[i] - (pre.wl[i] * l0 + pre.wr[i] * l1);
+}
+
+// Moved nodes with the contracted-free operation order of the position contract.
+template <int N>
+__device__ __forceinline__ void move_nodes(const double* xi, const double* A, const double* B, double z,
+                                           double (&xs)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) xs[i] = moved_coord(xi[i], A[i], B[i], z);
+}
+
+}  // namespace sl

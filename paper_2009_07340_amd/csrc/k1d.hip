@@ -1,0 +1,119 @@
+// One-dimensional resident step kernel.
+//
+// Samples never interact (Sec. 5: every Monte-Carlo sample is an independent
+// polynomial field), and a 1-D sample of K <= 256 elements is small (K*N
+// doubles), so one workgroup owns whole samples for all nsteps steps: each
+// lane holds one element's N node values in registers, the element traces are
+// exchanged through LDS (one barrier per step, double-buffered), and HBM is
+// touched only to load the samples at the start and store them at the end.
+//
+// Lane l of a 256-lane workgroup works on element e = l % K of sample slot
+// l / K; a workgroup carries floor(256 / K) samples.
+#include "sl_internal.hpp"
+#include "philox.hpp"
+#include "fit1d.hpp"
+
+namespace sl {
+
+constexpr int kResidentThreads = 256;
+
+int resident_1d_samples_per_block(int K) { return K <= kResidentThreads ? kResidentThreads / K : 0; }
+
+size_t resident_1d_lds_bytes(int K, int spb) { return sizeof(double) * 2 * 2 * (size_t)spb * K; }
+
+template <int N>
+__global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D p) {
+  extern __shared__ double lds_tr[];   // [2 buffers][spb][K][2]
+  const int K = p.K;
+  const int spb = p.samples_per_block;
+  const int lane = threadIdx.x;
+  const int slot = lane / K;
+  const int e = lane - slot * K;
+  const int64_t s = (int64_t)blockIdx.x * spb + slot;
+  const bool active = slot < spb && s < p.M;
+  const int64_t base = s * (int64_t)(K * N) + (int64_t)e * N;
+
+  // A, B and src are shared by all samples and re-read every step (cache hits)
+  const double* A = p.A + e * N;
+  const double* B = p.B + e * N;
+  const double* src = p.src + e * N;
+  double phi[N];
+  double Af0 = 0, Af1 = 0, Bf0 = 0, Bf1 = 0, ghL = 0, ghR = 0;
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) phi[i] = p.phi[base + i];
+    Af0 = p.Af[2 * e];
+    Af1 = p.Af[2 * e + 1];
+    Bf0 = p.Bf[2 * e];
+    Bf1 = p.Bf[2 * e + 1];
+    if (p.dirichlet) {
+      ghL = p.ghost[2 * e];
+      ghR = p.ghost[2 * e + 1];
+    }
+  }
+  const int stride = spb * K * 2;
+  for (int it = 0; it < p.nsteps; ++it) {
+    double* tr = lds_tr + (it & 1) * stride;
+    Fit1DPre<N> pre;
+    double z = 0.0;
+    if (active) {
+      z = normal_pair(p.seed, p.stream, (uint64_t)(p.step0 + it), (uint64_t)s).a;
+      double xs[N], f[N];
+      move_nodes<N>(p.xi, A, B, z, xs);
+#pragma unroll
+      for (int i = 0; i < N; ++i) f[i] = phi[i] * src[i];
+      fit1d_pre<N>(xs, f, p.xi, p.rec, pre);
+      tr[(slot * K + e) * 2 + 0] = pre.tL;
+      tr[(slot * K + e) * 2 + 1] = pre.tR;
+    }
+    __syncthreads();
+    if (active) {
+      // upwind (eq. bnd_update): disp > 0 takes the negative-side element
+      const double dL = __dadd_rn(Af0, __dmul_rn(Bf0, z));
+      const double dR = __dadd_rn(Af1, __dmul_rn(Bf1, z));
+      double nbL, nbR;
+      if (e > 0) nbL = tr[(slot * K + e - 1) * 2 + 1];
+      else nbL = p.dirichlet ? ghL : tr[(slot * K + K - 1) * 2 + 1];
+      if (e < K - 1) nbR = tr[(slot * K + e + 1) * 2 + 0];
+      else nbR = p.dirichlet ? ghR : tr[(slot * K) * 2 + 0];
+      const double gL = (dL > 0.0) ? nbL : pre.tL;
+      const double gR = (dR > 0.0) ? pre.tR : nbR;
+      fit1d_post<N>(pre, gL, gR, phi);
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) p.phi[base + i] = phi[i];
+  }
+}
+
+template <int N>
+static hipError_t launch_n(const Params1D& p, hipStream_t st) {
+  const int64_t blocks = (p.M + p.samples_per_block - 1) / p.samples_per_block;
+  const size_t lds = resident_1d_lds_bytes(p.K, p.samples_per_block);
+  hipLaunchKernelGGL(resident_1d_kernel<N>, dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_resident_1d(int N, const Params1D& p, hipStream_t st) {
+  switch (N) {
+    case 2: return launch_n<2>(p, st);
+    case 3: return launch_n<3>(p, st);
+    case 4: return launch_n<4>(p, st);
+    case 5: return launch_n<5>(p, st);
+    case 6: return launch_n<6>(p, st);
+    case 7: return launch_n<7>(p, st);
+    case 8: return launch_n<8>(p, st);
+    case 9: return launch_n<9>(p, st);
+    case 10: return launch_n<10>(p, st);
+    case 11: return launch_n<11>(p, st);
+    case 12: return launch_n<12>(p, st);
+    case 13: return launch_n<13>(p, st);
+    case 14: return launch_n<14>(p, st);
+    case 15: return launch_n<15>(p, st);
+    case 16: return launch_n<16>(p, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sl

@@ -1,0 +1,18 @@
+// Host-side tables (see tables.cpp).
+#pragma once
+#include <vector>
+#include "sl_internal.hpp"
+
+namespace sl {
+
+// Gauss nodes of order n on [0, 1], increasing, correctly rounded to float64:
+// family 0 = roots of P_n(2 xi - 1) (Gauss-Legendre), 1 = Chebyshev-Gauss.
+std::vector<double> gauss_nodes(int n, int family);
+LegendreRec legendre_recurrence();
+double min_node_spacing(const std::vector<double>& xi);
+// Lagrange interpolation matrix (to.size() x from.size(), row-major).
+std::vector<double> lagrange_matrix(const std::vector<double>& from, const std::vector<double>& to);
+// Orthonormal basis of the edge-value vectors of Q_{N-1} (4N x (4N-4)), column-major.
+std::vector<double> edge_range_basis(int N, const std::vector<double>& xi);
+
+}  // namespace sl

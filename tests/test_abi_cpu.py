@@ -1,0 +1,61 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol,
+and validates descriptors without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sl_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2009_07340_amd import binding as B
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTED) == names
+
+
+def test_required_bytes_counts_state_and_tables():
+    from paper_2009_07340_amd import binding as B
+    d = B.make_desc(1, 256, order=12, samples=1024)
+    nbytes = B.sl_required_bytes(d)
+    assert nbytes >= 1024 * 256 * 12 * 8
+    assert nbytes < 1024 * 256 * 12 * 8 * 1.1
+    d2 = B.make_desc(2, 64, 64, order=8, samples=256)
+    assert B.sl_required_bytes(d2) >= 256 * 4096 * 64 * 8
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dim=3, kx=4), -1), (dict(dim=1, kx=0), -1), (dict(dim=1, kx=4, order=1), -1),
+    (dict(dim=1, kx=4, order=17), -1), (dict(dim=1, kx=4, samples=0), -1),
+    (dict(dim=1, kx=4, box=(1.0, 0.0, 0.0, 1.0)), -1), (dict(dim=1, kx=4, precision=7), -1),
+])
+def test_invalid_descriptors_are_rejected_before_any_device_call(kw, code):
+    from paper_2009_07340_amd import binding as B
+    d = B.make_desc(**kw)
+    with pytest.raises(B.SLError) as ei:
+        B.sl_required_bytes(d)
+    assert ei.value.code == code
+    with pytest.raises(B.SLError) as ei:
+        B.sl_init_mesh(d)
+    assert ei.value.code == code
+    assert B.sl_last_error()
+
+
+def test_null_handle_calls_fail_cleanly():
+    from paper_2009_07340_amd import binding as B
+    for call in (lambda: B.sl_step(None, 1e-3, 1), lambda: B.sl_sync(None), lambda: B.sl_get_step(None)):
+        with pytest.raises(B.SLError) as ei:
+            call()
+        assert ei.value.code == -1
+    assert B._lib.sl_destroy(None) == 0
