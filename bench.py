@@ -1,0 +1,186 @@
+"""Throughput benchmark of the semi-Lagrangian Monte-Carlo step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4]
+                [--precision fp64|fp32_refine|bf16split_refine] [--no-cpu-baseline]
+
+One "step" is one pass of the whole hot path (Wiener increments, node moves,
+advected fits, trace exchange, constrained remap) over every sample of the
+workload.  The timed region holds exactly K steps with the samples resident
+in HBM; the value is Monte-Carlo node-updates per second (elements x nodes x
+samples x steps / seconds).  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X = {"fp64_vector_tflops": 78.6, "fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3,
+          "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0}
+
+
+def fit_flops_1d(N):
+    """Algorithmic float64 operations of one 1-D element fit and step in the nodal form the
+    kernel runs (see the design notes): moves 3N, carried values N, barycentric weights
+    2N^2 - 2N, two edge Lagrange rows 12N, traces and S 10N, multipliers 13, corrected
+    values 4N, Lagrange rows at the N Gauss nodes 6N^2 and their dot products 2N^2."""
+    return 10 * N * N + 28 * N + 13
+
+
+def fit_flops_2d_phase2(N):
+    """Algorithmic float64 operations of one 2-D fit in the second (constrained) phase:
+    Gram n^2 (n+1) (symmetric), right side 2n^2, Cholesky n^3/3, two solves 4n^2,
+    C_r^T = C^T U_r 2 n T R, Y = L^-1 C_r^T n^2 R, S = Y^T Y n R (R+1), Cholesky of S R^3/3,
+    multiplier solves 2R^2, Y lambda 2nR, L^-T solve 2n^2, evaluation at the nodes 2nN
+    (sum-factorised)  --  n = N^2, T = 4N, R = 4N - 4."""
+    n, T, R = N * N, 4 * N, 4 * N - 4
+    return n * n * (n + 1) + 2 * n * n + n ** 3 / 3.0 + 4 * n * n + 2 * n * T * R + n * n * R \
+        + n * R * (R + 1) + R ** 3 / 3.0 + 2 * R * R + 2 * n * R + 2 * n * n + 2 * n * N
+
+
+def kernel_name(wl):
+    return "resident_1d" if wl.dim == 1 else "fit2d_phase2"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--samples", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by samples, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2009_07340_amd import binding as B
+    from paper_2009_07340_amd import workloads as W
+    from paper_2009_07340_amd.problem import Problem
+
+    wl = W.WORKLOADS[args.workload]()
+    if args.samples:
+        wl.samples = args.samples
+    steps = args.steps if args.steps is not None else wl.steps
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    nbytes = Problem.required_bytes(wl, args.precision)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)       # device memory from torch
+    prob = Problem(wl, precision=args.precision, dev_ws=ws.data_ptr(), ws_bytes=nbytes,
+                   hip_stream=stream.cuda_stream)
+    prob.set_fields()
+    print(f"[bench] {wl.name}: K={wl.K} samples={wl.samples} dt={wl.dt} warmup={args.warmup} steps={steps}",
+          file=sys.stderr, flush=True)
+    if args.warmup:
+        prob.step(wl.dt, args.warmup)
+    torch.cuda.synchronize()
+    B.sl_profile(prob.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.step(wl.dt, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kname = kernel_name(wl)
+    launches, kms = B.sl_kernel_time(prob.h, kname)
+    B.sl_profile(prob.h, False)
+    elapsed = t1 - t0
+    nodes_per_sample = prob.nodes
+    node_updates = float(nodes_per_sample) * wl.samples * steps
+    value = node_updates / elapsed
+    mean = prob.mean()
+    finite = bool(np.all(np.isfinite(mean)))
+    print(f"[bench] timed {steps} steps in {elapsed * 1e3:.2f} ms; {kname}: {launches} launches {kms:.2f} ms; "
+          f"mean finite={finite} max|mean|={float(np.max(np.abs(mean))):.4g}", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel
+    if wl.dim == 1:
+        N = int(wl.order)
+        flops = fit_flops_1d(N) * wl.K * wl.samples * steps
+        achieved = flops / (kms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X["fp64_vector_tflops"],
+                "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_vector_tflops"], 4), "traffic": None,
+                "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
+                "flops_per_fit_step": round(fit_flops_1d(N), 1)}
+    else:
+        orders = wl.order_array()
+        per_launch = sum(fit_flops_2d_phase2(int(N)) for N in orders) * wl.samples
+        flops = per_launch * launches
+        achieved = flops / (kms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": MI355X["fp64_mfma_tflops"],
+                "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_mfma_tflops"], 4), "traffic": None,
+                "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
+                "flops_per_launch": per_launch}
+
+    if args.pmc_calibrate:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 1073741824 bytes read, 1073741824 written", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+    prob.close()
+    out = {
+        "metric": "MC node-updates/s at fixed L2 error vs FP64 oracle",
+        "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else args.precision, "data": "synthetic",
+        "config": {"workload": wl.name, "dim": wl.dim, "elements": wl.K, "order": int(wl.order) if np.isscalar(wl.order) else "mixed",
+                   "samples": wl.samples, "dt": wl.dt, "dt_specified": wl.dt_specified, "precision": args.precision,
+                   "fits_per_step": wl.K * wl.samples, "nodes_per_sample": nodes_per_sample,
+                   "element_sample_fits_per_s": wl.K * wl.samples * steps / elapsed},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, seconds):
+    """The FP64 oracle on the host, one thread, on a bounded sample of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import sl
+    x0, x1, y0, y1 = wl.box
+    mesh = sl.Mesh(dim=wl.dim, kx=wl.kx, ky=wl.ky, x0=x0, x1=x1, y0=y0, y1=y1, order=wl.order_array(), bc=wl.bc)
+    ax = []
+    for e in range(mesh.K):
+        N = int(mesh.order[e])
+        ax += [0, 0] if mesh.dim == 1 else [0] * (2 * N) + [1] * (2 * N)
+    a = wl.sample_fields(mesh.node_coords(), mesh.edge_coords(), np.array(ax))
+    f = sl.Fields(u=a["u"], D=a["D"], divu=a["divu"], un=a["un"], Dn=a["Dn"], ghost=a["ghost"])
+    ns = 8 if wl.dim == 1 else 1
+    samples = np.arange(ns)
+    phi = np.broadcast_to(a["phi0"], (ns, mesh.total_nodes)).copy()
+    done = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds and done < wl.steps:
+            z = sl.wiener_normals(mesh, wl.seed, done, samples)
+            phi, _ = sl.step(mesh, f, phi, wl.dt, z)
+            done += 1
+        el = time.perf_counter() - t0
+    value = float(mesh.total_nodes) * ns * done / el
+    print(f"[bench] cpu oracle: {ns} samples x {done} steps in {el:.2f} s", file=sys.stderr, flush=True)
+    return {"value": value, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{ns} of {wl.samples} samples x first {done} of {wl.steps} steps, all {wl.K} elements "
+                      f"(samples are independent, so the rate scales to the full run)"}
+
+
+if __name__ == "__main__":
+    main()

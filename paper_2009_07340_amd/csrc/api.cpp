@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -51,8 +52,11 @@ struct Layout {
   int64_t nodes = 0, edges = 0, M = 0;
   int maxN = 0;
   bool uniform = true;
+  std::vector<int> orders;          // distinct orders present, increasing
+  size_t ur_doubles = 0, interp_doubles = 0;
   // byte offsets in the workspace
-  size_t o_phi, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0, total;
+  size_t o_phi, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
+  size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff, total;
 };
 
 int make_layout(const sl_mesh_desc* d, Layout& L) {
@@ -92,6 +96,15 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.nodes = L.noff[L.K];
   L.edges = L.eoff[L.K];
   L.M = d->samples;
+  for (int N : L.order)
+    if (std::find(L.orders.begin(), L.orders.end(), N) == L.orders.end()) L.orders.push_back(N);
+  std::sort(L.orders.begin(), L.orders.end());
+  if (L.dim == 2) {
+    for (int N : L.orders) L.ur_doubles += (size_t)(4 * N) * (4 * N - 4);
+    for (int Nd : L.orders)
+      for (int Ns : L.orders)
+        if (Nd != Ns) L.interp_doubles += (size_t)Nd * Ns;
+  }
   if ((double)L.M * (double)L.nodes * 8.0 > 250e9) return fail(SL_ENOMEM, "state exceeds device memory");
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -110,6 +123,16 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_ghost = take(sizeof(double) * L.edges);
   L.o_mean = take(sizeof(double) * L.nodes);
   L.o_phi0 = take(sizeof(double) * L.nodes);
+  L.o_order = take(sizeof(int32_t) * L.K);
+  L.o_noff = take(sizeof(int64_t) * L.K);
+  L.o_eoff = take(sizeof(int64_t) * L.K);
+  L.o_nbr = take(sizeof(int32_t) * 4 * (size_t)L.K);
+  L.o_work = take(sizeof(int32_t) * L.K);
+  L.o_xitab = take(sizeof(double) * (sl::kMaxN + 1) * sl::kMaxN);
+  L.o_ur = take(sizeof(double) * (L.ur_doubles + 1));
+  L.o_uroff = take(sizeof(int64_t) * (sl::kMaxN + 1));
+  L.o_interp = take(sizeof(double) * (L.interp_doubles + 1));
+  L.o_interpoff = take(sizeof(int64_t) * (sl::kMaxN + 1) * (sl::kMaxN + 1));
   L.total = o;
   return SL_OK;
 }
@@ -126,6 +149,11 @@ struct sl_ctx {
   char* ws = nullptr;
   double *phi = nullptr, *tr = nullptr, *xi_node = nullptr, *A = nullptr, *B = nullptr, *src = nullptr;
   double *Af = nullptr, *Bf = nullptr, *ghost = nullptr, *mean = nullptr, *phi0 = nullptr;
+  // 2-D tables
+  int32_t *d_order = nullptr, *d_nbr = nullptr, *d_work = nullptr;
+  int64_t *d_noff = nullptr, *d_eoff = nullptr, *d_uroff = nullptr, *d_interpoff = nullptr;
+  double *d_xitab = nullptr, *d_ur = nullptr, *d_interp = nullptr;
+  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> groups;   // (N, (first work index, count))
   std::map<int, std::vector<double>> xi_tab;    // reference nodes per order
   sl::LegendreRec rec{};
   // host copies of the fields
@@ -136,6 +164,7 @@ struct sl_ctx {
   double coeff_dt = 0.0;
   double max_disp_ratio = 0.0;
   int64_t step = 0;
+  int algo_1d = 0;      // 0 nodal form, 1 Legendre normal equations (SL_1D_FIT=normal, for tests)
   // measurement
   bool profile = false;
   std::vector<PendingEvent> pending;
@@ -255,10 +284,10 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   int rc = make_layout(desc, h->L);
   if (rc) return rc;
   const Layout& L = h->L;
-  if (L.dim == 2) return fail(SL_EUNSUPPORTED, "two-dimensional meshes are not built into this library yet");
-  if (!L.uniform) return fail(SL_EUNSUPPORTED, "1-D meshes need a uniform order");
-  if (L.K > 256) return fail(SL_EUNSUPPORTED, "1-D meshes with more than 256 elements are not supported yet");
-  if (desc->precision != SL_PREC_FP64) return fail(SL_EUNSUPPORTED, "1-D path runs in float64 only");
+  if (L.dim == 1 && !L.uniform) return fail(SL_EUNSUPPORTED, "1-D meshes need a uniform order");
+  if (L.dim == 1 && L.K > 256) return fail(SL_EUNSUPPORTED, "1-D meshes with more than 256 elements are not supported yet");
+  if (L.dim == 2 && L.maxN > sl::kMaxN2D) return fail(SL_EUNSUPPORTED, "2-D meshes support N <= 10 in this build");
+  if (desc->precision != SL_PREC_FP64) return fail(SL_EUNSUPPORTED, "this build runs the float64 mode only");
   h->desc = *desc;
   h->desc.order = nullptr;
   h->hx = (desc->x1 - desc->x0) / L.kx;
@@ -268,6 +297,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   for (int N : L.order)
     if (!h->xi_tab.count(N)) h->xi_tab[N] = sl::gauss_nodes(N, h->family);
   h->rec = sl::legendre_recurrence();
+  if (const char* a = std::getenv("SL_1D_FIT")) h->algo_1d = std::strcmp(a, "normal") == 0 ? 1 : 0;
   if (dev_ws) {
     if (ws_bytes < L.total) return fail(SL_ENOMEM, "workspace smaller than sl_required_bytes");
     h->ws = (char*)dev_ws;
@@ -288,6 +318,84 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->ghost = (double*)(h->ws + L.o_ghost);
   h->mean = (double*)(h->ws + L.o_mean);
   h->phi0 = (double*)(h->ws + L.o_phi0);
+  h->d_order = (int32_t*)(h->ws + L.o_order);
+  h->d_noff = (int64_t*)(h->ws + L.o_noff);
+  h->d_eoff = (int64_t*)(h->ws + L.o_eoff);
+  h->d_nbr = (int32_t*)(h->ws + L.o_nbr);
+  h->d_work = (int32_t*)(h->ws + L.o_work);
+  h->d_xitab = (double*)(h->ws + L.o_xitab);
+  h->d_ur = (double*)(h->ws + L.o_ur);
+  h->d_uroff = (int64_t*)(h->ws + L.o_uroff);
+  h->d_interp = (double*)(h->ws + L.o_interp);
+  h->d_interpoff = (int64_t*)(h->ws + L.o_interpoff);
+  // element tables, work list grouped by order, node tables, U_r and trace interpolation
+  std::vector<int32_t> nbr(4 * (size_t)L.K, -1), work;
+  for (int e = 0; e < L.K; ++e) {
+    const int ex = e % L.kx, ey = e / L.kx;
+    const int dx[4] = {-1, 1, 0, 0}, dy[4] = {0, 0, -1, 1};
+    for (int w = 0; w < 4; ++w) {
+      int nx = ex + dx[w], ny = ey + dy[w];
+      if (desc->bc == SL_BC_PERIODIC) {
+        nx = (nx + L.kx) % L.kx;
+        ny = (ny + L.ky) % L.ky;
+        nbr[4 * e + w] = ny * L.kx + nx;
+      } else if (nx >= 0 && nx < L.kx && ny >= 0 && ny < L.ky) {
+        nbr[4 * e + w] = ny * L.kx + nx;
+      }
+    }
+  }
+  for (auto it = L.orders.rbegin(); it != L.orders.rend(); ++it) {   // largest fits first
+    const int N = *it;
+    const int64_t first = (int64_t)work.size();
+    for (int e = 0; e < L.K; ++e)
+      if (L.order[e] == N) work.push_back(e);
+    h->groups.push_back({N, {first, (int64_t)work.size() - first}});
+  }
+  std::vector<double> xitab((sl::kMaxN + 1) * sl::kMaxN, 0.0);
+  for (int N = 1; N <= sl::kMaxN; ++N) {
+    const auto xi = sl::gauss_nodes(N, h->family);
+    for (int i = 0; i < N; ++i) xitab[N * sl::kMaxN + i] = xi[i];
+  }
+  std::vector<double> ur(L.ur_doubles + 1, 0.0), interp(L.interp_doubles + 1, 0.0);
+  std::vector<int64_t> uroff(sl::kMaxN + 1, 0), interpoff((sl::kMaxN + 1) * (sl::kMaxN + 1), 0);
+  if (L.dim == 2) {
+    size_t o = 0;
+    for (int N : L.orders) {
+      const auto U = sl::edge_range_basis(N, h->xi_tab[N]);
+      uroff[N] = (int64_t)o;
+      std::copy(U.begin(), U.end(), ur.begin() + o);
+      o += U.size();
+    }
+    o = 0;
+    for (int Nd : L.orders)
+      for (int Ns : L.orders)
+        if (Nd != Ns) {
+          const auto Lm = sl::lagrange_matrix(h->xi_tab[Ns], h->xi_tab[Nd]);
+          interpoff[Nd * (sl::kMaxN + 1) + Ns] = (int64_t)o;
+          std::copy(Lm.begin(), Lm.end(), interp.begin() + o);
+          o += Lm.size();
+        }
+  }
+  std::vector<int64_t> noff64(L.noff.begin(), L.noff.end() - 1), eoff64(L.eoff.begin(), L.eoff.end() - 1);
+  std::vector<int32_t> order32(L.order.begin(), L.order.end());
+  struct Up { void* dst; const void* src; size_t bytes; };
+  const Up ups[] = {
+      {h->d_order, order32.data(), sizeof(int32_t) * L.K}, {h->d_noff, noff64.data(), sizeof(int64_t) * L.K},
+      {h->d_eoff, eoff64.data(), sizeof(int64_t) * L.K}, {h->d_nbr, nbr.data(), sizeof(int32_t) * nbr.size()},
+      {h->d_work, work.data(), sizeof(int32_t) * work.size()}, {h->d_xitab, xitab.data(), sizeof(double) * xitab.size()},
+      {h->d_ur, ur.data(), sizeof(double) * ur.size()}, {h->d_uroff, uroff.data(), sizeof(int64_t) * uroff.size()},
+      {h->d_interp, interp.data(), sizeof(double) * interp.size()},
+      {h->d_interpoff, interpoff.data(), sizeof(int64_t) * interpoff.size()}};
+  for (const auto& u : ups) {
+    if (hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+      if (h->own_ws) (void)hipFree(h->ws);
+      return fail(SL_EDEVICE, "table upload failed");
+    }
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) {
+    if (h->own_ws) (void)hipFree(h->ws);
+    return fail(SL_EDEVICE, "table upload failed");
+  }
   // reference coordinates of every node, [nodes][dim]
   std::vector<double> xin(L.nodes * L.dim);
   for (int e = 0; e < L.K; ++e) {
@@ -425,6 +533,46 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
   if (nsteps == 0) return SL_OK;
   if (int rc = update_coefficients(h, dt)) return rc;
   const Layout& L = h->L;
+  if (L.dim == 2) {
+    sl::Params2D p{};
+    p.xi_node = h->xi_node;
+    p.A = h->A;
+    p.B = h->B;
+    p.src = h->src;
+    p.Af = h->Af;
+    p.Bf = h->Bf;
+    p.ghost = h->ghost;
+    p.order = h->d_order;
+    p.noff = h->d_noff;
+    p.eoff = h->d_eoff;
+    p.nbr = h->d_nbr;
+    p.xi_tab = h->d_xitab;
+    p.ur = h->d_ur;
+    p.ur_off = h->d_uroff;
+    p.interp = h->d_interp;
+    p.interp_off = h->d_interpoff;
+    p.phi = h->phi;
+    p.tr = h->tr;
+    p.M = L.M;
+    p.nodes = L.nodes;
+    p.edges = L.edges;
+    p.seed = h->desc.seed;
+    p.stream = h->desc.stream_id;
+    p.rec = h->rec;
+    for (int it = 0; it < nsteps; ++it) {
+      p.step = h->step + it;
+      for (int phase = 1; phase <= 2; ++phase) {
+        ProfScope ps(h, phase == 1 ? "fit2d_phase1" : "fit2d_phase2");
+        for (const auto& g : h->groups) {
+          p.work = h->d_work + g.second.first;
+          p.block0 = 0;
+          SL_HIP(sl::launch_fit2d(phase, g.first, p, g.second.second * L.M, h->stream));
+        }
+      }
+    }
+    h->step += nsteps;
+    return SL_OK;
+  }
   const int N = L.order[0];
   sl::Params1D p{};
   p.A = h->A;
@@ -438,6 +586,7 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
   p.samples_per_block = sl::resident_1d_samples_per_block(L.K);
   p.dirichlet = h->desc.bc == SL_BC_DIRICHLET;
   p.nsteps = nsteps;
+  p.algo = h->algo_1d;
   p.M = L.M;
   p.step0 = h->step;
   p.seed = h->desc.seed;

@@ -150,6 +150,89 @@ __device__ __forceinline__ void fit1d_pre(const double (&xs)[N], const double (&
   }
 }
 
+// The same fit in nodal form: with V square, the constrained values at the
+// moved nodes are a = f - C*^T S^-1 (C* f - g), C* = C V^-1 the Lagrange
+// basis of the moved nodes evaluated at the edges and S = C* C*^T, and the
+// new values are Phi a with Phi = E V^-1 the Lagrange basis evaluated at the
+// Gauss nodes.  Lagrange rows come from the barycentric weights
+// w_j = 1 / prod_{m != j} (x*_j - x*_m) and prefix/suffix products, so the
+// whole fit costs O(N^2) operations and no N x N matrix is ever stored.
+template <int N>
+__device__ __forceinline__ void lagrange_row(const double (&xs)[N], const double (&w)[N], double x,
+                                             double (&l)[N]) {
+  double pre[N];
+  pre[0] = 1.0;
+#pragma unroll
+  for (int m = 1; m < N; ++m) pre[m] = pre[m - 1] * (x - xs[m - 1]);
+  double suf = 1.0;
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    l[j] = w[j] * pre[j] * suf;
+    suf *= (x - xs[j]);
+  }
+}
+
+// State of a nodal fit carried across the trace exchange (5N + 5 values).
+template <int N>
+struct Fit1DNodal {
+  double xs[N];     // moved nodes
+  double w[N];      // barycentric weights of the moved nodes
+  double a[N];      // carried values f (becomes the constrained values a)
+  double cl[N];     // C*: Lagrange rows of the moved nodes at xi = 0 ...
+  double cr[N];     // ... and at xi = 1
+  double s00, s01, s11;
+  double tL, tR;    // traces of p0
+};
+
+template <int N>
+__device__ __forceinline__ void fit1d_nodal_pre(Fit1DNodal<N>& st) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double p = 1.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m)
+      if (m != j) p *= (st.xs[j] - st.xs[m]);
+    st.w[j] = 1.0 / p;
+  }
+  lagrange_row<N>(st.xs, st.w, 0.0, st.cl);
+  lagrange_row<N>(st.xs, st.w, 1.0, st.cr);
+  double tL = 0.0, tR = 0.0, s00 = 0.0, s01 = 0.0, s11 = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    tL += st.cl[j] * st.a[j];
+    tR += st.cr[j] * st.a[j];
+    s00 += st.cl[j] * st.cl[j];
+    s01 += st.cl[j] * st.cr[j];
+    s11 += st.cr[j] * st.cr[j];
+  }
+  st.tL = tL;
+  st.tR = tR;
+  st.s00 = s00;
+  st.s01 = s01;
+  st.s11 = s11;
+}
+
+// After the exchange: a = f - C*^T lambda, lambda = S^-1 (t - g); phi = Phi a.
+template <int N>
+__device__ __forceinline__ void fit1d_nodal_post(Fit1DNodal<N>& st, const double* xi, double gL, double gR,
+                                                 double (&phi)[N]) {
+  const double r0 = st.tL - gL, r1 = st.tR - gR;
+  const double det = st.s00 * st.s11 - st.s01 * st.s01;
+  const double l0 = (st.s11 * r0 - st.s01 * r1) / det;
+  const double l1 = (st.s00 * r1 - st.s01 * r0) / det;
+#pragma unroll
+  for (int j = 0; j < N; ++j) st.a[j] -= st.cl[j] * l0 + st.cr[j] * l1;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double l[N];
+    lagrange_row<N>(st.xs, st.w, xi[i], l);
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) v += l[j] * st.a[j];
+    phi[i] = v;
+  }
+}
+
 // Phase after the exchange: new values from the boundary data gL, gR.
 template <int N>
 __device__ __forceinline__ void fit1d_post(const Fit1DPre<N>& pre, double gL, double gR, double (&phi)[N]) {

@@ -21,7 +21,7 @@ int resident_1d_samples_per_block(int K) { return K <= kResidentThreads ? kResid
 
 size_t resident_1d_lds_bytes(int K, int spb) { return sizeof(double) * 2 * 2 * (size_t)spb * K; }
 
-template <int N>
+template <int N, bool kNodal>
 __global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D p) {
   extern __shared__ double lds_tr[];   // [2 buffers][spb][K][2]
   const int K = p.K;
@@ -54,17 +54,29 @@ __global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D 
   const int stride = spb * K * 2;
   for (int it = 0; it < p.nsteps; ++it) {
     double* tr = lds_tr + (it & 1) * stride;
-    Fit1DPre<N> pre;
-    double z = 0.0;
+    Fit1DPre<N> pre;          // normal-equation form
+    Fit1DNodal<N> nod;        // nodal form
+    double z = 0.0, tL = 0.0, tR = 0.0;
     if (active) {
       z = normal_pair(p.seed, p.stream, (uint64_t)(p.step0 + it), (uint64_t)s).a;
-      double xs[N], f[N];
-      move_nodes<N>(p.xi, A, B, z, xs);
+      if constexpr (kNodal) {
+        move_nodes<N>(p.xi, A, B, z, nod.xs);
 #pragma unroll
-      for (int i = 0; i < N; ++i) f[i] = phi[i] * src[i];
-      fit1d_pre<N>(xs, f, p.xi, p.rec, pre);
-      tr[(slot * K + e) * 2 + 0] = pre.tL;
-      tr[(slot * K + e) * 2 + 1] = pre.tR;
+        for (int i = 0; i < N; ++i) nod.a[i] = phi[i] * src[i];
+        fit1d_nodal_pre<N>(nod);
+        tL = nod.tL;
+        tR = nod.tR;
+      } else {
+        double xs[N], f[N];
+        move_nodes<N>(p.xi, A, B, z, xs);
+#pragma unroll
+        for (int i = 0; i < N; ++i) f[i] = phi[i] * src[i];
+        fit1d_pre<N>(xs, f, p.xi, p.rec, pre);
+        tL = pre.tL;
+        tR = pre.tR;
+      }
+      tr[(slot * K + e) * 2 + 0] = tL;
+      tr[(slot * K + e) * 2 + 1] = tR;
     }
     __syncthreads();
     if (active) {
@@ -76,9 +88,10 @@ __global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D 
       else nbL = p.dirichlet ? ghL : tr[(slot * K + K - 1) * 2 + 1];
       if (e < K - 1) nbR = tr[(slot * K + e + 1) * 2 + 0];
       else nbR = p.dirichlet ? ghR : tr[(slot * K) * 2 + 0];
-      const double gL = (dL > 0.0) ? nbL : pre.tL;
-      const double gR = (dR > 0.0) ? pre.tR : nbR;
-      fit1d_post<N>(pre, gL, gR, phi);
+      const double gL = (dL > 0.0) ? nbL : tL;
+      const double gR = (dR > 0.0) ? tR : nbR;
+      if constexpr (kNodal) fit1d_nodal_post<N>(nod, p.xi, gL, gR, phi);
+      else fit1d_post<N>(pre, gL, gR, phi);
     }
   }
   if (active) {
@@ -91,7 +104,10 @@ template <int N>
 static hipError_t launch_n(const Params1D& p, hipStream_t st) {
   const int64_t blocks = (p.M + p.samples_per_block - 1) / p.samples_per_block;
   const size_t lds = resident_1d_lds_bytes(p.K, p.samples_per_block);
-  hipLaunchKernelGGL(resident_1d_kernel<N>, dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, p);
+  if (p.algo == 1)
+    hipLaunchKernelGGL((resident_1d_kernel<N, false>), dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, p);
+  else
+    hipLaunchKernelGGL((resident_1d_kernel<N, true>), dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, p);
   return hipGetLastError();
 }
 

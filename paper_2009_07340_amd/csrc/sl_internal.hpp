@@ -30,6 +30,7 @@ struct Params1D {
   int samples_per_block;
   int dirichlet;
   int nsteps;
+  int algo;              // 0: nodal (Lagrange) form, 1: Legendre normal equations
   int64_t M;
   int64_t step0;         // Philox step counter of the first step
   uint64_t seed;
@@ -38,7 +39,39 @@ struct Params1D {
   double xi[kMaxN];      // reference nodes
 };
 
+// Step inputs of one order group for the 2-D phase kernels.
+struct Params2D {
+  const double* xi_node;   // [nodes][2] reference coordinates
+  const double* A;         // [nodes][2]
+  const double* B;         // [nodes][2]
+  const double* src;       // [nodes]
+  const double* Af;        // [edges]
+  const double* Bf;        // [edges]
+  const double* ghost;     // [edges]
+  const int32_t* order;    // [K]
+  const int64_t* noff;     // [K] first node of element e
+  const int64_t* eoff;     // [K] first edge point of element e
+  const int32_t* nbr;      // [K][4] neighbour across W, E, S, N (-1: Dirichlet boundary)
+  const int32_t* work;     // elements of this launch (all of one order)
+  const double* xi_tab;    // [(kMaxN+1)][kMaxN] reference nodes of each order
+  const double* ur;        // U_r of each order, column-major (4N x (4N-4))
+  const int64_t* ur_off;   // [kMaxN+1]
+  const double* interp;    // Lagrange matrices between orders (Nd x Ns)
+  const int64_t* interp_off;  // [(kMaxN+1)^2], index Nd*(kMaxN+1) + Ns
+  double* phi;             // [M][nodes]
+  double* tr;              // [M][edges]
+  int64_t M, nodes, edges;
+  int64_t block0;          // first fit of this launch within the group
+  int64_t step;            // Philox step counter
+  uint64_t seed;
+  uint32_t stream;
+  LegendreRec rec;
+};
+
 // Host launchers (defined in the .hip files).
+hipError_t launch_fit2d(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st);
+size_t fit2d_lds_bytes(int N);
+constexpr int kMaxN2D = 10;   // largest order of the 2-D LDS-resident fit
 hipError_t launch_resident_1d(int N, const Params1D& p, hipStream_t st);
 size_t resident_1d_lds_bytes(int K, int samples_per_block);
 int resident_1d_samples_per_block(int K);

@@ -79,7 +79,14 @@ def _parity(B, wl, nsteps, samples_checked, M=None):
     return got, mean, ref, err
 
 
-def test_c1_full_parity_and_mean(B):
+@pytest.fixture(params=["nodal", "normal"])
+def algo(request, monkeypatch):
+    """The 1-D fit in nodal (Lagrange) form and in Legendre normal-equation form."""
+    monkeypatch.setenv("SL_1D_FIT", request.param)
+    return request.param
+
+
+def test_c1_full_parity_and_mean(B, algo):
     wl = W.c1_1d_const()
     got, mean, ref, err = _parity(B, wl, wl.steps, np.arange(wl.samples))
     assert err < TOL
@@ -87,14 +94,22 @@ def test_c1_full_parity_and_mean(B):
     assert np.all(np.isfinite(got))
 
 
-def test_c2_parity_sample_subset(B):
+def test_c2_parity_sample_subset(B, algo):
     wl = W.c2_1d_sine()
     idx = np.array([0, 1, 511, 1023])
     got, mean, ref, err = _parity(B, wl, 200, idx)
     assert err < TOL
 
 
-def test_small_ragged_cases(B):
+@pytest.mark.slow
+def test_c2_parity_full_length(B):
+    """All 1000 steps of the 1-D sinusoidal workload on a few samples."""
+    wl = W.c2_1d_sine()
+    got, mean, ref, err = _parity(B, wl, wl.steps, np.array([3, 700]))
+    assert err < TOL
+
+
+def test_small_ragged_cases(B, algo):
     """K not dividing the 256-lane workgroup, M not filling the last workgroup, several N."""
     for K, N, M in ((3, 2, 5), (7, 5, 37), (24, 9, 11), (200, 4, 3), (256, 16, 2), (1, 6, 4)):
         wl = W.c2_1d_sine()
@@ -104,7 +119,7 @@ def test_small_ragged_cases(B):
         assert err < TOL, (K, N, M, err)
 
 
-def test_dirichlet_parity(B):
+def test_dirichlet_parity(B, algo):
     wl = W.Workload("dir", 1, 12, 1, 7, 9, 1e-5, 15, 4,
                     u=lambda x, y: (0.7 + 0.3 * np.sin(6 * x), np.zeros(np.shape(x))),
                     D=lambda x, y: 0.004 * (1 + 0.5 * np.cos(3 * x)), divu=lambda x, y: 1.8 * np.cos(6 * x),
