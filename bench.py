@@ -95,6 +95,12 @@ def main():
     t1 = time.perf_counter()
     kname = kernel_name(wl)
     launches, kms = B.sl_kernel_time(prob.h, kname)
+    others = {}
+    for other in ("fit2d_phase1", "fit2d_phase2", "resident_1d"):
+        if other != kname:
+            n_o, ms_o = B.sl_kernel_time(prob.h, other)
+            if n_o:
+                others[other] = {"launches": n_o, "ms": round(ms_o, 4)}
     B.sl_profile(prob.h, False)
     elapsed = t1 - t0
     nodes_per_sample = prob.nodes
@@ -102,7 +108,7 @@ def main():
     value = node_updates / elapsed
     mean = prob.mean()
     finite = bool(np.all(np.isfinite(mean)))
-    print(f"[bench] timed {steps} steps in {elapsed * 1e3:.2f} ms; {kname}: {launches} launches {kms:.2f} ms; "
+    print(f"[bench] timed {steps} steps in {elapsed * 1e3:.2f} ms; {kname}: {launches} launches {kms:.2f} ms; {others} "
           f"mean finite={finite} max|mean|={float(np.max(np.abs(mean))):.4g}", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel
@@ -122,7 +128,7 @@ def main():
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": MI355X["fp64_mfma_tflops"],
                 "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_mfma_tflops"], 4), "traffic": None,
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
-                "flops_per_launch": per_launch}
+                "flops_per_launch": per_launch, "other_kernels": others}
 
     if args.pmc_calibrate:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

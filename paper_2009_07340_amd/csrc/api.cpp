@@ -287,7 +287,8 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   if (L.dim == 1 && !L.uniform) return fail(SL_EUNSUPPORTED, "1-D meshes need a uniform order");
   if (L.dim == 1 && L.K > 256) return fail(SL_EUNSUPPORTED, "1-D meshes with more than 256 elements are not supported yet");
   if (L.dim == 2 && L.maxN > sl::kMaxN2D) return fail(SL_EUNSUPPORTED, "2-D meshes support N <= 10 in this build");
-  if (desc->precision != SL_PREC_FP64) return fail(SL_EUNSUPPORTED, "this build runs the float64 mode only");
+  if (L.dim == 1 && desc->precision != SL_PREC_FP64)
+    return fail(SL_EUNSUPPORTED, "the 1-D fit runs in float64 only (it has no dense contraction to lower)");
   h->desc = *desc;
   h->desc.order = nullptr;
   h->hx = (desc->x1 - desc->x0) / L.kx;
@@ -559,6 +560,8 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
     p.seed = h->desc.seed;
     p.stream = h->desc.stream_id;
     p.rec = h->rec;
+    const int mode = h->desc.precision;
+    p.refine = h->desc.refine_iters >= 0 ? h->desc.refine_iters : (mode == SL_PREC_FP32_REFINE ? 2 : mode == SL_PREC_BF16SPLIT_REFINE ? 3 : 0);
     for (int it = 0; it < nsteps; ++it) {
       p.step = h->step + it;
       for (int phase = 1; phase <= 2; ++phase) {
@@ -566,7 +569,7 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
         for (const auto& g : h->groups) {
           p.work = h->d_work + g.second.first;
           p.block0 = 0;
-          SL_HIP(sl::launch_fit2d(phase, g.first, p, g.second.second * L.M, h->stream));
+          SL_HIP(sl::launch_fit2d(phase, g.first, mode, p, g.second.second * L.M, h->stream));
         }
       }
     }
@@ -719,7 +722,8 @@ int sl_diag(sl_handle h, sl_diag_t* out) {
   out->edge_points = h->L.edges;
   out->max_disp_ratio = h->max_disp_ratio;
   out->precision = h->desc.precision;
-  out->refine_iters = h->desc.refine_iters;
+  out->refine_iters = h->desc.refine_iters >= 0 ? h->desc.refine_iters
+                      : (h->desc.precision == SL_PREC_FP32_REFINE ? 2 : h->desc.precision == SL_PREC_BF16SPLIT_REFINE ? 3 : 0);
   out->device_bytes = h->L.total;
   return SL_OK;
 }

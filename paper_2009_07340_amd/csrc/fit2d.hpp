@@ -72,15 +72,20 @@ __device__ __forceinline__ constexpr int tblk(int I, int J) { return I * (I + 1)
 
 // In-place Cholesky of a 16x16 diagonal block whose first m rows/columns are
 // live (the rest is padding and becomes identity), and its inverse into Linv.
-// Lanes 0..15 hold one row each in registers; columns are broadcast with readlane.
-__device__ __forceinline__ void factor_diag(double* D, double* Linv, int m) {
-  const int r = lane_id() & 15;
+// Lanes 0..15 hold one row each in registers; each finished column goes
+// through a 16-entry LDS vector (col) and is read back with wave-uniform
+// addresses, so every lane sees it at the cost of one broadcast LDS read.
+__device__ __forceinline__ void factor_diag(double* D, double* Linv, int m, double* col) {
+  const int l = lane_id();
+  const int r = l & 15;
   double row[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) row[c] = (c <= r) ? D[r * BS + c] : 0.0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const double djj = bcast(row[j], j);
+    if (l == j) col[16] = row[j];
+    wave_sync();
+    const double djj = col[16];
     const double ljj = (j < m) ? sqrt(djj) : 1.0;
     const double inv = 1.0 / ljj;
     double lrj;
@@ -88,25 +93,31 @@ __device__ __forceinline__ void factor_diag(double* D, double* Linv, int m) {
     else if (r > j) lrj = (j < m && r < m) ? row[j] * inv : 0.0;
     else lrj = 0.0;
     row[j] = lrj;
+    if (l < 16) col[r] = lrj;
+    wave_sync();
 #pragma unroll
     for (int c = j + 1; c < 16; ++c) {
-      const double lcj = bcast(lrj, c);
+      const double lcj = col[c];
       if (r >= c) row[c] -= lrj * lcj;
     }
+    wave_sync();
   }
-  // inverse: lane c solves L x = e_c (column c of L^-1); L rows come from lane registers
+  if (l < 16) {
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) D[r * BS + cc] = row[cc];
+  }
+  wave_sync();
+  // inverse: lane c solves L x = e_c (column c of L^-1); rows of L read with uniform addresses
   double x[16];
   const int c = r;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     double acc = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-    for (int k = 0; k < i; ++k) acc -= bcast(row[k], i) * x[k];
-    x[i] = acc / bcast(row[i], i);
+    for (int k = 0; k < i; ++k) acc -= D[i * BS + k] * x[k];
+    x[i] = acc / D[i * BS + i];
   }
-  if (lane_id() < 16) {
-#pragma unroll
-    for (int cc = 0; cc < 16; ++cc) D[r * BS + cc] = row[cc];
+  if (l < 16) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) Linv[i * BS + c] = x[i];
   }
@@ -117,11 +128,11 @@ __device__ __forceinline__ void factor_diag(double* D, double* Linv, int m) {
 // blocks, live size n, padding -> identity).  Linv receives the inverses of
 // the diagonal blocks of L.
 template <int NB>
-__device__ __forceinline__ void cholesky(double* G, double* Linv, int n) {
+__device__ __forceinline__ void cholesky(double* G, double* Linv, int n, double* col) {
 #pragma unroll 1
   for (int kb = 0; kb < NB; ++kb) {
     const int m = n - 16 * kb < 16 ? n - 16 * kb : 16;
-    factor_diag(G + tblk(kb, kb) * BLK, Linv + kb * BLK, m);
+    factor_diag(G + tblk(kb, kb) * BLK, Linv + kb * BLK, m, col);
     const double* Li = Linv + kb * BLK;
     // panel: L(I,kb) = G(I,kb) Linv(kb)^T
 #pragma unroll 1

@@ -65,12 +65,13 @@ struct Params2D {
   int64_t step;            // Philox step counter
   uint64_t seed;
   uint32_t stream;
+  int refine;              // float64 refinement sweeps (mixed-precision modes)
   LegendreRec rec;
 };
 
 // Host launchers (defined in the .hip files).
-hipError_t launch_fit2d(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st);
-size_t fit2d_lds_bytes(int N);
+hipError_t launch_fit2d(int phase, int N, int mode, const Params2D& p, int64_t nfits, hipStream_t st);
+size_t fit2d_lds_bytes(int N, int mode);
 constexpr int kMaxN2D = 10;   // largest order of the 2-D LDS-resident fit
 hipError_t launch_resident_1d(int N, const Params1D& p, hipStream_t st);
 size_t resident_1d_lds_bytes(int K, int samples_per_block);

@@ -19,17 +19,18 @@ def B():
     return binding
 
 
-def _handle(B, wl, a, samples=None):
+def _handle(B, wl, a, samples=None, precision="fp64", refine=-1):
     order = wl.order if np.isscalar(wl.order) else wl.order_array()
-    desc = B.make_desc(2, wl.kx, wl.ky, wl.box, order, bc=wl.bc, samples=samples or wl.samples, seed=wl.seed)
+    desc = B.make_desc(2, wl.kx, wl.ky, wl.box, order, bc=wl.bc, samples=samples or wl.samples, seed=wl.seed,
+                       precision=precision, refine_iters=refine)
     h = B.sl_init_mesh(desc)
     B.sl_set_fields(h, a["u"], a["D"], a["divu"], a["un"], a["Dn"], a["ghost"], a["phi0"])
     return h
 
 
-def _parity(B, wl, nsteps, samples_checked):
+def _parity(B, wl, nsteps, samples_checked, precision="fp64", refine=-1):
     mesh, f, phi0, a = oracle_inputs(wl)
-    h = _handle(B, wl, a)
+    h = _handle(B, wl, a, precision=precision, refine=refine)
     try:
         B.sl_step(h, wl.dt, nsteps)
         got = B.sl_get_samples(h, 0, wl.samples)
@@ -37,7 +38,7 @@ def _parity(B, wl, nsteps, samples_checked):
         B.sl_destroy(h)
     ref = sl.run(mesh, f, phi0, wl.dt, nsteps, wl.seed, np.asarray(samples_checked))
     err = rel_l2(got[samples_checked], ref)
-    print(f"{wl.name} {wl.kx}x{wl.ky}: {nsteps} steps: rel L2 {err:.3e}", flush=True)
+    print(f"{wl.name} {wl.kx}x{wl.ky} {precision}: {nsteps} steps: rel L2 {err:.3e}", flush=True)
     return got, ref, err
 
 
@@ -125,3 +126,65 @@ def test_2d_mean_and_determinism(B):
     finally:
         B.sl_destroy(h1)
         B.sl_destroy(h2)
+
+
+MODES = ["fp32_refine", "bf16split_refine"]
+
+
+@pytest.mark.parametrize("precision", MODES)
+@pytest.mark.parametrize("N", [3, 6, 8, 10])
+def test_mixed_precision_small_parity(B, precision, N):
+    """float32 / bf16-split factorisations with float64 refinement reach the float64 tolerance."""
+    wl = _small(N, samples=2, rot=True)
+    got, ref, err = _parity(B, wl, 3, np.arange(2), precision=precision)
+    assert err < TOL, (precision, N, err)
+
+
+@pytest.mark.parametrize("precision", MODES)
+def test_mixed_precision_mixed_order_and_dirichlet(B, precision):
+    wl = W.c4_2d_rotation(kx=4, ky=4, samples=2, steps=3)
+    wl.order = np.array([6, 8, 10, 6, 8, 6, 10, 8, 10, 6, 8, 6, 8, 10, 6, 8], dtype=np.int32)
+    wl.dt = 2e-4
+    got, ref, err = _parity(B, wl, 2, np.arange(2), precision=precision)
+    assert err < TOL
+    wl = _small(5, kx=3, ky=2, samples=2, bc="dirichlet")
+    got, ref, err = _parity(B, wl, 2, np.arange(2), precision=precision)
+    assert err < TOL
+
+
+@pytest.mark.parametrize("precision", MODES)
+def test_mixed_precision_c3_subset(B, precision):
+    wl = W.c3_2d_const()
+    got, ref, err = _parity(B, wl, 2, np.array([7]), precision=precision)
+    assert err < TOL
+
+
+def test_refinement_is_what_recovers_accuracy(B):
+    """Without refinement sweeps the float32 path is only float32-accurate."""
+    wl = _small(8, samples=2, rot=True)
+    _, _, err0 = _parity(B, wl, 2, np.arange(2), precision="fp32_refine", refine=0)
+    _, _, err3 = _parity(B, wl, 2, np.arange(2), precision="fp32_refine", refine=3)
+    assert err0 > 1e-9
+    assert err3 < TOL
+
+
+@pytest.mark.parametrize("precision", MODES)
+def test_mixed_precision_all_samples_agree_with_fp64(B, precision):
+    """Every sample of the 64x64 workload (large displacements included) stays finite and
+    matches the float64 GPU path; sample 131 is also checked against the oracle."""
+    wl = W.c3_2d_const()
+    mesh, f, phi0, a = oracle_inputs(wl)
+    out = {}
+    for prec in ("fp64", precision):
+        h = _handle(B, wl, a, precision=prec)
+        try:
+            B.sl_step(h, wl.dt, 4)
+            out[prec] = B.sl_get_samples(h, 0, wl.samples)
+        finally:
+            B.sl_destroy(h)
+    assert np.all(np.isfinite(out[precision]))
+    err = rel_l2(out[precision], out["fp64"])
+    print(f"{precision} vs fp64, all {wl.samples} samples, 4 steps: rel L2 {err:.3e}", flush=True)
+    assert err < TOL
+    ref = sl.run(mesh, f, phi0, wl.dt, 4, wl.seed, np.array([131]))
+    assert rel_l2(out[precision][[131]], ref) < TOL
