@@ -91,72 +91,75 @@ __device__ __forceinline__ void store_acc_t(T* X, typename Mma<T>::acc_t r) {
 
 __device__ __forceinline__ constexpr int tblk(int I, int J) { return I * (I + 1) / 2 + J; }
 
-// Cholesky of one 16x16 diagonal block (first m rows live, padding -> identity)
-// and the inverse of the factor; executed by one wavefront.  Lanes 0..15 own a
-// row each; a finished column goes through col[0..16] in LDS and is read back
-// with wave-uniform addresses.
+// Broadcast lane src's value to the wavefront (src wave-uniform, a constant after unrolling).
+__device__ __forceinline__ double bcast(double x, int src) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_readlane(lo, src);
+  hi = __builtin_amdgcn_readlane(hi, src);
+  return __hiloint2double(hi, lo);
+}
+
+// Cholesky of one 16x16 diagonal block (first m rows live, padding -> identity);
+// the block is overwritten with the inverse of its factor, which is all the
+// panel update and the triangular solves need.  Executed by one wavefront.
+// Lanes 0..15 own a row each in registers; columns travel between lanes with
+// readlane broadcasts (no LDS round trips inside the factorisation).
 template <typename T>
-__device__ __forceinline__ void factor_diag(T* D, T* Linv, int m, double* col) {
+__device__ __forceinline__ void factor_diag(T* D, int m) {
   const int l = lane();
   const int r = l & 15;
   double row[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) row[c] = (c <= r) ? (double)D[r * BS + c] : 0.0;
+  double dinv[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    if (l == j) col[16] = row[j];
-    wave_sync();
-    const double djj = col[16];
+    const double djj = bcast(row[j], j);
     const double ljj = (j < m) ? sqrt(djj) : 1.0;
     const double inv = 1.0 / ljj;
+    dinv[j] = inv;
     double lrj;
     if (r == j) lrj = ljj;
     else if (r > j) lrj = (j < m && r < m) ? row[j] * inv : 0.0;
     else lrj = 0.0;
     row[j] = lrj;
-    if (l < 16) col[r] = lrj;
-    wave_sync();
 #pragma unroll
     for (int c = j + 1; c < 16; ++c) {
-      const double lcj = col[c];
+      const double lcj = bcast(lrj, c);
       if (r >= c) row[c] -= lrj * lcj;
     }
-    wave_sync();
   }
-  if (l < 16) {
-#pragma unroll
-    for (int cc = 0; cc < 16; ++cc) D[r * BS + cc] = (T)row[cc];
-  }
-  wave_sync();
+  // inverse: lane r solves L x = e_r (column r of L^-1); L[i][k] = readlane(row[k], i)
   double x[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     double acc = (i == r) ? 1.0 : 0.0;
 #pragma unroll
-    for (int k = 0; k < i; ++k) acc -= (double)D[i * BS + k] * x[k];
-    x[i] = acc / (double)D[i * BS + i];
+    for (int k = 0; k < i; ++k) acc -= bcast(row[k], i) * x[k];
+    x[i] = acc * dinv[i];
   }
   if (l < 16) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) Linv[i * BS + r] = (T)x[i];
+    for (int i = 0; i < 16; ++i) D[i * BS + r] = (T)x[i];
   }
   wave_sync();
 }
 
 // Blocked right-looking Cholesky of a packed lower block matrix (NB x NB blocks,
-// live size n).  Whole workgroup; diagonal blocks on wavefront 0, panel and
-// trailing blocks spread over the four wavefronts.
+// live size n).  Off-diagonal blocks end up holding L, diagonal blocks the
+// inverses of L's diagonal blocks.  Whole workgroup; diagonal blocks on
+// wavefront 0, panel and trailing blocks spread over the four wavefronts.
 template <typename T, int NB>
-__device__ __forceinline__ void cholesky(T* G, T* Linv, int n, double* col) {
+__device__ __forceinline__ void cholesky(T* G, int n) {
   const int w = wave();
 #pragma unroll 1
   for (int kb = 0; kb < NB; ++kb) {
     if (w == 0) {
       const int m = n - 16 * kb < 16 ? n - 16 * kb : 16;
-      factor_diag<T>(G + tblk(kb, kb) * BLK, Linv + kb * BLK, m, col);
+      factor_diag<T>(G + tblk(kb, kb) * BLK, m);
     }
     block_sync();
-    const T* Li = Linv + kb * BLK;
+    const T* Li = G + tblk(kb, kb) * BLK;
 #pragma unroll 1
     for (int I = kb + 1 + w; I < NB; I += 4) {
       T* P = G + tblk(I, kb) * BLK;
@@ -188,57 +191,43 @@ __device__ __forceinline__ void cholesky(T* G, T* Linv, int n, double* col) {
 
 // Triangular solves with the blocked factor, executed by wavefront 0 (the
 // caller brackets them with block_sync).  v: float64 vector of 16*NB entries in
-// LDS; tmp: 64 doubles.  Lanes are rows (16) x four partial-sum groups.
+// LDS.  Lanes 0..15 own one row of the current block each.
 template <typename T, int NB>
-__device__ __forceinline__ void forward_solve(const T* G, const T* Linv, double* v, double* tmp) {
-  const int l = lane(), r = l & 15, g = l >> 4;
+__device__ __forceinline__ void forward_solve(const T* G, double* v) {
+  const int l = lane(), r = l & 15;
 #pragma unroll 1
   for (int kb = 0; kb < NB; ++kb) {
-    double t = (g == 0) ? v[16 * kb + r] : 0.0;
+    double t = v[16 * kb + r];
     for (int J = 0; J < kb; ++J) {
       const T* LB = G + tblk(kb, J) * BLK;
 #pragma unroll
-      for (int c = 4 * g; c < 4 * g + 4; ++c) t -= (double)LB[r * BS + c] * v[16 * J + c];
+      for (int c = 0; c < 16; ++c) t -= (double)LB[r * BS + c] * v[16 * J + c];
     }
-    tmp[g * 16 + r] = t;
-    wave_sync();
-    if (g == 0) tmp[r] = tmp[r] + tmp[16 + r] + tmp[32 + r] + tmp[48 + r];
-    wave_sync();
-    const T* Li = Linv + kb * BLK;
+    const T* Li = G + tblk(kb, kb) * BLK;
     double y = 0.0;
 #pragma unroll
-    for (int c = 4 * g; c < 4 * g + 4; ++c) y += (double)Li[r * BS + c] * tmp[c];
-    wave_sync();
-    tmp[g * 16 + r] = y;
-    wave_sync();
-    if (g == 0) v[16 * kb + r] = tmp[r] + tmp[16 + r] + tmp[32 + r] + tmp[48 + r];
+    for (int c = 0; c < 16; ++c) y += (double)Li[r * BS + c] * bcast(t, c);
+    if (l < 16) v[16 * kb + r] = y;
     wave_sync();
   }
 }
 
 template <typename T, int NB>
-__device__ __forceinline__ void backward_solve(const T* G, const T* Linv, double* v, double* tmp) {
-  const int l = lane(), r = l & 15, g = l >> 4;
+__device__ __forceinline__ void backward_solve(const T* G, double* v) {
+  const int l = lane(), r = l & 15;
 #pragma unroll 1
   for (int kb = NB - 1; kb >= 0; --kb) {
-    double t = (g == 0) ? v[16 * kb + r] : 0.0;
+    double t = v[16 * kb + r];
     for (int J = kb + 1; J < NB; ++J) {
       const T* LB = G + tblk(J, kb) * BLK;
 #pragma unroll
-      for (int c = 4 * g; c < 4 * g + 4; ++c) t -= (double)LB[c * BS + r] * v[16 * J + c];
+      for (int c = 0; c < 16; ++c) t -= (double)LB[c * BS + r] * v[16 * J + c];
     }
-    tmp[g * 16 + r] = t;
-    wave_sync();
-    if (g == 0) tmp[r] = tmp[r] + tmp[16 + r] + tmp[32 + r] + tmp[48 + r];
-    wave_sync();
-    const T* Li = Linv + kb * BLK;
+    const T* Li = G + tblk(kb, kb) * BLK;
     double x = 0.0;
 #pragma unroll
-    for (int c = 4 * g; c < 4 * g + 4; ++c) x += (double)Li[c * BS + r] * tmp[c];
-    wave_sync();
-    tmp[g * 16 + r] = x;
-    wave_sync();
-    if (g == 0) v[16 * kb + r] = tmp[r] + tmp[16 + r] + tmp[32 + r] + tmp[48 + r];
+    for (int c = 0; c < 16; ++c) x += (double)Li[c * BS + r] * bcast(t, c);
+    if (l < 16) v[16 * kb + r] = x;
     wave_sync();
   }
 }

@@ -49,17 +49,11 @@ struct Lay {
   static constexpr int RB = (R + 15) / 16;
   static constexpr int RP = 16 * RB;
   static constexpr size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
-  // byte offsets
+  // byte offsets: [G][float64 scalars][basis tables | Y][S]; phase 1 needs the
+  // first three only, so it launches with less LDS (more fits per CU)
   static constexpr size_t oG = 0;
-  static constexpr size_t oLinv = a16(oG + sizeof(T) * NB * (NB + 1) / 2 * BLK);
-  static constexpr size_t oTab = a16(oLinv + sizeof(T) * NB * BLK);         // X1, Y1 (float64)
-  static constexpr size_t tabBytes = sizeof(double) * 2 * n * N;
-  static constexpr size_t yBytes = sizeof(double) * NB * RB * BLK;     // Y, S are float64 in every mode
-  // float64 mode: Y overwrites the basis tables once G is formed; mixed modes keep them
-  static constexpr size_t oY = MODE == 0 ? oTab : a16(oTab + tabBytes);
-  static constexpr size_t oS = a16(MODE == 0 ? oTab + (tabBytes > yBytes ? tabBytes : yBytes) : oY + yBytes);
-  static constexpr size_t oSinv = a16(oS + sizeof(double) * RB * (RB + 1) / 2 * BLK);
-  static constexpr size_t oD = a16(oSinv + sizeof(double) * RB * BLK);      // float64 scalars from here
+  static constexpr size_t gBytes = sizeof(T) * NB * (NB + 1) / 2 * BLK;
+  static constexpr size_t oD = a16(oG + gBytes);
   // double-element offsets relative to oD
   static constexpr int dBx = 0;
   static constexpr int dBy = dBx + N * N;
@@ -83,7 +77,14 @@ struct Lay {
   static constexpr int dYs = dXs + n;
   static constexpr int dRed = dYs + n;
   static constexpr int dEnd = dRed + 8;
-  static constexpr size_t total = oD + sizeof(double) * dEnd;
+  static constexpr size_t oTab = a16(oD + sizeof(double) * dEnd);          // X1, Y1 (float64)
+  static constexpr size_t tabBytes = sizeof(double) * 2 * n * N;
+  static constexpr size_t yBytes = sizeof(double) * NB * RB * BLK;       // Y, S are float64 in every mode
+  // float64 mode: Y overwrites the basis tables once G is formed; mixed modes keep them
+  static constexpr size_t oY = MODE == 0 ? oTab : a16(oTab + tabBytes);
+  static constexpr size_t oS = a16(MODE == 0 ? oTab + (tabBytes > yBytes ? tabBytes : yBytes) : oY + yBytes);
+  static constexpr size_t total = a16(oS + sizeof(double) * RB * (RB + 1) / 2 * BLK);
+  static constexpr size_t phase1 = a16(oTab + tabBytes);
 };
 
 template <int N, int MODE>
@@ -92,12 +93,10 @@ struct Ctx {
   using T = typename L::T;
   char* base;
   __device__ T* G() const { return (T*)(base + L::oG); }
-  __device__ T* Linv() const { return (T*)(base + L::oLinv); }
   __device__ double* X1() const { return (double*)(base + L::oTab); }
   __device__ double* Y1() const { return X1() + L::n * N; }
   __device__ double* Y() const { return (double*)(base + L::oY); }
   __device__ double* S() const { return (double*)(base + L::oS); }
-  __device__ double* Sinv() const { return (double*)(base + L::oSinv); }
   __device__ double* d(int off) const { return (double*)(base + L::oD) + off; }
 };
 
@@ -219,8 +218,8 @@ __device__ void g_solve(const Ctx<N, MODE>& x, double* v) {
   using L = Lay<N, MODE>;
   block_sync();
   if (wave() == 0) {
-    forward_solve<typename L::T, L::NB>(x.G(), x.Linv(), v, x.d(L::dTmp));
-    backward_solve<typename L::T, L::NB>(x.G(), x.Linv(), v, x.d(L::dTmp));
+    forward_solve<typename L::T, L::NB>(x.G(), v);
+    backward_solve<typename L::T, L::NB>(x.G(), v);
   }
   block_sync();
 }
@@ -230,8 +229,8 @@ __device__ void s_solve(const Ctx<N, MODE>& x, double* v) {
   using L = Lay<N, MODE>;
   block_sync();
   if (wave() == 0) {
-    forward_solve<double, L::RB>(x.S(), x.Sinv(), v, x.d(L::dTmp));
-    backward_solve<double, L::RB>(x.S(), x.Sinv(), v, x.d(L::dTmp));
+    forward_solve<double, L::RB>(x.S(), v);
+    backward_solve<double, L::RB>(x.S(), v);
   }
   block_sync();
 }
@@ -360,7 +359,7 @@ __device__ void setup_and_factor(const Params2D& p, const Ctx<N, MODE>& x, int e
     }
   }
   block_sync();
-  cholesky<T, NB>(G, x.Linv(), n, x.d(L::dCol));
+  cholesky<T, NB>(G, n);
   // c0 = G^-1 b (refined against float64 residuals in the mixed modes)
   double* c = x.d(L::dC);
   for (int i = t; i < L::NP; i += kThreads) c[i] = b[i];
@@ -496,7 +495,6 @@ __global__ __launch_bounds__(kThreads) void fit2d_phase2(Params2D p) {
   // that S below is the constraint Schur complement of the factored G to
   // float64 accuracy: S is far worse conditioned than G.
   T* Gm = x.G();
-  T* Lv = x.Linv();
   double* Sm = x.S();
   typedef Mma<double> M64;
 #pragma unroll 1
@@ -516,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void fit2d_phase2(Params2D p) {
       store_acc(Tb, acc);
       wave_sync();
       M64::acc_t out = zacc<double>();
-      const T* Li = Lv + kb * BLK;
+      const T* Li = Gm + tblk(kb, kb) * BLK;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) out = M64::mma((double)rowpat(Li, kk), colpat(Tb, kk), out);
       store_acc(Ykc, out);
@@ -544,7 +542,7 @@ __global__ __launch_bounds__(kThreads) void fit2d_phase2(Params2D p) {
     }
   }
   block_sync();
-  cholesky<double, RB>(Sm, x.Sinv(), R, x.d(L::dCol));
+  cholesky<double, RB>(Sm, R);
   // lambda = S^-1 rho_r; c = c0 - L^-T (Y lambda)
   double* lam = x.d(L::dLam);
   for (int i = t; i < L::RP; i += kThreads) lam[i] = rr[i];
@@ -562,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void fit2d_phase2(Params2D p) {
     wv[pr] = acc;
   }
   block_sync();
-  if (w == 0) backward_solve<T, NB>(Gm, Lv, wv, x.d(L::dTmp));
+  if (w == 0) backward_solve<T, NB>(Gm, wv);
   block_sync();
   for (int pr = t; pr < L::NP; pr += kThreads) c[pr] -= wv[pr];
   block_sync();
@@ -630,7 +628,7 @@ __global__ __launch_bounds__(kThreads) void fit2d_phase2(Params2D p) {
 
 template <int N, int MODE>
 static hipError_t launch_phase(int phase, const Params2D& p, int64_t nfits, hipStream_t st) {
-  const size_t lds = Lay<N, MODE>::total;
+  const size_t lds = phase == 1 ? Lay<N, MODE>::phase1 : Lay<N, MODE>::total;
   const int64_t chunk = (int64_t)1 << 30;
   for (int64_t b0 = 0; b0 < nfits; b0 += chunk) {
     Params2D q = p;
