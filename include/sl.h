@@ -168,11 +168,46 @@ int sl_set_fields(sl_handle h, const double* u, const double* D, const double* d
  * nsteps. */
 int sl_step(sl_handle h, double dt, int32_t nsteps);
 
-/* One batched pass: advance nh handles by nsteps steps each, handle i with
- * step dts[i], in shared launches.  Every handle's result equals sl_step on
- * that handle alone.  Work is enqueued on the first handle's stream; the
- * other handles' streams must not have pending work. */
+/* One batched pass (continuous batching of independent problems): advance nh
+ * distinct handles by nsteps steps each, handle i with step dts[i].  The 2-D
+ * handles of one precision mode share one persistent fused launch per phase
+ * and step (their fits of every order in one work list, largest orders
+ * first); the 1-D handles of one order share one resident launch.  Every
+ * handle's result is bitwise equal to sl_step on that handle alone.  All
+ * handles must have been created on the same stream; the batch is enqueued on
+ * it and replayed from a cached hipGraph when the first 2-D handle's schedule
+ * asks for graphs.  nh = 0 is a no-op; a repeated handle is SL_EINVAL. */
 int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t nsteps);
+
+/* Launch schedule of the 2-D step (Sec. 5 fixes only the result, which is the
+ * same bit for bit under every schedule):
+ *   fused = 0: one kernel per order group and phase, one workgroup per fit;
+ *   fused = 1: one persistent kernel per phase over all orders, `grid`
+ *              workgroups (0 = as many as fit on the device at once) pulling
+ *              fits from a device work counter;
+ *   graph = 1: the step is captured once as a hipGraph (device step counter,
+ *              counters cleared by a kernel) and replayed nsteps times.
+ * ms_per_step is what sl_autotune measured (0 if set by hand).  The 1-D step
+ * is one resident launch for all steps whatever the schedule. */
+typedef struct sl_schedule_t {
+  int32_t fused;
+  int32_t graph;
+  int32_t grid;
+  float ms_per_step;
+} sl_schedule_t;
+
+int sl_set_schedule(sl_handle h, const sl_schedule_t* s);
+int sl_get_schedule(sl_handle h, sl_schedule_t* s);
+
+/* Autotuner: time every candidate schedule (per-order / fused with several
+ * grid sizes, each direct and as a graph) over trial_steps steps of size dt
+ * and keep the fastest.  The samples and the step counter are restored
+ * afterwards (a temporary device copy of the samples is allocated for that).
+ * cache_path (may be NULL) names a text file of earlier choices keyed by
+ * dimension, elements per order, samples and precision: a hit applies the
+ * stored schedule without timing, a miss appends the new choice.  The chosen
+ * schedule is returned in *out (may be NULL). */
+int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_path, sl_schedule_t* out);
 
 /* Sample mean at every node (eq. averaged): out[nodes].  out_is_device != 0:
  * out is a device pointer and the call is asynchronous on the handle's

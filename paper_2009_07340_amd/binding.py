@@ -37,6 +37,10 @@ class sl_diag_t(C.Structure):
                 ("device_bytes", C.c_size_t)]
 
 
+class sl_schedule_t(C.Structure):
+    _fields_ = [("fused", C.c_int32), ("graph", C.c_int32), ("grid", C.c_int32), ("ms_per_step", C.c_float)]
+
+
 class SLError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"sl error {code}: {msg}")
@@ -70,6 +74,9 @@ _SIGS = {
     "sl_kernel_time": [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     "sl_diag": [_P, C.POINTER(sl_diag_t)],
     "sl_sync": [_P],
+    "sl_set_schedule": [_P, C.POINTER(sl_schedule_t)],
+    "sl_get_schedule": [_P, C.POINTER(sl_schedule_t)],
+    "sl_autotune": [_P, C.c_double, C.c_int32, C.c_char_p, C.POINTER(sl_schedule_t)],
     "sl_destroy": [_P],
 }
 for _name, _args in _SIGS.items():
@@ -253,6 +260,28 @@ def sl_diag(h):
     d = sl_diag_t()
     _check(_lib.sl_diag(h, C.byref(d)))
     return {k: getattr(d, k) for k, _ in d._fields_}
+
+
+def _sched_dict(s):
+    return {"fused": s.fused, "graph": s.graph, "grid": s.grid, "ms_per_step": s.ms_per_step}
+
+
+def sl_set_schedule(h, fused=0, graph=0, grid=0):
+    s = sl_schedule_t(int(fused), int(graph), int(grid), 0.0)
+    _check(_lib.sl_set_schedule(h, C.byref(s)))
+
+
+def sl_get_schedule(h):
+    s = sl_schedule_t()
+    _check(_lib.sl_get_schedule(h, C.byref(s)))
+    return _sched_dict(s)
+
+
+def sl_autotune(h, dt, trial_steps=3, cache_path=None):
+    s = sl_schedule_t()
+    path = None if cache_path is None else os.fspath(cache_path).encode()
+    _check(_lib.sl_autotune(h, float(dt), int(trial_steps), path, C.byref(s)))
+    return _sched_dict(s)
 
 
 def sl_sync(h):

@@ -7,10 +7,15 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <list>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -56,7 +61,8 @@ struct Layout {
   size_t ur_doubles = 0, interp_doubles = 0;
   // byte offsets in the workspace
   size_t o_phi, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
-  size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff, total;
+  size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
+  size_t o_params, o_dstep, o_ctr, total;
 };
 
 int make_layout(const sl_mesh_desc* d, Layout& L) {
@@ -133,6 +139,9 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_uroff = take(sizeof(int64_t) * (sl::kMaxN + 1));
   L.o_interp = take(sizeof(double) * (L.interp_doubles + 1));
   L.o_interpoff = take(sizeof(int64_t) * (sl::kMaxN + 1) * (sl::kMaxN + 1));
+  L.o_params = take(std::max(sizeof(sl::Params1D), sizeof(sl::Params2D)));
+  L.o_dstep = take(sizeof(int64_t));
+  L.o_ctr = take(2 * sizeof(unsigned long long));
   L.total = o;
   return SL_OK;
 }
@@ -165,6 +174,16 @@ struct sl_ctx {
   double max_disp_ratio = 0.0;
   int64_t step = 0;
   int algo_1d = 0;      // 0 nodal form, 1 Legendre normal equations (SL_1D_FIT=normal, for tests)
+  // launch schedule and its device-side state
+  uint64_t id = 0;                       // unique per handle (graph cache keys)
+  sl_schedule_t sched{0, 0, 0, 0.f};
+  sl::Params1D p1{};                     // step inputs (host copies; device copies at d_p1 / d_p2)
+  sl::Params2D p2{};
+  sl::Params1D* d_p1 = nullptr;
+  sl::Params2D* d_p2 = nullptr;
+  int64_t* d_step = nullptr;             // device step counter (fused / graph schedules)
+  unsigned long long* d_ctr = nullptr;   // work counters of the two phases
+  hipStream_t cap_stream = nullptr;      // private stream for graph capture
   // measurement
   bool profile = false;
   std::vector<PendingEvent> pending;
@@ -263,6 +282,299 @@ int update_coefficients(sl_ctx* h, double dt) {
   return SL_OK;
 }
 
+
+// ---------------------------------------------------------------- launch schedules
+
+int default_refine(int precision) {
+  return precision == SL_PREC_FP32_REFINE ? 2 : precision == SL_PREC_BF16SPLIT_REFINE ? 3 : 0;
+}
+
+// Step inputs of a handle (device pointers into its workspace); the device
+// copy is what the fused and batched kernels read.
+void build_params(sl_ctx* h) {
+  const Layout& L = h->L;
+  if (L.dim == 2) {
+    sl::Params2D& p = h->p2;
+    p = sl::Params2D{};
+    p.xi_node = h->xi_node;
+    p.A = h->A;
+    p.B = h->B;
+    p.src = h->src;
+    p.Af = h->Af;
+    p.Bf = h->Bf;
+    p.ghost = h->ghost;
+    p.order = h->d_order;
+    p.noff = h->d_noff;
+    p.eoff = h->d_eoff;
+    p.nbr = h->d_nbr;
+    p.work = h->d_work;
+    p.xi_tab = h->d_xitab;
+    p.ur = h->d_ur;
+    p.ur_off = h->d_uroff;
+    p.interp = h->d_interp;
+    p.interp_off = h->d_interpoff;
+    p.phi = h->phi;
+    p.tr = h->tr;
+    p.M = L.M;
+    p.nodes = L.nodes;
+    p.edges = L.edges;
+    p.block0 = 0;
+    p.step = 0;
+    p.step_ptr = h->d_step;
+    p.seed = h->desc.seed;
+    p.stream = h->desc.stream_id;
+    p.refine = h->desc.refine_iters >= 0 ? h->desc.refine_iters : default_refine(h->desc.precision);
+    p.rec = h->rec;
+  } else {
+    sl::Params1D& p = h->p1;
+    p = sl::Params1D{};
+    p.A = h->A;
+    p.B = h->B;
+    p.src = h->src;
+    p.Af = h->Af;
+    p.Bf = h->Bf;
+    p.ghost = h->ghost;
+    p.phi = h->phi;
+    p.K = L.K;
+    p.samples_per_block = sl::resident_1d_samples_per_block(L.K);
+    p.dirichlet = h->desc.bc == SL_BC_DIRICHLET;
+    p.nsteps = 0;
+    p.algo = h->algo_1d;
+    p.M = L.M;
+    p.step0 = 0;
+    p.seed = h->desc.seed;
+    p.stream = h->desc.stream_id;
+    p.rec = h->rec;
+    const auto& xi = h->xi_tab[L.order[0]];
+    for (size_t i = 0; i < xi.size(); ++i) p.xi[i] = xi[i];
+  }
+}
+
+int device_cus() {
+  int d = 0, c = 0;
+  if (hipGetDevice(&d) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || c <= 0) return 256;
+  return c;
+}
+
+// Set (set = 1, to each handle's host step counter) or advance the device
+// step counters of the handles and clear their work counters.
+int enqueue_counters(const std::vector<sl_ctx*>& hs, int set, hipStream_t st) {
+  for (size_t c0 = 0; c0 < hs.size(); c0 += sl::kMaxTasks) {
+    sl::StepArgs a{};
+    a.set = set;
+    a.n = (int)std::min<size_t>(sl::kMaxTasks, hs.size() - c0);
+    for (int i = 0; i < a.n; ++i) {
+      a.step[i] = hs[c0 + i]->d_step;
+      a.counter[i] = hs[c0 + i]->d_ctr;
+      a.value[i] = hs[c0 + i]->step;
+    }
+    SL_HIP(sl::launch_step_counters(a, st));
+  }
+  return SL_OK;
+}
+
+// Per-order launches of one phase for one handle.  devstep: the kernels read
+// the device step counter (graph capture), else the host counter `step`.
+int enqueue_perorder(sl_ctx* h, int phase, bool devstep, int64_t step, hipStream_t st) {
+  sl::Params2D p = h->p2;
+  p.step_ptr = devstep ? h->d_step : nullptr;
+  p.step = step;
+  for (const auto& g : h->groups) {
+    p.work = h->d_work + g.second.first;
+    p.block0 = 0;
+    SL_HIP(sl::launch_fit2d(phase, g.first, h->desc.precision, p, g.second.second * h->L.M, st));
+  }
+  return SL_OK;
+}
+
+// Persistent fused launches of one phase over a batch of 2-D handles: one
+// launch per precision mode (and per chunk of kMaxTasks handles / kMaxSegs
+// order segments), each chunk pulling work from its first handle's counter.
+int enqueue_fused(const std::vector<sl_ctx*>& hs, int phase, int grid_req, hipStream_t st) {
+  for (int mode = 0; mode <= 2; ++mode) {
+    std::vector<sl_ctx*> m;
+    for (sl_ctx* h : hs)
+      if (h->desc.precision == mode) m.push_back(h);
+    size_t i = 0;
+    while (i < m.size()) {
+      // take handles while the chunk's segments fit
+      size_t j = i, nseg = 0;
+      while (j < m.size() && j - i < (size_t)sl::kMaxTasks && nseg + m[j]->groups.size() <= (size_t)sl::kMaxSegs)
+        nseg += m[j++]->groups.size();
+      sl::Fused2DArgs a{};
+      struct S { int N, task; int64_t fit0, count; };
+      std::vector<S> segs;
+      for (size_t t = i; t < j; ++t) {
+        a.task[t - i] = m[t]->d_p2;
+        for (const auto& g : m[t]->groups)
+          segs.push_back({g.first, (int)(t - i), g.second.first * m[t]->L.M, g.second.second * m[t]->L.M});
+      }
+      std::stable_sort(segs.begin(), segs.end(), [](const S& x, const S& y) { return x.N > y.N; });
+      int64_t start = 0;
+      size_t lds = 0;
+      a.nseg = 0;
+      for (const S& g : segs) {
+        if (g.count == 0) continue;
+        a.seg[a.nseg] = sl::FusedSeg{start, g.fit0, g.task, g.N};
+        ++a.nseg;
+        start += g.count;
+        lds = std::max(lds, sl::fit2d_lds_bytes(g.N, mode, phase));
+      }
+      a.total = start;
+      a.counter = m[i]->d_ctr + (phase - 1);
+      if (a.total > 0) {
+        const int occ = sl::fit2d_fused_occupancy(phase, mode, lds);
+        if (occ <= 0) return fail(SL_EDEVICE, "fused kernel does not fit on a compute unit");
+        int64_t grid = grid_req > 0 ? grid_req : (int64_t)occ * device_cus();
+        grid = std::min<int64_t>(grid, a.total);
+        SL_HIP(sl::launch_fit2d_fused(phase, mode, a, (int)grid, lds, st));
+      }
+      i = j;
+    }
+  }
+  return SL_OK;
+}
+
+// One whole step (both phases and the counter advance) on the device step counters.
+int enqueue_device_step(const std::vector<sl_ctx*>& hs, int fused, int grid, hipStream_t st, sl_ctx* prof) {
+  for (int phase = 1; phase <= 2; ++phase) {
+    const char* name = fused ? (phase == 1 ? "fit2d_fused_phase1" : "fit2d_fused_phase2")
+                             : (phase == 1 ? "fit2d_phase1" : "fit2d_phase2");
+    std::unique_ptr<ProfScope> ps(prof ? new ProfScope(prof, name) : nullptr);
+    if (fused) {
+      if (int rc = enqueue_fused(hs, phase, grid, st)) return rc;
+    } else {
+      for (sl_ctx* h : hs)
+        if (int rc = enqueue_perorder(h, phase, true, 0, st)) return rc;
+    }
+  }
+  return enqueue_counters(hs, 0, st);
+}
+
+// Graph cache: one captured step per (handles, schedule), least recently used first out.
+struct GraphEntry {
+  std::vector<uint64_t> ids;
+  int fused, grid;
+  hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::list<GraphEntry> g_graphs;
+constexpr size_t kMaxGraphs = 16;
+uint64_t g_next_id = 1;
+
+void purge_graphs(uint64_t id) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+    if (std::find(it->ids.begin(), it->ids.end(), id) != it->ids.end()) {
+      (void)hipGraphExecDestroy(it->exec);
+      it = g_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+int get_graph(const std::vector<sl_ctx*>& hs, int fused, int grid, hipGraphExec_t* out) {
+  std::vector<uint64_t> ids;
+  for (sl_ctx* h : hs) ids.push_back(h->id);
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+      if (it->ids == ids && it->fused == fused && it->grid == grid) {
+        g_graphs.splice(g_graphs.begin(), g_graphs, it);
+        *out = it->exec;
+        return SL_OK;
+      }
+  }
+  sl_ctx* h0 = hs[0];
+  if (!h0->cap_stream) SL_HIP(hipStreamCreateWithFlags(&h0->cap_stream, hipStreamNonBlocking));
+  SL_HIP(hipStreamBeginCapture(h0->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue_device_step(hs, fused, grid, h0->cap_stream, nullptr);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h0->cap_stream, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess) return fail(SL_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ec));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return fail(SL_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  g_graphs.push_front(GraphEntry{ids, fused, grid, exec});
+  while (g_graphs.size() > kMaxGraphs) {
+    (void)hipGraphExecDestroy(g_graphs.back().exec);
+    g_graphs.pop_back();
+  }
+  *out = exec;
+  return SL_OK;
+}
+
+// nsteps steps of a set of 2-D handles (coefficients already current) under a schedule.
+int step_2d(const std::vector<sl_ctx*>& hs, int32_t nsteps, int fused, int graph, int grid, hipStream_t st) {
+  sl_ctx* h0 = hs[0];
+  if (!fused && !graph && hs.size() == 1) {
+    // per-order kernels with the host step counter
+    for (int it = 0; it < nsteps; ++it)
+      for (int phase = 1; phase <= 2; ++phase) {
+        ProfScope ps(h0, phase == 1 ? "fit2d_phase1" : "fit2d_phase2");
+        if (int rc = enqueue_perorder(h0, phase, false, h0->step + it, st)) return rc;
+      }
+  } else {
+    if (int rc = enqueue_counters(hs, 1, st)) return rc;
+    if (graph && !h0->profile) {
+      hipGraphExec_t exec = nullptr;
+      if (int rc = get_graph(hs, fused, grid, &exec)) return rc;
+      for (int it = 0; it < nsteps; ++it) SL_HIP(hipGraphLaunch(exec, st));
+    } else {
+      // direct launches (also what profiling uses, so that every kernel is timed)
+      for (int it = 0; it < nsteps; ++it)
+        if (int rc = enqueue_device_step(hs, fused, grid, st, h0->profile ? h0 : nullptr)) return rc;
+    }
+  }
+  for (sl_ctx* h : hs) h->step += nsteps;
+  return SL_OK;
+}
+
+// Batched resident 1-D launches: one per (order, fit form), chunks of kMaxTasks.
+int step_1d_batch(const std::vector<sl_ctx*>& hs, int32_t nsteps, hipStream_t st) {
+  std::map<std::pair<int, int>, std::vector<sl_ctx*>> by;
+  for (sl_ctx* h : hs) by[{h->L.order[0], h->algo_1d}].push_back(h);
+  for (auto& kv : by) {
+    const auto& v = kv.second;
+    for (size_t c0 = 0; c0 < v.size(); c0 += sl::kMaxTasks) {
+      sl::Batch1DArgs a{};
+      a.ntasks = (int)std::min<size_t>(sl::kMaxTasks, v.size() - c0);
+      a.nsteps = nsteps;
+      size_t lds = 0;
+      a.bstart[0] = 0;
+      for (int t = 0; t < a.ntasks; ++t) {
+        sl_ctx* h = v[c0 + t];
+        const int spb = h->p1.samples_per_block;
+        a.task[t] = h->d_p1;
+        a.step0[t] = h->step;
+        a.bstart[t + 1] = a.bstart[t] + (h->L.M + spb - 1) / spb;
+        lds = std::max(lds, sl::resident_1d_lds_bytes(h->L.K, spb));
+      }
+      ProfScope ps(v[c0], "resident_1d_batch");
+      SL_HIP(sl::launch_resident_1d_batch(kv.first.first, kv.first.second, a, lds, st));
+    }
+  }
+  for (sl_ctx* h : hs) h->step += nsteps;
+  return SL_OK;
+}
+
+std::string tune_key(const sl_ctx* h) {
+  std::ostringstream k;
+  const Layout& L = h->L;
+  k << "dim=" << L.dim << ";K=" << L.kx << "x" << L.ky << ";orders=";
+  for (const auto& g : h->groups) k << g.first << ":" << g.second.second << ",";
+  k << ";M=" << L.M << ";prec=" << h->desc.precision << ";refine=" << h->p2.refine << ";bc=" << h->desc.bc;
+  return k.str();
+}
+
 }  // namespace
 
 extern "C" {
@@ -329,6 +641,10 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_uroff = (int64_t*)(h->ws + L.o_uroff);
   h->d_interp = (double*)(h->ws + L.o_interp);
   h->d_interpoff = (int64_t*)(h->ws + L.o_interpoff);
+  h->d_p1 = (sl::Params1D*)(h->ws + L.o_params);
+  h->d_p2 = (sl::Params2D*)(h->ws + L.o_params);
+  h->d_step = (int64_t*)(h->ws + L.o_dstep);
+  h->d_ctr = (unsigned long long*)(h->ws + L.o_ctr);
   // element tables, work list grouped by order, node tables, U_r and trace interpolation
   std::vector<int32_t> nbr(4 * (size_t)L.K, -1), work;
   for (int e = 0; e < L.K; ++e) {
@@ -409,12 +725,20 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       if (L.dim == 2) xin[k * L.dim + 1] = xi[i / N];
     }
   }
+  build_params(h.get());
   hipError_t e1 = hipMemcpyAsync(h->xi_node, xin.data(), sizeof(double) * xin.size(), hipMemcpyHostToDevice, h->stream);
   hipError_t e2 = hipMemsetAsync(h->phi, 0, sizeof(double) * (size_t)L.M * L.nodes, h->stream);
+  hipError_t e4 = L.dim == 2 ? hipMemcpyAsync(h->d_p2, &h->p2, sizeof(sl::Params2D), hipMemcpyHostToDevice, h->stream)
+                             : hipMemcpyAsync(h->d_p1, &h->p1, sizeof(sl::Params1D), hipMemcpyHostToDevice, h->stream);
+  hipError_t e5 = hipMemsetAsync(h->ws + L.o_dstep, 0, L.o_ctr + 2 * sizeof(unsigned long long) - L.o_dstep, h->stream);
   hipError_t e3 = hipStreamSynchronize(h->stream);
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
     if (h->own_ws) (void)hipFree(h->ws);
     return fail(SL_EDEVICE, "initial upload failed");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    h->id = g_next_id++;
   }
   *out = h.release();
   return SL_OK;
@@ -534,69 +858,11 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
   if (nsteps == 0) return SL_OK;
   if (int rc = update_coefficients(h, dt)) return rc;
   const Layout& L = h->L;
-  if (L.dim == 2) {
-    sl::Params2D p{};
-    p.xi_node = h->xi_node;
-    p.A = h->A;
-    p.B = h->B;
-    p.src = h->src;
-    p.Af = h->Af;
-    p.Bf = h->Bf;
-    p.ghost = h->ghost;
-    p.order = h->d_order;
-    p.noff = h->d_noff;
-    p.eoff = h->d_eoff;
-    p.nbr = h->d_nbr;
-    p.xi_tab = h->d_xitab;
-    p.ur = h->d_ur;
-    p.ur_off = h->d_uroff;
-    p.interp = h->d_interp;
-    p.interp_off = h->d_interpoff;
-    p.phi = h->phi;
-    p.tr = h->tr;
-    p.M = L.M;
-    p.nodes = L.nodes;
-    p.edges = L.edges;
-    p.seed = h->desc.seed;
-    p.stream = h->desc.stream_id;
-    p.rec = h->rec;
-    const int mode = h->desc.precision;
-    p.refine = h->desc.refine_iters >= 0 ? h->desc.refine_iters : (mode == SL_PREC_FP32_REFINE ? 2 : mode == SL_PREC_BF16SPLIT_REFINE ? 3 : 0);
-    for (int it = 0; it < nsteps; ++it) {
-      p.step = h->step + it;
-      for (int phase = 1; phase <= 2; ++phase) {
-        ProfScope ps(h, phase == 1 ? "fit2d_phase1" : "fit2d_phase2");
-        for (const auto& g : h->groups) {
-          p.work = h->d_work + g.second.first;
-          p.block0 = 0;
-          SL_HIP(sl::launch_fit2d(phase, g.first, mode, p, g.second.second * L.M, h->stream));
-        }
-      }
-    }
-    h->step += nsteps;
-    return SL_OK;
-  }
+  if (L.dim == 2) return step_2d({h}, nsteps, h->sched.fused, h->sched.graph, h->sched.grid, h->stream);
   const int N = L.order[0];
-  sl::Params1D p{};
-  p.A = h->A;
-  p.B = h->B;
-  p.src = h->src;
-  p.Af = h->Af;
-  p.Bf = h->Bf;
-  p.ghost = h->ghost;
-  p.phi = h->phi;
-  p.K = L.K;
-  p.samples_per_block = sl::resident_1d_samples_per_block(L.K);
-  p.dirichlet = h->desc.bc == SL_BC_DIRICHLET;
+  sl::Params1D p = h->p1;
   p.nsteps = nsteps;
-  p.algo = h->algo_1d;
-  p.M = L.M;
   p.step0 = h->step;
-  p.seed = h->desc.seed;
-  p.stream = h->desc.stream_id;
-  p.rec = h->rec;
-  const auto& xi = h->xi_tab[N];
-  for (int i = 0; i < N; ++i) p.xi[i] = xi[i];
   {
     ProfScope ps(h, "resident_1d");
     SL_HIP(sl::launch_resident_1d(N, p, h->stream));
@@ -606,9 +872,138 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
 }
 
 int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t nsteps) {
-  if (!hs || !dts || nh < 0) return fail(SL_EINVAL, "bad batch arguments");
+  if (nh < 0 || nsteps < 0) return fail(SL_EINVAL, "nh and nsteps must be >= 0");
+  if (nh == 0 || nsteps == 0) return SL_OK;
+  if (!hs || !dts) return fail(SL_EINVAL, "null batch arrays");
+  std::vector<sl_ctx*> one, two;
+  for (int i = 0; i < nh; ++i) {
+    sl_ctx* h = hs[i];
+    if (!h) return fail(SL_EINVAL, "null handle in batch");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == h) return fail(SL_EINVAL, "a handle appears twice in the batch");
+    if (!h->fields_set) return fail(SL_ESTATE, "sl_set_fields must come before sl_step_batch");
+    if (!(dts[i] > 0) || !std::isfinite(dts[i])) return fail(SL_EINVAL, "dt must be finite and > 0");
+    if (h->stream != hs[0]->stream) return fail(SL_EINVAL, "all handles of a batch must share one stream");
+    (h->L.dim == 2 ? two : one).push_back(h);
+  }
   for (int i = 0; i < nh; ++i)
-    if (int rc = sl_step(hs[i], dts[i], nsteps)) return rc;
+    if (int rc = update_coefficients(hs[i], dts[i])) return rc;
+  hipStream_t st = hs[0]->stream;
+  if (!one.empty())
+    if (int rc = step_1d_batch(one, nsteps, st)) return rc;
+  if (!two.empty())
+    if (int rc = step_2d(two, nsteps, 1, two[0]->sched.graph, two[0]->sched.grid, st)) return rc;
+  return SL_OK;
+}
+
+int sl_set_schedule(sl_handle h, const sl_schedule_t* s) {
+  if (int rc = check_handle(h)) return rc;
+  if (!s) return fail(SL_EINVAL, "null schedule");
+  if ((s->fused != 0 && s->fused != 1) || (s->graph != 0 && s->graph != 1) || s->grid < 0 || s->grid > (1 << 24))
+    return fail(SL_EINVAL, "schedule: fused and graph are 0 or 1, 0 <= grid <= 2^24");
+  h->sched = *s;
+  return SL_OK;
+}
+
+int sl_get_schedule(sl_handle h, sl_schedule_t* s) {
+  if (int rc = check_handle(h)) return rc;
+  if (!s) return fail(SL_EINVAL, "null output");
+  *s = h->sched;
+  return SL_OK;
+}
+
+int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_path, sl_schedule_t* out) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->fields_set) return fail(SL_ESTATE, "sl_set_fields must come before sl_autotune");
+  if (!(dt > 0) || !std::isfinite(dt) || trial_steps < 1) return fail(SL_EINVAL, "dt > 0 and trial_steps >= 1 required");
+  const Layout& L = h->L;
+  if (L.dim == 1) {   // one resident launch for all steps: nothing to choose
+    if (out) *out = h->sched;
+    return SL_OK;
+  }
+  const std::string key = tune_key(h);
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      sl_schedule_t c{};
+      if (ls >> k >> c.fused >> c.graph >> c.grid >> c.ms_per_step && k == key) {
+        if (int rc = sl_set_schedule(h, &c)) return rc;
+        if (out) *out = h->sched;
+        return SL_OK;
+      }
+    }
+  }
+  if (int rc = update_coefficients(h, dt)) return rc;
+  // keep the samples and the step counter; trial steps advance both
+  const size_t bytes = sizeof(double) * (size_t)L.M * L.nodes;
+  void* snap = nullptr;
+  if (hipMalloc(&snap, bytes) != hipSuccess) return fail(SL_ENOMEM, "no device memory for the autotuner's copy of the samples");
+  const int64_t step0 = h->step;
+  const sl_schedule_t keep = h->sched;
+  const bool prof = h->profile;
+  h->profile = false;
+  int rc = SL_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<sl_schedule_t> cand;
+  for (int fused = 0; fused <= 1; ++fused)
+    for (int graph = 0; graph <= 1; ++graph) {
+      if (!fused) {
+        cand.push_back({0, graph, 0, 0.f});
+      } else {
+        cand.push_back({1, graph, 0, 0.f});                    // every resident workgroup
+        cand.push_back({1, graph, device_cus(), 0.f});         // one per compute unit
+        cand.push_back({1, graph, 2 * device_cus(), 0.f});
+      }
+    }
+  sl_schedule_t best{0, 0, 0, 0.f};
+  float best_ms = -1.f;
+  auto fail_dev = [&](hipError_t e) { return fail(SL_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); };
+  hipError_t e = hipMemcpyAsync(snap, h->phi, bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) rc = fail_dev(e);
+  for (size_t c = 0; c < cand.size() && rc == SL_OK; ++c) {
+    h->sched = cand[c];
+    rc = step_2d({h}, 1, cand[c].fused, cand[c].graph, cand[c].grid, h->stream);   // warm-up (and capture)
+    if (rc) break;
+    if ((e = hipEventRecord(e0, h->stream)) != hipSuccess) { rc = fail_dev(e); break; }
+    rc = step_2d({h}, trial_steps, cand[c].fused, cand[c].graph, cand[c].grid, h->stream);
+    if (rc) break;
+    if ((e = hipEventRecord(e1, h->stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+      rc = fail_dev(e);
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= trial_steps;
+    if (best_ms < 0 || ms < best_ms) {
+      best_ms = ms;
+      best = cand[c];
+      best.ms_per_step = ms;
+    }
+  }
+  // restore the samples and the step counter whatever happened
+  e = hipMemcpyAsync(h->phi, snap, bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(snap);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  h->step = step0;
+  h->profile = prof;
+  if (rc == SL_OK && e != hipSuccess) rc = fail_dev(e);
+  if (rc) {
+    h->sched = keep;
+    return rc;
+  }
+  h->sched = best;
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    o << key << " " << best.fused << " " << best.graph << " " << best.grid << " " << best.ms_per_step << "\n";
+  }
+  if (out) *out = best;
   return SL_OK;
 }
 
@@ -740,6 +1135,8 @@ int sl_destroy(sl_handle h) {
   if (!h) return SL_OK;
   (void)hipStreamSynchronize(h->stream);
   drain_events(h);
+  purge_graphs(h->id);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->own_ws && h->ws) (void)hipFree(h->ws);
   delete h;
   return SL_OK;

@@ -22,14 +22,14 @@ int resident_1d_samples_per_block(int K) { return K <= kResidentThreads ? kResid
 size_t resident_1d_lds_bytes(int K, int spb) { return sizeof(double) * 2 * 2 * (size_t)spb * K; }
 
 template <int N, bool kNodal>
-__global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D p) {
-  extern __shared__ double lds_tr[];   // [2 buffers][spb][K][2]
+__device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_tr, int64_t block, int64_t step0,
+                                                 int nsteps) {
   const int K = p.K;
   const int spb = p.samples_per_block;
   const int lane = threadIdx.x;
   const int slot = lane / K;
   const int e = lane - slot * K;
-  const int64_t s = (int64_t)blockIdx.x * spb + slot;
+  const int64_t s = block * spb + slot;
   const bool active = slot < spb && s < p.M;
   const int64_t base = s * (int64_t)(K * N) + (int64_t)e * N;
 
@@ -52,13 +52,13 @@ __global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D 
     }
   }
   const int stride = spb * K * 2;
-  for (int it = 0; it < p.nsteps; ++it) {
+  for (int it = 0; it < nsteps; ++it) {
     double* tr = lds_tr + (it & 1) * stride;
     Fit1DPre<N> pre;          // normal-equation form
     Fit1DNodal<N> nod;        // nodal form
     double z = 0.0, tL = 0.0, tR = 0.0;
     if (active) {
-      z = normal_pair(p.seed, p.stream, (uint64_t)(p.step0 + it), (uint64_t)s).a;
+      z = normal_pair(p.seed, p.stream, (uint64_t)(step0 + it), (uint64_t)s).a;
       if constexpr (kNodal) {
         move_nodes<N>(p.xi, A, B, z, nod.xs);
 #pragma unroll
@@ -97,6 +97,53 @@ __global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D 
   if (active) {
 #pragma unroll
     for (int i = 0; i < N; ++i) p.phi[base + i] = phi[i];
+  }
+}
+
+template <int N, bool kNodal>
+__global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D p) {
+  extern __shared__ double lds_tr[];   // [2 buffers][spb][K][2]
+  resident_1d_body<N, kNodal>(p, lds_tr, blockIdx.x, p.step0, p.nsteps);
+}
+
+// Several problems of one order in one launch; workgroup ranges per problem.
+template <int N, bool kNodal>
+__global__ __launch_bounds__(kResidentThreads) void resident_1d_batch_kernel(Batch1DArgs a) {
+  extern __shared__ double lds_tr[];
+  const int64_t b = blockIdx.x;
+  int t = 0;
+  while (t + 1 < a.ntasks && b >= a.bstart[t + 1]) ++t;
+  resident_1d_body<N, kNodal>(*a.task[t], lds_tr, b - a.bstart[t], a.step0[t], a.nsteps);
+}
+
+template <int N>
+static hipError_t launch_batch_n(const Batch1DArgs& a, int algo, size_t lds, hipStream_t st) {
+  const int64_t blocks = a.bstart[a.ntasks];
+  if (algo == 1)
+    hipLaunchKernelGGL((resident_1d_batch_kernel<N, false>), dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, a);
+  else
+    hipLaunchKernelGGL((resident_1d_batch_kernel<N, true>), dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_resident_1d_batch(int N, int algo, const Batch1DArgs& a, size_t lds, hipStream_t st) {
+  switch (N) {
+    case 2: return launch_batch_n<2>(a, algo, lds, st);
+    case 3: return launch_batch_n<3>(a, algo, lds, st);
+    case 4: return launch_batch_n<4>(a, algo, lds, st);
+    case 5: return launch_batch_n<5>(a, algo, lds, st);
+    case 6: return launch_batch_n<6>(a, algo, lds, st);
+    case 7: return launch_batch_n<7>(a, algo, lds, st);
+    case 8: return launch_batch_n<8>(a, algo, lds, st);
+    case 9: return launch_batch_n<9>(a, algo, lds, st);
+    case 10: return launch_batch_n<10>(a, algo, lds, st);
+    case 11: return launch_batch_n<11>(a, algo, lds, st);
+    case 12: return launch_batch_n<12>(a, algo, lds, st);
+    case 13: return launch_batch_n<13>(a, algo, lds, st);
+    case 14: return launch_batch_n<14>(a, algo, lds, st);
+    case 15: return launch_batch_n<15>(a, algo, lds, st);
+    case 16: return launch_batch_n<16>(a, algo, lds, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

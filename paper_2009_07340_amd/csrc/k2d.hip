@@ -387,15 +387,16 @@ __device__ __forceinline__ void fit_index(const Params2D& p, int64_t b, int& e, 
   e = p.work[w];
 }
 
+__device__ __forceinline__ int64_t step_counter(const Params2D& p) { return p.step_ptr ? *p.step_ptr : p.step; }
+
 template <int N, int MODE>
-__global__ __launch_bounds__(kThreads) void fit2d_phase1(Params2D p) {
-  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+__device__ __forceinline__ void phase1_body(const Params2D& p, char* lds_raw, int64_t fit) {
   using L = Lay<N, MODE>;
   Ctx<N, MODE> x{lds_raw};
   int e;
   int64_t s;
-  fit_index(p, blockIdx.x + p.block0, e, s);
-  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)p.step, (uint64_t)s);
+  fit_index(p, fit, e, s);
+  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)step_counter(p), (uint64_t)s);
   setup_and_factor<N, MODE>(p, x, e, s, z.a, z.b);
   double* tv = x.d(L::dT);
   op_C<N, MODE>(x, x.d(L::dC), tv);
@@ -405,16 +406,15 @@ __global__ __launch_bounds__(kThreads) void fit2d_phase1(Params2D p) {
 }
 
 template <int N, int MODE>
-__global__ __launch_bounds__(kThreads) void fit2d_phase2(Params2D p) {
-  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+__device__ __forceinline__ void phase2_body(const Params2D& p, char* lds_raw, int64_t fit) {
   using L = Lay<N, MODE>;
   using T = typename L::T;
   constexpr int n = L::n, NB = L::NB, TT = L::TT, R = L::R, RB = L::RB;
   Ctx<N, MODE> x{lds_raw};
   int e;
   int64_t s;
-  fit_index(p, blockIdx.x + p.block0, e, s);
-  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)p.step, (uint64_t)s);
+  fit_index(p, fit, e, s);
+  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)step_counter(p), (uint64_t)s);
   setup_and_factor<N, MODE>(p, x, e, s, z.a, z.b);
   const int t = tid(), l = lane(), w = wave();
   const int64_t eoff = p.eoff[e];
@@ -626,6 +626,122 @@ __global__ __launch_bounds__(kThreads) void fit2d_phase2(Params2D p) {
   (void)l;
 }
 
+// One kernel per order and phase: one workgroup per fit of the order group.
+template <int N, int MODE>
+__global__ __launch_bounds__(kThreads) void fit2d_phase1(Params2D p) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  phase1_body<N, MODE>(p, lds_raw, blockIdx.x + p.block0);
+}
+
+template <int N, int MODE>
+__global__ __launch_bounds__(kThreads) void fit2d_phase2(Params2D p) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  phase2_body<N, MODE>(p, lds_raw, blockIdx.x + p.block0);
+}
+
+// Persistent fused kernel over the fits of several orders (and of several
+// problems): a fixed grid of workgroups pulls work items from one list through
+// a device counter.  The list is made of segments (problem, order group),
+// ordered by order, largest first, so the most expensive fits start first and
+// the cheap ones fill the tail.  Every workgroup leaves the loop once the
+// counter passes the end of the list, so the grid always drains.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// One fit of the fused kernel, outlined so that each order gets its own
+// register allocation (the kernel needs as many registers as its largest
+// callee, not the union of every order's live values).  Arguments arrive in
+// vector registers and are made uniform again; the dynamic LDS is named here
+// so that its accesses stay LDS instructions.
+template <int N, int MODE, int PHASE>
+__device__ __attribute__((noinline)) void fused_fit(const Params2D* pp, int64_t fit) {
+  extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+  const uint64_t pv = (uint64_t)uniform64((int64_t)(uintptr_t)pp);
+  const Params2D& p = *(const Params2D*)(uintptr_t)pv;
+  fit = uniform64(fit);
+  if constexpr (PHASE == 1) phase1_body<N, MODE>(p, lds_raw, fit);
+  else phase2_body<N, MODE>(p, lds_raw, fit);
+}
+
+template <int MODE, int PHASE>
+__global__ __launch_bounds__(kThreads) void fit2d_fused(Fused2DArgs a) {
+  __shared__ int64_t item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(a.counter, 1ull);
+    __syncthreads();
+    const int64_t item = uniform64(item_sh);
+    __syncthreads();
+    if (item >= a.total) break;
+    int sg = 0;
+    while (sg + 1 < a.nseg && item >= a.seg[sg + 1].start) ++sg;
+    const Params2D* p = a.task[a.seg[sg].task];
+    const int64_t fit = a.seg[sg].fit0 + (item - a.seg[sg].start);
+    switch (a.seg[sg].N) {
+      case 2: fused_fit<2, MODE, PHASE>(p, fit); break;
+      case 3: fused_fit<3, MODE, PHASE>(p, fit); break;
+      case 4: fused_fit<4, MODE, PHASE>(p, fit); break;
+      case 5: fused_fit<5, MODE, PHASE>(p, fit); break;
+      case 6: fused_fit<6, MODE, PHASE>(p, fit); break;
+      case 7: fused_fit<7, MODE, PHASE>(p, fit); break;
+      case 8: fused_fit<8, MODE, PHASE>(p, fit); break;
+      case 9: fused_fit<9, MODE, PHASE>(p, fit); break;
+      case 10: fused_fit<10, MODE, PHASE>(p, fit); break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+// Set (set != 0) or advance the device step counters of a batch of problems
+// and clear their work counters; a kernel rather than a memset so that it can
+// sit inside a captured graph.
+__global__ void step_counters_kernel(StepArgs a) {
+  const int i = threadIdx.x;
+  if (i < a.n) {
+    if (a.set) *a.step[i] = a.value[i];
+    else *a.step[i] += 1;
+    a.counter[i][0] = 0ull;
+    a.counter[i][1] = 0ull;
+  }
+}
+
+hipError_t launch_step_counters(const StepArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(step_counters_kernel, dim3(1), dim3(kMaxTasks), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int MODE, int PHASE>
+static hipError_t fused_one(const Fused2DArgs& a, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((fit2d_fused<MODE, PHASE>), dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit2d_fused(int phase, int mode, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st) {
+  if (phase == 1) {
+    if (mode == 0) return fused_one<0, 1>(a, grid, lds, st);
+    if (mode == 1) return fused_one<1, 1>(a, grid, lds, st);
+    return fused_one<2, 1>(a, grid, lds, st);
+  }
+  if (mode == 0) return fused_one<0, 2>(a, grid, lds, st);
+  if (mode == 1) return fused_one<1, 2>(a, grid, lds, st);
+  return fused_one<2, 2>(a, grid, lds, st);
+}
+
+template <int MODE, int PHASE>
+static int fused_occ(size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2d_fused<MODE, PHASE>, kThreads, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+int fit2d_fused_occupancy(int phase, int mode, size_t lds) {
+  if (phase == 1) return mode == 0 ? fused_occ<0, 1>(lds) : mode == 1 ? fused_occ<1, 1>(lds) : fused_occ<2, 1>(lds);
+  return mode == 0 ? fused_occ<0, 2>(lds) : mode == 1 ? fused_occ<1, 2>(lds) : fused_occ<2, 2>(lds);
+}
+
 template <int N, int MODE>
 static hipError_t launch_phase(int phase, const Params2D& p, int64_t nfits, hipStream_t st) {
   const size_t lds = phase == 1 ? Lay<N, MODE>::phase1 : Lay<N, MODE>::total;
@@ -655,26 +771,26 @@ static hipError_t launch_modes(int phase, int mode, const Params2D& p, int64_t n
 }
 
 template <int N>
-static size_t lds_modes(int mode) {
+static size_t lds_modes(int mode, int phase) {
   switch (mode) {
-    case 0: return Lay<N, 0>::total;
-    case 1: return Lay<N, 1>::total;
-    case 2: return Lay<N, 2>::total;
+    case 0: return phase == 1 ? Lay<N, 0>::phase1 : Lay<N, 0>::total;
+    case 1: return phase == 1 ? Lay<N, 1>::phase1 : Lay<N, 1>::total;
+    case 2: return phase == 1 ? Lay<N, 2>::phase1 : Lay<N, 2>::total;
     default: return 0;
   }
 }
 
-size_t fit2d_lds_bytes(int N, int mode) {
+size_t fit2d_lds_bytes(int N, int mode, int phase) {
   switch (N) {
-    case 2: return lds_modes<2>(mode);
-    case 3: return lds_modes<3>(mode);
-    case 4: return lds_modes<4>(mode);
-    case 5: return lds_modes<5>(mode);
-    case 6: return lds_modes<6>(mode);
-    case 7: return lds_modes<7>(mode);
-    case 8: return lds_modes<8>(mode);
-    case 9: return lds_modes<9>(mode);
-    case 10: return lds_modes<10>(mode);
+    case 2: return lds_modes<2>(mode, phase);
+    case 3: return lds_modes<3>(mode, phase);
+    case 4: return lds_modes<4>(mode, phase);
+    case 5: return lds_modes<5>(mode, phase);
+    case 6: return lds_modes<6>(mode, phase);
+    case 7: return lds_modes<7>(mode, phase);
+    case 8: return lds_modes<8>(mode, phase);
+    case 9: return lds_modes<9>(mode, phase);
+    case 10: return lds_modes<10>(mode, phase);
     default: return 0;
   }
 }

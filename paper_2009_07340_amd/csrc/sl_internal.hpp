@@ -62,18 +62,62 @@ struct Params2D {
   double* tr;              // [M][edges]
   int64_t M, nodes, edges;
   int64_t block0;          // first fit of this launch within the group
-  int64_t step;            // Philox step counter
+  int64_t step;            // Philox step counter (used when step_ptr is null)
+  const int64_t* step_ptr; // device step counter (graph replay), or null
   uint64_t seed;
   uint32_t stream;
   int refine;              // float64 refinement sweeps (mixed-precision modes)
   LegendreRec rec;
 };
 
+// Fused persistent 2-D launch over several problems (each a device copy of its
+// Params2D with work pointing at the full order-sorted work list).  Segment k
+// covers work items [seg[k].start, seg[k+1].start) (the last one up to total):
+// order seg[k].N of problem seg[k].task, fit indices from seg[k].fit0 on.
+constexpr int kMaxTasks = 32;
+constexpr int kMaxSegs = 64;
+struct FusedSeg {
+  int64_t start;
+  int64_t fit0;
+  int32_t task;
+  int32_t N;
+};
+struct Fused2DArgs {
+  const Params2D* task[kMaxTasks];
+  FusedSeg seg[kMaxSegs];
+  int nseg;
+  int64_t total;
+  unsigned long long* counter;
+};
+
+// Device step and work counters of up to kMaxTasks problems.
+struct StepArgs {
+  int64_t* step[kMaxTasks];
+  unsigned long long* counter[kMaxTasks];   // two per problem (phase 1, phase 2)
+  int64_t value[kMaxTasks];
+  int n;
+  int set;
+};
+
+// Batched 1-D resident launch: problems of one order and form; workgroups
+// [bstart[t], bstart[t+1]) belong to problem t.
+struct Batch1DArgs {
+  const Params1D* task[kMaxTasks];
+  int64_t bstart[kMaxTasks + 1];
+  int64_t step0[kMaxTasks];
+  int ntasks;
+  int nsteps;
+};
+
 // Host launchers (defined in the .hip files).
 hipError_t launch_fit2d(int phase, int N, int mode, const Params2D& p, int64_t nfits, hipStream_t st);
-size_t fit2d_lds_bytes(int N, int mode);
+size_t fit2d_lds_bytes(int N, int mode, int phase);
+hipError_t launch_fit2d_fused(int phase, int mode, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
+int fit2d_fused_occupancy(int phase, int mode, size_t lds);
+hipError_t launch_step_counters(const StepArgs& a, hipStream_t st);
 constexpr int kMaxN2D = 10;   // largest order of the 2-D LDS-resident fit
 hipError_t launch_resident_1d(int N, const Params1D& p, hipStream_t st);
+hipError_t launch_resident_1d_batch(int N, int algo, const Batch1DArgs& a, size_t lds, hipStream_t st);
 size_t resident_1d_lds_bytes(int K, int samples_per_block);
 int resident_1d_samples_per_block(int K);
 

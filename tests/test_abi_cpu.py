@@ -59,3 +59,17 @@ def test_null_handle_calls_fail_cleanly():
             call()
         assert ei.value.code == -1
     assert B._lib.sl_destroy(None) == 0
+
+
+def test_schedule_and_batch_argument_checks_without_a_device():
+    from paper_2009_07340_amd import binding as B
+    with pytest.raises(B.SLError) as ei:
+        B.sl_set_schedule(None, 1, 1, 0)
+    assert ei.value.code == -1
+    with pytest.raises(B.SLError):
+        B.sl_get_schedule(None)
+    with pytest.raises(B.SLError):
+        B.sl_autotune(None, 1e-3, 2)
+    B.sl_step_batch([], [], 1)          # an empty batch is a no-op
+    with pytest.raises(B.SLError):
+        B.sl_step_batch([None], [1e-3], 1)
