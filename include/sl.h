@@ -241,6 +241,12 @@ int sl_kernel_time(sl_handle h, const char* name, int64_t* launches, double* ms)
 
 int sl_diag(sl_handle h, sl_diag_t* out);
 int sl_sync(sl_handle h);                 /* wait for the handle's stream */
+/* Move the handle to another HIP stream (NULL = the null stream); waits for
+ * the work pending on the old one first.  Lets a caller initialise a handle
+ * on a private stream and then join it to a batch stream. */
+int sl_set_stream(sl_handle h, void* hip_stream);
+/* Free and total bytes of the current device (hipMemGetInfo), for admission. */
+int sl_mem_info(size_t* free_bytes, size_t* total_bytes);
 const char* sl_last_error(void);          /* thread-local message of the last failure */
 int sl_destroy(sl_handle h);              /* waits, frees what the library allocated */
 

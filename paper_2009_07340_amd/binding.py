@@ -49,6 +49,14 @@ class SLError(RuntimeError):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"HIP library {LIB_PATH} is missing; build it with __graft_entry__.build()")
+# A process can hold only one HIP runtime: PyTorch wheels carry their own, and a
+# second one loaded beside it cannot open the device.  When torch is installed
+# its runtime is loaded first, so the library binds to it and device pointers
+# and streams from torch are valid here.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 _P = C.c_void_p
@@ -74,6 +82,8 @@ _SIGS = {
     "sl_kernel_time": [_P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     "sl_diag": [_P, C.POINTER(sl_diag_t)],
     "sl_sync": [_P],
+    "sl_set_stream": [_P, _P],
+    "sl_mem_info": [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
     "sl_set_schedule": [_P, C.POINTER(sl_schedule_t)],
     "sl_get_schedule": [_P, C.POINTER(sl_schedule_t)],
     "sl_autotune": [_P, C.c_double, C.c_int32, C.c_char_p, C.POINTER(sl_schedule_t)],
@@ -286,6 +296,16 @@ def sl_autotune(h, dt, trial_steps=3, cache_path=None):
 
 def sl_sync(h):
     _check(_lib.sl_sync(h))
+
+
+def sl_set_stream(h, hip_stream):
+    _check(_lib.sl_set_stream(h, _ptr(hip_stream)))
+
+
+def sl_mem_info():
+    f, t = C.c_size_t(), C.c_size_t()
+    _check(_lib.sl_mem_info(C.byref(f), C.byref(t)))
+    return f.value, t.value
 
 
 def sl_last_error():

@@ -1129,6 +1129,20 @@ int sl_sync(sl_handle h) {
   return SL_OK;
 }
 
+int sl_set_stream(sl_handle h, void* hip_stream) {
+  if (int rc = check_handle(h)) return rc;
+  drain_events(h);
+  SL_HIP(hipStreamSynchronize(h->stream));
+  h->stream = (hipStream_t)hip_stream;
+  return SL_OK;
+}
+
+int sl_mem_info(size_t* free_bytes, size_t* total_bytes) {
+  if (!free_bytes || !total_bytes) return fail(SL_EINVAL, "null output");
+  SL_HIP(hipMemGetInfo(free_bytes, total_bytes));
+  return SL_OK;
+}
+
 const char* sl_last_error(void) { return g_last_error.c_str(); }
 
 int sl_destroy(sl_handle h) {
