@@ -2,6 +2,8 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4]
                 [--precision fp64|fp32_refine|bf16split_refine] [--no-cpu-baseline]
+                [--schedule perorder|fused|perorder_graph|fused_graph|auto]
+python bench.py --serve [--serve-requests R] [--serve-rate HZ] [--serve-kmax K] [--serve-mmax M]
 
 One "step" is one pass of the whole hot path (Wiener increments, node moves,
 advected fits, trace exchange, constrained remap) over every sample of the
@@ -42,8 +44,43 @@ def fit_flops_2d_phase2(N):
         + n * R * (R + 1) + R ** 3 / 3.0 + 2 * R * R + 2 * n * R + 2 * n * n + 2 * n * N
 
 
-def kernel_name(wl):
-    return "resident_1d" if wl.dim == 1 else "fit2d_phase2"
+SCHEDULES = {"perorder": (0, 0), "fused": (1, 0), "perorder_graph": (0, 1), "fused_graph": (1, 1)}
+
+
+def kernel_name(wl, fused=0):
+    if wl.dim == 1:
+        return "resident_1d"
+    return "fit2d_fused_phase2" if fused else "fit2d_phase2"
+
+
+def kernel_sources_digest(wl):
+    """Digest of the sources the dominant kernel is built from (a stored HBM
+    traffic measurement is only valid for the kernel it was taken on)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2009_07340_amd", "csrc")
+    names = ["sl_internal.hpp", "philox.hpp", "fit1d.hpp"]
+    names += ["k1d.hip"] if wl.dim == 1 else ["k2d.hip", "blocks.hpp"]
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(csrc, n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(wl, kname, precision):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or
+    None when none matches this kernel source, workload and step count."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    key = f"{kname}|{wl.name}|{precision}"
+    e = table.get(key)
+    if not e or e.get("source_digest") != kernel_sources_digest(wl):
+        return None
+    return e["hbm_bytes_per_launch"]
 
 
 def main():
@@ -58,6 +95,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--schedule", default="perorder", choices=list(SCHEDULES) + ["auto"],
+                    help="2-D launch schedule (auto: the library's autotuner picks)")
+    ap.add_argument("--serve", action="store_true", help="run the serving stream instead")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-kmax", type=int, default=64)
+    ap.add_argument("--serve-mmax", type=int, default=128)
+    ap.add_argument("--serve-steps-scale", type=float, default=1.0)
+    ap.add_argument("--serve-max-active", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -70,6 +116,8 @@ def main():
     from paper_2009_07340_amd import workloads as W
     from paper_2009_07340_amd.problem import Problem
 
+    if args.serve:
+        return serve_bench(args)
     wl = W.WORKLOADS[args.workload]()
     if args.samples:
         wl.samples = args.samples
@@ -82,6 +130,14 @@ def main():
     prob = Problem(wl, precision=args.precision, dev_ws=ws.data_ptr(), ws_bytes=nbytes,
                    hip_stream=stream.cuda_stream)
     prob.set_fields()
+    fused = 0
+    if wl.dim == 2:
+        if args.schedule == "auto":
+            sched = B.sl_autotune(prob.h, wl.dt, 1)
+            print(f"[bench] autotuner: {sched}", file=sys.stderr, flush=True)
+        else:
+            B.sl_set_schedule(prob.h, *SCHEDULES[args.schedule], 0)
+        fused = B.sl_get_schedule(prob.h)["fused"]
     print(f"[bench] {wl.name}: K={wl.K} samples={wl.samples} dt={wl.dt} warmup={args.warmup} steps={steps}",
           file=sys.stderr, flush=True)
     if args.warmup:
@@ -93,15 +149,16 @@ def main():
     prob.step(wl.dt, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kname = kernel_name(wl)
+    kname = kernel_name(wl, fused)
     launches, kms = B.sl_kernel_time(prob.h, kname)
     others = {}
-    for other in ("fit2d_phase1", "fit2d_phase2", "resident_1d"):
+    for other in ("fit2d_phase1", "fit2d_phase2", "fit2d_fused_phase1", "fit2d_fused_phase2", "resident_1d"):
         if other != kname:
             n_o, ms_o = B.sl_kernel_time(prob.h, other)
             if n_o:
                 others[other] = {"launches": n_o, "ms": round(ms_o, 4)}
     B.sl_profile(prob.h, False)
+    sched_used = B.sl_get_schedule(prob.h) if wl.dim == 2 else None
     elapsed = t1 - t0
     nodes_per_sample = prob.nodes
     node_updates = float(nodes_per_sample) * wl.samples * steps
@@ -117,7 +174,8 @@ def main():
         flops = fit_flops_1d(N) * wl.K * wl.samples * steps
         achieved = flops / (kms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X["fp64_vector_tflops"],
-                "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_vector_tflops"], 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_vector_tflops"], 4),
+                "traffic": stored_traffic(wl, kname, args.precision),
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_fit_step": round(fit_flops_1d(N), 1)}
     else:
@@ -125,8 +183,10 @@ def main():
         per_launch = sum(fit_flops_2d_phase2(int(N)) for N in orders) * wl.samples
         flops = per_launch * launches
         achieved = flops / (kms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": MI355X["fp64_mfma_tflops"],
-                "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_mfma_tflops"], 4), "traffic": None,
+        peak = MI355X["fp64_mfma_tflops"] if args.precision == "fp64" else MI355X["fp32_mfma_tflops"]
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": stored_traffic(wl, kname, args.precision),
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_launch": per_launch, "other_kernels": others}
 
@@ -153,6 +213,45 @@ def main():
                    "element_sample_fits_per_s": wl.K * wl.samples * steps / elapsed},
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    if wl.dim == 2:
+        out["config"]["schedule"] = sched_used
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """The serving stream (Poisson arrivals, mixed 1-D / 2-D requests) through the
+    continuous-batching loop; one JSON line with p50/p99 latency and throughput."""
+    import torch
+    from paper_2009_07340_amd import binding as B
+    from paper_2009_07340_amd import serve
+    from paper_2009_07340_amd import workloads as W
+    torch.cuda.set_device(0)
+    stream = W.serving_requests(n=args.serve_requests, rate=args.serve_rate, kmax=args.serve_kmax,
+                                mmax=args.serve_mmax)
+    reqs = serve.requests_from_stream(stream, precision="fp32_refine", steps_scale=args.serve_steps_scale)
+    s_batch, s_admit = torch.cuda.Stream(), torch.cuda.Stream()
+    srv = serve.Server(B, max_active=args.serve_max_active, chunk_steps=16,
+                       batch_stream=s_batch.cuda_stream, admit_stream=s_admit.cuda_stream)
+    print(f"[serve] {len(reqs)} requests at {args.serve_rate}/s, K <= {args.serve_kmax}, M <= {args.serve_mmax}, "
+          f"budget {srv.budget / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    srv.run(reqs)
+    wall = time.perf_counter() - t0
+    st = serve.summarize(reqs)
+    unsupported = sum(1 for r in reqs if r.error and "admission" in r.error)
+    out = {
+        "metric": "serving p50/p99 latency", "value": st["p99_latency_s"], "unit": "s",
+        "higher_is_better": False, "n_gpus": 1, "dtype": "fp32_refine (2-D), f64 (1-D)", "data": "synthetic",
+        "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+        "p50_queue_wait_s": st["p50_queue_wait_s"], "arrival_rate_per_s": args.serve_rate,
+        "completed": st["completed"], "failed": st["failed"], "unsupported_shapes": unsupported,
+        "makespan_s": st["makespan_s"], "wall_s": wall, "node_updates_per_s": st["node_updates_per_s"],
+        "sustained_completions_per_s": st["completed_per_s"], "peak_active": srv.peak_active,
+        "iterations": srv.iterations, "peak_used_bytes": srv.peak_used,
+        "config": {"workload": "serving stream", "requests": args.serve_requests, "rate": args.serve_rate,
+                   "kmax": args.serve_kmax, "mmax": args.serve_mmax, "steps_scale": args.serve_steps_scale,
+                   "max_active": args.serve_max_active, "chunk_steps": 16},
     }
     print(json.dumps(out), flush=True)
 
