@@ -44,13 +44,42 @@ def fit_flops_2d_phase2(N):
         + n * R * (R + 1) + R ** 3 / 3.0 + 2 * R * R + 2 * n * R + 2 * n * n + 2 * n * N
 
 
+def fit_flops_2d_ref(N, phase, iters):
+    """Float64 operations of one 2-D fit with the reference-preconditioned solver, as
+    the kernel performs them (multiply-add = 2), for `iters` conjugate-gradient
+    iterations:  n = N^2, T = 4N, R = 4N - 4, H = N + 2.
+      set-up: moves and carried values 8n, 1-D tables 12 n N, b = V^T f 3n^2;
+      G p = V^T (V p): 2n(N^2 + N) + 3n^2;  G0^-1 v (Kronecker): 4N^3;
+      C c: 2T(N^2 + N);  C^T v: 6nN;  U_r^T, U_r: 2TR each;  S0^-1 w: 2R^2;
+      projection = 2 G0^-1 + C + U_r^T + S0^-1 + U_r + C^T + n;
+      phase 2 set-up: H tables 4H^2(N^2 + N), T U_r 3T^2 R, S0 2R^2 T (lower half R^2 T),
+      Cholesky, inverse and X^T X of S0 R^3;  evaluation 2n(N^2 + N)."""
+    n, T, R, H = N * N, 4 * N, 4 * N - 4, N + 2
+    setup = 8 * n + 12 * n * N + 3 * n * n
+    g_apply = 2 * n * (N * N + N) + 3 * n * n
+    g0 = 4 * N ** 3
+    c_op, ct_op, u_op, s_op = 2 * T * (N * N + N), 6 * n * N, 2 * T * R, 2 * R * R
+    if phase == 1:
+        start = g0 + 2 * n + g_apply + n + g0 + 4 * n
+        per_it = g_apply + 2 * n + 4 * n + g0 + 4 * n + 2 * n
+        return setup + start + iters * per_it + c_op
+    proj = 2 * g0 + c_op + 2 * u_op + s_op + ct_op + n
+    build = 4 * H * H * (N * N + N) + 3 * T * T * R + R * R * T + R ** 3 + u_op
+    start = proj + 2 * n + g_apply + n + proj + n + 4 * n
+    per_it = g_apply + 2 * n + 4 * n + proj + n + 4 * n + 2 * n
+    final = c_op + 2 * u_op + s_op + ct_op + g0 + n
+    return setup + build + start + iters * per_it + final + 2 * n * (N * N + N)
+
+
 SCHEDULES = {"perorder": (0, 0), "fused": (1, 0), "perorder_graph": (0, 1), "fused_graph": (1, 1)}
 
 
-def kernel_name(wl, fused=0):
+def kernel_name(wl, fused=0, solver=1):
     if wl.dim == 1:
         return "resident_1d"
-    return "fit2d_fused_phase2" if fused else "fit2d_phase2"
+    if fused:
+        return "fit2d_fused_phase2"
+    return "fit2r_phase2" if solver == 2 else "fit2d_phase2"
 
 
 def kernel_sources_digest(wl):
@@ -59,7 +88,7 @@ def kernel_sources_digest(wl):
     import hashlib
     csrc = os.path.join(ROOT, "paper_2009_07340_amd", "csrc")
     names = ["sl_internal.hpp", "philox.hpp", "fit1d.hpp"]
-    names += ["k1d.hip"] if wl.dim == 1 else ["k2d.hip", "blocks.hpp"]
+    names += ["k1d.hip"] if wl.dim == 1 else ["k2d.hip", "k2r.hip", "blocks.hpp"]
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(csrc, n), "rb") as f:
@@ -91,6 +120,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--samples", type=int, default=None)
+    ap.add_argument("--solver", default="auto", choices=["auto", "factor", "reference"],
+                    help="2-D least-squares solver (auto: reference for fp64, factor for the mixed modes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--pmc-calibrate", action="store_true",
@@ -125,10 +156,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    nbytes = Problem.required_bytes(wl, args.precision)
+    nbytes = Problem.required_bytes(wl, args.precision, solver=args.solver)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)       # device memory from torch
     prob = Problem(wl, precision=args.precision, dev_ws=ws.data_ptr(), ws_bytes=nbytes,
-                   hip_stream=stream.cuda_stream)
+                   hip_stream=stream.cuda_stream, solver=args.solver)
     prob.set_fields()
     fused = 0
     if wl.dim == 2:
@@ -138,21 +169,25 @@ def main():
         else:
             B.sl_set_schedule(prob.h, *SCHEDULES[args.schedule], 0)
         fused = B.sl_get_schedule(prob.h)["fused"]
+    solver = B.sl_diag(prob.h)["solver"]
     print(f"[bench] {wl.name}: K={wl.K} samples={wl.samples} dt={wl.dt} warmup={args.warmup} steps={steps}",
           file=sys.stderr, flush=True)
     if args.warmup:
         prob.step(wl.dt, args.warmup)
     torch.cuda.synchronize()
+    d0 = B.sl_diag(prob.h)
     B.sl_profile(prob.h, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     prob.step(wl.dt, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kname = kernel_name(wl, fused)
+    kname = kernel_name(wl, fused, solver)
     launches, kms = B.sl_kernel_time(prob.h, kname)
+    d1 = B.sl_diag(prob.h)
     others = {}
-    for other in ("fit2d_phase1", "fit2d_phase2", "fit2d_fused_phase1", "fit2d_fused_phase2", "resident_1d"):
+    for other in ("fit2d_phase1", "fit2d_phase2", "fit2r_phase1", "fit2r_phase2", "fit2d_fused_phase1",
+                  "fit2d_fused_phase2", "resident_1d"):
         if other != kname:
             n_o, ms_o = B.sl_kernel_time(prob.h, other)
             if n_o:
@@ -178,6 +213,23 @@ def main():
                 "traffic": stored_traffic(wl, kname, args.precision),
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_fit_step": round(fit_flops_1d(N), 1)}
+    elif solver == 2:
+        # float64 VALU work of the reference solver with the iteration counts of the timed steps
+        fits = wl.K * wl.samples * steps
+        it2 = (d1["solver_iterations"][1] - d0["solver_iterations"][1]) / fits
+        it1 = (d1["solver_iterations"][0] - d0["solver_iterations"][0]) / fits
+        orders = wl.order_array()
+        per_launch = sum(fit_flops_2d_ref(int(N), 2, it2) for N in orders) * wl.samples
+        flops = per_launch * launches
+        achieved = flops / (kms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X["fp64_vector_tflops"],
+                "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_vector_tflops"], 4),
+                "traffic": stored_traffic(wl, kname, args.precision),
+                "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
+                "flops_per_launch": per_launch, "mean_iterations": [round(it1, 3), round(it2, 3)],
+                "unconverged": [d1["solver_unconverged"][0] - d0["solver_unconverged"][0],
+                                d1["solver_unconverged"][1] - d0["solver_unconverged"][1]],
+                "other_kernels": others}
     else:
         orders = wl.order_array()
         per_launch = sum(fit_flops_2d_phase2(int(N)) for N in orders) * wl.samples
@@ -216,6 +268,7 @@ def main():
     }
     if wl.dim == 2:
         out["config"]["schedule"] = sched_used
+        out["config"]["solver"] = {1: "factor", 2: "reference"}[solver]
     print(json.dumps(out), flush=True)
 
 

@@ -89,6 +89,16 @@ enum {
   SL_PREC_BF16SPLIT_REFINE = 2 /* bf16 hi/lo split Gram products, float64 refinement */
 };
 
+/* Solvers of the 2-D constrained least-squares fit (Sec. 5.3); both give the
+ * same remap up to rounding:
+ *   SL_SOLVER_FACTOR: Gram matrix V^T V on the matrix cores, blocked Cholesky,
+ *     range-space constraint elimination (N <= 10; every precision mode);
+ *   SL_SOLVER_REFERENCE: conjugate gradients preconditioned by the Gram matrix
+ *     of the undisplaced nodes (a Kronecker product), projected onto the
+ *     constraints; float64 only; N <= 16;
+ *   SL_SOLVER_AUTO: REFERENCE for SL_PREC_FP64, FACTOR for the mixed modes. */
+enum { SL_SOLVER_AUTO = 0, SL_SOLVER_FACTOR = 1, SL_SOLVER_REFERENCE = 2 };
+
 typedef struct sl_ctx* sl_handle;
 
 /* Problem description (Sec. 3: box of K = kx*ky affine elements, N nodes
@@ -107,6 +117,10 @@ typedef struct sl_mesh_desc {
   uint32_t stream_id;     /* fourth Philox counter word (e.g. a request id) */
   int32_t precision;      /* SL_PREC_* */
   int32_t refine_iters;   /* FP64 refinement sweeps for the mixed modes; -1 = default */
+  int32_t solver;         /* 2-D least-squares solver, SL_SOLVER_* (0 = automatic) */
+  int32_t max_iter;       /* reference solver: iteration limit per fit, 0 = default (32) */
+  double tol;             /* reference solver: stop when the preconditioned residual, relative
+                             to the starting iterate, is below tol; 0 = default (1e-13) */
 } sl_mesh_desc;
 
 typedef struct sl_diag_t {
@@ -122,6 +136,9 @@ typedef struct sl_diag_t {
   int32_t precision;
   int32_t refine_iters;
   size_t device_bytes;        /* bytes of device memory the handle uses */
+  int32_t solver;             /* SL_SOLVER_FACTOR or SL_SOLVER_REFERENCE (2-D) */
+  int64_t solver_iterations[2];   /* reference solver, per phase: iterations summed over all fits so far */
+  int64_t solver_unconverged[2];  /* reference solver, per phase: fits that stopped at max_iter */
 } sl_diag_t;
 
 /* Device bytes sl_init_mesh needs for this description (state, traces, fields,

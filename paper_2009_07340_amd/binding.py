@@ -20,6 +20,9 @@ SL_BC_PERIODIC, SL_BC_DIRICHLET = 0, 1
 SL_NODES_GL, SL_NODES_CG = 0, 1
 SL_PREC_FP64, SL_PREC_FP32_REFINE, SL_PREC_BF16SPLIT_REFINE = 0, 1, 2
 
+SL_SOLVER_AUTO, SL_SOLVER_FACTOR, SL_SOLVER_REFERENCE = 0, 1, 2
+SOLVERS = {"auto": SL_SOLVER_AUTO, "factor": SL_SOLVER_FACTOR, "reference": SL_SOLVER_REFERENCE}
+
 PRECISIONS = {"fp64": SL_PREC_FP64, "fp32_refine": SL_PREC_FP32_REFINE, "bf16split_refine": SL_PREC_BF16SPLIT_REFINE}
 
 
@@ -28,13 +31,15 @@ class sl_mesh_desc(C.Structure):
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("n_uniform", C.c_int32), ("order", C.POINTER(C.c_int32)), ("nodes", C.c_int32),
                 ("bc", C.c_int32), ("samples", C.c_int64), ("seed", C.c_uint64), ("stream_id", C.c_uint32),
-                ("precision", C.c_int32), ("refine_iters", C.c_int32)]
+                ("precision", C.c_int32), ("refine_iters", C.c_int32), ("solver", C.c_int32),
+                ("max_iter", C.c_int32), ("tol", C.c_double)]
 
 
 class sl_diag_t(C.Structure):
     _fields_ = [("steps", C.c_int64), ("samples", C.c_int64), ("nodes", C.c_int64), ("edge_points", C.c_int64),
                 ("max_disp_ratio", C.c_double), ("precision", C.c_int32), ("refine_iters", C.c_int32),
-                ("device_bytes", C.c_size_t)]
+                ("device_bytes", C.c_size_t), ("solver", C.c_int32), ("solver_iterations", C.c_int64 * 2),
+                ("solver_unconverged", C.c_int64 * 2)]
 
 
 class sl_schedule_t(C.Structure):
@@ -122,7 +127,7 @@ def _f64(a, n=None):
 
 
 def make_desc(dim, kx, ky=1, box=(0.0, 1.0, 0.0, 1.0), order=8, nodes="gl", bc="periodic", samples=1,
-              seed=0, stream_id=0, precision="fp64", refine_iters=-1):
+              seed=0, stream_id=0, precision="fp64", refine_iters=-1, solver="auto", max_iter=0, tol=0.0):
     d = sl_mesh_desc()
     d.dim, d.kx, d.ky = dim, kx, ky if dim == 2 else 1
     d.x0, d.x1, d.y0, d.y1 = (float(v) for v in box)
@@ -138,6 +143,8 @@ def make_desc(dim, kx, ky=1, box=(0.0, 1.0, 0.0, 1.0), order=8, nodes="gl", bc="
     d.samples, d.seed, d.stream_id = int(samples), int(seed) & (2 ** 64 - 1), int(stream_id)
     d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     d.refine_iters = int(refine_iters)
+    d.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+    d.max_iter, d.tol = int(max_iter), float(tol)
     d._keep = keep
     return d
 
@@ -269,7 +276,11 @@ def sl_kernel_time(h, name):
 def sl_diag(h):
     d = sl_diag_t()
     _check(_lib.sl_diag(h, C.byref(d)))
-    return {k: getattr(d, k) for k, _ in d._fields_}
+    out = {}
+    for k, _ in d._fields_:
+        v = getattr(d, k)
+        out[k] = list(v) if isinstance(v, C.Array) else v
+    return out
 
 
 def _sched_dict(s):

@@ -62,7 +62,11 @@ struct Layout {
   // byte offsets in the workspace
   size_t o_phi, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
-  size_t o_params, o_dstep, o_ctr, total;
+  size_t o_params, o_dstep, o_ctr, o_stats, o_gxinv, total;
+  int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
+  size_t gx_doubles = 0;
+  int max_iter = 32;
+  double tol = 1e-13;
 };
 
 int make_layout(const sl_mesh_desc* d, Layout& L) {
@@ -77,6 +81,16 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   if (d->bc != SL_BC_PERIODIC && d->bc != SL_BC_DIRICHLET) return fail(SL_EINVAL, "unknown boundary condition");
   if (d->precision < SL_PREC_FP64 || d->precision > SL_PREC_BF16SPLIT_REFINE)
     return fail(SL_EINVAL, "unknown precision mode");
+  if (d->solver < SL_SOLVER_AUTO || d->solver > SL_SOLVER_REFERENCE) return fail(SL_EINVAL, "unknown solver");
+  if (d->max_iter < 0 || d->max_iter > 100000) return fail(SL_EINVAL, "max_iter must be in [0, 100000]");
+  if (!(d->tol >= 0.0) || !std::isfinite(d->tol) || d->tol >= 1.0) return fail(SL_EINVAL, "tol must be in [0, 1)");
+  if (d->solver == SL_SOLVER_REFERENCE && d->precision != SL_PREC_FP64)
+    return fail(SL_EINVAL, "the reference-preconditioned solver runs in float64 only");
+  L.solver = d->solver == SL_SOLVER_FACTOR ? SL_SOLVER_FACTOR
+             : d->solver == SL_SOLVER_REFERENCE ? SL_SOLVER_REFERENCE
+             : (d->precision == SL_PREC_FP64 ? SL_SOLVER_REFERENCE : SL_SOLVER_FACTOR);
+  if (d->max_iter > 0) L.max_iter = d->max_iter;
+  if (d->tol > 0.0) L.tol = d->tol;
   L.dim = d->dim;
   L.kx = d->kx;
   L.ky = d->dim == 2 ? d->ky : 1;
@@ -110,6 +124,7 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
     for (int Nd : L.orders)
       for (int Ns : L.orders)
         if (Nd != Ns) L.interp_doubles += (size_t)Nd * Ns;
+    for (int N : L.orders) L.gx_doubles += (size_t)N * N;
   }
   if ((double)L.M * (double)L.nodes * 8.0 > 250e9) return fail(SL_ENOMEM, "state exceeds device memory");
   size_t o = 0;
@@ -142,6 +157,8 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_params = take(std::max(sizeof(sl::Params1D), sizeof(sl::Params2D)));
   L.o_dstep = take(sizeof(int64_t));
   L.o_ctr = take(2 * sizeof(unsigned long long));
+  L.o_stats = take(4 * sizeof(unsigned long long));
+  L.o_gxinv = take(sizeof(double) * (L.gx_doubles + 1));
   L.total = o;
   return SL_OK;
 }
@@ -164,6 +181,7 @@ struct sl_ctx {
   double *d_xitab = nullptr, *d_ur = nullptr, *d_interp = nullptr;
   std::vector<std::pair<int, std::pair<int64_t, int64_t>>> groups;   // (N, (first work index, count))
   std::map<int, std::vector<double>> xi_tab;    // reference nodes per order
+  int64_t gx_off[sl::kMaxN + 1] = {0};          // offsets of the reference Gram inverses
   sl::LegendreRec rec{};
   // host copies of the fields
   std::vector<double> u, D, divu, un, Dn, ghost_h;
@@ -183,6 +201,8 @@ struct sl_ctx {
   sl::Params2D* d_p2 = nullptr;
   int64_t* d_step = nullptr;             // device step counter (fused / graph schedules)
   unsigned long long* d_ctr = nullptr;   // work counters of the two phases
+  unsigned long long* d_stats = nullptr; // reference solver statistics
+  double* d_gxinv = nullptr;
   hipStream_t cap_stream = nullptr;      // private stream for graph capture
   // measurement
   bool profile = false;
@@ -285,6 +305,11 @@ int update_coefficients(sl_ctx* h, double dt) {
 
 // ---------------------------------------------------------------- launch schedules
 
+const char* kernel_label(const sl_ctx* h, int phase) {
+  if (h->L.solver == SL_SOLVER_REFERENCE) return phase == 1 ? "fit2r_phase1" : "fit2r_phase2";
+  return phase == 1 ? "fit2d_phase1" : "fit2d_phase2";
+}
+
 int default_refine(int precision) {
   return precision == SL_PREC_FP32_REFINE ? 2 : precision == SL_PREC_BF16SPLIT_REFINE ? 3 : 0;
 }
@@ -324,6 +349,11 @@ void build_params(sl_ctx* h) {
     p.seed = h->desc.seed;
     p.stream = h->desc.stream_id;
     p.refine = h->desc.refine_iters >= 0 ? h->desc.refine_iters : default_refine(h->desc.precision);
+    p.gxinv = h->d_gxinv;
+    for (int N = 0; N <= sl::kMaxN; ++N) p.gx_off[N] = h->gx_off[N];
+    p.tol2 = L.tol * L.tol;
+    p.max_iter = L.max_iter;
+    p.stats = h->d_stats;
     p.rec = h->rec;
   } else {
     sl::Params1D& p = h->p1;
@@ -383,7 +413,10 @@ int enqueue_perorder(sl_ctx* h, int phase, bool devstep, int64_t step, hipStream
   for (const auto& g : h->groups) {
     p.work = h->d_work + g.second.first;
     p.block0 = 0;
-    SL_HIP(sl::launch_fit2d(phase, g.first, h->desc.precision, p, g.second.second * h->L.M, st));
+    if (h->L.solver == SL_SOLVER_REFERENCE)
+      SL_HIP(sl::launch_fit2r(phase, g.first, p, g.second.second * h->L.M, st));
+    else
+      SL_HIP(sl::launch_fit2d(phase, g.first, h->desc.precision, p, g.second.second * h->L.M, st));
   }
   return SL_OK;
 }
@@ -392,10 +425,12 @@ int enqueue_perorder(sl_ctx* h, int phase, bool devstep, int64_t step, hipStream
 // launch per precision mode (and per chunk of kMaxTasks handles / kMaxSegs
 // order segments), each chunk pulling work from its first handle's counter.
 int enqueue_fused(const std::vector<sl_ctx*>& hs, int phase, int grid_req, hipStream_t st) {
-  for (int mode = 0; mode <= 2; ++mode) {
+  for (int kind = 0; kind <= 3; ++kind) {
+    const int mode = kind == 3 ? 0 : kind;
     std::vector<sl_ctx*> m;
     for (sl_ctx* h : hs)
-      if (h->desc.precision == mode) m.push_back(h);
+      if ((h->L.solver == SL_SOLVER_REFERENCE) == (kind == 3) && (kind == 3 || h->desc.precision == mode))
+        m.push_back(h);
     size_t i = 0;
     while (i < m.size()) {
       // take handles while the chunk's segments fit
@@ -419,16 +454,19 @@ int enqueue_fused(const std::vector<sl_ctx*>& hs, int phase, int grid_req, hipSt
         a.seg[a.nseg] = sl::FusedSeg{start, g.fit0, g.task, g.N};
         ++a.nseg;
         start += g.count;
-        lds = std::max(lds, sl::fit2d_lds_bytes(g.N, mode, phase));
+        lds = std::max(lds, kind == 3 ? sl::fit2r_lds_bytes(g.N, phase) : sl::fit2d_lds_bytes(g.N, mode, phase));
       }
       a.total = start;
       a.counter = m[i]->d_ctr + (phase - 1);
       if (a.total > 0) {
-        const int occ = sl::fit2d_fused_occupancy(phase, mode, lds);
+        const int occ = kind == 3 ? sl::fit2r_fused_occupancy(phase, lds) : sl::fit2d_fused_occupancy(phase, mode, lds);
         if (occ <= 0) return fail(SL_EDEVICE, "fused kernel does not fit on a compute unit");
         int64_t grid = grid_req > 0 ? grid_req : (int64_t)occ * device_cus();
         grid = std::min<int64_t>(grid, a.total);
-        SL_HIP(sl::launch_fit2d_fused(phase, mode, a, (int)grid, lds, st));
+        if (kind == 3)
+          SL_HIP(sl::launch_fit2r_fused(phase, a, (int)grid, lds, st));
+        else
+          SL_HIP(sl::launch_fit2d_fused(phase, mode, a, (int)grid, lds, st));
       }
       i = j;
     }
@@ -440,7 +478,7 @@ int enqueue_fused(const std::vector<sl_ctx*>& hs, int phase, int grid_req, hipSt
 int enqueue_device_step(const std::vector<sl_ctx*>& hs, int fused, int grid, hipStream_t st, sl_ctx* prof) {
   for (int phase = 1; phase <= 2; ++phase) {
     const char* name = fused ? (phase == 1 ? "fit2d_fused_phase1" : "fit2d_fused_phase2")
-                             : (phase == 1 ? "fit2d_phase1" : "fit2d_phase2");
+                             : kernel_label(hs[0], phase);
     std::unique_ptr<ProfScope> ps(prof ? new ProfScope(prof, name) : nullptr);
     if (fused) {
       if (int rc = enqueue_fused(hs, phase, grid, st)) return rc;
@@ -519,7 +557,7 @@ int step_2d(const std::vector<sl_ctx*>& hs, int32_t nsteps, int fused, int graph
     // per-order kernels with the host step counter
     for (int it = 0; it < nsteps; ++it)
       for (int phase = 1; phase <= 2; ++phase) {
-        ProfScope ps(h0, phase == 1 ? "fit2d_phase1" : "fit2d_phase2");
+        ProfScope ps(h0, kernel_label(h0, phase));
         if (int rc = enqueue_perorder(h0, phase, false, h0->step + it, st)) return rc;
       }
   } else {
@@ -571,7 +609,8 @@ std::string tune_key(const sl_ctx* h) {
   const Layout& L = h->L;
   k << "dim=" << L.dim << ";K=" << L.kx << "x" << L.ky << ";orders=";
   for (const auto& g : h->groups) k << g.first << ":" << g.second.second << ",";
-  k << ";M=" << L.M << ";prec=" << h->desc.precision << ";refine=" << h->p2.refine << ";bc=" << h->desc.bc;
+  k << ";M=" << L.M << ";prec=" << h->desc.precision << ";refine=" << h->p2.refine << ";bc=" << h->desc.bc
+    << ";solver=" << L.solver;
   return k.str();
 }
 
@@ -598,7 +637,8 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   const Layout& L = h->L;
   if (L.dim == 1 && !L.uniform) return fail(SL_EUNSUPPORTED, "1-D meshes need a uniform order");
   if (L.dim == 1 && L.K > 256) return fail(SL_EUNSUPPORTED, "1-D meshes with more than 256 elements are not supported yet");
-  if (L.dim == 2 && L.maxN > sl::kMaxN2D) return fail(SL_EUNSUPPORTED, "2-D meshes support N <= 10 in this build");
+  if (L.dim == 2 && L.solver == SL_SOLVER_FACTOR && L.maxN > sl::kMaxN2D)
+    return fail(SL_EUNSUPPORTED, "the factorisation solver supports N <= 10; use the float64 reference solver for N <= 16");
   if (L.dim == 1 && desc->precision != SL_PREC_FP64)
     return fail(SL_EUNSUPPORTED, "the 1-D fit runs in float64 only (it has no dense contraction to lower)");
   h->desc = *desc;
@@ -645,6 +685,8 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_p2 = (sl::Params2D*)(h->ws + L.o_params);
   h->d_step = (int64_t*)(h->ws + L.o_dstep);
   h->d_ctr = (unsigned long long*)(h->ws + L.o_ctr);
+  h->d_stats = (unsigned long long*)(h->ws + L.o_stats);
+  h->d_gxinv = (double*)(h->ws + L.o_gxinv);
   // element tables, work list grouped by order, node tables, U_r and trace interpolation
   std::vector<int32_t> nbr(4 * (size_t)L.K, -1), work;
   for (int e = 0; e < L.K; ++e) {
@@ -693,6 +735,16 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
           o += Lm.size();
         }
   }
+  std::vector<double> gx(L.gx_doubles + 1, 0.0);
+  if (L.dim == 2) {
+    size_t o = 0;
+    for (int N : L.orders) {
+      const auto G = sl::reference_gram_inverse(h->xi_tab[N]);
+      h->gx_off[N] = (int64_t)o;
+      std::copy(G.begin(), G.end(), gx.begin() + o);
+      o += G.size();
+    }
+  }
   std::vector<int64_t> noff64(L.noff.begin(), L.noff.end() - 1), eoff64(L.eoff.begin(), L.eoff.end() - 1);
   std::vector<int32_t> order32(L.order.begin(), L.order.end());
   struct Up { void* dst; const void* src; size_t bytes; };
@@ -702,7 +754,8 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       {h->d_work, work.data(), sizeof(int32_t) * work.size()}, {h->d_xitab, xitab.data(), sizeof(double) * xitab.size()},
       {h->d_ur, ur.data(), sizeof(double) * ur.size()}, {h->d_uroff, uroff.data(), sizeof(int64_t) * uroff.size()},
       {h->d_interp, interp.data(), sizeof(double) * interp.size()},
-      {h->d_interpoff, interpoff.data(), sizeof(int64_t) * interpoff.size()}};
+      {h->d_interpoff, interpoff.data(), sizeof(int64_t) * interpoff.size()},
+      {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}};
   for (const auto& u : ups) {
     if (hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
       if (h->own_ws) (void)hipFree(h->ws);
@@ -730,7 +783,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   hipError_t e2 = hipMemsetAsync(h->phi, 0, sizeof(double) * (size_t)L.M * L.nodes, h->stream);
   hipError_t e4 = L.dim == 2 ? hipMemcpyAsync(h->d_p2, &h->p2, sizeof(sl::Params2D), hipMemcpyHostToDevice, h->stream)
                              : hipMemcpyAsync(h->d_p1, &h->p1, sizeof(sl::Params1D), hipMemcpyHostToDevice, h->stream);
-  hipError_t e5 = hipMemsetAsync(h->ws + L.o_dstep, 0, L.o_ctr + 2 * sizeof(unsigned long long) - L.o_dstep, h->stream);
+  hipError_t e5 = hipMemsetAsync(h->ws + L.o_dstep, 0, L.o_stats + 4 * sizeof(unsigned long long) - L.o_dstep, h->stream);
   hipError_t e3 = hipStreamSynchronize(h->stream);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
     if (h->own_ws) (void)hipFree(h->ws);
@@ -1120,6 +1173,16 @@ int sl_diag(sl_handle h, sl_diag_t* out) {
   out->refine_iters = h->desc.refine_iters >= 0 ? h->desc.refine_iters
                       : (h->desc.precision == SL_PREC_FP32_REFINE ? 2 : h->desc.precision == SL_PREC_BF16SPLIT_REFINE ? 3 : 0);
   out->device_bytes = h->L.total;
+  out->solver = h->L.dim == 2 ? h->L.solver : 0;
+  if (h->L.dim == 2) {
+    unsigned long long st[4] = {0, 0, 0, 0};
+    SL_HIP(hipStreamSynchronize(h->stream));
+    SL_HIP(hipMemcpy(st, h->d_stats, sizeof(st), hipMemcpyDeviceToHost));
+    for (int ph = 0; ph < 2; ++ph) {
+      out->solver_iterations[ph] = (int64_t)st[2 * ph];
+      out->solver_unconverged[ph] = (int64_t)st[2 * ph + 1];
+    }
+  }
   return SL_OK;
 }
 

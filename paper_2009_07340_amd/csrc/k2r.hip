@@ -1,0 +1,949 @@
+// Two-dimensional step, reference-preconditioned solver.
+//
+// The same constrained least-squares remap as the factorisation kernels
+// (Sec. 5.3, eqs. phi_stardef, h_star, remap_bnd, bnd_update, phi_star), solved
+// without forming or factoring the Gram matrix G = V^T V of the fit.
+//
+// The basis is centred on the mean node displacement, so a uniform
+// displacement leaves the moved-node basis matrix equal to the reference one,
+// V0 = Vx (x) Vx: the orthonormal Legendre basis at the Gauss nodes.  Its Gram
+// matrix is a Kronecker product, G0 = Gx (x) Gx with Gx = Vx^T Vx, and
+// G0^-1 = Gx^-1 (x) Gx^-1 costs 2 N^3 operations to apply.  Only the
+// non-uniform part of the displacement (velocity and diffusion varying across
+// the element) makes G differ from G0, so G0 is an excellent preconditioner:
+//
+//   phase 1 (unconstrained interpolant p0, traces at the own edge points):
+//     preconditioned conjugate gradients on G c = V^T f, preconditioner G0^-1,
+//     G applied matrix-free as V^T (V p) from the 1-D Legendre tables;
+//   phase 2 (constrained remap):
+//     projected preconditioned conjugate gradients on the equality-constrained
+//     problem  min |V c - f|^2  s.t.  C_r c = g_r  with the constraint
+//     preconditioner [[G0, C_r^T], [C_r, 0]]^-1, applied by the range-space
+//     formula with S0 = C_r G0^-1 C_r^T.  Every iterate satisfies the
+//     constraints; one final correction restores them to working accuracy.
+//
+// S0 needs no n x n work either: the edge-point rows of C are tensor products
+// of 1-D basis vectors, so C G0^-1 C^T is assembled from two (N+2) x (N+2)
+// tables of 1-D quadratic forms, and S0 = U_r^T (C G0^-1 C^T) U_r.  S0 is
+// factored (blocked Cholesky, matrix cores) and inverted explicitly once per
+// fit, so each iteration only applies dense matrix-vector products.
+//
+// The iteration count adapts to the fit: zero for a uniform displacement
+// (the preconditioner is then exact), a few for the smooth fields of the
+// workloads.  Fits that do not reach the tolerance within the iteration limit
+// are counted in a device statistic.  Everything is float64.  One workgroup
+// (four wavefronts) per fit, all of its data in LDS (N <= 16).
+#include "sl_internal.hpp"
+#include "philox.hpp"
+#include "fit1d.hpp"
+#include "blocks.hpp"
+
+namespace sl {
+
+using namespace blk;
+
+// LDS layout in doubles.  Phase 1 uses the first part only.  The block TU
+// (T U_r, 4N x R) used while S0 is assembled aliases [x .. Xblk], which is
+// not live at that time.
+template <int N>
+struct LayR {
+  static constexpr int n = N * N, TT = 4 * N, R = 4 * N - 4, RB = (R + 15) / 16, RP = 16 * RB, NH = N + 2;
+  static constexpr int nS = RB * (RB + 1) / 2;
+  static constexpr int oX1 = 0;
+  static constexpr int oY1 = oX1 + n * N;
+  static constexpr int oBx = oY1 + n * N;
+  static constexpr int oBy = oBx + N * N;
+  static constexpr int oEv = oBy + N * N;
+  static constexpr int oGxi = oEv + 4 * N;
+  static constexpr int oF = oGxi + N * N;
+  static constexpr int oB = oF + n;
+  static constexpr int oXv = oB + n;
+  static constexpr int oZ0 = oXv + n;
+  static constexpr int oR = oZ0 + n;
+  static constexpr int oGv = oR + n;
+  static constexpr int oP = oGv + n;
+  static constexpr int oQ = oP + n;
+  static constexpr int oT1 = oQ + n;
+  static constexpr int oT2 = oT1 + n;
+  static constexpr int oTr = oT2 + n;          // traces / edge vector
+  static constexpr int oXs = oTr + TT;
+  static constexpr int oYs = oXs + n;
+  static constexpr int oRed = oYs + n;
+  static constexpr int end1 = oRed + 16;
+  // phase 2 only
+  static constexpr int oXblk = end1;           // off-diagonal blocks of L^-1 of S0
+  static constexpr int oSblk = oXblk + nS * BLK;   // S0 -> its factor -> S0^-1 (lower blocks)
+  static constexpr int oE1 = oSblk + nS * BLK;
+  static constexpr int oGr = oE1 + TT;         // upwinded boundary data g
+  static constexpr int oW1 = oGr + TT;
+  static constexpr int oW2 = oW1 + RP;
+  static constexpr int oRr = oW2 + RP;         // g_r = U_r^T g
+  static constexpr int oHx = oRr + RP;
+  static constexpr int oHy = oHx + NH * NH;
+  // U_r is staged in LDS (column stride TT + 1) when it fits (N <= 13); then
+  // T U_r and U_r^T (T U_r) run on the matrix cores, the entries of
+  // T = C G0^-1 C^T formed on the fly from the H tables.  Larger orders read
+  // U_r from the cache and assemble S0 with scalar loops.
+  static constexpr int TTs = TT + 1;
+  static constexpr int endR = oHy + NH * NH;
+  static constexpr bool kUrLds = sizeof(double) * (endR + TTs * R) <= 156 * 1024;
+  static constexpr int US = kUrLds ? TTs : TT;        // column stride of U_r as used
+  static constexpr int oU = endR;
+  static constexpr int end2 = kUrLds ? endR + TTs * R : endR;
+  static constexpr int oTU = oXv;                     // T U_r, column stride US
+  static_assert(US * R <= oSblk - oXv, "T U_r must fit in the aliased region");
+  // per-wavefront scratch blocks of the S0^-1 computation (RB - 1 of them at
+  // most 4), over the iteration vectors, which are not live at that time
+  static constexpr int nTmp = RB - 1 < 4 ? RB - 1 : 4;
+  static constexpr int oTmp = oXv;
+  static_assert(nTmp * BLK <= oXblk - oXv, "scratch blocks must not overlap the inverse blocks");
+  static constexpr size_t bytes1 = sizeof(double) * end1;
+  static constexpr size_t bytes2 = sizeof(double) * end2;
+};
+
+// ---------------------------------------------------------------- helpers
+
+// Sum over the workgroup of a per-thread value; every thread gets the same
+// result (fixed summation order).  Contains two barriers.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane() == 0) red[wave()] = v;
+  block_sync();
+  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  block_sync();
+  return s;
+}
+
+// Two sums at once (one pair of barriers).
+__device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v0 += __shfl_xor(v0, o, 64);
+    v1 += __shfl_xor(v1, o, 64);
+  }
+  if (lane() == 0) {
+    red[wave()] = v0;
+    red[4 + wave()] = v1;
+  }
+  block_sync();
+  v0 = (red[0] + red[1]) + (red[2] + red[3]);
+  v1 = (red[4] + red[5]) + (red[6] + red[7]);
+  block_sync();
+}
+
+// r^T g and g^T g of the current iterate.  The stopping test uses g^T g: g is
+// the preconditioned (projected) residual, about the error of the iterate, and
+// its rounding noise enters g^T g only to second order (r^T g carries it to
+// first order once the constraints hold r away from zero).
+template <int N>
+__device__ __forceinline__ void block_rg_gg(const double* r, const double* g, double& rg, double& gg, double* red) {
+  double a = 0.0, c = 0.0;
+  for (int i = tid(); i < N * N; i += kThreads) {
+    a += r[i] * g[i];
+    c += g[i] * g[i];
+  }
+  block_sum2(a, c, red);
+  rg = a;
+  gg = c;
+}
+
+template <int N>
+__device__ __forceinline__ double block_dot(const double* a, const double* b, double* red) {
+  double v = 0.0;
+  for (int i = tid(); i < N * N; i += kThreads) v += a[i] * b[i];
+  return block_sum(v, red);
+}
+
+// out[i] = (V c)_i
+template <int N>
+__device__ void r_V(const double* X1, const double* Y1, const double* c, double* out) {
+  for (int i = tid(); i < N * N; i += kThreads) {
+    double xr[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) xr[k] = X1[i * N + k];
+    double v = 0.0;
+#pragma unroll 1
+    for (int ly = 0; ly < N; ++ly) {
+      double inner = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) inner += xr[k] * c[ly * N + k];
+      v += Y1[i * N + ly] * inner;
+    }
+    out[i] = v;
+  }
+}
+
+// out[p] = (V^T r)_p
+template <int N>
+__device__ void r_VT(const double* X1, const double* Y1, const double* r, double* out) {
+  for (int p = tid(); p < N * N; p += kThreads) {
+    const int k = p % N, ly = p / N;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < N * N; ++i) acc += X1[i * N + k] * Y1[i * N + ly] * r[i];
+    out[p] = acc;
+  }
+}
+
+// out = (Gx^-1 (x) Gx^-1) v  (c indexed [ly * N + k]); tmp n doubles.  Two barriers.
+template <int N>
+__device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double* out) {
+  for (int p = tid(); p < N * N; p += kThreads) {
+    const int k = p % N, ly = p / N;
+    double acc = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < N; ++kk) acc += gxi[k * N + kk] * v[ly * N + kk];
+    tmp[p] = acc;
+  }
+  block_sync();
+  for (int p = tid(); p < N * N; p += kThreads) {
+    const int k = p % N, ly = p / N;
+    double acc = 0.0;
+#pragma unroll
+    for (int ll = 0; ll < N; ++ll) acc += gxi[ly * N + ll] * tmp[ll * N + k];
+    out[p] = acc;
+  }
+  block_sync();
+}
+
+// out[q] = (C c)_q: the polynomial at own edge point q (W, E, S, N blocks of N)
+template <int N>
+__device__ void r_C(const double* Bx, const double* By, const double* Ev, const double* c, double* out) {
+  for (int q = tid(); q < 4 * N; q += kThreads) {
+    const int w = q / N, j = q % N;
+    double t = 0.0;
+#pragma unroll 1
+    for (int ly = 0; ly < N; ++ly) {
+      double inner = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double bx = (w == 0) ? Ev[k] : (w == 1) ? Ev[N + k] : Bx[j * N + k];
+        inner += bx * c[ly * N + k];
+      }
+      const double by = (w < 2) ? By[j * N + ly] : (w == 2) ? Ev[2 * N + ly] : Ev[3 * N + ly];
+      t += by * inner;
+    }
+    out[q] = t;
+  }
+}
+
+// out[p] = (C^T v)_p
+template <int N>
+__device__ void r_CT(const double* Bx, const double* By, const double* Ev, const double* v, double* out) {
+  for (int p = tid(); p < N * N; p += kThreads) {
+    const int k = p % N, ly = p / N;
+    const double e0 = Ev[k], e1 = Ev[N + k], f0 = Ev[2 * N + ly], f1 = Ev[3 * N + ly];
+    double acc = 0.0;
+#pragma unroll 2
+    for (int j = 0; j < N; ++j)
+      acc += By[j * N + ly] * (e0 * v[j] + e1 * v[N + j]) + Bx[j * N + k] * (f0 * v[2 * N + j] + f1 * v[3 * N + j]);
+    out[p] = acc;
+  }
+}
+
+// out[c] = (U_r^T v)_c for c < RP (zero padding); U column-major 4N x R, column stride US
+template <int N>
+__device__ void r_UT(const double* U, const double* v, double* out) {
+  using L = LayR<N>;
+  for (int c = tid(); c < L::RP; c += kThreads) {
+    double acc = 0.0;
+    if (c < L::R) {
+#pragma unroll 4
+      for (int q = 0; q < L::TT; ++q) acc += U[c * L::US + q] * v[q];
+    }
+    out[c] = acc;
+  }
+}
+
+// out[q] = (U_r w)_q
+template <int N>
+__device__ void r_U(const double* U, const double* w, double* out) {
+  using L = LayR<N>;
+  for (int q = tid(); q < L::TT; q += kThreads) {
+    double acc = 0.0;
+#pragma unroll 4
+    for (int c = 0; c < L::R; ++c) acc += U[c * L::US + q] * w[c];
+    out[q] = acc;
+  }
+}
+
+// out = S0^-1 w with S0^-1 stored as lower blocks (symmetric)
+template <int N>
+__device__ void r_Sinv(const double* Sb, const double* w, double* out) {
+  using L = LayR<N>;
+  for (int c = tid(); c < L::RP; c += kThreads) {
+    const int I = c >> 4, r = c & 15;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int J = 0; J < L::RB; ++J) {
+      if (J <= I) {
+        const double* blk = Sb + tblk(I, J) * BLK + r * BS;
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) acc += blk[cc] * w[16 * J + cc];
+      } else {
+        const double* blk = Sb + tblk(J, I) * BLK + r;
+#pragma unroll
+        for (int cc = 0; cc < 16; ++cc) acc += blk[cc * BS] * w[16 * J + cc];
+      }
+    }
+    out[c] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- per-fit set-up
+
+// Moves (eq. def_dx), carried values (eq. advection_phi), centred 1-D tables,
+// b = V^T f; returns the mean displacement (dbx, dby) in registers.
+template <int N>
+__device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double za, double zb) {
+  using L = LayR<N>;
+  constexpr int n = L::n;
+  const int t = tid();
+  const int64_t noff = p.noff[e];
+  double* xs = lds + L::oXs;
+  double* ys = lds + L::oYs;
+  double* f = lds + L::oF;
+  double* red = lds + L::oRed;
+  double sx = 0.0, sy = 0.0;
+  for (int i = t; i < n; i += kThreads) {
+    const int64_t k = noff + i;
+    const double x0 = p.xi_node[2 * k], y0 = p.xi_node[2 * k + 1];
+    const double xm = moved_coord(x0, p.A[2 * k], p.B[2 * k], za);
+    const double ym = moved_coord(y0, p.A[2 * k + 1], p.B[2 * k + 1], zb);
+    xs[i] = xm;
+    ys[i] = ym;
+    f[i] = p.phi[s * p.nodes + k] * p.src[k];
+    sx += xm - x0;
+    sy += ym - y0;
+  }
+  const double* gsrc = p.gxinv + p.gx_off[N];
+  double* gxi = lds + L::oGxi;
+  for (int i = t; i < N * N; i += kThreads) gxi[i] = gsrc[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_xor(sx, o, 64);
+    sy += __shfl_xor(sy, o, 64);
+  }
+  if (lane() == 0) {
+    red[wave()] = sx;
+    red[4 + wave()] = sy;
+  }
+  block_sync();
+  const double dbx = (red[0] + red[1] + red[2] + red[3]) / n;
+  const double dby = (red[4] + red[5] + red[6] + red[7]) / n;
+  double* X1 = lds + L::oX1;
+  double* Y1 = lds + L::oY1;
+  for (int i = t; i < n; i += kThreads) {
+    double px[N], py[N];
+    legendre_eval<N>(xs[i] - dbx, p.rec, px);
+    legendre_eval<N>(ys[i] - dby, p.rec, py);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      X1[i * N + k] = px[k];
+      Y1[i * N + k] = py[k];
+    }
+  }
+  double* Bx = lds + L::oBx;
+  double* By = lds + L::oBy;
+  double* Ev = lds + L::oEv;
+  if (t < N) {
+    double px[N], py[N];
+    legendre_eval<N>(p.xi_tab[N * kMaxN + t] - dbx, p.rec, px);
+    legendre_eval<N>(p.xi_tab[N * kMaxN + t] - dby, p.rec, py);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      Bx[t * N + k] = px[k];
+      By[t * N + k] = py[k];
+    }
+  } else if (t >= 64 && t < 68) {
+    const int w = t - 64;
+    double q[N];
+    const double a = (w == 0) ? -dbx : (w == 1) ? 1.0 - dbx : (w == 2) ? -dby : 1.0 - dby;
+    legendre_eval<N>(a, p.rec, q);
+#pragma unroll
+    for (int k = 0; k < N; ++k) Ev[w * N + k] = q[k];
+  }
+  block_sync();
+  r_VT<N>(X1, Y1, f, lds + L::oB);
+  block_sync();
+}
+
+// G v = V^T (V v) into out (tmp: n doubles).  Two barriers.
+template <int N>
+__device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, double* out) {
+  using L = LayR<N>;
+  r_V<N>(lds + L::oX1, lds + L::oY1, v, tmp);
+  block_sync();
+  r_VT<N>(lds + L::oX1, lds + L::oY1, tmp, out);
+  block_sync();
+}
+
+// Solver statistics of one fit: stats[2 (phase - 1)] += iterations,
+// stats[2 (phase - 1) + 1] += 1 when the tolerance was not reached.
+__device__ __forceinline__ void count_fit(const Params2D& p, int phase, int iters, bool converged) {
+  if (tid() == 0 && p.stats) {
+    atomicAdd(p.stats + 2 * (phase - 1), (unsigned long long)iters);
+    if (!converged) atomicAdd(p.stats + 2 * (phase - 1) + 1, 1ull);
+  }
+}
+
+// ---------------------------------------------------------------- phase 1
+
+template <int N>
+__device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, int64_t fit) {
+  using L = LayR<N>;
+  constexpr int n = L::n;
+  const int64_t w = fit / p.M;
+  const int64_t s = fit - w * p.M;
+  const int e = p.work[w];
+  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)(p.step_ptr ? *p.step_ptr : p.step), (uint64_t)s);
+  r_setup<N>(p, lds, e, s, z.a, z.b);
+  const int t = tid();
+  const double* gxi = lds + L::oGxi;
+  double* b = lds + L::oB;
+  double* x = lds + L::oXv;
+  double* r = lds + L::oR;
+  double* g = lds + L::oGv;
+  double* pv = lds + L::oP;
+  double* q = lds + L::oQ;
+  double* t1 = lds + L::oT1;
+  double* red = lds + L::oRed;
+  // preconditioned conjugate gradients on G c = b from c = G0^-1 b
+  r_G0inv<N>(gxi, b, t1, x);
+  const double xx = block_dot<N>(x, x, red);
+  r_G<N>(lds, x, t1, r);
+  for (int i = t; i < n; i += kThreads) r[i] -= b[i];
+  block_sync();
+  r_G0inv<N>(gxi, r, t1, g);
+  double rg, gg;
+  block_rg_gg<N>(r, g, rg, gg, red);
+  const double stop = p.tol2 * xx;
+  int it = 0;
+  if (gg > stop) {
+    for (int i = t; i < n; i += kThreads) pv[i] = -g[i];
+    block_sync();
+    for (it = 1; it <= p.max_iter; ++it) {
+      r_G<N>(lds, pv, t1, q);
+      const double pq = block_dot<N>(pv, q, red);
+      const double alpha = rg / pq;
+      for (int i = t; i < n; i += kThreads) {
+        x[i] += alpha * pv[i];
+        r[i] += alpha * q[i];
+      }
+      block_sync();
+      r_G0inv<N>(gxi, r, t1, g);
+      double rg1;
+      block_rg_gg<N>(r, g, rg1, gg, red);
+      if (gg <= stop) break;
+      const double beta = rg1 / rg;
+      rg = rg1;
+      for (int i = t; i < n; i += kThreads) pv[i] = beta * pv[i] - g[i];
+      block_sync();
+    }
+  }
+  count_fit(p, 1, it > p.max_iter ? p.max_iter : it, gg <= stop);
+  // traces of p0 at the own edge points (eq. remap_bnd)
+  double* tv = lds + L::oTr;
+  r_C<N>(lds + L::oBx, lds + L::oBy, lds + L::oEv, x, tv);
+  block_sync();
+  const int64_t eoff = p.eoff[e];
+  for (int qq = t; qq < L::TT; qq += kThreads) p.tr[s * p.edges + eoff + qq] = tv[qq];
+}
+
+// ---------------------------------------------------------------- phase 2
+
+// Constraint preconditioner, first block:  out = G0^-1 (r - C_r^T y) with
+// y = S0^-1 (C_r G0^-1 r - rhs2); rhs2 may be null (zero).  Leaves
+// z0 = G0^-1 r, y (in w2) and C_r^T y (in t2) behind.  Scratch: t1, e1, w1.
+template <int N>
+__device__ void r_Pproj(double* lds, const double* U, const double* rin, const double* rhs2, double* out) {
+  using L = LayR<N>;
+  const double* gxi = lds + L::oGxi;
+  double* z0 = lds + L::oZ0;
+  double* t1 = lds + L::oT1;
+  double* t2 = lds + L::oT2;
+  double* e1 = lds + L::oE1;
+  double* w1 = lds + L::oW1;
+  double* w2 = lds + L::oW2;
+  const double* Bx = lds + L::oBx;
+  const double* By = lds + L::oBy;
+  const double* Ev = lds + L::oEv;
+  r_G0inv<N>(gxi, rin, t1, z0);
+  r_C<N>(Bx, By, Ev, z0, e1);
+  block_sync();
+  r_UT<N>(U, e1, w1);
+  block_sync();
+  if (rhs2) {
+    for (int c = tid(); c < L::R; c += kThreads) w1[c] -= rhs2[c];
+    block_sync();
+  }
+  r_Sinv<N>(lds + L::oSblk, w1, w2);
+  block_sync();
+  r_U<N>(U, w2, e1);
+  block_sync();
+  r_CT<N>(Bx, By, Ev, e1, t2);
+  block_sync();
+  r_G0inv<N>(gxi, t2, t1, out);
+  for (int i = tid(); i < N * N; i += kThreads) out[i] = z0[i] - out[i];
+  block_sync();
+}
+
+template <int N>
+__device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, int64_t fit) {
+  using L = LayR<N>;
+  constexpr int n = L::n, TT = L::TT, R = L::R, RB = L::RB, NH = L::NH;
+  const int64_t w = fit / p.M;
+  const int64_t s = fit - w * p.M;
+  const int e = p.work[w];
+  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)(p.step_ptr ? *p.step_ptr : p.step), (uint64_t)s);
+  r_setup<N>(p, lds, e, s, z.a, z.b);
+  const int t = tid(), wv = wave();
+  const int64_t eoff = p.eoff[e];
+  const double* U = p.ur + p.ur_off[N];
+  if constexpr (L::kUrLds) {
+    double* Ul = lds + L::oU;
+    for (int i = t; i < TT * R; i += kThreads) Ul[(i / TT) * L::TTs + i % TT] = U[i];
+    U = Ul;   // visible to all threads after the barrier that follows the H tables
+  }
+  const double* gxi = lds + L::oGxi;
+  const double* Bx = lds + L::oBx;
+  const double* By = lds + L::oBy;
+  const double* Ev = lds + L::oEv;
+  double* gv = lds + L::oGr;
+  // upwinded boundary data (eq. bnd_update)
+  for (int q = t; q < TT; q += kThreads) {
+    const int ew = q / N, j = q % N;
+    const double tq = p.tr[s * p.edges + eoff + q];
+    const double zd = (ew < 2) ? z.a : z.b;
+    const double disp = __dadd_rn(p.Af[eoff + q], __dmul_rn(p.Bf[eoff + q], zd));
+    const bool pos = disp > 0.0;
+    const bool take_nbr = (ew == 0 || ew == 2) ? pos : !pos;   // W, S: neighbour is the negative side
+    double g = tq;
+    if (take_nbr) {
+      const int nb = p.nbr[4 * e + ew];
+      if (nb < 0) {
+        g = p.ghost[eoff + q];
+      } else {
+        const int Ns = p.order[nb];
+        const double* src = p.tr + s * p.edges + p.eoff[nb] + (ew ^ 1) * Ns;
+        if (Ns == N) {
+          g = src[j];
+        } else {   // trace of another order: Lagrange interpolation to this element's abscissae
+          const double* Lm = p.interp + p.interp_off[N * (kMaxN + 1) + Ns] + j * Ns;
+          double acc = 0.0;
+          for (int m = 0; m < Ns; ++m) acc += Lm[m] * src[m];
+          g = acc;
+        }
+      }
+    }
+    gv[q] = g;
+  }
+  // 1-D quadratic forms H[a][b] = v_a^T Gx^-1 v_b over {psi(0 - d), psi(1 - d), psi(xi_j - d)}
+  double* Hx = lds + L::oHx;
+  double* Hy = lds + L::oHy;
+  for (int idx = t; idx < 2 * NH * NH; idx += kThreads) {
+    const int dir = idx / (NH * NH), ab = idx % (NH * NH), a = ab / NH, bb = ab % NH;
+    const double* va = (a == 0) ? Ev + 2 * dir * N : (a == 1) ? Ev + (2 * dir + 1) * N : (dir == 0 ? Bx : By) + (a - 2) * N;
+    const double* vb = (bb == 0) ? Ev + 2 * dir * N : (bb == 1) ? Ev + (2 * dir + 1) * N : (dir == 0 ? Bx : By) + (bb - 2) * N;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+      double inner = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < N; ++kk) inner += gxi[k * N + kk] * vb[kk];
+      acc += va[k] * inner;
+    }
+    (dir == 0 ? Hx : Hy)[ab] = acc;
+  }
+  block_sync();
+  double* rr = lds + L::oRr;
+  r_UT<N>(U, gv, rr);                    // g_r = U_r^T g
+  // TU = (C G0^-1 C^T) U_r, entry (q1, q2) of C G0^-1 C^T = Hx[xa1][xa2] Hy[ya1][ya2];
+  // then S0 = U_r^T TU into lower blocks (zero padding)
+  double* TU = lds + L::oTU;
+  double* Sb = lds + L::oSblk;
+  typedef Mma<double> M64;
+  if constexpr (L::kUrLds) {
+    constexpr int TTs = L::TTs, QB = (TT + 15) / 16;
+    const int l = lane(), lr = l & 15, lk = l >> 4;
+#pragma unroll 1
+    for (int bidx = wv; bidx < QB * RB; bidx += 4) {
+      const int I = bidx / RB, C = bidx % RB;
+      const int q1 = 16 * I + lr, c = 16 * C + lr;
+      const int w1 = q1 / N, j1 = q1 % N;
+      const int xa1 = (w1 == 0) ? 0 : (w1 == 1) ? 1 : 2 + j1;
+      const int ya1 = (w1 == 2) ? 0 : (w1 == 3) ? 1 : 2 + j1;
+      M64::acc_t acc = zacc<double>();
+#pragma unroll 1
+      for (int kk = 0; kk < TT / 4; ++kk) {
+        const int q = 4 * kk + lk;
+        const int w2 = q / N, j2 = q % N;
+        const int xa2 = (w2 == 0) ? 0 : (w2 == 1) ? 1 : 2 + j2;
+        const int ya2 = (w2 == 2) ? 0 : (w2 == 3) ? 1 : 2 + j2;
+        const double a = q1 < TT ? Hx[xa1 * NH + xa2] * Hy[ya1 * NH + ya2] : 0.0;
+        const double bv = c < R ? U[c * TTs + q] : 0.0;
+        acc = M64::mma(a, bv, acc);
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int row = 16 * I + M64::row(l, s4);
+        if (row < TT && c < R) TU[c * TTs + row] = acc[s4];
+      }
+    }
+    block_sync();
+#pragma unroll 1
+    for (int bidx = wv; bidx < L::nS; bidx += 4) {
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= bidx) ++I;
+      const int J = bidx - I * (I + 1) / 2;
+      const int c1 = 16 * I + lr, c2 = 16 * J + lr;
+      M64::acc_t acc = zacc<double>();
+#pragma unroll 1
+      for (int kk = 0; kk < TT / 4; ++kk) {
+        const int q = 4 * kk + lk;
+        const double a = c1 < R ? U[c1 * TTs + q] : 0.0;
+        const double bv = c2 < R ? TU[c2 * TTs + q] : 0.0;
+        acc = M64::mma(a, bv, acc);
+      }
+      store_acc(Sb + bidx * BLK, acc);
+    }
+    block_sync();
+  } else {
+    for (int idx = t; idx < TT * R; idx += kThreads) {
+      const int q1 = idx % TT, c = idx / TT;
+      const int w1 = q1 / N, j1 = q1 % N;
+      const int xa1 = (w1 == 0) ? 0 : (w1 == 1) ? 1 : 2 + j1;
+      const int ya1 = (w1 == 2) ? 0 : (w1 == 3) ? 1 : 2 + j1;
+      const double* Uc = U + c * TT;
+      double acc = 0.0;
+#pragma unroll 1
+      for (int w2 = 0; w2 < 4; ++w2) {
+#pragma unroll 4
+        for (int j2 = 0; j2 < N; ++j2) {
+          const int xa2 = (w2 == 0) ? 0 : (w2 == 1) ? 1 : 2 + j2;
+          const int ya2 = (w2 == 2) ? 0 : (w2 == 3) ? 1 : 2 + j2;
+          acc += Hx[xa1 * NH + xa2] * Hy[ya1 * NH + ya2] * Uc[w2 * N + j2];
+        }
+      }
+      TU[c * TT + q1] = acc;
+    }
+    block_sync();
+    for (int idx = t; idx < L::nS * 256; idx += kThreads) {
+      const int bidx = idx >> 8, rc = idx & 255, rI = rc >> 4, cJ = rc & 15;
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= bidx) ++I;
+      const int J = bidx - I * (I + 1) / 2;
+      const int c1 = 16 * I + rI, c2 = 16 * J + cJ;
+      double acc = 0.0;
+      if (c1 < R && c2 < R) {
+        const double* Uc = U + c1 * TT;
+        const double* Tc = TU + c2 * TT;
+#pragma unroll 4
+        for (int q = 0; q < TT; ++q) acc += Uc[q] * Tc[q];
+      }
+      Sb[bidx * BLK + rI * BS + cJ] = acc;
+    }
+    block_sync();
+  }
+  cholesky<double, RB>(Sb, R);
+  // L^-1: X_IJ = -L_II^-1 sum_{K=J}^{I-1} L_IK X_KJ (column J on wavefront J mod 4)
+  double* Xb = lds + L::oXblk;
+  if constexpr (RB > 1) {
+    double* Tmp = lds + L::oTmp;
+#pragma unroll 1
+    for (int J = wv; J < RB; J += 4) {
+#pragma unroll 1
+      for (int I = J + 1; I < RB; ++I) {
+        M64::acc_t acc = zacc<double>();
+#pragma unroll 1
+        for (int K = J; K < I; ++K) {
+          const double* LIK = Sb + tblk(I, K) * BLK;
+          const double* XKJ = (K == J) ? Sb + tblk(J, J) * BLK : Xb + tblk(K, J) * BLK;
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) acc = M64::mma(rowpat(LIK, kk), colpat(XKJ, kk), acc);
+        }
+        double* Tb = Tmp + wv * BLK;
+        store_acc(Tb, acc);
+        wave_sync();
+        M64::acc_t out = zacc<double>();
+        const double* Di = Sb + tblk(I, I) * BLK;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) out = M64::mma(-rowpat(Di, kk), colpat(Tb, kk), out);
+        store_acc(Xb + tblk(I, J) * BLK, out);
+        wave_sync();
+      }
+    }
+    block_sync();
+  }
+  // S0^-1 = X^T X, lower blocks, accumulated in registers then stored over the factor
+  {
+    constexpr int kMaxPer = (L::nS + 3) / 4;
+    M64::acc_t accs[kMaxPer];
+    int bi = 0, slot = 0;
+#pragma unroll 1
+    for (int I = 0; I < RB; ++I) {
+#pragma unroll 1
+      for (int J = 0; J <= I; ++J, ++bi) {
+        if ((bi & 3) != wv) continue;
+        M64::acc_t acc = zacc<double>();
+#pragma unroll 1
+        for (int K = I; K < RB; ++K) {
+          const double* XKI = (K == I) ? Sb + tblk(I, I) * BLK : Xb + tblk(K, I) * BLK;
+          const double* XKJ = (K == J) ? Sb + tblk(J, J) * BLK : Xb + tblk(K, J) * BLK;
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) acc = M64::mma(colpat(XKI, kk), colpat(XKJ, kk), acc);
+        }
+#pragma unroll
+        for (int sI = 0; sI < kMaxPer; ++sI)
+          if (sI == slot) accs[sI] = acc;
+        ++slot;
+      }
+    }
+    block_sync();
+    bi = 0;
+    slot = 0;
+#pragma unroll 1
+    for (int I = 0; I < RB; ++I) {
+#pragma unroll 1
+      for (int J = 0; J <= I; ++J, ++bi) {
+        if ((bi & 3) != wv) continue;
+#pragma unroll
+        for (int sI = 0; sI < kMaxPer; ++sI)
+          if (sI == slot) store_acc(Sb + tblk(I, J) * BLK, accs[sI]);
+        ++slot;
+      }
+    }
+    block_sync();
+  }
+  // particular solution x0 = first block of [[G0, C_r^T], [C_r, 0]]^-1 [b; g_r]
+  double* b = lds + L::oB;
+  double* x = lds + L::oXv;
+  double* r = lds + L::oR;
+  double* g = lds + L::oGv;
+  double* pv = lds + L::oP;
+  double* q = lds + L::oQ;
+  double* t1 = lds + L::oT1;
+  double* red = lds + L::oRed;
+  r_Pproj<N>(lds, U, b, rr, x);
+  const double xx = block_dot<N>(x, x, red);
+  r_G<N>(lds, x, t1, r);
+  for (int i = t; i < n; i += kThreads) r[i] -= b[i];
+  block_sync();
+  r_Pproj<N>(lds, U, r, nullptr, g);
+  // residual update: r -= C_r^T y with the projection's multipliers (left in t2
+  // by r_Pproj), which leaves g unchanged but keeps r, and with it the
+  // rounding noise of the next projections, at the size of the error
+  double* t2 = lds + L::oT2;
+  for (int i = t; i < n; i += kThreads) r[i] -= t2[i];
+  double rg, gg;
+  block_rg_gg<N>(r, g, rg, gg, red);
+  const double stop = p.tol2 * xx;
+  int it = 0;
+  if (gg > stop) {
+    for (int i = t; i < n; i += kThreads) pv[i] = -g[i];
+    block_sync();
+    for (it = 1; it <= p.max_iter; ++it) {
+      r_G<N>(lds, pv, t1, q);
+      const double pq = block_dot<N>(pv, q, red);
+      const double alpha = rg / pq;
+      for (int i = t; i < n; i += kThreads) {
+        x[i] += alpha * pv[i];
+        r[i] += alpha * q[i];
+      }
+      block_sync();
+      r_Pproj<N>(lds, U, r, nullptr, g);
+      for (int i = t; i < n; i += kThreads) r[i] -= t2[i];
+      double rg1;
+      block_rg_gg<N>(r, g, rg1, gg, red);
+      if (gg <= stop) break;
+      const double beta = rg1 / rg;
+      rg = rg1;
+      for (int i = t; i < n; i += kThreads) pv[i] = beta * pv[i] - g[i];
+      block_sync();
+    }
+  }
+  count_fit(p, 2, it > p.max_iter ? p.max_iter : it, gg <= stop);
+  // restore C_r x = g_r to working accuracy: x -= G0^-1 C_r^T S0^-1 (C_r x - g_r)
+  {
+    double* zz = lds + L::oZ0;
+    double* e1 = lds + L::oE1;
+    double* w1 = lds + L::oW1;
+    double* w2 = lds + L::oW2;
+    r_C<N>(Bx, By, Ev, x, e1);
+    block_sync();
+    r_UT<N>(U, e1, w1);
+    block_sync();
+    for (int c = t; c < R; c += kThreads) w1[c] -= rr[c];
+    block_sync();
+    r_Sinv<N>(lds + L::oSblk, w1, w2);
+    block_sync();
+    r_U<N>(U, w2, e1);
+    block_sync();
+    r_CT<N>(Bx, By, Ev, e1, t2);
+    block_sync();
+    r_G0inv<N>(gxi, t2, t1, zz);
+    for (int i = t; i < n; i += kThreads) x[i] -= zz[i];
+    block_sync();
+  }
+  // new values at the Gauss nodes (eq. phi_star)
+  const int64_t noff = p.noff[e];
+  for (int i = t; i < n; i += kThreads) {
+    const int ix = i % N, iy = i / N;
+    double bxr[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) bxr[k] = Bx[ix * N + k];
+    double v = 0.0;
+#pragma unroll 1
+    for (int ly = 0; ly < N; ++ly) {
+      double inner = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) inner += bxr[k] * x[ly * N + k];
+      v += By[iy * N + ly] * inner;
+    }
+    p.phi[s * p.nodes + noff + i] = v;
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void fit2r_phase1(Params2D p) {
+  extern __shared__ __attribute__((aligned(16))) double lds_r1[];
+  r_phase1_body<N>(p, lds_r1, blockIdx.x + p.block0);
+}
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void fit2r_phase2(Params2D p) {
+  extern __shared__ __attribute__((aligned(16))) double lds_r2[];
+  r_phase2_body<N>(p, lds_r2, blockIdx.x + p.block0);
+}
+
+template <int N>
+static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStream_t st) {
+  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayR<N>::bytes2;
+  const int64_t chunk = (int64_t)1 << 30;
+  for (int64_t b0 = 0; b0 < nfits; b0 += chunk) {
+    Params2D q = p;
+    q.block0 = p.block0 + b0;
+    const int64_t nb = (nfits - b0) < chunk ? (nfits - b0) : chunk;
+    if (phase == 1)
+      hipLaunchKernelGGL((fit2r_phase1<N>), dim3((unsigned)nb), dim3(kThreads), lds, st, q);
+    else
+      hipLaunchKernelGGL((fit2r_phase2<N>), dim3((unsigned)nb), dim3(kThreads), lds, st, q);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st) {
+  switch (N) {
+    case 2: return launch_r<2>(phase, p, nfits, st);
+    case 3: return launch_r<3>(phase, p, nfits, st);
+    case 4: return launch_r<4>(phase, p, nfits, st);
+    case 5: return launch_r<5>(phase, p, nfits, st);
+    case 6: return launch_r<6>(phase, p, nfits, st);
+    case 7: return launch_r<7>(phase, p, nfits, st);
+    case 8: return launch_r<8>(phase, p, nfits, st);
+    case 9: return launch_r<9>(phase, p, nfits, st);
+    case 10: return launch_r<10>(phase, p, nfits, st);
+    case 11: return launch_r<11>(phase, p, nfits, st);
+    case 12: return launch_r<12>(phase, p, nfits, st);
+    case 13: return launch_r<13>(phase, p, nfits, st);
+    case 14: return launch_r<14>(phase, p, nfits, st);
+    case 15: return launch_r<15>(phase, p, nfits, st);
+    case 16: return launch_r<16>(phase, p, nfits, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Persistent fused kernel over every order (2..16) of several problems, as
+// the factorisation kernels' fused form: segments largest order first, a
+// device work counter, each order outlined with its own registers.
+__device__ __forceinline__ int64_t uniform64r(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int N, int PHASE>
+__device__ __attribute__((noinline)) void fused_fit_r(const Params2D* pp, int64_t fit) {
+  extern __shared__ __attribute__((aligned(16))) double lds_rf[];
+  const Params2D& p = *(const Params2D*)(uintptr_t)(uint64_t)uniform64r((int64_t)(uintptr_t)pp);
+  fit = uniform64r(fit);
+  if constexpr (PHASE == 1) r_phase1_body<N>(p, lds_rf, fit);
+  else r_phase2_body<N>(p, lds_rf, fit);
+}
+
+template <int PHASE>
+__global__ __launch_bounds__(kThreads) void fit2r_fused(Fused2DArgs a) {
+  __shared__ int64_t item_sh;
+  for (;;) {
+    if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(a.counter, 1ull);
+    __syncthreads();
+    const int64_t item = uniform64r(item_sh);
+    __syncthreads();
+    if (item >= a.total) break;
+    int sg = 0;
+    while (sg + 1 < a.nseg && item >= a.seg[sg + 1].start) ++sg;
+    const Params2D* p = a.task[a.seg[sg].task];
+    const int64_t fit = a.seg[sg].fit0 + (item - a.seg[sg].start);
+    switch (a.seg[sg].N) {
+      case 2: fused_fit_r<2, PHASE>(p, fit); break;
+      case 3: fused_fit_r<3, PHASE>(p, fit); break;
+      case 4: fused_fit_r<4, PHASE>(p, fit); break;
+      case 5: fused_fit_r<5, PHASE>(p, fit); break;
+      case 6: fused_fit_r<6, PHASE>(p, fit); break;
+      case 7: fused_fit_r<7, PHASE>(p, fit); break;
+      case 8: fused_fit_r<8, PHASE>(p, fit); break;
+      case 9: fused_fit_r<9, PHASE>(p, fit); break;
+      case 10: fused_fit_r<10, PHASE>(p, fit); break;
+      case 11: fused_fit_r<11, PHASE>(p, fit); break;
+      case 12: fused_fit_r<12, PHASE>(p, fit); break;
+      case 13: fused_fit_r<13, PHASE>(p, fit); break;
+      case 14: fused_fit_r<14, PHASE>(p, fit); break;
+      case 15: fused_fit_r<15, PHASE>(p, fit); break;
+      case 16: fused_fit_r<16, PHASE>(p, fit); break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_fit2r_fused(int phase, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st) {
+  if (phase == 1) hipLaunchKernelGGL((fit2r_fused<1>), dim3(grid), dim3(kThreads), lds, st, a);
+  else hipLaunchKernelGGL((fit2r_fused<2>), dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+int fit2r_fused_occupancy(int phase, size_t lds) {
+  int nb = 0;
+  hipError_t e = phase == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2r_fused<1>, kThreads, lds)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2r_fused<2>, kThreads, lds);
+  return e == hipSuccess ? nb : 0;
+}
+
+template <int N>
+static size_t lds_r(int phase) { return phase == 1 ? LayR<N>::bytes1 : LayR<N>::bytes2; }
+
+size_t fit2r_lds_bytes(int N, int phase) {
+  switch (N) {
+    case 2: return lds_r<2>(phase);
+    case 3: return lds_r<3>(phase);
+    case 4: return lds_r<4>(phase);
+    case 5: return lds_r<5>(phase);
+    case 6: return lds_r<6>(phase);
+    case 7: return lds_r<7>(phase);
+    case 8: return lds_r<8>(phase);
+    case 9: return lds_r<9>(phase);
+    case 10: return lds_r<10>(phase);
+    case 11: return lds_r<11>(phase);
+    case 12: return lds_r<12>(phase);
+    case 13: return lds_r<13>(phase);
+    case 14: return lds_r<14>(phase);
+    case 15: return lds_r<15>(phase);
+    case 16: return lds_r<16>(phase);
+    default: return 0;
+  }
+}
+
+}  // namespace sl

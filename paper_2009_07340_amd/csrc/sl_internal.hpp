@@ -67,6 +67,12 @@ struct Params2D {
   uint64_t seed;
   uint32_t stream;
   int refine;              // float64 refinement sweeps (mixed-precision modes)
+  // reference-preconditioned solver
+  const double* gxinv;     // Gx^-1 of each order (N x N, row-major)
+  int64_t gx_off[kMaxN + 1];
+  double tol2;             // stop when g^T g <= tol2 * x0^T x0 (g: preconditioned residual)
+  int max_iter;
+  unsigned long long* stats;   // per phase: iterations summed over fits, fits that hit max_iter
   LegendreRec rec;
 };
 
@@ -115,6 +121,11 @@ size_t fit2d_lds_bytes(int N, int mode, int phase);
 hipError_t launch_fit2d_fused(int phase, int mode, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
 int fit2d_fused_occupancy(int phase, int mode, size_t lds);
 hipError_t launch_step_counters(const StepArgs& a, hipStream_t st);
+hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st);
+size_t fit2r_lds_bytes(int N, int phase);
+hipError_t launch_fit2r_fused(int phase, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
+int fit2r_fused_occupancy(int phase, size_t lds);
+constexpr int kMaxNRef = 16;  // largest order of the reference-preconditioned 2-D solver
 constexpr int kMaxN2D = 10;   // largest order of the 2-D LDS-resident fit
 hipError_t launch_resident_1d(int N, const Params1D& p, hipStream_t st);
 hipError_t launch_resident_1d_batch(int N, int algo, const Batch1DArgs& a, size_t lds, hipStream_t st);

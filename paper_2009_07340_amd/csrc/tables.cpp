@@ -164,4 +164,59 @@ std::vector<double> edge_range_basis(int N, const std::vector<double>& xi) {
   return U;
 }
 
+std::vector<double> reference_gram_inverse(const std::vector<double>& xi) {
+  const int N = (int)xi.size();
+  // Vx[i][k] = psi_k(xi_i), the same three-term recurrence as the device tables
+  std::vector<long double> V(N * N), G(N * N, 0.0L), Inv(N * N, 0.0L);
+  for (int i = 0; i < N; ++i) {
+    const long double x = 2.0L * xi[i] - 1.0L;
+    long double pm = 1.0L, pc = 0.0L;
+    V[i * N + 0] = 1.0L;
+    if (N > 1) {
+      pc = std::sqrt(3.0L) * x;
+      V[i * N + 1] = pc;
+    }
+    for (int k = 1; k + 1 < N; ++k) {
+      const long double a = std::sqrt((2.0L * k + 3.0L) * (2.0L * k + 1.0L)) / (k + 1.0L);
+      const long double b = k * std::sqrt(2.0L * k + 3.0L) / ((k + 1.0L) * std::sqrt(2.0L * k - 1.0L));
+      const long double pn = a * x * pc - b * pm;
+      pm = pc;
+      pc = pn;
+      V[i * N + k + 1] = pn;
+    }
+  }
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b)
+      for (int i = 0; i < N; ++i) G[a * N + b] += V[i * N + a] * V[i * N + b];
+  // Gauss-Jordan with partial pivoting on [G | I]
+  for (int i = 0; i < N; ++i) Inv[i * N + i] = 1.0L;
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < N; ++r)
+      if (std::fabs(G[r * N + c]) > std::fabs(G[piv * N + c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < N; ++k) {
+        std::swap(G[c * N + k], G[piv * N + k]);
+        std::swap(Inv[c * N + k], Inv[piv * N + k]);
+      }
+    const long double d = G[c * N + c];
+    for (int k = 0; k < N; ++k) {
+      G[c * N + k] /= d;
+      Inv[c * N + k] /= d;
+    }
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      const long double f = G[r * N + c];
+      if (f == 0.0L) continue;
+      for (int k = 0; k < N; ++k) {
+        G[r * N + k] -= f * G[c * N + k];
+        Inv[r * N + k] -= f * Inv[c * N + k];
+      }
+    }
+  }
+  std::vector<double> out(N * N);
+  for (int i = 0; i < N * N; ++i) out[i] = (double)Inv[i];
+  return out;
+}
+
 }  // namespace sl

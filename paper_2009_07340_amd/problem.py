@@ -8,20 +8,21 @@ from . import binding as B
 
 class Problem:
     def __init__(self, wl, precision="fp64", samples=None, seed=None, stream_id=0, dev_ws=None,
-                 ws_bytes=0, hip_stream=None, nodes="gl", refine_iters=-1):
+                 ws_bytes=0, hip_stream=None, nodes="gl", refine_iters=-1, solver="auto"):
         self.wl = wl
         self.M = int(samples if samples is not None else wl.samples)
         self.desc = B.make_desc(wl.dim, wl.kx, wl.ky, wl.box, wl.order if np.isscalar(wl.order) else wl.order_array(),
                                 nodes=nodes, bc=wl.bc, samples=self.M,
                                 seed=wl.seed if seed is None else seed, stream_id=stream_id,
-                                precision=precision, refine_iters=refine_iters)
+                                precision=precision, refine_iters=refine_iters, solver=solver)
         self.h = B.sl_init_mesh(self.desc, dev_ws, ws_bytes, hip_stream)
         self.nodes, self.edges, self.K = B.sl_sizes(self.h)
 
     @staticmethod
-    def required_bytes(wl, precision="fp64", samples=None):
+    def required_bytes(wl, precision="fp64", samples=None, solver="auto"):
         d = B.make_desc(wl.dim, wl.kx, wl.ky, wl.box, wl.order if np.isscalar(wl.order) else wl.order_array(),
-                        bc=wl.bc, samples=int(samples if samples is not None else wl.samples), precision=precision)
+                        bc=wl.bc, samples=int(samples if samples is not None else wl.samples), precision=precision,
+                        solver=solver)
         return B.sl_required_bytes(d)
 
     def coords(self):

@@ -19,26 +19,30 @@ def B():
     return binding
 
 
-def _handle(B, wl, a, samples=None, precision="fp64", refine=-1):
+def _handle(B, wl, a, samples=None, precision="fp64", refine=-1, solver="auto"):
     order = wl.order if np.isscalar(wl.order) else wl.order_array()
     desc = B.make_desc(2, wl.kx, wl.ky, wl.box, order, bc=wl.bc, samples=samples or wl.samples, seed=wl.seed,
-                       precision=precision, refine_iters=refine)
+                       precision=precision, refine_iters=refine, solver=solver)
     h = B.sl_init_mesh(desc)
     B.sl_set_fields(h, a["u"], a["D"], a["divu"], a["un"], a["Dn"], a["ghost"], a["phi0"])
     return h
 
 
-def _parity(B, wl, nsteps, samples_checked, precision="fp64", refine=-1):
+def _parity(B, wl, nsteps, samples_checked, precision="fp64", refine=-1, solver="auto"):
     mesh, f, phi0, a = oracle_inputs(wl)
-    h = _handle(B, wl, a, precision=precision, refine=refine)
+    h = _handle(B, wl, a, precision=precision, refine=refine, solver=solver)
     try:
         B.sl_step(h, wl.dt, nsteps)
         got = B.sl_get_samples(h, 0, wl.samples)
+        diag = B.sl_diag(h)
     finally:
         B.sl_destroy(h)
     ref = sl.run(mesh, f, phi0, wl.dt, nsteps, wl.seed, np.asarray(samples_checked))
     err = rel_l2(got[samples_checked], ref)
-    print(f"{wl.name} {wl.kx}x{wl.ky} {precision}: {nsteps} steps: rel L2 {err:.3e}", flush=True)
+    print(f"{wl.name} {wl.kx}x{wl.ky} {precision} solver {diag['solver']}: {nsteps} steps: rel L2 {err:.3e}; "
+          f"iterations {diag['solver_iterations']}, unconverged {diag['solver_unconverged']}", flush=True)
+    if diag["solver"] == 2:
+        assert diag["solver_unconverged"] == [0, 0]
     return got, ref, err
 
 
@@ -68,46 +72,100 @@ def test_positions_bitwise_2d(B):
         B.sl_destroy(h)
 
 
-@pytest.mark.parametrize("N", [2, 3, 4, 5, 6, 7, 8, 9, 10])
-def test_small_periodic_parity_every_order(B, N):
-    wl = _small(N)
-    got, ref, err = _parity(B, wl, 3, np.arange(wl.samples))
-    assert err < TOL, (N, err)
+@pytest.mark.parametrize("N,solver", [(N, "factor") for N in range(2, 11)] +
+                         [(N, "reference") for N in range(2, 17)])
+def test_small_periodic_parity_every_order(B, N, solver):
+    wl = _small(N, rot=True)
+    got, ref, err = _parity(B, wl, 3, np.arange(wl.samples), solver=solver)
+    assert err < TOL, (N, solver, err)
 
 
-def test_rectangular_mesh_and_rotation(B):
+@pytest.mark.parametrize("solver", ["factor", "reference"])
+def test_rectangular_mesh_and_rotation(B, solver):
     wl = _small(6, kx=4, ky=2, samples=4, rot=True)
-    got, ref, err = _parity(B, wl, 4, np.arange(4))
+    got, ref, err = _parity(B, wl, 4, np.arange(4), solver=solver)
     assert err < TOL
 
 
-@pytest.mark.parametrize("N", [3, 8])
-def test_dirichlet_parity_2d(B, N):
+@pytest.mark.parametrize("N,solver", [(3, "factor"), (8, "factor"), (3, "reference"), (8, "reference"),
+                                      (13, "reference")])
+def test_dirichlet_parity_2d(B, N, solver):
     wl = _small(N, kx=3, ky=2, samples=2, bc="dirichlet")
-    got, ref, err = _parity(B, wl, 3, np.arange(2))
+    got, ref, err = _parity(B, wl, 3, np.arange(2), solver=solver)
     assert err < TOL
 
 
-def test_mixed_order_parity(B):
+@pytest.mark.parametrize("solver", ["factor", "reference"])
+def test_mixed_order_parity(B, solver):
     """Neighbours of different order: traces interpolated between Gauss abscissae."""
     wl = W.c4_2d_rotation(kx=4, ky=4, samples=3, steps=3)
     wl.order = np.array([6, 8, 10, 6, 8, 6, 10, 8, 10, 6, 8, 6, 8, 10, 6, 8], dtype=np.int32)
     wl.dt = 2e-4
-    got, ref, err = _parity(B, wl, 3, np.arange(3))
+    got, ref, err = _parity(B, wl, 3, np.arange(3), solver=solver)
     assert err < TOL
 
 
-def test_c3_full_size_sample_subset(B):
+def test_mixed_high_orders_reference_solver(B):
+    """Orders up to 16 side by side (reference solver only)."""
+    wl = W.c4_2d_rotation(kx=3, ky=3, samples=2, steps=2)
+    wl.order = np.array([11, 16, 12, 14, 13, 15, 16, 11, 12], dtype=np.int32)
+    wl.dt = 5e-5
+    got, ref, err = _parity(B, wl, 2, np.arange(2), solver="reference")
+    assert err < TOL
+
+
+def test_reference_solver_iterations(B):
+    """A uniform displacement (constant fields) makes the preconditioner exact: no
+    iterations; the rotation needs a few per fit and every fit converges."""
     wl = W.c3_2d_const()
-    got, ref, err = _parity(B, wl, 2, np.array([0, 255]))
+    wl.kx = wl.ky = 8
+    wl.samples = 4
+    mesh, f, phi0, a = oracle_inputs(wl)
+    h = _handle(B, wl, a, solver="reference")
+    try:
+        B.sl_step(h, wl.dt, 2)
+        d = B.sl_diag(h)
+    finally:
+        B.sl_destroy(h)
+    fits = wl.K * wl.samples * 2
+    print("constant fields:", d["solver_iterations"], "iterations over", fits, "fits per phase", flush=True)
+    assert d["solver_unconverged"] == [0, 0]
+    assert d["solver_iterations"][0] <= fits // 10 and d["solver_iterations"][1] <= fits // 10
+    wl = W.c4_2d_rotation(kx=8, ky=8, samples=4, steps=2)
+    mesh, f, phi0, a = oracle_inputs(wl)
+    h = _handle(B, wl, a, solver="reference")
+    try:
+        B.sl_step(h, wl.dt, 2)
+        d = B.sl_diag(h)
+    finally:
+        B.sl_destroy(h)
+    fits = wl.K * wl.samples * 2
+    print("rotation:", d["solver_iterations"], "iterations over", fits, "fits per phase", flush=True)
+    assert d["solver_unconverged"] == [0, 0]
+    assert d["solver_iterations"][1] <= 6 * fits
+
+
+@pytest.mark.parametrize("solver", ["factor", "reference"])
+def test_c3_full_size_sample_subset(B, solver):
+    wl = W.c3_2d_const()
+    got, ref, err = _parity(B, wl, 2, np.array([0, 255]), solver=solver)
     assert err < TOL
     assert np.all(np.isfinite(got))
 
 
 @pytest.mark.slow
-def test_c4_full_size_one_sample(B):
+@pytest.mark.parametrize("solver", ["factor", "reference"])
+def test_c4_full_size_one_sample(B, solver):
     wl = W.c4_2d_rotation()
-    got, ref, err = _parity(B, wl, 1, np.array([511]))
+    got, ref, err = _parity(B, wl, 1, np.array([511]), solver=solver)
+    assert err < TOL
+
+
+def test_c4_full_size_reference_solver_subset(B):
+    """The 128 x 128 mixed-order rotation at full size (all 512 samples on the
+    device), two samples checked against the oracle."""
+    wl = W.c4_2d_rotation()
+    got, ref, err = _parity(B, wl, 1, np.array([0, 301]), solver="reference")
     assert err < TOL
 
 
@@ -188,3 +246,18 @@ def test_mixed_precision_all_samples_agree_with_fp64(B, precision):
     assert err < TOL
     ref = sl.run(mesh, f, phi0, wl.dt, 4, wl.seed, np.array([131]))
     assert rel_l2(out[precision][[131]], ref) < TOL
+
+
+@pytest.mark.parametrize("solver", ["factor", "reference"])
+def test_serving_shapes_large_displacements(B, solver):
+    """2-D requests of the serving stream (coarse meshes, sinusoidal drift, the
+    largest time step the stream allows): the preconditioner is far from exact
+    here, the solver must still converge to the oracle's remap."""
+    reqs = [r for r in W.serving_requests(n=120, kmax=25, mmax=40) if r["dim"] == 2]
+    reqs = [r for r in reqs if r["N"] <= (10 if solver == "factor" else 16)][:6]
+    assert len(reqs) >= 4
+    for r in reqs:
+        wl = W.request_workload(r)
+        wl.samples = 2
+        got, ref, err = _parity(B, wl, 2, np.arange(2), solver=solver)
+        assert err < TOL, (r["id"], r["N"], r["kx"], err)
