@@ -60,7 +60,7 @@ struct Layout {
   std::vector<int> orders;          // distinct orders present, increasing
   size_t ur_doubles = 0, interp_doubles = 0;
   // byte offsets in the workspace
-  size_t o_phi, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
+  size_t o_phi, o_phi2, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
   size_t o_params, o_dstep, o_ctr, o_stats, o_gxinv, total;
   int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
@@ -134,6 +134,8 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
     return at;
   };
   L.o_phi = take(sizeof(double) * (size_t)L.M * L.nodes);
+  // 1-D meshes of more than 256 elements step out of place (tiled kernel)
+  L.o_phi2 = take(L.dim == 1 && L.K > 256 ? sizeof(double) * (size_t)L.M * L.nodes : 0);
   L.o_tr = take(L.dim == 2 ? sizeof(double) * (size_t)L.M * L.edges : 0);
   L.o_xi = take(sizeof(double) * L.nodes * L.dim);
   L.o_A = take(sizeof(double) * L.nodes * L.dim);
@@ -173,7 +175,7 @@ struct sl_ctx {
   hipStream_t stream = nullptr;
   bool own_ws = false;
   char* ws = nullptr;
-  double *phi = nullptr, *tr = nullptr, *xi_node = nullptr, *A = nullptr, *B = nullptr, *src = nullptr;
+  double *phi = nullptr, *phi2 = nullptr, *tr = nullptr, *xi_node = nullptr, *A = nullptr, *B = nullptr, *src = nullptr;
   double *Af = nullptr, *Bf = nullptr, *ghost = nullptr, *mean = nullptr, *phi0 = nullptr;
   // 2-D tables
   int32_t *d_order = nullptr, *d_nbr = nullptr, *d_work = nullptr;
@@ -577,9 +579,17 @@ int step_2d(const std::vector<sl_ctx*>& hs, int32_t nsteps, int fused, int graph
 }
 
 // Batched resident 1-D launches: one per (order, fit form), chunks of kMaxTasks.
+int step_1d(sl_ctx* h, int32_t nsteps, hipStream_t st);
+
 int step_1d_batch(const std::vector<sl_ctx*>& hs, int32_t nsteps, hipStream_t st) {
   std::map<std::pair<int, int>, std::vector<sl_ctx*>> by;
-  for (sl_ctx* h : hs) by[{h->L.order[0], h->algo_1d}].push_back(h);
+  std::vector<sl_ctx*> tiled;
+  for (sl_ctx* h : hs) {
+    if (h->L.K > 256) tiled.push_back(h);
+    else by[{h->L.order[0], h->algo_1d}].push_back(h);
+  }
+  for (sl_ctx* h : tiled)
+    if (int rc = step_1d(h, nsteps, st)) return rc;
   for (auto& kv : by) {
     const auto& v = kv.second;
     for (size_t c0 = 0; c0 < v.size(); c0 += sl::kMaxTasks) {
@@ -600,7 +610,32 @@ int step_1d_batch(const std::vector<sl_ctx*>& hs, int32_t nsteps, hipStream_t st
       SL_HIP(sl::launch_resident_1d_batch(kv.first.first, kv.first.second, a, lds, st));
     }
   }
-  for (sl_ctx* h : hs) h->step += nsteps;
+  for (auto& kv : by)
+    for (sl_ctx* h : kv.second) h->step += nsteps;
+  return SL_OK;
+}
+
+// nsteps 1-D steps of one handle: one resident launch for all steps (K <= 256),
+// else one tiled launch per step, out of place, ending in the primary buffer.
+int step_1d(sl_ctx* h, int32_t nsteps, hipStream_t st) {
+  const Layout& L = h->L;
+  const int N = L.order[0];
+  sl::Params1D p = h->p1;
+  p.nsteps = nsteps;
+  p.step0 = h->step;
+  if (L.K <= 256) {
+    ProfScope ps(h, "resident_1d");
+    SL_HIP(sl::launch_resident_1d(N, p, st));
+  } else {
+    double* buf[2] = {h->phi, h->phi2};
+    for (int it = 0; it < nsteps; ++it) {
+      ProfScope ps(h, "tiled_1d");
+      SL_HIP(sl::launch_tiled_1d(N, p, buf[it & 1], buf[(it + 1) & 1], h->step + it, st));
+    }
+    if (nsteps & 1)
+      SL_HIP(hipMemcpyAsync(h->phi, h->phi2, sizeof(double) * (size_t)L.M * L.nodes, hipMemcpyDeviceToDevice, st));
+  }
+  h->step += nsteps;
   return SL_OK;
 }
 
@@ -636,7 +671,6 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   if (rc) return rc;
   const Layout& L = h->L;
   if (L.dim == 1 && !L.uniform) return fail(SL_EUNSUPPORTED, "1-D meshes need a uniform order");
-  if (L.dim == 1 && L.K > 256) return fail(SL_EUNSUPPORTED, "1-D meshes with more than 256 elements are not supported yet");
   if (L.dim == 2 && L.solver == SL_SOLVER_FACTOR && L.maxN > sl::kMaxN2D)
     return fail(SL_EUNSUPPORTED, "the factorisation solver supports N <= 10; use the float64 reference solver for N <= 16");
   if (L.dim == 1 && desc->precision != SL_PREC_FP64)
@@ -661,6 +695,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
     h->own_ws = true;
   }
   h->phi = (double*)(h->ws + L.o_phi);
+  h->phi2 = (double*)(h->ws + L.o_phi2);
   h->tr = (double*)(h->ws + L.o_tr);
   h->xi_node = (double*)(h->ws + L.o_xi);
   h->A = (double*)(h->ws + L.o_A);
@@ -912,16 +947,7 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
   if (int rc = update_coefficients(h, dt)) return rc;
   const Layout& L = h->L;
   if (L.dim == 2) return step_2d({h}, nsteps, h->sched.fused, h->sched.graph, h->sched.grid, h->stream);
-  const int N = L.order[0];
-  sl::Params1D p = h->p1;
-  p.nsteps = nsteps;
-  p.step0 = h->step;
-  {
-    ProfScope ps(h, "resident_1d");
-    SL_HIP(sl::launch_resident_1d(N, p, h->stream));
-  }
-  h->step += nsteps;
-  return SL_OK;
+  return step_1d(h, nsteps, h->stream);
 }
 
 int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t nsteps) {

@@ -116,6 +116,111 @@ __global__ __launch_bounds__(kResidentThreads) void resident_1d_batch_kernel(Bat
   resident_1d_body<N, kNodal>(*a.task[t], lds_tr, b - a.bstart[t], a.step0[t], a.nsteps);
 }
 
+// Tiled one-dimensional step for meshes of more than 256 elements: one launch
+// per step, one 256-lane workgroup per (sample, tile of 254 elements).  Lane
+// 1 + i owns element e0 + i of the tile; lanes 0 and 255 recompute the fits
+// of the two neighbouring elements (the halo) so that every owned element has
+// both neighbour traces without a second pass.  The samples are read from
+// phi_in and written to phi_out (the halo elements are read by two tiles, so
+// the step cannot update in place).
+constexpr int kTile1D = kResidentThreads - 2;
+
+int tiled_1d_tiles(int K) { return (K + kTile1D - 1) / kTile1D; }
+
+template <int N, bool kNodal>
+__global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, const double* phi_in,
+                                                                    double* phi_out, int64_t step) {
+  __shared__ double trL[kResidentThreads], trR[kResidentThreads];
+  const int K = p.K;
+  const int tiles = (K + kTile1D - 1) / kTile1D;
+  const int64_t s = blockIdx.x / tiles;
+  const int tile = blockIdx.x - (int)(s * tiles);
+  const int e0 = tile * kTile1D;
+  const int lane = threadIdx.x;
+  int e = e0 + lane - 1;                       // element of this lane (lanes 0 / 255: halo)
+  const int owned_end = e0 + kTile1D < K ? e0 + kTile1D : K;
+  const bool owned = lane >= 1 && e < owned_end;
+  bool live = owned || lane == 0 || e == owned_end;   // own fits, left halo, right halo
+  if (e < 0 || e >= K) {
+    if (p.dirichlet) live = false;            // beyond the boundary: the ghost value is used
+    else e = (e + K) % K;                     // periodic image
+  }
+  const double z = normal_pair(p.seed, p.stream, (uint64_t)step, (uint64_t)s).a;
+  Fit1DNodal<N> nod;
+  Fit1DPre<N> pre;
+  double tL = 0.0, tR = 0.0;
+  if (live) {
+    const double* A = p.A + e * N;
+    const double* B = p.B + e * N;
+    const double* src = p.src + e * N;
+    const double* ph = phi_in + s * (int64_t)(K * N) + (int64_t)e * N;
+    if constexpr (kNodal) {
+      move_nodes<N>(p.xi, A, B, z, nod.xs);
+#pragma unroll
+      for (int i = 0; i < N; ++i) nod.a[i] = ph[i] * src[i];
+      fit1d_nodal_pre<N>(nod);
+      tL = nod.tL;
+      tR = nod.tR;
+    } else {
+      double xs[N], f[N];
+      move_nodes<N>(p.xi, A, B, z, xs);
+#pragma unroll
+      for (int i = 0; i < N; ++i) f[i] = ph[i] * src[i];
+      fit1d_pre<N>(xs, f, p.xi, p.rec, pre);
+      tL = pre.tL;
+      tR = pre.tR;
+    }
+  }
+  trL[lane] = tL;
+  trR[lane] = tR;
+  __syncthreads();
+  if (owned) {
+    const double dL = __dadd_rn(p.Af[2 * e], __dmul_rn(p.Bf[2 * e], z));
+    const double dR = __dadd_rn(p.Af[2 * e + 1], __dmul_rn(p.Bf[2 * e + 1], z));
+    const double nbL = (p.dirichlet && e == 0) ? p.ghost[2 * e] : trR[lane - 1];
+    const double nbR = (p.dirichlet && e == K - 1) ? p.ghost[2 * e + 1] : trL[lane + 1];
+    const double gL = (dL > 0.0) ? nbL : tL;
+    const double gR = (dR > 0.0) ? tR : nbR;
+    double phi[N];
+    if constexpr (kNodal) fit1d_nodal_post<N>(nod, p.xi, gL, gR, phi);
+    else fit1d_post<N>(pre, gL, gR, phi);
+    double* out = phi_out + s * (int64_t)(K * N) + (int64_t)e * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = phi[i];
+  }
+}
+
+template <int N>
+static hipError_t launch_tiled_n(const Params1D& p, const double* in, double* out, int64_t step, hipStream_t st) {
+  const int64_t blocks = p.M * (int64_t)tiled_1d_tiles(p.K);
+  if (p.algo == 1)
+    hipLaunchKernelGGL((tiled_1d_kernel<N, false>), dim3((unsigned)blocks), dim3(kResidentThreads), 0, st, p, in, out, step);
+  else
+    hipLaunchKernelGGL((tiled_1d_kernel<N, true>), dim3((unsigned)blocks), dim3(kResidentThreads), 0, st, p, in, out, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiled_1d(int N, const Params1D& p, const double* in, double* out, int64_t step, hipStream_t st) {
+  switch (N) {
+    case 2: return launch_tiled_n<2>(p, in, out, step, st);
+    case 3: return launch_tiled_n<3>(p, in, out, step, st);
+    case 4: return launch_tiled_n<4>(p, in, out, step, st);
+    case 5: return launch_tiled_n<5>(p, in, out, step, st);
+    case 6: return launch_tiled_n<6>(p, in, out, step, st);
+    case 7: return launch_tiled_n<7>(p, in, out, step, st);
+    case 8: return launch_tiled_n<8>(p, in, out, step, st);
+    case 9: return launch_tiled_n<9>(p, in, out, step, st);
+    case 10: return launch_tiled_n<10>(p, in, out, step, st);
+    case 11: return launch_tiled_n<11>(p, in, out, step, st);
+    case 12: return launch_tiled_n<12>(p, in, out, step, st);
+    case 13: return launch_tiled_n<13>(p, in, out, step, st);
+    case 14: return launch_tiled_n<14>(p, in, out, step, st);
+    case 15: return launch_tiled_n<15>(p, in, out, step, st);
+    case 16: return launch_tiled_n<16>(p, in, out, step, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int N>
 static hipError_t launch_batch_n(const Batch1DArgs& a, int algo, size_t lds, hipStream_t st) {
   const int64_t blocks = a.bstart[a.ntasks];

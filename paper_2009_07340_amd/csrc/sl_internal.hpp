@@ -128,6 +128,8 @@ int fit2r_fused_occupancy(int phase, size_t lds);
 constexpr int kMaxNRef = 16;  // largest order of the reference-preconditioned 2-D solver
 constexpr int kMaxN2D = 10;   // largest order of the 2-D LDS-resident fit
 hipError_t launch_resident_1d(int N, const Params1D& p, hipStream_t st);
+hipError_t launch_tiled_1d(int N, const Params1D& p, const double* in, double* out, int64_t step, hipStream_t st);
+int tiled_1d_tiles(int K);
 hipError_t launch_resident_1d_batch(int N, int algo, const Batch1DArgs& a, size_t lds, hipStream_t st);
 size_t resident_1d_lds_bytes(int K, int samples_per_block);
 int resident_1d_samples_per_block(int K);

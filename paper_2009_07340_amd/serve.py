@@ -55,9 +55,12 @@ class Request:
         return self.nodes * self.wl.samples * self.steps
 
 
-def requests_from_stream(stream, precision="fp32_refine", steps_scale=1.0):
-    """Request objects from ``workloads.serving_requests`` dicts.  The 1-D fit
-    has no dense contraction and runs in float64 whatever the requested mode."""
+def requests_from_stream(stream, precision="fp64", steps_scale=1.0):
+    """Request objects from ``workloads.serving_requests`` dicts.  precision is
+    the 2-D mode: "fp64" runs the reference-preconditioned solver (every order
+    up to 16; the fastest 2-D path), the mixed modes run the factorisation
+    solver (orders up to 10).  The 1-D fit has no dense contraction and runs in
+    float64 whatever the requested mode."""
     out = []
     for r in stream:
         wl = W.request_workload(r)

@@ -119,6 +119,21 @@ def test_small_ragged_cases(B, algo):
         assert err < TOL, (K, N, M, err)
 
 
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_tiled_meshes_beyond_256_elements(B, algo, bc):
+    """More elements than one workgroup holds: tiles of 254 elements with a
+    recomputed halo, out-of-place steps (odd and even counts), ragged last tile."""
+    for K, N, M, steps in ((300, 5, 3, 3), (509, 12, 2, 4), (762, 4, 2, 1)):
+        wl = W.c2_1d_sine()
+        wl.kx, wl.order, wl.samples, wl.dt = K, N, M, 2e-7
+        if bc == "dirichlet":
+            wl.bc = "dirichlet"
+            wl.ghost = lambda x, y, t: 0.3 + 0.0 * x
+        got, mean, ref, err = _parity(B, wl, steps, np.arange(M))
+        assert err < TOL, (K, N, M, bc, err)
+        assert rel_l2(mean, sl.mean(got)) < 1e-14
+
+
 def test_dirichlet_parity(B, algo):
     wl = W.Workload("dir", 1, 12, 1, 7, 9, 1e-5, 15, 4,
                     u=lambda x, y: (0.7 + 0.3 * np.sin(6 * x), np.zeros(np.shape(x))),

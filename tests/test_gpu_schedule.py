@@ -104,7 +104,12 @@ def _batch_members():
     e = W.c1_1d_const()
     e.kx, e.order, e.samples, e.bc = 5, 3, 7, "dirichlet"
     e.ghost = lambda x, y, t: 0.1 + 0.0 * x
-    return [(a, "fp64", 2e-4), (b, "fp64", 3e-4), (c, "fp32_refine", 1e-4), (d, "fp64", 1e-4), (e, "fp64", 2e-4)]
+    f = W.c2_1d_sine()            # more than 256 elements: tiled steps
+    f.kx, f.order, f.samples = 400, 6, 3
+    g = W.c4_2d_rotation(kx=2, ky=2, samples=2, steps=3)
+    g.order = np.array([12, 16, 14, 11], dtype=np.int32)
+    return [(a, "fp64", 2e-4), (b, "fp64", 3e-4), (c, "fp32_refine", 1e-4), (d, "fp64", 1e-4), (e, "fp64", 2e-4),
+            (f, "fp64", 2e-7), (g, "fp64", 5e-5)]
 
 
 @pytest.mark.parametrize("graph", [0, 1])

@@ -37,7 +37,7 @@ def _alone(B, r):
 
 def test_each_request_is_the_same_alone_and_in_the_mix(B):
     stream = W.serving_requests(n=40, rate=50.0, kmax=36, mmax=48)
-    reqs = serve.requests_from_stream(stream, precision="fp32_refine", steps_scale=0.04)
+    reqs = serve.requests_from_stream(stream, steps_scale=0.04)
     for r in reqs:
         r.arrival *= 0.25          # 200 requests/s
     reqs[0].steps = 3000           # a long request that is on the device while the others arrive
@@ -46,11 +46,7 @@ def test_each_request_is_the_same_alone_and_in_the_mix(B):
     s = serve.summarize(reqs)
     print(s, f"peak active {srv.peak_active}, iterations {srv.iterations}", flush=True)
     ok = [r for r in reqs if r.mean is not None]
-    unsupported = [r for r in reqs if r.error]
-    # only shapes this build does not implement may fail, and they fail cleanly
-    for r in unsupported:
-        assert "admission" in r.error and r.wl.dim == 2 and int(np.max(r.wl.order_array())) > 10, r.error
-    assert len(ok) >= 25
+    assert len(ok) == len(reqs), [r.error for r in reqs if r.error]
     # later arrivals were admitted into the running batch of the long request
     joined = {i for ids in srv.batch_log if 0 in ids for i in ids if i != 0}
     assert len(joined) >= 20, sorted(joined)
@@ -67,12 +63,27 @@ def test_each_request_is_the_same_alone_and_in_the_mix(B):
     assert rel_l2(r.mean, sl.mean(ref)) < 1e-11
 
 
+def test_mixed_precision_requests_in_the_mix(B):
+    """2-D requests in the float32 + refinement mode (factorisation solver) mixed
+    with float64 ones; orders above 10 are rejected cleanly in that mode."""
+    stream = W.serving_requests(n=24, rate=100.0, kmax=25, mmax=32, seed=5)
+    reqs = serve.requests_from_stream(stream, precision="fp32_refine", steps_scale=0.03)
+    srv = serve.Server(B, budget_bytes=1 << 30, max_active=8, chunk_steps=3)
+    srv.run(reqs)
+    for r in reqs:
+        if r.error:
+            assert "admission" in r.error and r.wl.dim == 2 and int(r.wl.order) > 10, r.error
+        else:
+            want, _ = _alone(B, r)
+            assert np.array_equal(r.mean, want), r.id
+    assert sum(r.mean is not None for r in reqs) >= 12
+
+
 def test_serving_with_separate_admission_and_batch_streams(B):
     torch = pytest.importorskip("torch")
     s_batch, s_admit = torch.cuda.Stream(), torch.cuda.Stream()
     stream = W.serving_requests(n=12, rate=200.0, kmax=16, mmax=32, seed=77)
-    reqs = [r for r in serve.requests_from_stream(stream, steps_scale=0.03)
-            if r.wl.dim == 1 or int(r.wl.order) <= 10]
+    reqs = serve.requests_from_stream(stream, steps_scale=0.03)
     srv = serve.Server(B, budget_bytes=1 << 30, max_active=6, chunk_steps=3,
                        batch_stream=s_batch.cuda_stream, admit_stream=s_admit.cuda_stream)
     srv.run(reqs)
