@@ -282,7 +282,7 @@ def serve_bench(args):
     torch.cuda.set_device(0)
     stream = W.serving_requests(n=args.serve_requests, rate=args.serve_rate, kmax=args.serve_kmax,
                                 mmax=args.serve_mmax)
-    reqs = serve.requests_from_stream(stream, precision="fp32_refine", steps_scale=args.serve_steps_scale)
+    reqs = serve.requests_from_stream(stream, precision=args.precision, steps_scale=args.serve_steps_scale)
     s_batch, s_admit = torch.cuda.Stream(), torch.cuda.Stream()
     srv = serve.Server(B, max_active=args.serve_max_active, chunk_steps=16,
                        batch_stream=s_batch.cuda_stream, admit_stream=s_admit.cuda_stream)
@@ -295,7 +295,8 @@ def serve_bench(args):
     unsupported = sum(1 for r in reqs if r.error and "admission" in r.error)
     out = {
         "metric": "serving p50/p99 latency", "value": st["p99_latency_s"], "unit": "s",
-        "higher_is_better": False, "n_gpus": 1, "dtype": "fp32_refine (2-D), f64 (1-D)", "data": "synthetic",
+        "higher_is_better": False, "n_gpus": 1,
+        "dtype": "f64" if args.precision == "fp64" else f"{args.precision} (2-D), f64 (1-D)", "data": "synthetic",
         "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
         "p50_queue_wait_s": st["p50_queue_wait_s"], "arrival_rate_per_s": args.serve_rate,
         "completed": st["completed"], "failed": st["failed"], "unsupported_shapes": unsupported,

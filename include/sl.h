@@ -186,10 +186,13 @@ int sl_set_fields(sl_handle h, const double* u, const double* D, const double* d
 int sl_step(sl_handle h, double dt, int32_t nsteps);
 
 /* One batched pass (continuous batching of independent problems): advance nh
- * distinct handles by nsteps steps each, handle i with step dts[i].  The 2-D
- * handles of one precision mode share one persistent fused launch per phase
- * and step (their fits of every order in one work list, largest orders
- * first); the 1-D handles of one order share one resident launch.  Every
+ * distinct handles by nsteps steps each, handle i with step dts[i].  Under the
+ * first 2-D handle's schedule: fused = 0, the fits of one order from every
+ * reference-solver handle share one launch per phase (factorisation handles
+ * keep their per-order launches); fused = 1, the handles of one precision
+ * mode share one persistent launch per phase (every order in one work list,
+ * largest orders first).  The 1-D handles of one order and at most 256
+ * elements share one resident launch; larger 1-D meshes step on their own.  Every
  * handle's result is bitwise equal to sl_step on that handle alone.  All
  * handles must have been created on the same stream; the batch is enqueued on
  * it and replayed from a cached hipGraph when the first 2-D handle's schedule

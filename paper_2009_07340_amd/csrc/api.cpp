@@ -476,17 +476,52 @@ int enqueue_fused(const std::vector<sl_ctx*>& hs, int phase, int grid_req, hipSt
   return SL_OK;
 }
 
+// Batched launches of one phase, one per order: the reference-solver fits of
+// every handle that have order N go into one launch (chunks of kMaxTasks
+// handles); factorisation handles get their per-order launches.
+int enqueue_multi(const std::vector<sl_ctx*>& hs, int phase, hipStream_t st) {
+  std::vector<sl_ctx*> ref;
+  for (sl_ctx* h : hs) {
+    if (h->L.solver == SL_SOLVER_REFERENCE) ref.push_back(h);
+    else if (int rc = enqueue_perorder(h, phase, true, 0, st)) return rc;
+  }
+  for (int N = sl::kMaxNRef; N >= 2; --N) {
+    std::vector<std::pair<sl_ctx*, std::pair<int64_t, int64_t>>> segs;   // (handle, (fit0, count))
+    for (sl_ctx* h : ref)
+      for (const auto& g : h->groups)
+        if (g.first == N && g.second.second > 0)
+          segs.push_back({h, {g.second.first * h->L.M, g.second.second * h->L.M}});
+    for (size_t c0 = 0; c0 < segs.size(); c0 += sl::kMaxTasks) {
+      sl::Fused2DArgs a{};
+      const size_t nc = std::min<size_t>(sl::kMaxTasks, segs.size() - c0);
+      int64_t start = 0;
+      for (size_t i = 0; i < nc; ++i) {
+        a.task[i] = segs[c0 + i].first->d_p2;
+        a.seg[i] = sl::FusedSeg{start, segs[c0 + i].second.first, (int32_t)i, N};
+        start += segs[c0 + i].second.second;
+      }
+      a.nseg = (int)nc;
+      a.total = start;
+      if (start > 0x7fffffff) return fail(SL_EUNSUPPORTED, "too many fits of one order in one batch");
+      SL_HIP(sl::launch_fit2r_multi(phase, N, a, st));
+    }
+  }
+  return SL_OK;
+}
+
 // One whole step (both phases and the counter advance) on the device step counters.
 int enqueue_device_step(const std::vector<sl_ctx*>& hs, int fused, int grid, hipStream_t st, sl_ctx* prof) {
   for (int phase = 1; phase <= 2; ++phase) {
     const char* name = fused ? (phase == 1 ? "fit2d_fused_phase1" : "fit2d_fused_phase2")
-                             : kernel_label(hs[0], phase);
+                       : hs.size() > 1 ? (phase == 1 ? "fit2d_batch_phase1" : "fit2d_batch_phase2")
+                                       : kernel_label(hs[0], phase);
     std::unique_ptr<ProfScope> ps(prof ? new ProfScope(prof, name) : nullptr);
     if (fused) {
       if (int rc = enqueue_fused(hs, phase, grid, st)) return rc;
+    } else if (hs.size() > 1) {
+      if (int rc = enqueue_multi(hs, phase, st)) return rc;
     } else {
-      for (sl_ctx* h : hs)
-        if (int rc = enqueue_perorder(h, phase, true, 0, st)) return rc;
+      if (int rc = enqueue_perorder(hs[0], phase, true, 0, st)) return rc;
     }
   }
   return enqueue_counters(hs, 0, st);
@@ -971,7 +1006,7 @@ int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t ns
   if (!one.empty())
     if (int rc = step_1d_batch(one, nsteps, st)) return rc;
   if (!two.empty())
-    if (int rc = step_2d(two, nsteps, 1, two[0]->sched.graph, two[0]->sched.grid, st)) return rc;
+    if (int rc = step_2d(two, nsteps, two[0]->sched.fused, two[0]->sched.graph, two[0]->sched.grid, st)) return rc;
   return SL_OK;
 }
 

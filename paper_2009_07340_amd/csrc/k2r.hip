@@ -856,6 +856,50 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
   }
 }
 
+// One order of several problems in one launch: one workgroup per fit of the
+// segments (problem, order group) of the argument table, all of order N.
+template <int N, int PHASE>
+__global__ __launch_bounds__(kThreads) void fit2r_multi(Fused2DArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double lds_rm[];
+  const int64_t item = blockIdx.x;
+  int sg = 0;
+  while (sg + 1 < a.nseg && item >= a.seg[sg + 1].start) ++sg;
+  const Params2D& p = *a.task[a.seg[sg].task];
+  const int64_t fit = a.seg[sg].fit0 + (item - a.seg[sg].start);
+  if constexpr (PHASE == 1) r_phase1_body<N>(p, lds_rm, fit);
+  else r_phase2_body<N>(p, lds_rm, fit);
+}
+
+template <int N>
+static hipError_t multi_n(int phase, const Fused2DArgs& a, hipStream_t st) {
+  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayR<N>::bytes2;
+  if (a.total <= 0) return hipSuccess;
+  if (phase == 1) hipLaunchKernelGGL((fit2r_multi<N, 1>), dim3((unsigned)a.total), dim3(kThreads), lds, st, a);
+  else hipLaunchKernelGGL((fit2r_multi<N, 2>), dim3((unsigned)a.total), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit2r_multi(int phase, int N, const Fused2DArgs& a, hipStream_t st) {
+  switch (N) {
+    case 2: return multi_n<2>(phase, a, st);
+    case 3: return multi_n<3>(phase, a, st);
+    case 4: return multi_n<4>(phase, a, st);
+    case 5: return multi_n<5>(phase, a, st);
+    case 6: return multi_n<6>(phase, a, st);
+    case 7: return multi_n<7>(phase, a, st);
+    case 8: return multi_n<8>(phase, a, st);
+    case 9: return multi_n<9>(phase, a, st);
+    case 10: return multi_n<10>(phase, a, st);
+    case 11: return multi_n<11>(phase, a, st);
+    case 12: return multi_n<12>(phase, a, st);
+    case 13: return multi_n<13>(phase, a, st);
+    case 14: return multi_n<14>(phase, a, st);
+    case 15: return multi_n<15>(phase, a, st);
+    case 16: return multi_n<16>(phase, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // Persistent fused kernel over every order (2..16) of several problems, as
 // the factorisation kernels' fused form: segments largest order first, a
 // device work counter, each order outlined with its own registers.

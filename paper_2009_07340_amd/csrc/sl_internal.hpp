@@ -125,6 +125,7 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 size_t fit2r_lds_bytes(int N, int phase);
 hipError_t launch_fit2r_fused(int phase, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
 int fit2r_fused_occupancy(int phase, size_t lds);
+hipError_t launch_fit2r_multi(int phase, int N, const Fused2DArgs& a, hipStream_t st);
 constexpr int kMaxNRef = 16;  // largest order of the reference-preconditioned 2-D solver
 constexpr int kMaxN2D = 10;   // largest order of the 2-D LDS-resident fit
 hipError_t launch_resident_1d(int N, const Params1D& p, hipStream_t st);

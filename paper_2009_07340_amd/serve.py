@@ -5,9 +5,10 @@ admitted when a slot is free and its device footprint (``sl_required_bytes``:
 samples, traces, fields, tables) fits in what the admitted requests leave of
 the memory budget; its particle and field state then stays resident on the
 device until it finishes.  Every iteration advances all admitted requests by
-a common chunk of steps in ONE ``sl_step_batch`` call (2-D problems share the
-persistent fused kernel, 1-D problems of one order share one resident
-launch), so requests that arrive while others run join the next iteration and
+a common chunk of steps in ONE ``sl_step_batch`` call (the 2-D fits of one
+order from every request share one launch per phase, or with ``fused`` all
+orders share one persistent launch; 1-D problems of one order share one
+resident launch), so requests that arrive while others run join the next iteration and
 their work overlaps on the device.  While a chunk runs, the host prepares and
 uploads newly admitted requests on a separate stream.
 
@@ -73,7 +74,7 @@ def requests_from_stream(stream, precision="fp64", steps_scale=1.0):
 class Server:
     """backend: the binding module (or a stand-in with the same functions)."""
 
-    def __init__(self, backend=None, budget_bytes=None, max_active=32, chunk_steps=16, graph=True,
+    def __init__(self, backend=None, budget_bytes=None, max_active=32, chunk_steps=16, graph=True, fused=False,
                  max_bypass_wait=5.0, batch_stream=None, admit_stream=None, clock=time.perf_counter,
                  sleep=time.sleep):
         if backend is None:
@@ -86,6 +87,7 @@ class Server:
         self.max_active = int(max_active)
         self.chunk_steps = int(chunk_steps)
         self.graph = 1 if graph else 0
+        self.fused = 1 if fused else 0
         self.max_bypass_wait = float(max_bypass_wait)
         self.batch_stream = batch_stream
         self.admit_stream = admit_stream
@@ -119,7 +121,7 @@ class Server:
             exy, axis = B.sl_edge_coords(h, r.wl.dim)
             a = r.wl.sample_fields(xy, exy, axis, 0.0)
             B.sl_set_fields(h, a["u"], a["D"], a["divu"], a["un"], a["Dn"], a["ghost"], a["phi0"])
-            B.sl_set_schedule(h, 1, self.graph, 0)
+            B.sl_set_schedule(h, self.fused, self.graph, 0)
             B.sl_set_stream(h, self.batch_stream)
         except Exception:
             B.sl_destroy(h)

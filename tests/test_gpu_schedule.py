@@ -112,8 +112,8 @@ def _batch_members():
             (f, "fp64", 2e-7), (g, "fp64", 5e-5)]
 
 
-@pytest.mark.parametrize("graph", [0, 1])
-def test_batch_equals_each_problem_alone(B, graph):
+@pytest.mark.parametrize("fused,graph", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_batch_equals_each_problem_alone(B, fused, graph):
     members = _batch_members()
     alone = []
     for wl, prec, dt in members:
@@ -128,7 +128,7 @@ def test_batch_equals_each_problem_alone(B, graph):
     try:
         for wl, prec, dt in members:
             h, _ = _make(B, wl, prec)
-            B.sl_set_schedule(h, 1, graph, 0)
+            B.sl_set_schedule(h, fused, graph, 0)
             hs.append(h)
         dts = [dt for _, _, dt in members]
         B.sl_step_batch(hs, dts, 2)
@@ -142,8 +142,9 @@ def test_batch_equals_each_problem_alone(B, graph):
             B.sl_destroy(h)
 
 
-def test_batch_of_many_problems_is_chunked(B):
-    """More problems than one fused launch takes: chunked launches, same results."""
+@pytest.mark.parametrize("fused", [0, 1])
+def test_batch_of_many_problems_is_chunked(B, fused):
+    """More problems than one launch takes: chunked launches, same results."""
     members = []
     for i in range(40):
         wl = W.c3_2d_const()
@@ -162,7 +163,7 @@ def test_batch_of_many_problems_is_chunked(B):
             B.sl_destroy(h)
         for wl in members:
             h, _ = _make(B, wl)
-            B.sl_set_schedule(h, 1, 1, 0)
+            B.sl_set_schedule(h, fused, 1, 0)
             hs.append(h)
         B.sl_step_batch(hs, [wl.dt for wl in members], 2)
         for wl, h, want in zip(members, hs, alone):

@@ -157,7 +157,8 @@ def test_late_arrivals_join_a_running_batch():
 
 def test_stream_requests_keep_the_specified_shapes():
     stream = W.serving_requests(n=50, kmax=64, mmax=128)
-    reqs = serve.requests_from_stream(stream)
-    for r, d in zip(reqs, stream):
-        assert (r.wl.dim, r.wl.kx, r.wl.ky, r.wl.samples, r.steps) == (d["dim"], d["kx"], d["ky"], d["M"], d["steps"])
-        assert r.precision == ("fp64" if d["dim"] == 1 else "fp32_refine")
+    for prec in ("fp64", "fp32_refine"):
+        reqs = serve.requests_from_stream(stream, precision=prec)
+        for r, d in zip(reqs, stream):
+            assert (r.wl.dim, r.wl.kx, r.wl.ky, r.wl.samples, r.steps) == (d["dim"], d["kx"], d["ky"], d["M"], d["steps"])
+            assert r.precision == ("fp64" if d["dim"] == 1 else prec)
