@@ -184,16 +184,48 @@ struct Fit1DNodal {
   double tL, tR;    // traces of p0
 };
 
+// Reciprocals of the node products, four per division: 1/a = b c d / (a b c d).
+template <int N>
+__device__ __forceinline__ void reciprocals(const double (&p)[N], double (&w)[N]) {
+#pragma unroll
+  for (int g = 0; g + 4 <= N; g += 4) {
+    const double ab = p[g] * p[g + 1], cd = p[g + 2] * p[g + 3];
+    const double r = 1.0 / (ab * cd);
+    const double rab = r * ab, rcd = r * cd;
+    w[g] = rcd * p[g + 1];
+    w[g + 1] = rcd * p[g];
+    w[g + 2] = rab * p[g + 3];
+    w[g + 3] = rab * p[g + 2];
+  }
+  constexpr int g = N - N % 4;
+  if constexpr (N % 4 == 3) {
+    const double ab = p[g] * p[g + 1];
+    const double r = 1.0 / (ab * p[g + 2]);
+    const double rc = r * p[g + 2];
+    w[g] = rc * p[g + 1];
+    w[g + 1] = rc * p[g];
+    w[g + 2] = r * ab;
+  } else if constexpr (N % 4 == 2) {
+    const double r = 1.0 / (p[g] * p[g + 1]);
+    w[g] = r * p[g + 1];
+    w[g + 1] = r * p[g];
+  } else if constexpr (N % 4 == 1) {
+    w[g] = 1.0 / p[g];
+  }
+}
+
 template <int N>
 __device__ __forceinline__ void fit1d_nodal_pre(Fit1DNodal<N>& st) {
+  double pj[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     double p = 1.0;
 #pragma unroll
     for (int m = 0; m < N; ++m)
       if (m != j) p *= (st.xs[j] - st.xs[m]);
-    st.w[j] = 1.0 / p;
+    pj[j] = p;
   }
+  reciprocals<N>(pj, st.w);
   lagrange_row<N>(st.xs, st.w, 0.0, st.cl);
   lagrange_row<N>(st.xs, st.w, 1.0, st.cr);
   double tL = 0.0, tR = 0.0, s00 = 0.0, s01 = 0.0, s11 = 0.0;
@@ -217,9 +249,9 @@ template <int N>
 __device__ __forceinline__ void fit1d_nodal_post(Fit1DNodal<N>& st, const double* xi, double gL, double gR,
                                                  double (&phi)[N]) {
   const double r0 = st.tL - gL, r1 = st.tR - gR;
-  const double det = st.s00 * st.s11 - st.s01 * st.s01;
-  const double l0 = (st.s11 * r0 - st.s01 * r1) / det;
-  const double l1 = (st.s00 * r1 - st.s01 * r0) / det;
+  const double idet = 1.0 / (st.s00 * st.s11 - st.s01 * st.s01);
+  const double l0 = (st.s11 * r0 - st.s01 * r1) * idet;
+  const double l1 = (st.s00 * r1 - st.s01 * r0) * idet;
 #pragma unroll
   for (int j = 0; j < N; ++j) st.a[j] -= st.cl[j] * l0 + st.cr[j] * l1;
 #pragma unroll

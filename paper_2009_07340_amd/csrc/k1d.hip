@@ -21,9 +21,13 @@ int resident_1d_samples_per_block(int K) { return K <= kResidentThreads ? kResid
 
 size_t resident_1d_lds_bytes(int K, int spb) { return sizeof(double) * 2 * 2 * (size_t)spb * K; }
 
+// The Wiener increment of a (sample, step) is the same for every element of
+// the sample, so it is drawn once, not once per lane: every P = 256 / spb
+// steps the 256 lanes draw the increments of the next P steps of the spb
+// samples (lane l: sample slot l / P, step l % P ahead) into zbuf.
 template <int N, bool kNodal>
-__device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_tr, int64_t block, int64_t step0,
-                                                 int nsteps) {
+__device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_tr, double* zbuf, int64_t block,
+                                                 int64_t step0, int nsteps) {
   const int K = p.K;
   const int spb = p.samples_per_block;
   const int lane = threadIdx.x;
@@ -52,13 +56,21 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
     }
   }
   const int stride = spb * K * 2;
+  const int P = kResidentThreads / spb;
   for (int it = 0; it < nsteps; ++it) {
     double* tr = lds_tr + (it & 1) * stride;
     Fit1DPre<N> pre;          // normal-equation form
     Fit1DNodal<N> nod;        // nodal form
     double z = 0.0, tL = 0.0, tR = 0.0;
+    if (it % P == 0) {
+      const int zs = lane / P, zk = lane - zs * P;
+      const int64_t sz = block * spb + zs;
+      if (zs < spb && sz < p.M && it + zk < nsteps)
+        zbuf[lane] = normal_pair(p.seed, p.stream, (uint64_t)(step0 + it + zk), (uint64_t)sz).a;
+      __syncthreads();
+    }
     if (active) {
-      z = normal_pair(p.seed, p.stream, (uint64_t)(step0 + it), (uint64_t)s).a;
+      z = zbuf[slot * P + it % P];
       if constexpr (kNodal) {
         move_nodes<N>(p.xi, A, B, z, nod.xs);
 #pragma unroll
@@ -103,17 +115,19 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
 template <int N, bool kNodal>
 __global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D p) {
   extern __shared__ double lds_tr[];   // [2 buffers][spb][K][2]
-  resident_1d_body<N, kNodal>(p, lds_tr, blockIdx.x, p.step0, p.nsteps);
+  __shared__ double zbuf[kResidentThreads];
+  resident_1d_body<N, kNodal>(p, lds_tr, zbuf, blockIdx.x, p.step0, p.nsteps);
 }
 
 // Several problems of one order in one launch; workgroup ranges per problem.
 template <int N, bool kNodal>
 __global__ __launch_bounds__(kResidentThreads) void resident_1d_batch_kernel(Batch1DArgs a) {
   extern __shared__ double lds_tr[];
+  __shared__ double zbuf[kResidentThreads];
   const int64_t b = blockIdx.x;
   int t = 0;
   while (t + 1 < a.ntasks && b >= a.bstart[t + 1]) ++t;
-  resident_1d_body<N, kNodal>(*a.task[t], lds_tr, b - a.bstart[t], a.step0[t], a.nsteps);
+  resident_1d_body<N, kNodal>(*a.task[t], lds_tr, zbuf, b - a.bstart[t], a.step0[t], a.nsteps);
 }
 
 // Tiled one-dimensional step for meshes of more than 256 elements: one launch
