@@ -24,9 +24,9 @@
 //
 // S0 needs no n x n work either: the edge-point rows of C are tensor products
 // of 1-D basis vectors, so C G0^-1 C^T is assembled from two (N+2) x (N+2)
-// tables of 1-D quadratic forms, and S0 = U_r^T (C G0^-1 C^T) U_r.  S0 is
-// factored (blocked Cholesky, matrix cores) and inverted explicitly once per
-// fit, so each iteration only applies dense matrix-vector products.
+// tables of 1-D quadratic forms, and S0 = U_r^T (C G0^-1 C^T) U_r (matrix
+// cores).  S0 is inverted explicitly once per fit (Gauss-Jordan, one barrier
+// per pivot), so each iteration only applies dense matrix-vector products.
 //
 // The iteration count adapts to the fit: zero for a uniform displacement
 // (the preconditioner is then exact), a few for the smooth fields of the
@@ -42,13 +42,11 @@ namespace sl {
 
 using namespace blk;
 
-// LDS layout in doubles.  Phase 1 uses the first part only.  The block TU
-// (T U_r, 4N x R) used while S0 is assembled aliases [x .. Xblk], which is
-// not live at that time.
+// LDS layout in doubles.  Phase 1 uses the first part only.
 template <int N>
 struct LayR {
   static constexpr int n = N * N, TT = 4 * N, R = 4 * N - 4, RB = (R + 15) / 16, RP = 16 * RB, NH = N + 2;
-  static constexpr int nS = RB * (RB + 1) / 2;
+  static constexpr int Rs = R + 1;             // row stride of the dense S0 / S0^-1
   static constexpr int oX1 = 0;
   static constexpr int oY1 = oX1 + n * N;
   static constexpr int oBx = oY1 + n * N;
@@ -70,10 +68,13 @@ struct LayR {
   static constexpr int oYs = oXs + n;
   static constexpr int oRed = oYs + n;
   static constexpr int end1 = oRed + 16;
-  // phase 2 only
-  static constexpr int oXblk = end1;           // off-diagonal blocks of L^-1 of S0
-  static constexpr int oSblk = oXblk + nS * BLK;   // S0 -> its factor -> S0^-1 (lower blocks)
-  static constexpr int oE1 = oSblk + nS * BLK;
+  // phase 2 only.  T U_r (used while S0 is assembled) aliases [x .. end of
+  // phase 1] and, when larger, the space up to S0.
+  static constexpr int TTs = TT + 1;
+  static constexpr int tuMax = TTs * R;
+  static constexpr int oSd = (end1 > oXv + tuMax ? end1 : oXv + tuMax);   // S0, then S0^-1 (dense, R x Rs)
+  static constexpr int oPiv = oSd + R * Rs;    // Gauss-Jordan pivot row and column, two buffers
+  static constexpr int oE1 = oPiv + 4 * R;
   static constexpr int oGr = oE1 + TT;         // upwinded boundary data g
   static constexpr int oW1 = oGr + TT;
   static constexpr int oW2 = oW1 + RP;
@@ -84,19 +85,13 @@ struct LayR {
   // T U_r and U_r^T (T U_r) run on the matrix cores, the entries of
   // T = C G0^-1 C^T formed on the fly from the H tables.  Larger orders read
   // U_r from the cache and assemble S0 with scalar loops.
-  static constexpr int TTs = TT + 1;
   static constexpr int endR = oHy + NH * NH;
   static constexpr bool kUrLds = sizeof(double) * (endR + TTs * R) <= 156 * 1024;
   static constexpr int US = kUrLds ? TTs : TT;        // column stride of U_r as used
   static constexpr int oU = endR;
   static constexpr int end2 = kUrLds ? endR + TTs * R : endR;
   static constexpr int oTU = oXv;                     // T U_r, column stride US
-  static_assert(US * R <= oSblk - oXv, "T U_r must fit in the aliased region");
-  // per-wavefront scratch blocks of the S0^-1 computation (RB - 1 of them at
-  // most 4), over the iteration vectors, which are not live at that time
-  static constexpr int nTmp = RB - 1 < 4 ? RB - 1 : 4;
-  static constexpr int oTmp = oXv;
-  static_assert(nTmp * BLK <= oXblk - oXv, "scratch blocks must not overlap the inverse blocks");
+  static_assert(US * R <= oSd - oXv, "T U_r must fit in the aliased region");
   static constexpr size_t bytes1 = sizeof(double) * end1;
   static constexpr size_t bytes2 = sizeof(double) * end2;
 };
@@ -186,9 +181,11 @@ __device__ void r_VT(const double* X1, const double* Y1, const double* r, double
   }
 }
 
-// out = (Gx^-1 (x) Gx^-1) v  (c indexed [ly * N + k]); tmp n doubles.  Two barriers.
+// out = (Gx^-1 (x) Gx^-1) v  (c indexed [ly * N + k]), or minuend - that when
+// minuend is given; tmp n doubles.  Two barriers.
 template <int N>
-__device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double* out) {
+__device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double* out,
+                        const double* minuend = nullptr) {
   for (int p = tid(); p < N * N; p += kThreads) {
     const int k = p % N, ly = p / N;
     double acc = 0.0;
@@ -202,7 +199,7 @@ __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double*
     double acc = 0.0;
 #pragma unroll
     for (int ll = 0; ll < N; ++ll) acc += gxi[ly * N + ll] * tmp[ll * N + k];
-    out[p] = acc;
+    out[p] = minuend ? minuend[p] - acc : acc;
   }
   block_sync();
 }
@@ -268,24 +265,15 @@ __device__ void r_U(const double* U, const double* w, double* out) {
   }
 }
 
-// out = S0^-1 w with S0^-1 stored as lower blocks (symmetric)
+// out = S0^-1 w (dense, row stride Rs), out padded with zeros to RP
 template <int N>
-__device__ void r_Sinv(const double* Sb, const double* w, double* out) {
+__device__ void r_Sinv(const double* Sd, const double* w, double* out) {
   using L = LayR<N>;
   for (int c = tid(); c < L::RP; c += kThreads) {
-    const int I = c >> 4, r = c & 15;
     double acc = 0.0;
-#pragma unroll 1
-    for (int J = 0; J < L::RB; ++J) {
-      if (J <= I) {
-        const double* blk = Sb + tblk(I, J) * BLK + r * BS;
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) acc += blk[cc] * w[16 * J + cc];
-      } else {
-        const double* blk = Sb + tblk(J, I) * BLK + r;
-#pragma unroll
-        for (int cc = 0; cc < 16; ++cc) acc += blk[cc * BS] * w[16 * J + cc];
-      }
+    if (c < L::R) {
+#pragma unroll 4
+      for (int j = 0; j < L::R; ++j) acc += Sd[c * L::Rs + j] * w[j];
     }
     out[c] = acc;
   }
@@ -478,14 +466,61 @@ __device__ void r_Pproj(double* lds, const double* U, const double* rin, const d
     for (int c = tid(); c < L::R; c += kThreads) w1[c] -= rhs2[c];
     block_sync();
   }
-  r_Sinv<N>(lds + L::oSblk, w1, w2);
+  r_Sinv<N>(lds + L::oSd, w1, w2);
   block_sync();
   r_U<N>(U, w2, e1);
   block_sync();
   r_CT<N>(Bx, By, Ev, e1, t2);
   block_sync();
-  r_G0inv<N>(gxi, t2, t1, out);
-  for (int i = tid(); i < N * N; i += kThreads) out[i] = z0[i] - out[i];
+  r_G0inv<N>(gxi, t2, t1, out, z0);
+}
+
+// In-place Gauss-Jordan inversion of the dense SPD matrix S (R x R, row stride
+// Rs): R pivot steps, each thread keeping its elements in registers and the
+// pivot row and column passing through LDS (two buffers, one barrier a step).
+template <int N>
+__device__ void r_invert_S(double* Sd, double* piv) {
+  using L = LayR<N>;
+  constexpr int R = L::R, RR = R * R, kE = (RR + kThreads - 1) / kThreads;
+  const int t = tid();
+  double a[kE];
+#pragma unroll
+  for (int m = 0; m < kE; ++m) {
+    const int idx = t + kThreads * m;
+    a[m] = idx < RR ? Sd[(idx / R) * L::Rs + idx % R] : 0.0;
+  }
+#pragma unroll 1
+  for (int k = 0; k < R; ++k) {
+    double* prow = piv + (k & 1) * 2 * R;
+    double* pcol = prow + R;
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+      const int idx = t + kThreads * m;
+      if (idx < RR) {
+        const int i = idx / R, j = idx - i * R;
+        if (i == k) prow[j] = a[m];
+        if (j == k) pcol[i] = a[m];
+      }
+    }
+    block_sync();
+    const double pinv = 1.0 / prow[k];
+#pragma unroll
+    for (int m = 0; m < kE; ++m) {
+      const int idx = t + kThreads * m;
+      if (idx < RR) {
+        const int i = idx / R, j = idx - i * R;
+        if (i == k && j == k) a[m] = pinv;
+        else if (i == k) a[m] = prow[j] * pinv;
+        else if (j == k) a[m] = -pcol[i] * pinv;
+        else a[m] -= pcol[i] * prow[j] * pinv;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kE; ++m) {
+    const int idx = t + kThreads * m;
+    if (idx < RR) Sd[(idx / R) * L::Rs + idx % R] = a[m];
+  }
   block_sync();
 }
 
@@ -560,9 +595,10 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* rr = lds + L::oRr;
   r_UT<N>(U, gv, rr);                    // g_r = U_r^T g
   // TU = (C G0^-1 C^T) U_r, entry (q1, q2) of C G0^-1 C^T = Hx[xa1][xa2] Hy[ya1][ya2];
-  // then S0 = U_r^T TU into lower blocks (zero padding)
+  // then S0 = U_r^T TU, dense
   double* TU = lds + L::oTU;
-  double* Sb = lds + L::oSblk;
+  double* Sd = lds + L::oSd;
+  constexpr int Rs = L::Rs;
   typedef Mma<double> M64;
   if constexpr (L::kUrLds) {
     constexpr int TTs = L::TTs, QB = (TT + 15) / 16;
@@ -592,8 +628,9 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       }
     }
     block_sync();
+    // S0 blocks (I, J), J <= I, written to both triangles
 #pragma unroll 1
-    for (int bidx = wv; bidx < L::nS; bidx += 4) {
+    for (int bidx = wv; bidx < RB * (RB + 1) / 2; bidx += 4) {
       int I = 0;
       while ((I + 1) * (I + 2) / 2 <= bidx) ++I;
       const int J = bidx - I * (I + 1) / 2;
@@ -606,7 +643,16 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
         const double bv = c2 < R ? TU[c2 * TTs + q] : 0.0;
         acc = M64::mma(a, bv, acc);
       }
-      store_acc(Sb + bidx * BLK, acc);
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        // lower triangle only, mirrored: the two triangles of a diagonal block
+        // are computed separately and need not agree to the last bit
+        const int row = 16 * I + M64::row(l, s4), col = c2;
+        if (row < R && col < R && row >= col) {
+          Sd[row * Rs + col] = acc[s4];
+          Sd[col * Rs + row] = acc[s4];
+        }
+      }
     }
     block_sync();
   } else {
@@ -629,93 +675,20 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       TU[c * TT + q1] = acc;
     }
     block_sync();
-    for (int idx = t; idx < L::nS * 256; idx += kThreads) {
-      const int bidx = idx >> 8, rc = idx & 255, rI = rc >> 4, cJ = rc & 15;
-      int I = 0;
-      while ((I + 1) * (I + 2) / 2 <= bidx) ++I;
-      const int J = bidx - I * (I + 1) / 2;
-      const int c1 = 16 * I + rI, c2 = 16 * J + cJ;
+    for (int idx = t; idx < R * R; idx += kThreads) {
+      const int c1 = idx / R, c2 = idx % R;
+      if (c2 > c1) continue;
+      const double* Uc = U + c1 * TT;
+      const double* Tc = TU + c2 * TT;
       double acc = 0.0;
-      if (c1 < R && c2 < R) {
-        const double* Uc = U + c1 * TT;
-        const double* Tc = TU + c2 * TT;
 #pragma unroll 4
-        for (int q = 0; q < TT; ++q) acc += Uc[q] * Tc[q];
-      }
-      Sb[bidx * BLK + rI * BS + cJ] = acc;
+      for (int q = 0; q < TT; ++q) acc += Uc[q] * Tc[q];
+      Sd[c1 * Rs + c2] = acc;
+      Sd[c2 * Rs + c1] = acc;
     }
     block_sync();
   }
-  cholesky<double, RB>(Sb, R);
-  // L^-1: X_IJ = -L_II^-1 sum_{K=J}^{I-1} L_IK X_KJ (column J on wavefront J mod 4)
-  double* Xb = lds + L::oXblk;
-  if constexpr (RB > 1) {
-    double* Tmp = lds + L::oTmp;
-#pragma unroll 1
-    for (int J = wv; J < RB; J += 4) {
-#pragma unroll 1
-      for (int I = J + 1; I < RB; ++I) {
-        M64::acc_t acc = zacc<double>();
-#pragma unroll 1
-        for (int K = J; K < I; ++K) {
-          const double* LIK = Sb + tblk(I, K) * BLK;
-          const double* XKJ = (K == J) ? Sb + tblk(J, J) * BLK : Xb + tblk(K, J) * BLK;
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) acc = M64::mma(rowpat(LIK, kk), colpat(XKJ, kk), acc);
-        }
-        double* Tb = Tmp + wv * BLK;
-        store_acc(Tb, acc);
-        wave_sync();
-        M64::acc_t out = zacc<double>();
-        const double* Di = Sb + tblk(I, I) * BLK;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) out = M64::mma(-rowpat(Di, kk), colpat(Tb, kk), out);
-        store_acc(Xb + tblk(I, J) * BLK, out);
-        wave_sync();
-      }
-    }
-    block_sync();
-  }
-  // S0^-1 = X^T X, lower blocks, accumulated in registers then stored over the factor
-  {
-    constexpr int kMaxPer = (L::nS + 3) / 4;
-    M64::acc_t accs[kMaxPer];
-    int bi = 0, slot = 0;
-#pragma unroll 1
-    for (int I = 0; I < RB; ++I) {
-#pragma unroll 1
-      for (int J = 0; J <= I; ++J, ++bi) {
-        if ((bi & 3) != wv) continue;
-        M64::acc_t acc = zacc<double>();
-#pragma unroll 1
-        for (int K = I; K < RB; ++K) {
-          const double* XKI = (K == I) ? Sb + tblk(I, I) * BLK : Xb + tblk(K, I) * BLK;
-          const double* XKJ = (K == J) ? Sb + tblk(J, J) * BLK : Xb + tblk(K, J) * BLK;
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) acc = M64::mma(colpat(XKI, kk), colpat(XKJ, kk), acc);
-        }
-#pragma unroll
-        for (int sI = 0; sI < kMaxPer; ++sI)
-          if (sI == slot) accs[sI] = acc;
-        ++slot;
-      }
-    }
-    block_sync();
-    bi = 0;
-    slot = 0;
-#pragma unroll 1
-    for (int I = 0; I < RB; ++I) {
-#pragma unroll 1
-      for (int J = 0; J <= I; ++J, ++bi) {
-        if ((bi & 3) != wv) continue;
-#pragma unroll
-        for (int sI = 0; sI < kMaxPer; ++sI)
-          if (sI == slot) store_acc(Sb + tblk(I, J) * BLK, accs[sI]);
-        ++slot;
-      }
-    }
-    block_sync();
-  }
+  r_invert_S<N>(Sd, lds + L::oPiv);
   // particular solution x0 = first block of [[G0, C_r^T], [C_r, 0]]^-1 [b; g_r]
   double* b = lds + L::oB;
   double* x = lds + L::oXv;
@@ -765,7 +738,8 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   }
   count_fit(p, 2, it > p.max_iter ? p.max_iter : it, gg <= stop);
   // restore C_r x = g_r to working accuracy: x -= G0^-1 C_r^T S0^-1 (C_r x - g_r)
-  {
+  // (after any iteration; the starting iterate satisfies it already)
+  if (it > 0) {
     double* zz = lds + L::oZ0;
     double* e1 = lds + L::oE1;
     double* w1 = lds + L::oW1;
@@ -776,7 +750,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     block_sync();
     for (int c = t; c < R; c += kThreads) w1[c] -= rr[c];
     block_sync();
-    r_Sinv<N>(lds + L::oSblk, w1, w2);
+    r_Sinv<N>(lds + L::oSd, w1, w2);
     block_sync();
     r_U<N>(U, w2, e1);
     block_sync();
