@@ -64,7 +64,8 @@ struct LayR {
   static constexpr int oT1 = oQ + n;
   static constexpr int oT2 = oT1 + n;
   static constexpr int oTr = oT2 + n;          // traces / edge vector
-  static constexpr int oXs = oTr + TT;
+  static constexpr int oUc = oTr + TT;         // edge contractions (phase 1)
+  static constexpr int oXs = oUc + TT;
   static constexpr int oYs = oXs + n;
   static constexpr int oRed = oYs + n;
   static constexpr int end1 = oRed + 16;
@@ -74,8 +75,9 @@ struct LayR {
   static constexpr int tuMax = TTs * R;
   static constexpr int oSd = (end1 > oXv + tuMax ? end1 : oXv + tuMax);   // S0, then S0^-1 (dense, R x Rs)
   static constexpr int oPiv = oSd + R * Rs;    // Gauss-Jordan pivot row and column, two buffers
-  static constexpr int oE1 = oPiv + 4 * R;
-  static constexpr int oGr = oE1 + TT;         // upwinded boundary data g
+  static constexpr int oE1 = oPiv + 4 * R + 4;
+  static constexpr int oE2 = oE1 + TT;           // contraction vectors
+  static constexpr int oGr = oE2 + TT;         // upwinded boundary data g
   static constexpr int oW1 = oGr + TT;
   static constexpr int oW2 = oW1 + RP;
   static constexpr int oRr = oW2 + RP;         // g_r = U_r^T g
@@ -90,6 +92,11 @@ struct LayR {
   static constexpr int US = kUrLds ? TTs : TT;        // column stride of U_r as used
   static constexpr int oU = endR;
   static constexpr int end2 = kUrLds ? endR + TTs * R : endR;
+  // With U_r staged, the edge operators of the projection use the 4 (R x N)
+  // tables M (formed once per fit over the staged U_r, which is not needed
+  // afterwards): C_r z and C_r^T y then take two short stages each.
+  static constexpr bool kM = kUrLds;
+  static_assert(!kM || 4 * R * N <= TTs * R, "M tables replace the staged U_r");
   static constexpr int oTU = oXv;                     // T U_r, column stride US
   static_assert(US * R <= oSd - oXv, "T U_r must fit in the aliased region");
   static constexpr size_t bytes1 = sizeof(double) * end1;
@@ -279,6 +286,84 @@ __device__ void r_Sinv(const double* Sd, const double* w, double* out) {
   }
 }
 
+// One-dimensional contractions of a coefficient array c[ly][k] with the edge
+// basis vectors: out[0..N) = sum_k p0x[k] c[.][k], out[N..2N) with p1x,
+// out[2N..3N) = sum_ly p0y[ly] c[ly][.], out[3N..4N) with p1y.
+template <int N>
+__device__ void r_edge_contract(const double* Ev, const double* c, double* out) {
+  for (int o = tid(); o < 4 * N; o += kThreads) {
+    const int w = o / N, m = o % N;
+    const double* e = Ev + w * N;
+    double acc = 0.0;
+    if (w < 2) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) acc += e[k] * c[m * N + k];
+    } else {
+#pragma unroll
+      for (int ly = 0; ly < N; ++ly) acc += e[ly] * c[ly * N + m];
+    }
+    out[o] = acc;
+  }
+}
+
+// Traces at the own edge points from the contractions u of r_edge_contract:
+// W, E point j = sum_ly By[j][ly] u_{W,E}[ly]; S, N point j = sum_k Bx[j][k] u_{S,N}[k].
+template <int N>
+__device__ void r_traces_from(const double* Bx, const double* By, const double* u, double* out) {
+  for (int q = tid(); q < 4 * N; q += kThreads) {
+    const int w = q / N, j = q % N;
+    const double* B = (w < 2) ? By + j * N : Bx + j * N;
+    const double* v = u + w * N;
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc += B[m] * v[m];
+    out[q] = acc;
+  }
+}
+
+// C_r z from the contractions u: w[c] = sum_w sum_m M_w[c][m] u_w[m] - rhs2[c],
+// with M_W[c][ly] = sum_j U_W[j][c] By[j][ly] (and E), M_S[c][k] = sum_j U_S[j][c] Bx[j][k]
+// (and N), stored as Mm[(w R + c) N + m].
+template <int N>
+__device__ void r_M_apply(const double* Mm, const double* u, const double* rhs2, double* out) {
+  using L = LayR<N>;
+  for (int c = tid(); c < L::RP; c += kThreads) {
+    double acc = 0.0;
+    if (c < L::R) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const double* Mr = Mm + (w * L::R + c) * N;
+#pragma unroll
+        for (int m = 0; m < N; ++m) acc += Mr[m] * u[w * N + m];
+      }
+      if (rhs2) acc -= rhs2[c];
+    }
+    out[c] = acc;
+  }
+}
+
+// y-weighted edge vectors yv[w N + m] = sum_c M_w[c][m] y[c]
+template <int N>
+__device__ void r_MT_apply(const double* Mm, const double* y, double* yv) {
+  using L = LayR<N>;
+  for (int o = tid(); o < 4 * N; o += kThreads) {
+    const int w = o / N, m = o % N;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int c = 0; c < L::R; ++c) acc += Mm[(w * L::R + c) * N + m] * y[c];
+    yv[o] = acc;
+  }
+}
+
+// C_r^T y from yv: out[(ly, k)] = p0x[k] yW[ly] + p1x[k] yE[ly] + p0y[ly] yS[k] + p1y[ly] yN[k]
+template <int N>
+__device__ void r_outer_edges(const double* Ev, const double* yv, double* out) {
+  for (int p = tid(); p < N * N; p += kThreads) {
+    const int k = p % N, ly = p / N;
+    out[p] = Ev[k] * yv[ly] + Ev[N + k] * yv[N + ly] + Ev[2 * N + ly] * yv[2 * N + k] + Ev[3 * N + ly] * yv[3 * N + k];
+  }
+}
+
 // ---------------------------------------------------------------- per-fit set-up
 
 // Moves (eq. def_dx), carried values (eq. advection_phi), centred 1-D tables,
@@ -433,7 +518,10 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   count_fit(p, 1, it > p.max_iter ? p.max_iter : it, gg <= stop);
   // traces of p0 at the own edge points (eq. remap_bnd)
   double* tv = lds + L::oTr;
-  r_C<N>(lds + L::oBx, lds + L::oBy, lds + L::oEv, x, tv);
+  double* uc = lds + L::oUc;
+  r_edge_contract<N>(lds + L::oEv, x, uc);
+  block_sync();
+  r_traces_from<N>(lds + L::oBx, lds + L::oBy, uc, tv);
   block_sync();
   const int64_t eoff = p.eoff[e];
   for (int qq = t; qq < L::TT; qq += kThreads) p.tr[s * p.edges + eoff + qq] = tv[qq];
@@ -458,68 +546,91 @@ __device__ void r_Pproj(double* lds, const double* U, const double* rin, const d
   const double* By = lds + L::oBy;
   const double* Ev = lds + L::oEv;
   r_G0inv<N>(gxi, rin, t1, z0);
-  r_C<N>(Bx, By, Ev, z0, e1);
-  block_sync();
-  r_UT<N>(U, e1, w1);
-  block_sync();
-  if (rhs2) {
-    for (int c = tid(); c < L::R; c += kThreads) w1[c] -= rhs2[c];
+  if constexpr (L::kM) {
+    double* u = lds + L::oE2;
+    const double* Mm = lds + L::oU;
+    r_edge_contract<N>(Ev, z0, u);
+    block_sync();
+    r_M_apply<N>(Mm, u, rhs2, w1);
+    block_sync();
+    r_Sinv<N>(lds + L::oSd, w1, w2);
+    block_sync();
+    r_MT_apply<N>(Mm, w2, u);
+    block_sync();
+    r_outer_edges<N>(Ev, u, t2);
+    block_sync();
+  } else {
+    r_C<N>(Bx, By, Ev, z0, e1);
+    block_sync();
+    r_UT<N>(U, e1, w1);
+    block_sync();
+    if (rhs2) {
+      for (int c = tid(); c < L::R; c += kThreads) w1[c] -= rhs2[c];
+      block_sync();
+    }
+    r_Sinv<N>(lds + L::oSd, w1, w2);
+    block_sync();
+    r_U<N>(U, w2, e1);
+    block_sync();
+    r_CT<N>(Bx, By, Ev, e1, t2);
     block_sync();
   }
-  r_Sinv<N>(lds + L::oSd, w1, w2);
-  block_sync();
-  r_U<N>(U, w2, e1);
-  block_sync();
-  r_CT<N>(Bx, By, Ev, e1, t2);
-  block_sync();
   r_G0inv<N>(gxi, t2, t1, out, z0);
 }
 
 // In-place Gauss-Jordan inversion of the dense SPD matrix S (R x R, row stride
-// Rs): R pivot steps, each thread keeping its elements in registers and the
-// pivot row and column passing through LDS (two buffers, one barrier a step).
+// Rs; SPD, so no pivoting): R pivot steps.  Each thread keeps a strided piece
+// of one row in registers (TPR threads per row); the pivot row and column and
+// the pivot's reciprocal pass through LDS (two buffers, one barrier a step).
 template <int N>
 __device__ void r_invert_S(double* Sd, double* piv) {
   using L = LayR<N>;
-  constexpr int R = L::R, RR = R * R, kE = (RR + kThreads - 1) / kThreads;
+  constexpr int R = L::R, TPR = kThreads / R, kE = (R + TPR - 1) / TPR;
   const int t = tid();
+  const int i = t / TPR, chunk = t - i * TPR;
+  const bool live = i < R;
   double a[kE];
 #pragma unroll
   for (int m = 0; m < kE; ++m) {
-    const int idx = t + kThreads * m;
-    a[m] = idx < RR ? Sd[(idx / R) * L::Rs + idx % R] : 0.0;
+    const int j = chunk + TPR * m;
+    a[m] = (live && j < R) ? Sd[i * L::Rs + j] : 0.0;
   }
 #pragma unroll 1
   for (int k = 0; k < R; ++k) {
-    double* prow = piv + (k & 1) * 2 * R;
+    double* prow = piv + (k & 1) * (2 * R + 2);
     double* pcol = prow + R;
+    if (live) {
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
-      const int idx = t + kThreads * m;
-      if (idx < RR) {
-        const int i = idx / R, j = idx - i * R;
-        if (i == k) prow[j] = a[m];
-        if (j == k) pcol[i] = a[m];
+      for (int m = 0; m < kE; ++m) {
+        const int j = chunk + TPR * m;
+        if (j < R) {
+          if (i == k) prow[j] = a[m];
+          if (j == k) pcol[i] = a[m];
+          if (i == k && j == k) pcol[R] = 1.0 / a[m];
+        }
       }
     }
     block_sync();
-    const double pinv = 1.0 / prow[k];
+    if (live) {
+      const double pinv = pcol[R];
+      const double pc = pcol[i] * pinv;
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
-      const int idx = t + kThreads * m;
-      if (idx < RR) {
-        const int i = idx / R, j = idx - i * R;
-        if (i == k && j == k) a[m] = pinv;
-        else if (i == k) a[m] = prow[j] * pinv;
-        else if (j == k) a[m] = -pcol[i] * pinv;
-        else a[m] -= pcol[i] * prow[j] * pinv;
+      for (int m = 0; m < kE; ++m) {
+        const int j = chunk + TPR * m;
+        const double pr = prow[j < R ? j : 0];
+        double v = a[m] - pc * pr;            // i != k, j != k
+        if (j == k) v = -pc;
+        if (i == k) v = (j == k) ? pinv : pr * pinv;
+        a[m] = v;
       }
     }
   }
+  if (live) {
 #pragma unroll
-  for (int m = 0; m < kE; ++m) {
-    const int idx = t + kThreads * m;
-    if (idx < RR) Sd[(idx / R) * L::Rs + idx % R] = a[m];
+    for (int m = 0; m < kE; ++m) {
+      const int j = chunk + TPR * m;
+      if (j < R) Sd[i * L::Rs + j] = a[m];
+    }
   }
   block_sync();
 }
@@ -688,6 +799,21 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     }
     block_sync();
   }
+  if constexpr (L::kM) {
+    double* Mt = lds + L::oTU;     // T U_r is no longer needed
+    for (int idx = t; idx < 4 * R * N; idx += kThreads) {
+      const int w = idx / (R * N), rem = idx - w * (R * N), c = rem / N, m = rem % N;
+      const double* Uc = U + c * L::TTs + w * N;
+      const double* B = (w < 2) ? By : Bx;
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc += Uc[j] * B[j * N + m];
+      Mt[idx] = acc;
+    }
+    block_sync();
+    double* Mm = lds + L::oU;      // over the staged U_r
+    for (int idx = t; idx < 4 * R * N; idx += kThreads) Mm[idx] = Mt[idx];
+  }
   r_invert_S<N>(Sd, lds + L::oPiv);
   // particular solution x0 = first block of [[G0, C_r^T], [C_r, 0]]^-1 [b; g_r]
   double* b = lds + L::oB;
@@ -744,18 +870,33 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     double* e1 = lds + L::oE1;
     double* w1 = lds + L::oW1;
     double* w2 = lds + L::oW2;
-    r_C<N>(Bx, By, Ev, x, e1);
-    block_sync();
-    r_UT<N>(U, e1, w1);
-    block_sync();
-    for (int c = t; c < R; c += kThreads) w1[c] -= rr[c];
-    block_sync();
-    r_Sinv<N>(lds + L::oSd, w1, w2);
-    block_sync();
-    r_U<N>(U, w2, e1);
-    block_sync();
-    r_CT<N>(Bx, By, Ev, e1, t2);
-    block_sync();
+    if constexpr (L::kM) {
+      double* u = lds + L::oE2;
+      const double* Mm = lds + L::oU;
+      r_edge_contract<N>(Ev, x, u);
+      block_sync();
+      r_M_apply<N>(Mm, u, rr, w1);
+      block_sync();
+      r_Sinv<N>(lds + L::oSd, w1, w2);
+      block_sync();
+      r_MT_apply<N>(Mm, w2, u);
+      block_sync();
+      r_outer_edges<N>(Ev, u, t2);
+      block_sync();
+    } else {
+      r_C<N>(Bx, By, Ev, x, e1);
+      block_sync();
+      r_UT<N>(U, e1, w1);
+      block_sync();
+      for (int c = t; c < R; c += kThreads) w1[c] -= rr[c];
+      block_sync();
+      r_Sinv<N>(lds + L::oSd, w1, w2);
+      block_sync();
+      r_U<N>(U, w2, e1);
+      block_sync();
+      r_CT<N>(Bx, By, Ev, e1, t2);
+      block_sync();
+    }
     r_G0inv<N>(gxi, t2, t1, zz);
     for (int i = t; i < n; i += kThreads) x[i] -= zz[i];
     block_sync();
