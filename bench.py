@@ -26,12 +26,13 @@ MI355X = {"fp64_vector_tflops": 78.6, "fp64_mfma_tflops": 78.6, "fp32_mfma_tflop
 
 
 def fit_flops_1d(N):
-    """Algorithmic float64 operations of one 1-D element fit and step in the nodal form the
-    kernel runs (see the design notes): moves 3N, carried values N, barycentric weights
-    2N^2 - 2N, two edge Lagrange rows 12N, traces and S 10N, multipliers 13, corrected
-    values 4N, Lagrange rows at the N Gauss nodes 6N^2 and their dot products 2N^2."""
-    return 10 * N * N + 28 * N + 13
-
+    """Float64 operations of one 1-D element fit and step in the nodal form the kernel
+    runs (multiply-add = 2, division = 1): moves 3N, carried values N, node products
+    for the barycentric weights 1.5N(N-1) (each difference once), their reciprocals
+    2.5N (one division per four), the two edge Lagrange rows 12N - 4, traces and S 10N,
+    multipliers 14, corrected and weighted values 5N, evaluation at the N Gauss nodes
+    6N^2 - N (differences, prefix and suffix products, accumulation)."""
+    return (15 * N * N + 62 * N + 20) // 2
 
 def fit_flops_2d_phase2(N):
     """Algorithmic float64 operations of one 2-D fit in the second (constrained) phase:

@@ -216,14 +216,18 @@ __device__ __forceinline__ void reciprocals(const double (&p)[N], double (&w)[N]
 
 template <int N>
 __device__ __forceinline__ void fit1d_nodal_pre(Fit1DNodal<N>& st) {
+  // p_j = prod_{m != j} (x*_j - x*_m), each difference formed once
   double pj[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    double p = 1.0;
+  for (int j = 0; j < N; ++j) pj[j] = 1.0;
 #pragma unroll
-    for (int m = 0; m < N; ++m)
-      if (m != j) p *= (st.xs[j] - st.xs[m]);
-    pj[j] = p;
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int m = j + 1; m < N; ++m) {
+      const double d = st.xs[j] - st.xs[m];
+      pj[j] *= d;
+      pj[m] *= -d;
+    }
   }
   reciprocals<N>(pj, st.w);
   lagrange_row<N>(st.xs, st.w, 0.0, st.cl);
@@ -252,15 +256,26 @@ __device__ __forceinline__ void fit1d_nodal_post(Fit1DNodal<N>& st, const double
   const double idet = 1.0 / (st.s00 * st.s11 - st.s01 * st.s01);
   const double l0 = (st.s11 * r0 - st.s01 * r1) * idet;
   const double l1 = (st.s00 * r1 - st.s01 * r0) * idet;
+  // phi_i = sum_j w_j a_j prod_{m != j} (xi_i - x*_m): the weights folded into
+  // the values once, then prefix and suffix products of the differences
+  double wa[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) st.a[j] -= st.cl[j] * l0 + st.cr[j] * l1;
+  for (int j = 0; j < N; ++j) wa[j] = st.w[j] * (st.a[j] - (st.cl[j] * l0 + st.cr[j] * l1));
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    double l[N];
-    lagrange_row<N>(st.xs, st.w, xi[i], l);
-    double v = 0.0;
+    double d[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) v += l[j] * st.a[j];
+    for (int m = 0; m < N; ++m) d[m] = xi[i] - st.xs[m];
+    double pre[N];
+    pre[0] = 1.0;
+#pragma unroll
+    for (int m = 1; m < N; ++m) pre[m] = pre[m - 1] * d[m - 1];
+    double suf = 1.0, v = 0.0;
+#pragma unroll
+    for (int j = N - 1; j >= 0; --j) {
+      v += wa[j] * (pre[j] * suf);
+      suf *= d[j];
+    }
     phi[i] = v;
   }
 }
