@@ -74,8 +74,8 @@ struct LayR {
   static constexpr int TTs = TT + 1;
   static constexpr int tuMax = TTs * R;
   static constexpr int oSd = (end1 > oXv + tuMax ? end1 : oXv + tuMax);   // S0, then S0^-1 (dense, R x Rs)
-  static constexpr int oPiv = oSd + R * Rs;    // Gauss-Jordan pivot row and column, two buffers
-  static constexpr int oE1 = oPiv + 4 * R + 4;
+  static constexpr int oPiv = oSd + R * Rs;    // Gauss-Jordan pivot rows and columns, two buffers
+  static constexpr int oE1 = oPiv + 16 * R;
   static constexpr int oE2 = oE1 + TT;           // contraction vectors
   static constexpr int oGr = oE2 + TT;         // upwinded boundary data g
   static constexpr int oW1 = oGr + TT;
@@ -578,14 +578,18 @@ __device__ void r_Pproj(double* lds, const double* U, const double* rin, const d
   r_G0inv<N>(gxi, t2, t1, out, z0);
 }
 
-// In-place Gauss-Jordan inversion of the dense SPD matrix S (R x R, row stride
-// Rs; SPD, so no pivoting): R pivot steps.  Each thread keeps a strided piece
-// of one row in registers (TPR threads per row); the pivot row and column and
-// the pivot's reciprocal pass through LDS (two buffers, one barrier a step).
+// In-place block Gauss-Jordan inversion of the dense SPD matrix S (R x R, row
+// stride Rs; R = 4(N - 1) is a multiple of 4): R / 4 steps, each eliminating a
+// 4 x 4 pivot block K (SPD, so no pivoting):
+//   S_KK <- P^-1,  S_Kj <- P^-1 S_Kj,  S_iK <- -S_iK P^-1,  S_ij <- S_ij - S_iK P^-1 S_Kj.
+// Each thread keeps a strided piece of one row in registers (TPR threads per
+// row); the pivot rows and columns pass through LDS (two buffers, one barrier
+// a step) and every thread inverts the 4 x 4 pivot block itself.
 template <int N>
 __device__ void r_invert_S(double* Sd, double* piv) {
   using L = LayR<N>;
   constexpr int R = L::R, TPR = kThreads / R, kE = (R + TPR - 1) / TPR;
+  static_assert(R % 4 == 0, "R is a multiple of 4");
   const int t = tid();
   const int i = t / TPR, chunk = t - i * TPR;
   const bool live = i < R;
@@ -596,31 +600,80 @@ __device__ void r_invert_S(double* Sd, double* piv) {
     a[m] = (live && j < R) ? Sd[i * L::Rs + j] : 0.0;
   }
 #pragma unroll 1
-  for (int k = 0; k < R; ++k) {
-    double* prow = piv + (k & 1) * (2 * R + 2);
-    double* pcol = prow + R;
+  for (int k0 = 0; k0 < R; k0 += 4) {
+    double* prow = piv + ((k0 >> 2) & 1) * 8 * R;   // [4][R] pivot rows
+    double* pcol = prow + 4 * R;                     // [R][4] pivot columns
+    const bool inK = i >= k0 && i < k0 + 4;
     if (live) {
 #pragma unroll
       for (int m = 0; m < kE; ++m) {
         const int j = chunk + TPR * m;
         if (j < R) {
-          if (i == k) prow[j] = a[m];
-          if (j == k) pcol[i] = a[m];
-          if (i == k && j == k) pcol[R] = 1.0 / a[m];
+          if (inK) prow[(i - k0) * R + j] = a[m];
+          if (j >= k0 && j < k0 + 4) pcol[i * 4 + (j - k0)] = a[m];
         }
       }
     }
     block_sync();
     if (live) {
-      const double pinv = pcol[R];
-      const double pc = pcol[i] * pinv;
+      // P^-1 by scalar Gauss-Jordan on the 4 x 4 block
+      double P[4][4];
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) P[pp][qq] = pcol[(k0 + pp) * 4 + qq];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double pinv = 1.0 / P[k][k];
+        double rk[4], ck[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          rk[q] = P[k][q];
+          ck[q] = P[q][k];
+        }
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            if (pp == k && qq == k) P[pp][qq] = pinv;
+            else if (pp == k) P[pp][qq] = rk[qq] * pinv;
+            else if (qq == k) P[pp][qq] = -ck[pp] * pinv;
+            else P[pp][qq] -= ck[pp] * rk[qq] * pinv;
+          }
+      }
+      // this row's coefficients: C = S_iK P^-1 (rows of K take P^-1 itself)
+      double C[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp) acc += pcol[i * 4 + pp] * P[pp][q];
+        C[q] = acc;
+      }
+      double Prow[4] = {0.0, 0.0, 0.0, 0.0};
+      if (inK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int pp = 0; pp < 4; ++pp)
+            if (pp == i - k0) Prow[q] = P[pp][q];
+        }
+      }
 #pragma unroll
       for (int m = 0; m < kE; ++m) {
         const int j = chunk + TPR * m;
-        const double pr = prow[j < R ? j : 0];
-        double v = a[m] - pc * pr;            // i != k, j != k
-        if (j == k) v = -pc;
-        if (i == k) v = (j == k) ? pinv : pr * pinv;
+        const int jj = j < R ? j : 0;
+        const bool jK = jj >= k0 && jj < k0 + 4;
+        double v;
+        if (jK) {
+          const int q = jj - k0;
+          v = inK ? (q == 0 ? Prow[0] : q == 1 ? Prow[1] : q == 2 ? Prow[2] : Prow[3])
+                  : -(q == 0 ? C[0] : q == 1 ? C[1] : q == 2 ? C[2] : C[3]);
+        } else {
+          const double r0 = prow[jj], r1 = prow[R + jj], r2 = prow[2 * R + jj], r3 = prow[3 * R + jj];
+          if (inK) v = Prow[0] * r0 + Prow[1] * r1 + Prow[2] * r2 + Prow[3] * r3;
+          else v = a[m] - (C[0] * r0 + C[1] * r1 + C[2] * r2 + C[3] * r3);
+        }
         a[m] = v;
       }
     }
