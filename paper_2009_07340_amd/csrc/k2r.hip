@@ -53,9 +53,9 @@ struct LayR {
   static constexpr int oBy = oBx + N * N;
   static constexpr int oEv = oBy + N * N;
   static constexpr int oGxi = oEv + 4 * N;
-  static constexpr int oF = oGxi + N * N;
-  static constexpr int oB = oF + n;
-  static constexpr int oXv = oB + n;
+  static constexpr int oB = oGxi + N * N;
+  static constexpr int oF = oB + n;
+  static constexpr int oXv = oF + n;
   static constexpr int oZ0 = oXv + n;
   static constexpr int oR = oZ0 + n;
   static constexpr int oGv = oR + n;
@@ -69,25 +69,32 @@ struct LayR {
   static constexpr int oYs = oXs + n;
   static constexpr int oRed = oYs + n;
   static constexpr int end1 = oRed + 16;
-  // phase 2 only.  T U_r (used while S0 is assembled) aliases [x .. end of
-  // phase 1] and, when larger, the space up to S0.
+  // Phase 2.  Regions that are dead at the time hold short-lived data:
+  //   [f .. end of phase 1] (f, the iteration vectors, the phase-1 edge vectors,
+  //   the moved coordinates) holds T U_r while S0 is assembled, then the M
+  //   tables before they move over the staged U_r, then the Gauss-Jordan pivot
+  //   buffers; the phase-1 edge vectors are the projection's edge vectors;
+  //   S0's own space holds the H tables until S0 is written.
   static constexpr int TTs = TT + 1;
   static constexpr int tuMax = TTs * R;
-  static constexpr int oSd = (end1 > oXv + tuMax ? end1 : oXv + tuMax);   // S0, then S0^-1 (dense, R x Rs)
-  static constexpr int oPiv = oSd + R * Rs;    // Gauss-Jordan pivot rows and columns, two buffers
-  static constexpr int oE1 = oPiv + 16 * R;
-  static constexpr int oE2 = oE1 + TT;           // contraction vectors
-  static constexpr int oGr = oE2 + TT;         // upwinded boundary data g
+  static constexpr int oTU = oF;                      // T U_r, column stride US
+  static constexpr int oSd = (end1 > oTU + tuMax ? end1 : oTU + tuMax);   // S0, then S0^-1 (dense, R x Rs)
+  static constexpr int oPiv = oTU;                    // Gauss-Jordan pivot rows and columns, two buffers
+  static_assert(16 * R <= oSd - oTU, "pivot buffers must fit in the aliased region");
+  static constexpr int oE1 = oTr;
+  static constexpr int oE2 = oUc;                     // contraction vectors
+  static constexpr int oGr = oSd + R * Rs;            // upwinded boundary data g
   static constexpr int oW1 = oGr + TT;
-  static constexpr int oW2 = oW1 + RP;
-  static constexpr int oRr = oW2 + RP;         // g_r = U_r^T g
-  static constexpr int oHx = oRr + RP;
+  static constexpr int oW2 = oW1 + R;
+  static constexpr int oRr = oW2 + R;                 // g_r = U_r^T g
+  static constexpr bool kHinS = 2 * NH * NH <= R * Rs;
+  static constexpr int oHx = kHinS ? oSd : oRr + R;
   static constexpr int oHy = oHx + NH * NH;
   // U_r is staged in LDS (column stride TT + 1) when it fits (N <= 13); then
   // T U_r and U_r^T (T U_r) run on the matrix cores, the entries of
   // T = C G0^-1 C^T formed on the fly from the H tables.  Larger orders read
   // U_r from the cache and assemble S0 with scalar loops.
-  static constexpr int endR = oHy + NH * NH;
+  static constexpr int endR = kHinS ? oRr + R : oHy + NH * NH;
   static constexpr bool kUrLds = sizeof(double) * (endR + TTs * R) <= 156 * 1024;
   static constexpr int US = kUrLds ? TTs : TT;        // column stride of U_r as used
   static constexpr int oU = endR;
@@ -97,8 +104,8 @@ struct LayR {
   // afterwards): C_r z and C_r^T y then take two short stages each.
   static constexpr bool kM = kUrLds;
   static_assert(!kM || 4 * R * N <= TTs * R, "M tables replace the staged U_r");
-  static constexpr int oTU = oXv;                     // T U_r, column stride US
-  static_assert(US * R <= oSd - oXv, "T U_r must fit in the aliased region");
+  static_assert(!kM || 4 * R * N <= oSd - oTU, "M tables are formed in the aliased region");
+  static_assert(US * R <= oSd - oTU, "T U_r must fit in the aliased region");
   static constexpr size_t bytes1 = sizeof(double) * end1;
   static constexpr size_t bytes2 = sizeof(double) * end2;
 };
@@ -246,16 +253,14 @@ __device__ void r_CT(const double* Bx, const double* By, const double* Ev, const
   }
 }
 
-// out[c] = (U_r^T v)_c for c < RP (zero padding); U column-major 4N x R, column stride US
+// out[c] = (U_r^T v)_c, c < R; U column-major 4N x R, column stride US
 template <int N>
 __device__ void r_UT(const double* U, const double* v, double* out) {
   using L = LayR<N>;
-  for (int c = tid(); c < L::RP; c += kThreads) {
+  for (int c = tid(); c < L::R; c += kThreads) {
     double acc = 0.0;
-    if (c < L::R) {
 #pragma unroll 4
-      for (int q = 0; q < L::TT; ++q) acc += U[c * L::US + q] * v[q];
-    }
+    for (int q = 0; q < L::TT; ++q) acc += U[c * L::US + q] * v[q];
     out[c] = acc;
   }
 }
@@ -272,16 +277,14 @@ __device__ void r_U(const double* U, const double* w, double* out) {
   }
 }
 
-// out = S0^-1 w (dense, row stride Rs), out padded with zeros to RP
+// out = S0^-1 w (dense, row stride Rs)
 template <int N>
 __device__ void r_Sinv(const double* Sd, const double* w, double* out) {
   using L = LayR<N>;
-  for (int c = tid(); c < L::RP; c += kThreads) {
+  for (int c = tid(); c < L::R; c += kThreads) {
     double acc = 0.0;
-    if (c < L::R) {
 #pragma unroll 4
-      for (int j = 0; j < L::R; ++j) acc += Sd[c * L::Rs + j] * w[j];
-    }
+    for (int j = 0; j < L::R; ++j) acc += Sd[c * L::Rs + j] * w[j];
     out[c] = acc;
   }
 }
@@ -327,17 +330,15 @@ __device__ void r_traces_from(const double* Bx, const double* By, const double* 
 template <int N>
 __device__ void r_M_apply(const double* Mm, const double* u, const double* rhs2, double* out) {
   using L = LayR<N>;
-  for (int c = tid(); c < L::RP; c += kThreads) {
+  for (int c = tid(); c < L::R; c += kThreads) {
     double acc = 0.0;
-    if (c < L::R) {
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const double* Mr = Mm + (w * L::R + c) * N;
+    for (int w = 0; w < 4; ++w) {
+      const double* Mr = Mm + (w * L::R + c) * N;
 #pragma unroll
-        for (int m = 0; m < N; ++m) acc += Mr[m] * u[w * N + m];
-      }
-      if (rhs2) acc -= rhs2[c];
+      for (int m = 0; m < N; ++m) acc += Mr[m] * u[w * N + m];
     }
+    if (rhs2) acc -= rhs2[c];
     out[c] = acc;
   }
 }
@@ -866,6 +867,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     block_sync();
     double* Mm = lds + L::oU;      // over the staged U_r
     for (int idx = t; idx < 4 * R * N; idx += kThreads) Mm[idx] = Mt[idx];
+    block_sync();                  // the pivot buffers reuse the space of Mt
   }
   r_invert_S<N>(Sd, lds + L::oPiv);
   // particular solution x0 = first block of [[G0, C_r^T], [C_r, 0]]^-1 [b; g_r]
