@@ -23,6 +23,11 @@
 
 namespace sl {
 
+// The fit arithmetic below may fuse multiply-adds (it is held to the oracle by a
+// tolerance); moved positions and edge displacements come from the helpers
+// above, which keep contraction off.  Switched off again at the end of the file.
+#pragma clang fp contract(fast)
+
 template <int N>
 __device__ __forceinline__ void legendre_eval(double t, const LegendreRec& rec, double (&psi)[N]) {
   const double x = 2.0 * t - 1.0;
@@ -298,5 +303,7 @@ __device__ __forceinline__ void move_nodes(const double* xi, const double* A, co
 #pragma unroll
   for (int i = 0; i < N; ++i) xs[i] = moved_coord(xi[i], A[i], B[i], z);
 }
+
+#pragma clang fp contract(off)
 
 }  // namespace sl

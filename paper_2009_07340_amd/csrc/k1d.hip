@@ -93,8 +93,8 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
     __syncthreads();
     if (active) {
       // upwind (eq. bnd_update): disp > 0 takes the negative-side element
-      const double dL = __dadd_rn(Af0, __dmul_rn(Bf0, z));
-      const double dR = __dadd_rn(Af1, __dmul_rn(Bf1, z));
+      const double dL = edge_disp(Af0, Bf0, z);
+      const double dR = edge_disp(Af1, Bf1, z);
       double nbL, nbR;
       if (e > 0) nbL = tr[(slot * K + e - 1) * 2 + 1];
       else nbL = p.dirichlet ? ghL : tr[(slot * K + K - 1) * 2 + 1];
@@ -189,8 +189,8 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
   trR[lane] = tR;
   __syncthreads();
   if (owned) {
-    const double dL = __dadd_rn(p.Af[2 * e], __dmul_rn(p.Bf[2 * e], z));
-    const double dR = __dadd_rn(p.Af[2 * e + 1], __dmul_rn(p.Bf[2 * e + 1], z));
+    const double dL = edge_disp(p.Af[2 * e], p.Bf[2 * e], z);
+    const double dR = edge_disp(p.Af[2 * e + 1], p.Bf[2 * e + 1], z);
     const double nbL = (p.dirichlet && e == 0) ? p.ghost[2 * e] : trR[lane - 1];
     const double nbR = (p.dirichlet && e == K - 1) ? p.ghost[2 * e + 1] : trL[lane + 1];
     const double gL = (dL > 0.0) ? nbL : tL;

@@ -426,7 +426,7 @@ __device__ __forceinline__ void phase2_body(const Params2D& p, char* lds_raw, in
     const int ew = q / N, j = q % N;
     const double tq = p.tr[s * p.edges + eoff + q];
     const double zd = (ew < 2) ? z.a : z.b;
-    const double disp = __dadd_rn(p.Af[eoff + q], __dmul_rn(p.Bf[eoff + q], zd));
+    const double disp = edge_disp(p.Af[eoff + q], p.Bf[eoff + q], zd);
     const bool pos = disp > 0.0;
     const bool take_nbr = (ew == 0 || ew == 2) ? pos : !pos;   // W, S: neighbour is the negative side
     double g = tq;

@@ -40,6 +40,11 @@
 
 namespace sl {
 
+// Solver arithmetic may fuse multiply-adds (the fit is held to the oracle by a
+// tolerance); moved positions and edge displacements come from helpers defined
+// with contraction off.
+#pragma clang fp contract(fast)
+
 using namespace blk;
 
 // LDS layout in doubles.  Phase 1 uses the first part only.
@@ -716,7 +721,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     const int ew = q / N, j = q % N;
     const double tq = p.tr[s * p.edges + eoff + q];
     const double zd = (ew < 2) ? z.a : z.b;
-    const double disp = __dadd_rn(p.Af[eoff + q], __dmul_rn(p.Bf[eoff + q], zd));
+    const double disp = edge_disp(p.Af[eoff + q], p.Bf[eoff + q], zd);
     const bool pos = disp > 0.0;
     const bool take_nbr = (ew == 0 || ew == 2) ? pos : !pos;   // W, S: neighbour is the negative side
     double g = tq;

@@ -119,4 +119,11 @@ __device__ __forceinline__ double moved_coord(double xi, double A, double B, dou
   return __dadd_rn(xi, __dadd_rn(A, __dmul_rn(B, z)));
 }
 
+// Displacement A + B z of a moved edge point, rounded as in moved_coord, so the
+// sign that picks the upwind side agrees with the moved positions.  Defined
+// here, outside the fit code that enables contraction.
+__device__ __forceinline__ double edge_disp(double A, double B, double z) {
+  return __dadd_rn(A, __dmul_rn(B, z));
+}
+
 }  // namespace sl
