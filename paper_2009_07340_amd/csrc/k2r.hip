@@ -52,9 +52,13 @@ template <int N>
 struct LayR {
   static constexpr int n = N * N, TT = 4 * N, R = 4 * N - 4, RB = (R + 15) / 16, RP = 16 * RB, NH = N + 2;
   static constexpr int Rs = R + 1;             // row stride of the dense S0 / S0^-1
+  // X1, Y1: the 1-D basis at the moved nodes, stored by basis index with an
+  // odd row stride (XS = n + 1) so that lanes walking the nodes and lanes
+  // walking the basis index both hit distinct LDS banks.
+  static constexpr int XS = n + 1;
   static constexpr int oX1 = 0;
-  static constexpr int oY1 = oX1 + n * N;
-  static constexpr int oBx = oY1 + n * N;
+  static constexpr int oY1 = oX1 + N * XS;
+  static constexpr int oBx = oY1 + N * XS;
   static constexpr int oBy = oBx + N * N;
   static constexpr int oEv = oBy + N * N;
   static constexpr int oGxi = oEv + 4 * N;
@@ -88,18 +92,23 @@ struct LayR {
   static_assert(16 * R <= oSd - oTU, "pivot buffers must fit in the aliased region");
   static constexpr int oE1 = oTr;
   static constexpr int oE2 = oUc;                     // contraction vectors
-  static constexpr int oGr = oSd + R * Rs;            // upwinded boundary data g
-  static constexpr int oW1 = oGr + TT;
+  // The projection's two R-vectors sit in the gap between the phase-1 layout
+  // and S0 when there is one (dead there after S0 is assembled and inverted).
+  static constexpr bool kWinGap = oSd - end1 >= 2 * R;
+  static constexpr int oW1 = kWinGap ? end1 : oSd + R * Rs;
   static constexpr int oW2 = oW1 + R;
-  static constexpr int oRr = oW2 + R;                 // g_r = U_r^T g
-  static constexpr bool kHinS = 2 * NH * NH <= R * Rs;
+  static constexpr int oRr = kWinGap ? oSd + R * Rs : oW2 + R;   // g_r = U_r^T g
+  // The H tables and the upwinded boundary data g live in S0's space when they
+  // fit there: both are dead once T U_r and g_r are formed, before S0 is written.
+  static constexpr bool kHinS = 2 * NH * NH + TT <= R * Rs;
   static constexpr int oHx = kHinS ? oSd : oRr + R;
   static constexpr int oHy = oHx + NH * NH;
-  // U_r is staged in LDS (column stride TT + 1) when it fits (N <= 13); then
+  static constexpr int oGr = oHy + NH * NH;           // upwinded boundary data g
+  // U_r is staged in LDS (column stride TT + 1) when it fits (N <= 15); then
   // T U_r and U_r^T (T U_r) run on the matrix cores, the entries of
   // T = C G0^-1 C^T formed on the fly from the H tables.  Larger orders read
   // U_r from the cache and assemble S0 with scalar loops.
-  static constexpr int endR = kHinS ? oRr + R : oHy + NH * NH;
+  static constexpr int endR = kHinS ? oRr + R : oGr + TT;
   static constexpr bool kUrLds = sizeof(double) * (endR + TTs * R) <= 156 * 1024;
   static constexpr int US = kUrLds ? TTs : TT;        // column stride of U_r as used
   static constexpr int oU = endR;
@@ -113,6 +122,11 @@ struct LayR {
   static_assert(US * R <= oSd - oTU, "T U_r must fit in the aliased region");
   static constexpr size_t bytes1 = sizeof(double) * end1;
   static constexpr size_t bytes2 = sizeof(double) * end2;
+  // Workgroups per CU that the LDS admits (one wave per SIMD each): the
+  // register budget is asked to admit as many, phase 2 at most 5 (more would
+  // spill its registers).
+  static constexpr int lds_waves(size_t b, int cap) { return (160 * 1024) / b > (size_t)cap ? cap : (int)((160 * 1024) / b); }
+  static constexpr int waves1 = lds_waves(bytes1, 8), waves2 = lds_waves(bytes2, 5);
 };
 
 // ---------------------------------------------------------------- helpers
@@ -175,14 +189,14 @@ __device__ void r_V(const double* X1, const double* Y1, const double* c, double*
   for (int i = tid(); i < N * N; i += kThreads) {
     double xr[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) xr[k] = X1[i * N + k];
+    for (int k = 0; k < N; ++k) xr[k] = X1[k * LayR<N>::XS + i];
     double v = 0.0;
 #pragma unroll 1
     for (int ly = 0; ly < N; ++ly) {
       double inner = 0.0;
 #pragma unroll
       for (int k = 0; k < N; ++k) inner += xr[k] * c[ly * N + k];
-      v += Y1[i * N + ly] * inner;
+      v += Y1[ly * LayR<N>::XS + i] * inner;
     }
     out[i] = v;
   }
@@ -195,7 +209,7 @@ __device__ void r_VT(const double* X1, const double* Y1, const double* r, double
     const int k = p % N, ly = p / N;
     double acc = 0.0;
 #pragma unroll 4
-    for (int i = 0; i < N * N; ++i) acc += X1[i * N + k] * Y1[i * N + ly] * r[i];
+    for (int i = 0; i < N * N; ++i) acc += X1[k * LayR<N>::XS + i] * Y1[ly * LayR<N>::XS + i] * r[i];
     out[p] = acc;
   }
 }
@@ -419,8 +433,8 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double
     legendre_eval<N>(ys[i] - dby, p.rec, py);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      X1[i * N + k] = px[k];
-      Y1[i * N + k] = py[k];
+      X1[k * L::XS + i] = px[k];
+      Y1[k * L::XS + i] = py[k];
     }
   }
   double* Bx = lds + L::oBx;
@@ -981,13 +995,13 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
 }
 
 template <int N>
-__global__ __launch_bounds__(kThreads) void fit2r_phase1(Params2D p) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LayR<N>::waves1))) void fit2r_phase1(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r1[];
   r_phase1_body<N>(p, lds_r1, blockIdx.x + p.block0);
 }
 
 template <int N>
-__global__ __launch_bounds__(kThreads) void fit2r_phase2(Params2D p) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LayR<N>::waves2))) void fit2r_phase2(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r2[];
   r_phase2_body<N>(p, lds_r2, blockIdx.x + p.block0);
 }
@@ -1034,7 +1048,8 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 // One order of several problems in one launch: one workgroup per fit of the
 // segments (problem, order group) of the argument table, all of order N.
 template <int N, int PHASE>
-__global__ __launch_bounds__(kThreads) void fit2r_multi(Fused2DArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::waves1 : LayR<N>::waves2)))
+void fit2r_multi(Fused2DArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds_rm[];
   const int64_t item = blockIdx.x;
   int sg = 0;
