@@ -31,8 +31,8 @@ def fit_flops_1d(N):
     for the barycentric weights 1.5N(N-1) (each difference once), their reciprocals
     2.5N (one division per four), the two edge Lagrange rows 12N - 4, traces and S 10N,
     multipliers 14, corrected and weighted values 5N, evaluation at the N Gauss nodes
-    6N^2 - N (differences, prefix and suffix products, accumulation)."""
-    return (15 * N * N + 62 * N + 20) // 2
+    5N^2 - 5N (differences, then a Horner scheme over the prefix products)."""
+    return (13 * N * N + 54 * N + 20) // 2
 
 def fit_flops_2d_phase2(N):
     """Algorithmic float64 operations of one 2-D fit in the second (constrained) phase:

@@ -261,25 +261,22 @@ __device__ __forceinline__ void fit1d_nodal_post(Fit1DNodal<N>& st, const double
   const double idet = 1.0 / (st.s00 * st.s11 - st.s01 * st.s01);
   const double l0 = (st.s11 * r0 - st.s01 * r1) * idet;
   const double l1 = (st.s00 * r1 - st.s01 * r0) * idet;
-  // phi_i = sum_j w_j a_j prod_{m != j} (xi_i - x*_m): the weights folded into
-  // the values once, then prefix and suffix products of the differences
+  // phi_i = sum_j w_j a_j prod_{m != j} (xi_i - x*_m), with the weights folded
+  // into the values once.  With d_m = xi_i - x*_m and P_j = prod_{m < j} d_m the
+  // sum is sum_j wa_j P_j prod_{m > j} d_m, a Horner scheme over j:
+  // v <- v d_j + wa_j P_j, P <- P d_j (three operations a node pair).
   double wa[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) wa[j] = st.w[j] * (st.a[j] - (st.cl[j] * l0 + st.cr[j] * l1));
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    double d[N];
+    double v = wa[0], dprev = xi[i] - st.xs[0], P = 1.0;
 #pragma unroll
-    for (int m = 0; m < N; ++m) d[m] = xi[i] - st.xs[m];
-    double pre[N];
-    pre[0] = 1.0;
-#pragma unroll
-    for (int m = 1; m < N; ++m) pre[m] = pre[m - 1] * d[m - 1];
-    double suf = 1.0, v = 0.0;
-#pragma unroll
-    for (int j = N - 1; j >= 0; --j) {
-      v += wa[j] * (pre[j] * suf);
-      suf *= d[j];
+    for (int j = 1; j < N; ++j) {
+      P = (j == 1) ? dprev : P * dprev;
+      const double d = xi[i] - st.xs[j];
+      v = v * d + wa[j] * P;
+      dprev = d;
     }
     phi[i] = v;
   }
