@@ -104,12 +104,13 @@ struct LayR {
   static constexpr int oHx = kHinS ? oSd : oRr + R;
   static constexpr int oHy = oHx + NH * NH;
   static constexpr int oGr = oHy + NH * NH;           // upwinded boundary data g
-  // U_r is staged in LDS (column stride TT + 1) when it fits (N <= 15); then
   // T U_r and U_r^T (T U_r) run on the matrix cores, the entries of
-  // T = C G0^-1 C^T formed on the fly from the H tables.  Larger orders read
-  // U_r from the cache and assemble S0 with scalar loops.
+  // T = C G0^-1 C^T formed on the fly from the H tables.  U_r is staged in LDS
+  // (column stride TT + 1) when it fits and costs no occupancy (phase-2
+  // workgroups a CU, at most 5); otherwise it is read from the cache.
   static constexpr int endR = kHinS ? oRr + R : oGr + TT;
-  static constexpr bool kUrLds = sizeof(double) * (endR + TTs * R) <= 156 * 1024;
+  static constexpr size_t kCU = 160 * 1024, bU = sizeof(double) * (endR + TTs * R), bNoU = sizeof(double) * endR;
+  static constexpr bool kUrLds = bU <= 156 * 1024 && (kCU / bU > 5 ? 5 : kCU / bU) >= (kCU / bNoU > 5 ? 5 : kCU / bNoU);
   static constexpr int US = kUrLds ? TTs : TT;        // column stride of U_r as used
   static constexpr int oU = endR;
   static constexpr int end2 = kUrLds ? endR + TTs * R : endR;
@@ -784,8 +785,8 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* Sd = lds + L::oSd;
   constexpr int Rs = L::Rs;
   typedef Mma<double> M64;
-  if constexpr (L::kUrLds) {
-    constexpr int TTs = L::TTs, QB = (TT + 15) / 16;
+  {
+    constexpr int TTs = L::TTs, US = L::US, QB = (TT + 15) / 16;
     const int l = lane(), lr = l & 15, lk = l >> 4;
 #pragma unroll 1
     for (int bidx = wv; bidx < QB * RB; bidx += 4) {
@@ -795,14 +796,14 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       const int xa1 = (w1 == 0) ? 0 : (w1 == 1) ? 1 : 2 + j1;
       const int ya1 = (w1 == 2) ? 0 : (w1 == 3) ? 1 : 2 + j1;
       M64::acc_t acc = zacc<double>();
-#pragma unroll 1
+#pragma unroll 4
       for (int kk = 0; kk < TT / 4; ++kk) {
         const int q = 4 * kk + lk;
         const int w2 = q / N, j2 = q % N;
         const int xa2 = (w2 == 0) ? 0 : (w2 == 1) ? 1 : 2 + j2;
         const int ya2 = (w2 == 2) ? 0 : (w2 == 3) ? 1 : 2 + j2;
         const double a = q1 < TT ? Hx[xa1 * NH + xa2] * Hy[ya1 * NH + ya2] : 0.0;
-        const double bv = c < R ? U[c * TTs + q] : 0.0;
+        const double bv = c < R ? U[c * US + q] : 0.0;
         acc = M64::mma(a, bv, acc);
       }
 #pragma unroll
@@ -820,10 +821,10 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       const int J = bidx - I * (I + 1) / 2;
       const int c1 = 16 * I + lr, c2 = 16 * J + lr;
       M64::acc_t acc = zacc<double>();
-#pragma unroll 1
+#pragma unroll 4
       for (int kk = 0; kk < TT / 4; ++kk) {
         const int q = 4 * kk + lk;
-        const double a = c1 < R ? U[c1 * TTs + q] : 0.0;
+        const double a = c1 < R ? U[c1 * US + q] : 0.0;
         const double bv = c2 < R ? TU[c2 * TTs + q] : 0.0;
         acc = M64::mma(a, bv, acc);
       }
@@ -837,38 +838,6 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
           Sd[col * Rs + row] = acc[s4];
         }
       }
-    }
-    block_sync();
-  } else {
-    for (int idx = t; idx < TT * R; idx += kThreads) {
-      const int q1 = idx % TT, c = idx / TT;
-      const int w1 = q1 / N, j1 = q1 % N;
-      const int xa1 = (w1 == 0) ? 0 : (w1 == 1) ? 1 : 2 + j1;
-      const int ya1 = (w1 == 2) ? 0 : (w1 == 3) ? 1 : 2 + j1;
-      const double* Uc = U + c * TT;
-      double acc = 0.0;
-#pragma unroll 1
-      for (int w2 = 0; w2 < 4; ++w2) {
-#pragma unroll 4
-        for (int j2 = 0; j2 < N; ++j2) {
-          const int xa2 = (w2 == 0) ? 0 : (w2 == 1) ? 1 : 2 + j2;
-          const int ya2 = (w2 == 2) ? 0 : (w2 == 3) ? 1 : 2 + j2;
-          acc += Hx[xa1 * NH + xa2] * Hy[ya1 * NH + ya2] * Uc[w2 * N + j2];
-        }
-      }
-      TU[c * TT + q1] = acc;
-    }
-    block_sync();
-    for (int idx = t; idx < R * R; idx += kThreads) {
-      const int c1 = idx / R, c2 = idx % R;
-      if (c2 > c1) continue;
-      const double* Uc = U + c1 * TT;
-      const double* Tc = TU + c2 * TT;
-      double acc = 0.0;
-#pragma unroll 4
-      for (int q = 0; q < TT; ++q) acc += Uc[q] * Tc[q];
-      Sd[c1 * Rs + c2] = acc;
-      Sd[c2 * Rs + c1] = acc;
     }
     block_sync();
   }
