@@ -203,15 +203,28 @@ __device__ void r_V(const double* X1, const double* Y1, const double* c, double*
   }
 }
 
-// out[p] = (V^T r)_p
+// out[p] = (V^T r)_p, p = (ly, k): the N x N matrix Y1 diag(r) X1^T as one
+// 16 x 16 float64 matrix-core tile (K = n in steps of 4), by wavefront 0.
 template <int N>
-__device__ void r_VT(const double* X1, const double* Y1, const double* r, double* out) {
-  for (int p = tid(); p < N * N; p += kThreads) {
-    const int k = p % N, ly = p / N;
-    double acc = 0.0;
+__device__ void r_VT_mc(const double* X1, const double* Y1, const double* r, double* out) {
+  typedef Mma<double> M64;
+  if (wave() != 0) return;
+  constexpr int n = N * N, XS = LayR<N>::XS;
+  const int l = lane(), lr = l & 15, lk = l >> 4;
+  const bool col = lr < N;
+  M64::acc_t acc = zacc<double>();
 #pragma unroll 4
-    for (int i = 0; i < N * N; ++i) acc += X1[k * LayR<N>::XS + i] * Y1[ly * LayR<N>::XS + i] * r[i];
-    out[p] = acc;
+  for (int kk = 0; kk < (n + 3) / 4; ++kk) {
+    const int i = 4 * kk + lk;
+    const bool ok = col && i < n;
+    const double a = ok ? Y1[lr * XS + i] : 0.0;          // A[ly][i]
+    const double b = ok ? r[i] * X1[lr * XS + i] : 0.0;   // B[i][k]
+    acc = M64::mma(a, b, acc);
+  }
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const int ly = M64::row(l, s4);
+    if (ly < N && col) out[ly * N + lr] = acc[s4];
   }
 }
 
@@ -459,7 +472,7 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double
     for (int k = 0; k < N; ++k) Ev[w * N + k] = q[k];
   }
   block_sync();
-  r_VT<N>(X1, Y1, f, lds + L::oB);
+  r_VT_mc<N>(X1, Y1, f, lds + L::oB);
   block_sync();
 }
 
@@ -469,7 +482,7 @@ __device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, d
   using L = LayR<N>;
   r_V<N>(lds + L::oX1, lds + L::oY1, v, tmp);
   block_sync();
-  r_VT<N>(lds + L::oX1, lds + L::oY1, tmp, out);
+  r_VT_mc<N>(lds + L::oX1, lds + L::oY1, tmp, out);
   block_sync();
 }
 
