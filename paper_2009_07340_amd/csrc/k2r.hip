@@ -47,6 +47,14 @@ namespace sl {
 
 using namespace blk;
 
+// 1 / d for a positive normal d: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
 // LDS layout in doubles.  Phase 1 uses the first part only.
 template <int N>
 struct LayR {
@@ -88,8 +96,8 @@ struct LayR {
   static constexpr int tuMax = TTs * R;
   static constexpr int oTU = oF;                      // T U_r, column stride US
   static constexpr int oSd = (end1 > oTU + tuMax ? end1 : oTU + tuMax);   // S0, then S0^-1 (dense, R x Rs)
-  static constexpr int oPiv = oTU;                    // Gauss-Jordan pivot rows and columns, two buffers
-  static_assert(16 * R <= oSd - oTU, "pivot buffers must fit in the aliased region");
+  static constexpr int oPiv = oTU;                    // Gauss-Jordan pivot rows, two buffers
+  static_assert(8 * R <= oSd - oTU, "pivot buffers must fit in the aliased region");
   static constexpr int oE1 = oTr;
   static constexpr int oE2 = oUc;                     // contraction vectors
   // The projection's two R-vectors sit in the gap between the phase-1 layout
@@ -616,9 +624,14 @@ __device__ void r_Pproj(double* lds, const double* U, const double* rin, const d
 // stride Rs; R = 4(N - 1) is a multiple of 4): R / 4 steps, each eliminating a
 // 4 x 4 pivot block K (SPD, so no pivoting):
 //   S_KK <- P^-1,  S_Kj <- P^-1 S_Kj,  S_iK <- -S_iK P^-1,  S_ij <- S_ij - S_iK P^-1 S_Kj.
-// Each thread keeps a strided piece of one row in registers (TPR threads per
-// row); the pivot rows and columns pass through LDS (two buffers, one barrier
-// a step) and every thread inverts the 4 x 4 pivot block itself.
+// Between steps the working matrix keeps the structure of a partial inverse of
+// an SPD matrix: its eliminated and remaining diagonal blocks are symmetric and
+// the block from eliminated rows to remaining columns is minus the transpose of
+// its mirror, so a row's part of the pivot columns is read from the pivot rows
+// (negated for rows already eliminated).  Each thread keeps a strided piece of
+// one row in registers (TPR threads per row); the pivot rows pass through LDS
+// (two buffers, one barrier a step) and every thread inverts the 4 x 4 pivot
+// block itself.
 template <int N>
 __device__ void r_invert_S(double* Sd, double* piv) {
   using L = LayR<N>;
@@ -635,17 +648,13 @@ __device__ void r_invert_S(double* Sd, double* piv) {
   }
 #pragma unroll 1
   for (int k0 = 0; k0 < R; k0 += 4) {
-    double* prow = piv + ((k0 >> 2) & 1) * 8 * R;   // [4][R] pivot rows
-    double* pcol = prow + 4 * R;                     // [R][4] pivot columns
+    double* prow = piv + ((k0 >> 2) & 1) * 4 * R;   // [4][R] pivot rows, two buffers
     const bool inK = i >= k0 && i < k0 + 4;
-    if (live) {
+    if (live && inK) {
 #pragma unroll
       for (int m = 0; m < kE; ++m) {
         const int j = chunk + TPR * m;
-        if (j < R) {
-          if (inK) prow[(i - k0) * R + j] = a[m];
-          if (j >= k0 && j < k0 + 4) pcol[i * 4 + (j - k0)] = a[m];
-        }
+        if (j < R) prow[(i - k0) * R + j] = a[m];
       }
     }
     block_sync();
@@ -655,10 +664,10 @@ __device__ void r_invert_S(double* Sd, double* piv) {
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) P[pp][qq] = pcol[(k0 + pp) * 4 + qq];
+        for (int qq = 0; qq < 4; ++qq) P[pp][qq] = prow[pp * R + k0 + qq];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const double pinv = 1.0 / P[k][k];
+        const double pinv = rcp_nr(P[k][k]);
         double rk[4], ck[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -676,12 +685,16 @@ __device__ void r_invert_S(double* Sd, double* piv) {
           }
       }
       // this row's coefficients: C = S_iK P^-1 (rows of K take P^-1 itself)
+      const double sg = (i < k0) ? -1.0 : 1.0;
+      double sK[4];
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) sK[pp] = sg * prow[pp * R + i];
       double C[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         double acc = 0.0;
 #pragma unroll
-        for (int pp = 0; pp < 4; ++pp) acc += pcol[i * 4 + pp] * P[pp][q];
+        for (int pp = 0; pp < 4; ++pp) acc += sK[pp] * P[pp][q];
         C[q] = acc;
       }
       double Prow[4] = {0.0, 0.0, 0.0, 0.0};
