@@ -47,14 +47,6 @@ namespace sl {
 
 using namespace blk;
 
-// 1 / d for a positive normal d: hardware estimate and two Newton steps.
-__device__ __forceinline__ double rcp_nr(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-#pragma unroll
-  for (int k = 0; k < 2; ++k) r = fma(r, fma(-d, r, 1.0), r);
-  return r;
-}
-
 // LDS layout in doubles.  Phase 1 uses the first part only.
 template <int N>
 struct LayR {
@@ -630,8 +622,8 @@ __device__ void r_Pproj(double* lds, const double* U, const double* rin, const d
 // its mirror, so a row's part of the pivot columns is read from the pivot rows
 // (negated for rows already eliminated).  Each thread keeps a strided piece of
 // one row in registers (TPR threads per row); the pivot rows pass through LDS
-// (two buffers, one barrier a step) and every thread inverts the 4 x 4 pivot
-// block itself.
+// (two buffers, one barrier a step) and every thread solves with the 4 x 4
+// pivot block itself (Cholesky, two triangular solves).
 template <int N>
 __device__ void r_invert_S(double* Sd, double* piv) {
   using L = LayR<N>;
@@ -659,52 +651,46 @@ __device__ void r_invert_S(double* Sd, double* piv) {
     }
     block_sync();
     if (live) {
-      // P^-1 by scalar Gauss-Jordan on the 4 x 4 block
-      double P[4][4];
+      // this row's coefficients x = P^-1 rhs, rhs = S_iK^T (P symmetric) or, for
+      // a row of K, the unit vector (x is then that row of P^-1): Cholesky of
+      // the 4 x 4 pivot block (lower triangle) and two triangular solves
+      double Pl[4][4];
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp)
 #pragma unroll
-        for (int qq = 0; qq < 4; ++qq) P[pp][qq] = prow[pp * R + k0 + qq];
+        for (int qq = 0; qq <= pp; ++qq) Pl[pp][qq] = prow[pp * R + k0 + qq];
+      double dinv[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double pinv = rcp_nr(P[k][k]);
-        double rk[4], ck[4];
+      for (int jj = 0; jj < 4; ++jj) {
+        double d = Pl[jj][jj];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          rk[q] = P[k][q];
-          ck[q] = P[q][k];
+        for (int kk = 0; kk < jj; ++kk) d -= Pl[jj][kk] * Pl[jj][kk];
+        dinv[jj] = rsqrt_nr(d);
+#pragma unroll
+        for (int ii = jj + 1; ii < 4; ++ii) {
+          double v = Pl[ii][jj];
+#pragma unroll
+          for (int kk = 0; kk < jj; ++kk) v -= Pl[ii][kk] * Pl[jj][kk];
+          Pl[ii][jj] = v * dinv[jj];
         }
-#pragma unroll
-        for (int pp = 0; pp < 4; ++pp)
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) {
-            if (pp == k && qq == k) P[pp][qq] = pinv;
-            else if (pp == k) P[pp][qq] = rk[qq] * pinv;
-            else if (qq == k) P[pp][qq] = -ck[pp] * pinv;
-            else P[pp][qq] -= ck[pp] * rk[qq] * pinv;
-          }
       }
-      // this row's coefficients: C = S_iK P^-1 (rows of K take P^-1 itself)
       const double sg = (i < k0) ? -1.0 : 1.0;
-      double sK[4];
+      double x[4];
 #pragma unroll
-      for (int pp = 0; pp < 4; ++pp) sK[pp] = sg * prow[pp * R + i];
-      double C[4];
+      for (int pp = 0; pp < 4; ++pp) x[pp] = inK ? (i - k0 == pp ? 1.0 : 0.0) : sg * prow[pp * R + i];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double acc = 0.0;
+      for (int ii = 0; ii < 4; ++ii) {
+        double v = x[ii];
 #pragma unroll
-        for (int pp = 0; pp < 4; ++pp) acc += sK[pp] * P[pp][q];
-        C[q] = acc;
+        for (int kk = 0; kk < ii; ++kk) v -= Pl[ii][kk] * x[kk];
+        x[ii] = v * dinv[ii];
       }
-      double Prow[4] = {0.0, 0.0, 0.0, 0.0};
-      if (inK) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+      for (int ii = 3; ii >= 0; --ii) {
+        double v = x[ii];
 #pragma unroll
-          for (int pp = 0; pp < 4; ++pp)
-            if (pp == i - k0) Prow[q] = P[pp][q];
-        }
+        for (int kk = ii + 1; kk < 4; ++kk) v -= Pl[kk][ii] * x[kk];
+        x[ii] = v * dinv[ii];
       }
 #pragma unroll
       for (int m = 0; m < kE; ++m) {
@@ -714,12 +700,12 @@ __device__ void r_invert_S(double* Sd, double* piv) {
         double v;
         if (jK) {
           const int q = jj - k0;
-          v = inK ? (q == 0 ? Prow[0] : q == 1 ? Prow[1] : q == 2 ? Prow[2] : Prow[3])
-                  : -(q == 0 ? C[0] : q == 1 ? C[1] : q == 2 ? C[2] : C[3]);
+          const double xq = (q == 0) ? x[0] : (q == 1) ? x[1] : (q == 2) ? x[2] : x[3];
+          v = inK ? xq : -xq;
         } else {
           const double r0 = prow[jj], r1 = prow[R + jj], r2 = prow[2 * R + jj], r3 = prow[3 * R + jj];
-          if (inK) v = Prow[0] * r0 + Prow[1] * r1 + Prow[2] * r2 + Prow[3] * r3;
-          else v = a[m] - (C[0] * r0 + C[1] * r1 + C[2] * r2 + C[3] * r3);
+          const double xr = x[0] * r0 + x[1] * r1 + x[2] * r2 + x[3] * r3;
+          v = inK ? xr : a[m] - xr;
         }
         a[m] = v;
       }
