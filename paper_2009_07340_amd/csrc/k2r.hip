@@ -771,21 +771,31 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     }
     gv[q] = g;
   }
-  // 1-D quadratic forms H[a][b] = v_a^T Gx^-1 v_b over {psi(0 - d), psi(1 - d), psi(xi_j - d)}
+  // 1-D quadratic forms H[a][b] = v_a^T Gx^-1 v_b over {psi(0 - d), psi(1 - d), psi(xi_j - d)}:
+  // first W[b] = Gx^-1 v_b (in the space T U_r takes later), then H[a][b] = v_a . W[b]
   double* Hx = lds + L::oHx;
   double* Hy = lds + L::oHy;
+  double* Wt = lds + L::oTU;   // [dir][b][N]
+  static_assert(2 * NH * N <= L::TTs * R, "W fits where T U_r goes");
+  auto hvec = [&](int dir, int a) -> const double* {
+    return (a == 0) ? Ev + 2 * dir * N : (a == 1) ? Ev + (2 * dir + 1) * N : (dir == 0 ? Bx : By) + (a - 2) * N;
+  };
+  for (int idx = t; idx < 2 * NH * N; idx += kThreads) {
+    const int db = idx / N, k = idx - db * N, dir = db / NH, bb = db - dir * NH;
+    const double* vb = hvec(dir, bb);
+    double acc = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < N; ++kk) acc += gxi[k * N + kk] * vb[kk];
+    Wt[idx] = acc;
+  }
+  block_sync();
   for (int idx = t; idx < 2 * NH * NH; idx += kThreads) {
     const int dir = idx / (NH * NH), ab = idx % (NH * NH), a = ab / NH, bb = ab % NH;
-    const double* va = (a == 0) ? Ev + 2 * dir * N : (a == 1) ? Ev + (2 * dir + 1) * N : (dir == 0 ? Bx : By) + (a - 2) * N;
-    const double* vb = (bb == 0) ? Ev + 2 * dir * N : (bb == 1) ? Ev + (2 * dir + 1) * N : (dir == 0 ? Bx : By) + (bb - 2) * N;
+    const double* va = hvec(dir, a);
+    const double* wb = Wt + (dir * NH + bb) * N;
     double acc = 0.0;
-#pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-      double inner = 0.0;
 #pragma unroll
-      for (int kk = 0; kk < N; ++kk) inner += gxi[k * N + kk] * vb[kk];
-      acc += va[k] * inner;
-    }
+    for (int k = 0; k < N; ++k) acc += va[k] * wb[k];
     (dir == 0 ? Hx : Hy)[ab] = acc;
   }
   block_sync();
