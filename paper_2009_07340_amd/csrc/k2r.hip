@@ -80,10 +80,10 @@ struct LayR {
   static constexpr int end1 = oRed + 16;
   // Phase 2.  Regions that are dead at the time hold short-lived data:
   //   [f .. end of phase 1] (f, the iteration vectors, the phase-1 edge vectors,
-  //   the moved coordinates) holds T U_r while S0 is assembled, then the M
-  //   tables before they move over the staged U_r, then the Gauss-Jordan pivot
-  //   buffers; the phase-1 edge vectors are the projection's edge vectors;
-  //   S0's own space holds the H tables until S0 is written.
+  //   the moved coordinates) holds Gx^-1 applied to the 1-D edge vectors while
+  //   the H tables are formed, then T U_r while S0 is assembled, then the
+  //   Gauss-Jordan pivot buffers; the phase-1 edge vectors are the projection's
+  //   edge vectors; S0's own space holds the H tables until S0 is written.
   static constexpr int TTs = TT + 1;
   static constexpr int tuMax = TTs * R;
   static constexpr int oTU = oF;                      // T U_r, column stride US
@@ -119,7 +119,6 @@ struct LayR {
   // afterwards): C_r z and C_r^T y then take two short stages each.
   static constexpr bool kM = kUrLds;
   static_assert(!kM || 4 * R * N <= TTs * R, "M tables replace the staged U_r");
-  static_assert(!kM || 4 * R * N <= oSd - oTU, "M tables are formed in the aliased region");
   static_assert(US * R <= oSd - oTU, "T U_r must fit in the aliased region");
   static constexpr size_t bytes1 = sizeof(double) * end1;
   static constexpr size_t bytes2 = sizeof(double) * end2;
@@ -864,20 +863,37 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     block_sync();
   }
   if constexpr (L::kM) {
-    double* Mt = lds + L::oTU;     // T U_r is no longer needed
-    for (int idx = t; idx < 4 * R * N; idx += kThreads) {
-      const int w = idx / (R * N), rem = idx - w * (R * N), c = rem / N, m = rem % N;
-      const double* Uc = U + c * L::TTs + w * N;
-      const double* B = (w < 2) ? By : Bx;
-      double acc = 0.0;
+    // M_w = U_w^T B_w (R x N, K = N) on the matrix cores, RB tiles a wavefront,
+    // held in registers until every read of the staged U_r is done, then
+    // written over it
+    const int l = lane(), lr = l & 15, lk = l >> 4;
+    M64::acc_t macc[RB];
 #pragma unroll
-      for (int j = 0; j < N; ++j) acc += Uc[j] * B[j * N + m];
-      Mt[idx] = acc;
+    for (int u = 0; u < RB; ++u) {
+      const int tl = wv + 4 * u, w = tl / RB, rt = tl - w * RB;
+      const double* Bw = (w < 2) ? By : Bx;
+      const int c = 16 * rt + lr;
+      M64::acc_t acc = zacc<double>();
+#pragma unroll
+      for (int st = 0; st < (N + 3) / 4; ++st) {
+        const int j = 4 * st + lk;
+        const double av = (c < R && j < N) ? U[c * L::TTs + w * N + j] : 0.0;   // A[c][j]
+        const double bv = (lr < N && j < N) ? Bw[j * N + lr] : 0.0;             // B[j][m]
+        acc = M64::mma(av, bv, acc);
+      }
+      macc[u] = acc;
     }
     block_sync();
-    double* Mm = lds + L::oU;      // over the staged U_r
-    for (int idx = t; idx < 4 * R * N; idx += kThreads) Mm[idx] = Mt[idx];
-    block_sync();                  // the pivot buffers reuse the space of Mt
+    double* Mm = lds + L::oU;
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int tl = wv + 4 * u, w = tl / RB, rt = tl - w * RB;
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int c = 16 * rt + M64::row(l, s4);
+        if (c < R && lr < N) Mm[(w * R + c) * N + lr] = macc[u][s4];
+      }
+    }
   }
   r_invert_S<N>(Sd, lds + L::oPiv);
   // particular solution x0 = first block of [[G0, C_r^T], [C_r, 0]]^-1 [b; g_r]
