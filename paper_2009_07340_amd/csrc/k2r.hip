@@ -440,35 +440,33 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double
   const double dby = (red[4] + red[5] + red[6] + red[7]) / n;
   double* X1 = lds + L::oX1;
   double* Y1 = lds + L::oY1;
-  for (int i = t; i < n; i += kThreads) {
-    double px[N], py[N];
-    legendre_eval<N>(xs[i] - dbx, p.rec, px);
-    legendre_eval<N>(ys[i] - dby, p.rec, py);
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      X1[k * L::XS + i] = px[k];
-      Y1[k * L::XS + i] = py[k];
-    }
-  }
   double* Bx = lds + L::oBx;
   double* By = lds + L::oBy;
   double* Ev = lds + L::oEv;
-  if (t < N) {
-    double px[N], py[N];
-    legendre_eval<N>(p.xi_tab[N * kMaxN + t] - dbx, p.rec, px);
-    legendre_eval<N>(p.xi_tab[N * kMaxN + t] - dby, p.rec, py);
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      Bx[t * N + k] = px[k];
-      By[t * N + k] = py[k];
+  // one basis evaluation an item: the n moved nodes in x, then in y, the N
+  // Gauss abscissae of the edges in x and in y, the 4 edge coordinates
+  for (int it = t; it < 2 * n + 2 * N + 4; it += kThreads) {
+    double arg;
+    double* dst;
+    int stride = 1;
+    if (it < 2 * n) {
+      const int dir = it >= n, i = it - dir * n;
+      arg = dir ? ys[i] - dby : xs[i] - dbx;
+      dst = (dir ? Y1 : X1) + i;
+      stride = L::XS;
+    } else if (it < 2 * n + 2 * N) {
+      const int u = it - 2 * n, dir = u >= N, row = u - dir * N;
+      arg = p.xi_tab[N * kMaxN + row] - (dir ? dby : dbx);
+      dst = (dir ? By : Bx) + row * N;
+    } else {
+      const int w = it - 2 * n - 2 * N;
+      arg = (w == 0) ? -dbx : (w == 1) ? 1.0 - dbx : (w == 2) ? -dby : 1.0 - dby;
+      dst = Ev + w * N;
     }
-  } else if (t >= 64 && t < 68) {
-    const int w = t - 64;
     double q[N];
-    const double a = (w == 0) ? -dbx : (w == 1) ? 1.0 - dbx : (w == 2) ? -dby : 1.0 - dby;
-    legendre_eval<N>(a, p.rec, q);
+    legendre_eval<N>(arg, p.rec, q);
 #pragma unroll
-    for (int k = 0; k < N; ++k) Ev[w * N + k] = q[k];
+    for (int k = 0; k < N; ++k) dst[k * stride] = q[k];
   }
   block_sync();
   r_VT_mc<N>(X1, Y1, f, lds + L::oB);
