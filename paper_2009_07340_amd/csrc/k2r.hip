@@ -473,6 +473,21 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double
   block_sync();
 }
 
+// The Wiener increments of sample s in this step (eq. def_dx), drawn only by the
+// wavefronts that use them (the node moves and the edge displacements: the
+// first max(n, 4N) threads); the others get zeros they never read.
+template <int N>
+__device__ __forceinline__ Normal2 fit_increments(const Params2D& p, int64_t s) {
+  constexpr int kUse = (N * N > 4 * N ? N * N : 4 * N);
+  double za = 0.0, zb = 0.0;
+  if (__builtin_amdgcn_readfirstlane(tid() >> 6) < (kUse + 63) / 64) {
+    const Normal2 d = normal_pair(p.seed, p.stream, (uint64_t)(p.step_ptr ? *p.step_ptr : p.step), (uint64_t)s);
+    za = d.a;
+    zb = d.b;
+  }
+  return Normal2{za, zb};
+}
+
 // G v = V^T (V v) into out (tmp: n doubles).  Two barriers.
 template <int N>
 __device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, double* out) {
@@ -501,7 +516,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
-  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)(p.step_ptr ? *p.step_ptr : p.step), (uint64_t)s);
+  const Normal2 z = fit_increments<N>(p, s);
   r_setup<N>(p, lds, e, s, z.a, z.b);
   const int t = tid();
   const double* gxi = lds + L::oGxi;
@@ -725,7 +740,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
-  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)(p.step_ptr ? *p.step_ptr : p.step), (uint64_t)s);
+  const Normal2 z = fit_increments<N>(p, s);
   r_setup<N>(p, lds, e, s, z.a, z.b);
   const int t = tid(), wv = wave();
   const int64_t eoff = p.eoff[e];
