@@ -159,7 +159,7 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_params = take(std::max(sizeof(sl::Params1D), sizeof(sl::Params2D)));
   L.o_dstep = take(sizeof(int64_t));
   L.o_ctr = take(2 * sizeof(unsigned long long));
-  L.o_stats = take(4 * sizeof(unsigned long long));
+  L.o_stats = take(4 * sl::kStatSlots * sizeof(unsigned long long));
   L.o_gxinv = take(sizeof(double) * (L.gx_doubles + 1));
   L.total = o;
   return SL_OK;
@@ -853,7 +853,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   hipError_t e2 = hipMemsetAsync(h->phi, 0, sizeof(double) * (size_t)L.M * L.nodes, h->stream);
   hipError_t e4 = L.dim == 2 ? hipMemcpyAsync(h->d_p2, &h->p2, sizeof(sl::Params2D), hipMemcpyHostToDevice, h->stream)
                              : hipMemcpyAsync(h->d_p1, &h->p1, sizeof(sl::Params1D), hipMemcpyHostToDevice, h->stream);
-  hipError_t e5 = hipMemsetAsync(h->ws + L.o_dstep, 0, L.o_stats + 4 * sizeof(unsigned long long) - L.o_dstep, h->stream);
+  hipError_t e5 = hipMemsetAsync(h->ws + L.o_dstep, 0, L.o_stats + 4 * sl::kStatSlots * sizeof(unsigned long long) - L.o_dstep, h->stream);
   hipError_t e3 = hipStreamSynchronize(h->stream);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
     if (h->own_ws) (void)hipFree(h->ws);
@@ -1236,12 +1236,16 @@ int sl_diag(sl_handle h, sl_diag_t* out) {
   out->device_bytes = h->L.total;
   out->solver = h->L.dim == 2 ? h->L.solver : 0;
   if (h->L.dim == 2) {
-    unsigned long long st[4] = {0, 0, 0, 0};
+    unsigned long long st[4 * sl::kStatSlots];
     SL_HIP(hipStreamSynchronize(h->stream));
     SL_HIP(hipMemcpy(st, h->d_stats, sizeof(st), hipMemcpyDeviceToHost));
     for (int ph = 0; ph < 2; ++ph) {
-      out->solver_iterations[ph] = (int64_t)st[2 * ph];
-      out->solver_unconverged[ph] = (int64_t)st[2 * ph + 1];
+      out->solver_iterations[ph] = 0;
+      out->solver_unconverged[ph] = 0;
+      for (int k = 0; k < sl::kStatSlots; ++k) {
+        out->solver_iterations[ph] += (int64_t)st[4 * k + 2 * ph];
+        out->solver_unconverged[ph] += (int64_t)st[4 * k + 2 * ph + 1];
+      }
     }
   }
   return SL_OK;

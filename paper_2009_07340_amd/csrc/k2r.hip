@@ -500,10 +500,13 @@ __device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, d
 
 // Solver statistics of one fit: stats[2 (phase - 1)] += iterations,
 // stats[2 (phase - 1) + 1] += 1 when the tolerance was not reached.
+// Called after the fit's last barrier: a workgroup barrier waits for the
+// memory operations in flight, atomics included.
 __device__ __forceinline__ void count_fit(const Params2D& p, int phase, int iters, bool converged) {
   if (tid() == 0 && p.stats) {
-    atomicAdd(p.stats + 2 * (phase - 1), (unsigned long long)iters);
-    if (!converged) atomicAdd(p.stats + 2 * (phase - 1) + 1, 1ull);
+    unsigned long long* c = p.stats + 4 * (blockIdx.x & (kStatSlots - 1)) + 2 * (phase - 1);
+    atomicAdd(c, (unsigned long long)iters);
+    if (!converged) atomicAdd(c + 1, 1ull);
   }
 }
 
@@ -561,7 +564,6 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
       block_sync();
     }
   }
-  count_fit(p, 1, it > p.max_iter ? p.max_iter : it, gg <= stop);
   // traces of p0 at the own edge points (eq. remap_bnd)
   double* tv = lds + L::oTr;
   double* uc = lds + L::oUc;
@@ -571,6 +573,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   block_sync();
   const int64_t eoff = p.eoff[e];
   for (int qq = t; qq < L::TT; qq += kThreads) p.tr[s * p.edges + eoff + qq] = tv[qq];
+  count_fit(p, 1, it > p.max_iter ? p.max_iter : it, gg <= stop);
 }
 
 // ---------------------------------------------------------------- phase 2
@@ -956,7 +959,6 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       block_sync();
     }
   }
-  count_fit(p, 2, it > p.max_iter ? p.max_iter : it, gg <= stop);
   // restore C_r x = g_r to working accuracy: x -= G0^-1 C_r^T S0^-1 (C_r x - g_r)
   // (after any iteration; the starting iterate satisfies it already)
   if (it > 0) {
@@ -1012,6 +1014,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     }
     p.phi[s * p.nodes + noff + i] = v;
   }
+  count_fit(p, 2, it > p.max_iter ? p.max_iter : it, gg <= stop);
 }
 
 template <int N>

@@ -6,6 +6,10 @@
 
 namespace sl {
 
+// Solver statistics are spread over this many counter slots (by workgroup) so
+// that the per-fit atomics of a launch do not all meet at one address.
+constexpr int kStatSlots = 64;
+
 constexpr int kMaxN = 16;        // largest nodes per direction supported
 constexpr int kMaxAttempts = 64; // polar-method retries before z = 0
 
@@ -72,7 +76,7 @@ struct Params2D {
   int64_t gx_off[kMaxN + 1];
   double tol2;             // stop when g^T g <= tol2 * x0^T x0 (g: preconditioned residual)
   int max_iter;
-  unsigned long long* stats;   // per phase: iterations summed over fits, fits that hit max_iter
+  unsigned long long* stats;   // [kStatSlots][2 phases][2]: iterations summed over fits, fits that hit max_iter
   LegendreRec rec;
 };
 
