@@ -132,18 +132,19 @@ struct LayR {
 // ---------------------------------------------------------------- helpers
 
 // Sum over the workgroup of a per-thread value; every thread gets the same
-// result (fixed summation order).  Contains two barriers.
+// result (fixed summation order).  One barrier: the slots in red are read
+// after it and written again only by a later sum, which the callers keep
+// behind at least one other barrier (dot products use red, the pair of
+// residual norms red + 8).
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   if (lane() == 0) red[wave()] = v;
   block_sync();
-  const double s = (red[0] + red[1]) + (red[2] + red[3]);
-  block_sync();
-  return s;
+  return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Two sums at once (one pair of barriers).
+// Two sums at once (one barrier, as above).
 __device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -157,7 +158,6 @@ __device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) 
   block_sync();
   v0 = (red[0] + red[1]) + (red[2] + red[3]);
   v1 = (red[4] + red[5]) + (red[6] + red[7]);
-  block_sync();
 }
 
 // r^T g and g^T g of the current iterate.  The stopping test uses g^T g: g is
@@ -539,7 +539,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   block_sync();
   r_G0inv<N>(gxi, r, t1, g);
   double rg, gg;
-  block_rg_gg<N>(r, g, rg, gg, red);
+  block_rg_gg<N>(r, g, rg, gg, red + 8);
   const double stop = p.tol2 * xx;
   int it = 0;
   if (gg > stop) {
@@ -556,7 +556,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
       block_sync();
       r_G0inv<N>(gxi, r, t1, g);
       double rg1;
-      block_rg_gg<N>(r, g, rg1, gg, red);
+      block_rg_gg<N>(r, g, rg1, gg, red + 8);
       if (gg <= stop) break;
       const double beta = rg1 / rg;
       rg = rg1;
@@ -933,7 +933,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* t2 = lds + L::oT2;
   for (int i = t; i < n; i += kThreads) r[i] -= t2[i];
   double rg, gg;
-  block_rg_gg<N>(r, g, rg, gg, red);
+  block_rg_gg<N>(r, g, rg, gg, red + 8);
   const double stop = p.tol2 * xx;
   int it = 0;
   if (gg > stop) {
@@ -951,7 +951,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       r_Pproj<N>(lds, U, r, nullptr, g);
       for (int i = t; i < n; i += kThreads) r[i] -= t2[i];
       double rg1;
-      block_rg_gg<N>(r, g, rg1, gg, red);
+      block_rg_gg<N>(r, g, rg1, gg, red + 8);
       if (gg <= stop) break;
       const double beta = rg1 / rg;
       rg = rg1;
