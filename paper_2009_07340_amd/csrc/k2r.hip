@@ -642,7 +642,9 @@ __device__ void r_Pproj(double* lds, const double* U, const double* rin, const d
 template <int N>
 __device__ void r_invert_S(double* Sd, double* piv) {
   using L = LayR<N>;
-  constexpr int R = L::R, TPR = kThreads / R, kE = (R + TPR - 1) / TPR;
+  // two wavefronts hold the matrix up to R = 32 (the per-step pivot solve is
+  // repeated by every wavefront that holds rows), the whole workgroup beyond
+  constexpr int R = L::R, NTH = R <= 32 ? 128 : kThreads, TPR = NTH / R, kE = (R + TPR - 1) / TPR;
   static_assert(R % 4 == 0, "R is a multiple of 4");
   const int t = tid();
   const int i = t / TPR, chunk = t - i * TPR;
