@@ -205,7 +205,8 @@ __device__ void r_V(const double* X1, const double* Y1, const double* c, double*
 // out[p] = (V^T r)_p, p = (ly, k): the N x N matrix Y1 diag(r) X1^T as one
 // 16 x 16 float64 matrix-core tile (K = n in steps of 4), by wavefront 0.
 template <int N>
-__device__ void r_VT_mc(const double* X1, const double* Y1, const double* r, double* out) {
+__device__ void r_VT_mc(const double* X1, const double* Y1, const double* r, double* out,
+                        const double* dotw = nullptr, double* dot_out = nullptr) {
   typedef Mma<double> M64;
   if (wave() != 0) return;
   constexpr int n = N * N, XS = LayR<N>::XS;
@@ -220,18 +221,29 @@ __device__ void r_VT_mc(const double* X1, const double* Y1, const double* r, dou
     const double b = ok ? r[i] * X1[lr * XS + i] : 0.0;   // B[i][k]
     acc = M64::mma(a, b, acc);
   }
+  double d = 0.0;
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
     const int ly = M64::row(l, s4);
-    if (ly < N && col) out[ly * N + lr] = acc[s4];
+    if (ly < N && col) {
+      out[ly * N + lr] = acc[s4];
+      if (dotw) d += dotw[ly * N + lr] * acc[s4];
+    }
+  }
+  if (dotw) {   // <dotw, out> from the accumulators, summed across the wavefront
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    if (l == 0) *dot_out = d;
   }
 }
 
 // out = (Gx^-1 (x) Gx^-1) v  (c indexed [ly * N + k]), or minuend - that when
-// minuend is given; tmp n doubles.  Two barriers.
+// minuend is given; tmp n doubles.  Two barriers.  With rr given, the
+// per-wavefront partial sums of rr . out and out . out are left in
+// red2[0..3] and red2[4..7] (readable after the second barrier).
 template <int N>
 __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double* out,
-                        const double* minuend = nullptr) {
+                        const double* minuend = nullptr, const double* rr = nullptr, double* red2 = nullptr) {
   for (int p = tid(); p < N * N; p += kThreads) {
     const int k = p % N, ly = p / N;
     double acc = 0.0;
@@ -240,12 +252,29 @@ __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double*
     tmp[p] = acc;
   }
   block_sync();
+  double a = 0.0, c = 0.0;
   for (int p = tid(); p < N * N; p += kThreads) {
     const int k = p % N, ly = p / N;
     double acc = 0.0;
 #pragma unroll
     for (int ll = 0; ll < N; ++ll) acc += gxi[ly * N + ll] * tmp[ll * N + k];
-    out[p] = minuend ? minuend[p] - acc : acc;
+    const double o = minuend ? minuend[p] - acc : acc;
+    out[p] = o;
+    if (rr) {
+      a += rr[p] * o;
+      c += o * o;
+    }
+  }
+  if (rr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 64);
+      c += __shfl_xor(c, o, 64);
+    }
+    if (lane() == 0) {
+      red2[wave()] = a;
+      red2[4 + wave()] = c;
+    }
   }
   block_sync();
 }
@@ -489,12 +518,13 @@ __device__ __forceinline__ Normal2 fit_increments(const Params2D& p, int64_t s) 
 }
 
 // G v = V^T (V v) into out (tmp: n doubles).  Two barriers.
+// With dot_out given, <v, G v> is left there too (readable after the return).
 template <int N>
-__device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, double* out) {
+__device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, double* out, double* dot_out = nullptr) {
   using L = LayR<N>;
   r_V<N>(lds + L::oX1, lds + L::oY1, v, tmp);
   block_sync();
-  r_VT_mc<N>(lds + L::oX1, lds + L::oY1, tmp, out);
+  r_VT_mc<N>(lds + L::oX1, lds + L::oY1, tmp, out, dot_out ? v : nullptr, dot_out);
   block_sync();
 }
 
@@ -537,26 +567,26 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   r_G<N>(lds, x, t1, r);
   for (int i = t; i < n; i += kThreads) r[i] -= b[i];
   block_sync();
-  r_G0inv<N>(gxi, r, t1, g);
-  double rg, gg;
-  block_rg_gg<N>(r, g, rg, gg, red + 8);
+  r_G0inv<N>(gxi, r, t1, g, nullptr, r, red + 8);   // with r^T g and g^T g
+  double rg = (red[8] + red[9]) + (red[10] + red[11]);
+  double gg = (red[12] + red[13]) + (red[14] + red[15]);
   const double stop = p.tol2 * xx;
   int it = 0;
   if (gg > stop) {
     for (int i = t; i < n; i += kThreads) pv[i] = -g[i];
     block_sync();
     for (it = 1; it <= p.max_iter; ++it) {
-      r_G<N>(lds, pv, t1, q);
-      const double pq = block_dot<N>(pv, q, red);
+      r_G<N>(lds, pv, t1, q, red);   // q = G pv and pv^T q
+      const double pq = red[0];
       const double alpha = rg / pq;
       for (int i = t; i < n; i += kThreads) {
         x[i] += alpha * pv[i];
         r[i] += alpha * q[i];
       }
       block_sync();
-      r_G0inv<N>(gxi, r, t1, g);
-      double rg1;
-      block_rg_gg<N>(r, g, rg1, gg, red + 8);
+      r_G0inv<N>(gxi, r, t1, g, nullptr, r, red + 8);
+      const double rg1 = (red[8] + red[9]) + (red[10] + red[11]);
+      gg = (red[12] + red[13]) + (red[14] + red[15]);
       if (gg <= stop) break;
       const double beta = rg1 / rg;
       rg = rg1;
@@ -942,8 +972,8 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     for (int i = t; i < n; i += kThreads) pv[i] = -g[i];
     block_sync();
     for (it = 1; it <= p.max_iter; ++it) {
-      r_G<N>(lds, pv, t1, q);
-      const double pq = block_dot<N>(pv, q, red);
+      r_G<N>(lds, pv, t1, q, red);   // q = G pv and pv^T q
+      const double pq = red[0];
       const double alpha = rg / pq;
       for (int i = t; i < n; i += kThreads) {
         x[i] += alpha * pv[i];
