@@ -189,13 +189,22 @@ struct Fit1DNodal {
   double tL, tR;    // traces of p0
 };
 
-// Reciprocals of the node products, four per division: 1/a = b c d / (a b c d).
+// 1 / d for a normal, nonzero d: hardware estimate refined by two Newton steps
+// (about 1 ulp; the fit is held to the oracle by a tolerance).
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
+// Reciprocals of the node products, four per reciprocal: 1/a = b c d / (a b c d).
 template <int N>
 __device__ __forceinline__ void reciprocals(const double (&p)[N], double (&w)[N]) {
 #pragma unroll
   for (int g = 0; g + 4 <= N; g += 4) {
     const double ab = p[g] * p[g + 1], cd = p[g + 2] * p[g + 3];
-    const double r = 1.0 / (ab * cd);
+    const double r = recip(ab * cd);
     const double rab = r * ab, rcd = r * cd;
     w[g] = rcd * p[g + 1];
     w[g + 1] = rcd * p[g];
@@ -205,17 +214,17 @@ __device__ __forceinline__ void reciprocals(const double (&p)[N], double (&w)[N]
   constexpr int g = N - N % 4;
   if constexpr (N % 4 == 3) {
     const double ab = p[g] * p[g + 1];
-    const double r = 1.0 / (ab * p[g + 2]);
+    const double r = recip(ab * p[g + 2]);
     const double rc = r * p[g + 2];
     w[g] = rc * p[g + 1];
     w[g + 1] = rc * p[g];
     w[g + 2] = r * ab;
   } else if constexpr (N % 4 == 2) {
-    const double r = 1.0 / (p[g] * p[g + 1]);
+    const double r = recip(p[g] * p[g + 1]);
     w[g] = r * p[g + 1];
     w[g + 1] = r * p[g];
   } else if constexpr (N % 4 == 1) {
-    w[g] = 1.0 / p[g];
+    w[g] = recip(p[g]);
   }
 }
 
@@ -258,7 +267,7 @@ template <int N>
 __device__ __forceinline__ void fit1d_nodal_post(Fit1DNodal<N>& st, const double* xi, double gL, double gR,
                                                  double (&phi)[N]) {
   const double r0 = st.tL - gL, r1 = st.tR - gR;
-  const double idet = 1.0 / (st.s00 * st.s11 - st.s01 * st.s01);
+  const double idet = recip(st.s00 * st.s11 - st.s01 * st.s01);
   const double l0 = (st.s11 * r0 - st.s01 * r1) * idet;
   const double l1 = (st.s00 * r1 - st.s01 * r0) * idet;
   // phi_i = sum_j w_j a_j prod_{m != j} (xi_i - x*_m), with the weights folded
