@@ -29,7 +29,7 @@ def fit_flops_1d(N):
     """Float64 operations of one 1-D element fit and step in the nodal form the kernel
     runs (multiply-add = 2, division = 1): moves 3N, carried values N, node products
     for the barycentric weights 1.5N(N-1) (each difference once), their reciprocals
-    2.5N (one division per four), the two edge Lagrange rows 12N - 4, traces and S 10N,
+    2.5N (one reciprocal per four), the two edge Lagrange rows 12N - 4, traces and S 10N,
     multipliers 14, corrected and weighted values 5N, evaluation at the N Gauss nodes
     5N^2 - 5N (differences, then a Horner scheme over the prefix products)."""
     return (13 * N * N + 54 * N + 20) // 2
