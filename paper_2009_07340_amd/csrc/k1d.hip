@@ -25,9 +25,16 @@ size_t resident_1d_lds_bytes(int K, int spb) { return sizeof(double) * 2 * 2 * (
 // the sample, so it is drawn once, not once per lane: every P = 256 / spb
 // steps the 256 lanes draw the increments of the next P steps of the spb
 // samples (lane l: sample slot l / P, step l % P ahead) into zbuf.
+// From order 9 to 13 the registers hold two wavefronts a SIMD and the LDS has
+// room to stage A and B of the workgroup's elements once, [i][e]
+// (lanes read consecutive words): the moves at the top of every step then wait
+// on LDS, not on the cache.
 template <int N, bool kNodal>
-__device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_tr, double* zbuf, int64_t block,
-                                                 int64_t step0, int nsteps) {
+constexpr bool resident_stages_ab() { return kNodal && N >= 9 && N <= 13; }
+
+template <int N, bool kNodal>
+__device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_tr, double* zbuf, double* abl,
+                                                 int64_t block, int64_t step0, int nsteps) {
   const int K = p.K;
   const int spb = p.samples_per_block;
   const int lane = threadIdx.x;
@@ -41,6 +48,14 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
   const double* A = p.A + e * N;
   const double* B = p.B + e * N;
   const double* src = p.src + e * N;
+  if constexpr (resident_stages_ab<N, kNodal>()) {
+    for (int x = lane; x < K * N; x += kResidentThreads) {
+      const int ex = x / N, ix = x - ex * N;
+      abl[ix * K + ex] = p.A[x];
+      abl[(N + ix) * K + ex] = p.B[x];
+    }
+    __syncthreads();
+  }
   double phi[N];
   double Af0 = 0, Af1 = 0, Bf0 = 0, Bf1 = 0, ghL = 0, ghR = 0;
   if (active) {
@@ -72,7 +87,12 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
     if (active) {
       z = zbuf[slot * P + it % P];
       if constexpr (kNodal) {
-        move_nodes<N>(p.xi, A, B, z, nod.xs);
+        if constexpr (resident_stages_ab<N, kNodal>()) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) nod.xs[i] = moved_coord(p.xi[i], abl[i * K + e], abl[(N + i) * K + e], z);
+        } else {
+          move_nodes<N>(p.xi, A, B, z, nod.xs);
+        }
 #pragma unroll
         for (int i = 0; i < N; ++i) nod.a[i] = phi[i] * src[i];
         fit1d_nodal_pre<N>(nod);
@@ -116,7 +136,8 @@ template <int N, bool kNodal>
 __global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D p) {
   extern __shared__ double lds_tr[];   // [2 buffers][spb][K][2]
   __shared__ double zbuf[kResidentThreads];
-  resident_1d_body<N, kNodal>(p, lds_tr, zbuf, blockIdx.x, p.step0, p.nsteps);
+  __shared__ double abl[resident_stages_ab<N, kNodal>() ? 2 * N * kResidentThreads : 1];
+  resident_1d_body<N, kNodal>(p, lds_tr, zbuf, abl, blockIdx.x, p.step0, p.nsteps);
 }
 
 // Several problems of one order in one launch; workgroup ranges per problem.
@@ -124,10 +145,11 @@ template <int N, bool kNodal>
 __global__ __launch_bounds__(kResidentThreads) void resident_1d_batch_kernel(Batch1DArgs a) {
   extern __shared__ double lds_tr[];
   __shared__ double zbuf[kResidentThreads];
+  __shared__ double abl[resident_stages_ab<N, kNodal>() ? 2 * N * kResidentThreads : 1];
   const int64_t b = blockIdx.x;
   int t = 0;
   while (t + 1 < a.ntasks && b >= a.bstart[t + 1]) ++t;
-  resident_1d_body<N, kNodal>(*a.task[t], lds_tr, zbuf, b - a.bstart[t], a.step0[t], a.nsteps);
+  resident_1d_body<N, kNodal>(*a.task[t], lds_tr, zbuf, abl, b - a.bstart[t], a.step0[t], a.nsteps);
 }
 
 // Tiled one-dimensional step for meshes of more than 256 elements: one launch
