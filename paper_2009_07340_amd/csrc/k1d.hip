@@ -57,7 +57,15 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
     __syncthreads();
   }
   double phi[N];
+  // orders 9-12: the source factors stay in registers across the steps (the
+  // registers still admit two wavefronts a SIMD); otherwise re-read each step
+  constexpr bool kSrcReg = kNodal && N >= 9 && N <= 12;
+  double srcv[N];
   double Af0 = 0, Af1 = 0, Bf0 = 0, Bf1 = 0, ghL = 0, ghR = 0;
+  if constexpr (kSrcReg) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) srcv[i] = active ? src[i] : 0.0;
+  }
   if (active) {
 #pragma unroll
     for (int i = 0; i < N; ++i) phi[i] = p.phi[base + i];
@@ -94,7 +102,7 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
           move_nodes<N>(p.xi, A, B, z, nod.xs);
         }
 #pragma unroll
-        for (int i = 0; i < N; ++i) nod.a[i] = phi[i] * src[i];
+        for (int i = 0; i < N; ++i) nod.a[i] = phi[i] * (kSrcReg ? srcv[i] : src[i]);
         fit1d_nodal_pre<N>(nod);
         tL = nod.tL;
         tR = nod.tR;
