@@ -119,6 +119,17 @@ def test_small_ragged_cases(B, algo):
         assert err < TOL, (K, N, M, err)
 
 
+def test_every_order_parity(B):
+    """Every order 2..16 of the resident kernel (nodal form), each with its own
+    register and LDS plan (staged step coefficients at orders 9-13, source
+    factors held in registers at 9-12): a mesh of 20 elements, 3 samples."""
+    for N in range(2, 17):
+        wl = W.c2_1d_sine()
+        wl.kx, wl.order, wl.samples, wl.dt = 20, N, 3, 2e-6
+        got, mean, ref, err = _parity(B, wl, 6, np.arange(3))
+        assert err < TOL, (N, err)
+
+
 @pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
 def test_tiled_meshes_beyond_256_elements(B, algo, bc):
     """More elements than one workgroup holds: tiles of 254 elements with a
