@@ -1,6 +1,6 @@
 """Throughput benchmark of the semi-Lagrangian Monte-Carlo step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c3|c2|c1]
                 [--precision fp64|fp32_refine|bf16split_refine] [--no-cpu-baseline]
                 [--schedule perorder|fused|perorder_graph|fused_graph|auto]
 python bench.py --serve [--serve-requests R] [--serve-rate HZ] [--serve-kmax K] [--serve-mmax M]
@@ -10,6 +10,13 @@ advected fits, trace exchange, constrained remap) over every sample of the
 workload.  The timed region holds exactly K steps with the samples resident
 in HBM; the value is Monte-Carlo node-updates per second (elements x nodes x
 samples x steps / seconds).  Prints one JSON line.
+
+The default workload is the largest one that fits one GPU: the 2-D 128 x 128
+mixed-order (N in {6, 8, 10}) solid-body rotation with 512 samples, float64.
+Before the warm-up the same handle takes a few untimed check steps; samples
+0..P-1 after them are compared with the float64 CPU oracle run over the same
+steps (``l2_vs_oracle``), and the oracle's run time gives ``cpu_baseline``
+(one host thread on one sample, and P worker processes side by side).
 """
 import argparse
 import json
@@ -116,15 +123,19 @@ def stored_traffic(wl, kname, precision):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's step count, at most 20 in 2-D)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--check-steps", type=int, default=None,
+                    help="untimed steps compared with the oracle before the warm-up (default 2 in 2-D, 20 in 1-D)")
+    ap.add_argument("--check-samples", type=int, default=None,
+                    help="samples compared with the oracle (default: one per worker process)")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--solver", default="auto", choices=["auto", "factor", "reference"],
                     help="2-D least-squares solver (auto: reference for fp64, factor for the mixed modes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--pmc-calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM counters)")
     ap.add_argument("--schedule", default="perorder", choices=list(SCHEDULES) + ["auto"],
@@ -143,17 +154,28 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
-    from paper_2009_07340_amd import binding as B
     from paper_2009_07340_amd import workloads as W
-    from paper_2009_07340_amd.problem import Problem
 
     if args.serve:
         return serve_bench(args)
     wl = W.WORKLOADS[args.workload]()
     if args.samples:
         wl.samples = args.samples
-    steps = args.steps if args.steps is not None else wl.steps
+    steps = args.steps if args.steps is not None else (min(wl.steps, 20) if wl.dim == 2 else wl.steps)
+    check_steps = args.check_steps if args.check_steps is not None else (2 if wl.dim == 2 else min(200, wl.steps))
+    workers = cpu_share()
+    per_worker = 1 if wl.dim == 2 else 8
+    check_samples = min(wl.samples, args.check_samples or workers * per_worker)
+    # The oracle leg runs first, in worker processes started before this
+    # process touches the GPU: the check samples over the check steps, and
+    # the timings of the CPU baseline.
+    oracle = None
+    if not args.no_cpu_baseline and check_steps > 0:
+        oracle = oracle_leg(args.workload, wl.samples, check_samples, check_steps, workers, per_worker)
+    # the GPU library (and torch's HIP runtime) only from here on
+    import torch
+    from paper_2009_07340_amd import binding as B
+    from paper_2009_07340_amd.problem import Problem
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -171,8 +193,21 @@ def main():
             B.sl_set_schedule(prob.h, *SCHEDULES[args.schedule], 0)
         fused = B.sl_get_schedule(prob.h)["fused"]
     solver = B.sl_diag(prob.h)["solver"]
-    print(f"[bench] {wl.name}: K={wl.K} samples={wl.samples} dt={wl.dt} warmup={args.warmup} steps={steps}",
-          file=sys.stderr, flush=True)
+    print(f"[bench] {wl.name}: K={wl.K} samples={wl.samples} dt={wl.dt} check={check_steps} warmup={args.warmup} "
+          f"steps={steps}", file=sys.stderr, flush=True)
+    l2 = None
+    if check_steps > 0:
+        prob.step(wl.dt, check_steps)             # untimed: compared with the oracle
+        got = prob.samples(0, check_samples)
+        if oracle is not None:
+            ref = oracle["ref"]
+            dif = np.abs(got - ref)
+            l2 = {"rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                  "max_abs_over_max_ref": float(dif.max() / np.abs(ref).max()),
+                  "samples": check_samples, "steps": check_steps, "tol": 1e-11}
+            l2["pass"] = bool(l2["rel_l2"] <= 1e-11 and l2["max_abs_over_max_ref"] <= 1e-11)
+            print(f"[bench] vs oracle after {check_steps} steps on {check_samples} samples: rel L2 "
+                  f"{l2['rel_l2']:.3e}, max|d|/max|ref| {l2['max_abs_over_max_ref']:.3e}", file=sys.stderr, flush=True)
     if args.warmup:
         prob.step(wl.dt, args.warmup)
     torch.cuda.synchronize()
@@ -251,9 +286,7 @@ def main():
         torch.cuda.synchronize()
         print("[bench] calibration copy: 1073741824 bytes read, 1073741824 written", file=sys.stderr, flush=True)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, args.cpu_seconds)
+    cpu = oracle["cpu_baseline"] if oracle is not None else None
     prob.close()
     out = {
         "metric": "MC node-updates/s at fixed L2 error vs FP64 oracle",
@@ -266,6 +299,7 @@ def main():
                    "element_sample_fits_per_s": wl.K * wl.samples * steps / elapsed},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "l2_vs_oracle": l2,
     }
     if wl.dim == 2:
         out["config"]["schedule"] = sched_used
@@ -311,11 +345,25 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, seconds):
-    """The FP64 oracle on the host, one thread, on a bounded sample of the same workload."""
+def cpu_share():
+    """Worker processes for the oracle leg: the host cores this process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_job(job):
+    """One worker of the oracle leg: the float64 oracle, one host thread, on the
+    given global samples of a workload for `steps` steps from its initial field.
+    Returns (samples x nodes array, seconds)."""
+    key, samples, steps = job
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import sl
+    from paper_2009_07340_amd import workloads as W
+    wl = W.WORKLOADS[key]()
     x0, x1, y0, y1 = wl.box
     mesh = sl.Mesh(dim=wl.dim, kx=wl.kx, ky=wl.ky, x0=x0, x1=x1, y0=y0, y1=y1, order=wl.order_array(), bc=wl.bc)
     ax = []
@@ -324,22 +372,49 @@ def cpu_baseline(wl, seconds):
         ax += [0, 0] if mesh.dim == 1 else [0] * (2 * N) + [1] * (2 * N)
     a = wl.sample_fields(mesh.node_coords(), mesh.edge_coords(), np.array(ax))
     f = sl.Fields(u=a["u"], D=a["D"], divu=a["divu"], un=a["un"], Dn=a["Dn"], ghost=a["ghost"])
-    ns = 8 if wl.dim == 1 else 1
-    samples = np.arange(ns)
-    phi = np.broadcast_to(a["phi0"], (ns, mesh.total_nodes)).copy()
-    done = 0
+    samples = np.asarray(samples, dtype=np.int64)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds and done < wl.steps:
-            z = sl.wiener_normals(mesh, wl.seed, done, samples)
-            phi, _ = sl.step(mesh, f, phi, wl.dt, z)
-            done += 1
+        phi = sl.run(mesh, f, a["phi0"], wl.dt, steps, wl.seed, samples)
         el = time.perf_counter() - t0
-    value = float(mesh.total_nodes) * ns * done / el
-    print(f"[bench] cpu oracle: {ns} samples x {done} steps in {el:.2f} s", file=sys.stderr, flush=True)
-    return {"value": value, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{ns} of {wl.samples} samples x first {done} of {wl.steps} steps, all {wl.K} elements "
-                      f"(samples are independent, so the rate scales to the full run)"}
+    return phi, el
+
+
+def oracle_leg(key, total_samples, check_samples, check_steps, workers, per_worker):
+    """The oracle on the host: reference values of samples 0..check_samples-1
+    after check_steps steps, and the CPU baseline.
+
+    One host thread: the first per_worker samples over one step (2-D) or the
+    check steps (1-D), alone.  `workers` threads: one process per host core,
+    each running per_worker of the check samples over the check steps at the
+    same time; the rate is all their node-updates over the wall time."""
+    import multiprocessing as mp
+    import numpy as np
+    from paper_2009_07340_amd import workloads as W
+    wl = W.WORKLOADS[key]()
+    jobs = [(key, list(range(s0, min(s0 + per_worker, check_samples))), check_steps)
+            for s0 in range(0, check_samples, per_worker)]
+    single_steps = 1 if wl.dim == 2 else check_steps
+    ctx = mp.get_context("spawn")           # fresh interpreters: nothing of this process's runtime is inherited
+    with ctx.Pool(processes=min(workers, len(jobs))) as pool:
+        _, t_single = pool.apply(_oracle_job, ((key, list(range(per_worker)), single_steps),))
+        t0 = time.perf_counter()
+        out = pool.map(_oracle_job, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+    ref = np.concatenate([o[0] for o in out], axis=0)
+    nodes = ref.shape[1]
+    single = float(nodes) * per_worker * single_steps / t_single
+    multi = float(nodes) * check_samples * check_steps / wall
+    print(f"[bench] cpu oracle: 1 thread {per_worker} samples x {single_steps} steps in {t_single:.2f} s; "
+          f"{len(jobs)} processes {check_samples} samples x {check_steps} steps in {wall:.2f} s",
+          file=sys.stderr, flush=True)
+    cpu = {"value": multi, "unit": "node-updates/s", "cores": min(workers, len(jobs)), "kind": "oracle",
+           "sample": f"samples 0..{check_samples - 1} of {total_samples} x the first {check_steps} of "
+                     f"{wl.steps} steps, all {wl.K} elements, one sample group per process (samples are "
+                     f"independent, so the rate scales to the full run)",
+           "single_thread": {"value": single, "cores": 1,
+                             "sample": f"{per_worker} sample(s) x {single_steps} step(s), one process alone"}}
+    return {"ref": ref, "cpu_baseline": cpu}
 
 
 if __name__ == "__main__":

@@ -69,14 +69,17 @@
 extern "C" {
 #endif
 
-#define SL_ABI_VERSION 1
+#define SL_ABI_VERSION 2
 
 enum sl_status {
   SL_OK = 0,
   SL_EINVAL = -1,        /* invalid argument or descriptor */
-  SL_ENOMEM = -2,        /* device or host allocation failed, or workspace too small */
+  SL_ENOMEM = -2,        /* device or host allocation failed, or workspace too small (tests can
+                            force it: environment SL_FAULT=alloc fails every device allocation
+                            of the library, SL_FAULT=host the handle's host allocation; a call
+                            that fails this way leaves nothing allocated behind) */
   SL_EDEVICE = -3,       /* a HIP runtime call failed; the handle should be destroyed */
-  SL_ENONFINITE = -4,    /* non-finite input values */
+  SL_ENONFINITE = -4,    /* non-finite input values, or non-finite samples met by sl_mean */
   SL_ESTATE = -5,        /* call out of order (e.g. step before fields were set) */
   SL_EUNSUPPORTED = -6   /* valid request this build does not implement */
 };
@@ -139,6 +142,18 @@ typedef struct sl_diag_t {
   int32_t solver;             /* SL_SOLVER_FACTOR or SL_SOLVER_REFERENCE (2-D) */
   int64_t solver_iterations[2];   /* reference solver, per phase: iterations summed over all fits so far */
   int64_t solver_unconverged[2];  /* reference solver, per phase: fits that stopped at max_iter */
+  int64_t escapes;            /* moved nodes (per sample, step, node and direction) whose reference
+                                 coordinate left [0, 1] since the handle was created: the step
+                                 restriction of Sec. 5.2 (eq. 1d_timestep) keeps particles inside
+                                 their element; the library allows the move (the interpolant is
+                                 extrapolated, never clamped) and counts it here */
+  double max_residual;        /* largest relative residual a fit's solver left since the handle was
+                                 created: reference solver sqrt(g^T g / x0^T x0) at its stop (g the
+                                 preconditioned residual, the quantity its tolerance bounds);
+                                 factorisation solver in the mixed modes the relative size of the
+                                 last float64 refinement correction, max|dc| / max|c|; 0 where
+                                 neither applies (1-D, float64 factorisation); NaN if a fit met one */
+  int64_t nonfinite;          /* non-finite sample values met by the last sl_mean (0: all finite) */
 } sl_diag_t;
 
 /* Device bytes sl_init_mesh needs for this description (state, traces, fields,
@@ -231,7 +246,12 @@ int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_p
 
 /* Sample mean at every node (eq. averaged): out[nodes].  out_is_device != 0:
  * out is a device pointer and the call is asynchronous on the handle's
- * stream; otherwise out is host memory and the call waits. */
+ * stream (the count of non-finite samples it met is in sl_diag().nonfinite
+ * afterwards); otherwise out is host memory, the call waits and returns
+ * SL_ENONFINITE (with out written) when any sample value was not finite.
+ * The sum runs in a fixed order (samples in chunks whose count depends only
+ * on the sizes, the chunks added in order), so repeated calls agree bit for
+ * bit.  Uses partial sums in the handle's workspace. */
 int sl_mean(sl_handle h, double* out, int32_t out_is_device);
 
 /* Copy ns samples starting at s0 ([ns][nodes]) out of / into the handle (for

@@ -49,6 +49,22 @@ struct PendingEvent {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+size_t stats_bytes() { return sizeof(unsigned long long) * sl::kStatSlots * sl::kStatStride; }
+
+// Allocation-failure injection for tests: SL_FAULT=alloc makes every device
+// allocation of the library fail (SL_ENOMEM), SL_FAULT=host the host allocation
+// of a handle's context.  Read at each allocation.
+bool fault_is(const char* what) {
+  const char* f = std::getenv("SL_FAULT");
+  return f && std::strcmp(f, what) == 0;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (fault_is("alloc")) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
 // Sizes derived from a descriptor (shared by sl_required_bytes and sl_init_mesh).
 struct Layout {
   int dim = 1, kx = 1, ky = 1, K = 1;
@@ -62,7 +78,7 @@ struct Layout {
   // byte offsets in the workspace
   size_t o_phi, o_phi2, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
-  size_t o_params, o_dstep, o_ctr, o_stats, o_gxinv, total;
+  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, total;
   int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
   size_t gx_doubles = 0;
   int max_iter = 32;
@@ -159,7 +175,12 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_params = take(std::max(sizeof(sl::Params1D), sizeof(sl::Params2D)));
   L.o_dstep = take(sizeof(int64_t));
   L.o_ctr = take(2 * sizeof(unsigned long long));
-  L.o_stats = take(4 * sl::kStatSlots * sizeof(unsigned long long));
+  L.o_nonf = take(sizeof(unsigned long long));
+  L.o_stats = take(stats_bytes());
+  {
+    const int64_t C = sl::mean_chunks(L.M, L.nodes);     // partial sums of the sample mean
+    L.o_mpart = take(C > 1 ? sizeof(double) * (size_t)C * L.nodes : 0);
+  }
   L.o_gxinv = take(sizeof(double) * (L.gx_doubles + 1));
   L.total = o;
   return SL_OK;
@@ -203,7 +224,9 @@ struct sl_ctx {
   sl::Params2D* d_p2 = nullptr;
   int64_t* d_step = nullptr;             // device step counter (fused / graph schedules)
   unsigned long long* d_ctr = nullptr;   // work counters of the two phases
-  unsigned long long* d_stats = nullptr; // reference solver statistics
+  unsigned long long* d_stats = nullptr; // diagnostics slots (solver statistics, escapes, residuals)
+  unsigned long long* d_nonf = nullptr;  // non-finite values seen by the last sample mean
+  double* d_mpart = nullptr;             // partial sums of the sample mean
   double* d_gxinv = nullptr;
   hipStream_t cap_stream = nullptr;      // private stream for graph capture
   // measurement
@@ -376,6 +399,7 @@ void build_params(sl_ctx* h) {
     p.step0 = 0;
     p.seed = h->desc.seed;
     p.stream = h->desc.stream_id;
+    p.stats = h->d_stats;
     p.rec = h->rec;
     const auto& xi = h->xi_tab[L.order[0]];
     for (size_t i = 0; i < xi.size(); ++i) p.xi[i] = xi[i];
@@ -700,7 +724,7 @@ int sl_required_bytes(const sl_mesh_desc* desc, size_t* bytes) {
 int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* hip_stream, sl_handle* out) {
   if (!out) return fail(SL_EINVAL, "null output handle");
   *out = nullptr;
-  std::unique_ptr<sl_ctx> h(new (std::nothrow) sl_ctx());
+  std::unique_ptr<sl_ctx> h(fault_is("host") ? nullptr : new (std::nothrow) sl_ctx());
   if (!h) return fail(SL_ENOMEM, "host allocation failed");
   int rc = make_layout(desc, h->L);
   if (rc) return rc;
@@ -725,7 +749,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
     h->ws = (char*)dev_ws;
   } else {
     void* p = nullptr;
-    if (hipMalloc(&p, L.total) != hipSuccess) return fail(SL_ENOMEM, "hipMalloc of the workspace failed");
+    if (dev_malloc(&p, L.total) != hipSuccess) return fail(SL_ENOMEM, "hipMalloc of the workspace failed");
     h->ws = (char*)p;
     h->own_ws = true;
   }
@@ -756,6 +780,8 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_step = (int64_t*)(h->ws + L.o_dstep);
   h->d_ctr = (unsigned long long*)(h->ws + L.o_ctr);
   h->d_stats = (unsigned long long*)(h->ws + L.o_stats);
+  h->d_nonf = (unsigned long long*)(h->ws + L.o_nonf);
+  h->d_mpart = (double*)(h->ws + L.o_mpart);
   h->d_gxinv = (double*)(h->ws + L.o_gxinv);
   // element tables, work list grouped by order, node tables, U_r and trace interpolation
   std::vector<int32_t> nbr(4 * (size_t)L.K, -1), work;
@@ -853,7 +879,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   hipError_t e2 = hipMemsetAsync(h->phi, 0, sizeof(double) * (size_t)L.M * L.nodes, h->stream);
   hipError_t e4 = L.dim == 2 ? hipMemcpyAsync(h->d_p2, &h->p2, sizeof(sl::Params2D), hipMemcpyHostToDevice, h->stream)
                              : hipMemcpyAsync(h->d_p1, &h->p1, sizeof(sl::Params1D), hipMemcpyHostToDevice, h->stream);
-  hipError_t e5 = hipMemsetAsync(h->ws + L.o_dstep, 0, L.o_stats + 4 * sl::kStatSlots * sizeof(unsigned long long) - L.o_dstep, h->stream);
+  hipError_t e5 = hipMemsetAsync(h->ws + L.o_dstep, 0, L.o_stats + stats_bytes() - L.o_dstep, h->stream);
   hipError_t e3 = hipStreamSynchronize(h->stream);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess) {
     if (h->own_ws) (void)hipFree(h->ws);
@@ -1054,7 +1080,7 @@ int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_p
   // keep the samples and the step counter; trial steps advance both
   const size_t bytes = sizeof(double) * (size_t)L.M * L.nodes;
   void* snap = nullptr;
-  if (hipMalloc(&snap, bytes) != hipSuccess) return fail(SL_ENOMEM, "no device memory for the autotuner's copy of the samples");
+  if (dev_malloc(&snap, bytes) != hipSuccess) return fail(SL_ENOMEM, "no device memory for the autotuner's copy of the samples");
   const int64_t step0 = h->step;
   const sl_schedule_t keep = h->sched;
   const bool prof = h->profile;
@@ -1128,11 +1154,14 @@ int sl_mean(sl_handle h, double* out, int32_t out_is_device) {
   double* dst = out_is_device ? out : h->mean;
   {
     ProfScope ps(h, "mean");
-    SL_HIP(sl::launch_mean(h->phi, dst, L.M, L.nodes, h->stream));
+    SL_HIP(sl::launch_mean(h->phi, dst, h->d_mpart, L.M, L.nodes, h->d_nonf, h->stream));
   }
   if (!out_is_device) {
+    unsigned long long bad = 0;
     SL_HIP(hipMemcpyAsync(out, h->mean, sizeof(double) * L.nodes, hipMemcpyDeviceToHost, h->stream));
+    SL_HIP(hipMemcpyAsync(&bad, h->d_nonf, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
     SL_HIP(hipStreamSynchronize(h->stream));
+    if (bad) return fail(SL_ENONFINITE, std::to_string(bad) + " non-finite sample values at the nodes");
   }
   return SL_OK;
 }
@@ -1176,7 +1205,7 @@ int sl_debug_normals(sl_handle h, int64_t n, int64_t s0, int64_t ns, double* out
   if (!out || ns < 0 || s0 < 0 || n < 0) return fail(SL_EINVAL, "bad arguments");
   if (ns == 0) return SL_OK;
   double* d = nullptr;
-  SL_HIP(hipMalloc(&d, sizeof(double) * 2 * ns));
+  if (dev_malloc((void**)&d, sizeof(double) * 2 * ns) != hipSuccess) return fail(SL_ENOMEM, "no device memory for the normals");
   hipError_t e = sl::launch_debug_normals(d, h->desc.seed, h->desc.stream_id, n, s0, ns, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(out, d, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -1193,7 +1222,7 @@ int sl_debug_positions(sl_handle h, double dt, double* out) {
   const Layout& L = h->L;
   const size_t n = (size_t)L.M * L.nodes * L.dim;
   double* d = nullptr;
-  SL_HIP(hipMalloc(&d, sizeof(double) * n));
+  if (dev_malloc((void**)&d, sizeof(double) * n) != hipSuccess) return fail(SL_ENOMEM, "no device memory for the positions");
   hipError_t e = sl::launch_debug_positions(d, h->xi_node, h->A, h->B, L.dim, L.nodes, L.M, h->desc.seed,
                                             h->desc.stream_id, h->step, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(out, d, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream);
@@ -1235,19 +1264,23 @@ int sl_diag(sl_handle h, sl_diag_t* out) {
                       : (h->desc.precision == SL_PREC_FP32_REFINE ? 2 : h->desc.precision == SL_PREC_BF16SPLIT_REFINE ? 3 : 0);
   out->device_bytes = h->L.total;
   out->solver = h->L.dim == 2 ? h->L.solver : 0;
-  if (h->L.dim == 2) {
-    unsigned long long st[4 * sl::kStatSlots];
-    SL_HIP(hipStreamSynchronize(h->stream));
-    SL_HIP(hipMemcpy(st, h->d_stats, sizeof(st), hipMemcpyDeviceToHost));
+  std::vector<unsigned long long> st(sl::kStatSlots * sl::kStatStride);
+  unsigned long long nonf = 0;
+  SL_HIP(hipStreamSynchronize(h->stream));
+  SL_HIP(hipMemcpy(st.data(), h->d_stats, stats_bytes(), hipMemcpyDeviceToHost));
+  SL_HIP(hipMemcpy(&nonf, h->d_nonf, sizeof(nonf), hipMemcpyDeviceToHost));
+  unsigned long long rmax = 0;
+  for (int k = 0; k < sl::kStatSlots; ++k) {
+    const unsigned long long* c = st.data() + (size_t)k * sl::kStatStride;
     for (int ph = 0; ph < 2; ++ph) {
-      out->solver_iterations[ph] = 0;
-      out->solver_unconverged[ph] = 0;
-      for (int k = 0; k < sl::kStatSlots; ++k) {
-        out->solver_iterations[ph] += (int64_t)st[4 * k + 2 * ph];
-        out->solver_unconverged[ph] += (int64_t)st[4 * k + 2 * ph + 1];
-      }
+      out->solver_iterations[ph] += (int64_t)c[2 * ph];
+      out->solver_unconverged[ph] += (int64_t)c[2 * ph + 1];
     }
+    out->escapes += (int64_t)c[sl::kStatEscapes];
+    rmax = std::max(rmax, c[sl::kStatResidual]);
   }
+  std::memcpy(&out->max_residual, &rmax, sizeof(double));
+  out->nonfinite = (int64_t)nonf;
   return SL_OK;
 }
 

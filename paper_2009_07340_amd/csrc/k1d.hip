@@ -80,6 +80,7 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
   }
   const int stride = spb * K * 2;
   const int P = kResidentThreads / spb;
+  int esc = 0;   // moved nodes outside [0, 1] over the launch (diagnostics)
   for (int it = 0; it < nsteps; ++it) {
     double* tr = lds_tr + (it & 1) * stride;
     Fit1DPre<N> pre;          // normal-equation form
@@ -102,7 +103,10 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
           move_nodes<N>(p.xi, A, B, z, nod.xs);
         }
 #pragma unroll
-        for (int i = 0; i < N; ++i) nod.a[i] = phi[i] * (kSrcReg ? srcv[i] : src[i]);
+        for (int i = 0; i < N; ++i) {
+          nod.a[i] = phi[i] * (kSrcReg ? srcv[i] : src[i]);
+          esc += escaped(nod.xs[i]);
+        }
         fit1d_nodal_pre<N>(nod);
         tL = nod.tL;
         tR = nod.tR;
@@ -110,7 +114,10 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
         double xs[N], f[N];
         move_nodes<N>(p.xi, A, B, z, xs);
 #pragma unroll
-        for (int i = 0; i < N; ++i) f[i] = phi[i] * src[i];
+        for (int i = 0; i < N; ++i) {
+          f[i] = phi[i] * src[i];
+          esc += escaped(xs[i]);
+        }
         fit1d_pre<N>(xs, f, p.xi, p.rec, pre);
         tL = pre.tL;
         tR = pre.tR;
@@ -138,6 +145,9 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
 #pragma unroll
     for (int i = 0; i < N; ++i) p.phi[base + i] = phi[i];
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) esc += __shfl_xor(esc, o, 64);
+  if ((lane & 63) == 0) stat_add(p.stats, kStatEscapes, (unsigned long long)esc);
 }
 
 template <int N, bool kNodal>
@@ -193,6 +203,7 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
   Fit1DNodal<N> nod;
   Fit1DPre<N> pre;
   double tL = 0.0, tR = 0.0;
+  int esc = 0;
   if (live) {
     const double* A = p.A + e * N;
     const double* B = p.B + e * N;
@@ -201,7 +212,10 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
     if constexpr (kNodal) {
       move_nodes<N>(p.xi, A, B, z, nod.xs);
 #pragma unroll
-      for (int i = 0; i < N; ++i) nod.a[i] = ph[i] * src[i];
+      for (int i = 0; i < N; ++i) {
+        nod.a[i] = ph[i] * src[i];
+        esc += owned ? escaped(nod.xs[i]) : 0;
+      }
       fit1d_nodal_pre<N>(nod);
       tL = nod.tL;
       tR = nod.tR;
@@ -209,12 +223,18 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
       double xs[N], f[N];
       move_nodes<N>(p.xi, A, B, z, xs);
 #pragma unroll
-      for (int i = 0; i < N; ++i) f[i] = ph[i] * src[i];
+      for (int i = 0; i < N; ++i) {
+        f[i] = ph[i] * src[i];
+        esc += owned ? escaped(xs[i]) : 0;
+      }
       fit1d_pre<N>(xs, f, p.xi, p.rec, pre);
       tL = pre.tL;
       tR = pre.tR;
     }
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) esc += __shfl_xor(esc, o, 64);
+  if ((lane & 63) == 0) stat_add(p.stats, kStatEscapes, (unsigned long long)esc);
   trL[lane] = tL;
   trR[lane] = tR;
   __syncthreads();

@@ -76,7 +76,7 @@ struct Lay {
   static constexpr int dXs = dR2 + RP;
   static constexpr int dYs = dXs + n;
   static constexpr int dRed = dYs + n;
-  static constexpr int dEnd = dRed + 8;
+  static constexpr int dEnd = dRed + 16;
   static constexpr size_t oTab = a16(oD + sizeof(double) * dEnd);          // X1, Y1 (float64)
   static constexpr size_t tabBytes = sizeof(double) * 2 * n * N;
   static constexpr size_t yBytes = sizeof(double) * NB * RB * BLK;       // Y, S are float64 in every mode
@@ -240,8 +240,8 @@ __device__ void s_solve(const Ctx<N, MODE>& x, double* v) {
 // Moved nodes, carried values, centred basis tables, b = V^T f, Gram on the
 // matrix cores, Cholesky, c0 (refined in the mixed modes).
 template <int N, int MODE>
-__device__ void setup_and_factor(const Params2D& p, const Ctx<N, MODE>& x, int e, int64_t s, double za,
-                                 double zb) {
+__device__ int setup_and_factor(const Params2D& p, const Ctx<N, MODE>& x, int e, int64_t s, double za,
+                                double zb) {
   using L = Lay<N, MODE>;
   using T = typename L::T;
   constexpr int n = L::n, NB = L::NB;
@@ -252,6 +252,7 @@ __device__ void setup_and_factor(const Params2D& p, const Ctx<N, MODE>& x, int e
   double* f = x.d(L::dF);
   double* red = x.d(L::dRed);
   double sx = 0.0, sy = 0.0;
+  int esc = 0;
   for (int i = t; i < L::NP; i += kThreads) {
     if (i < n) {
       const int64_t k = noff + i;
@@ -263,6 +264,7 @@ __device__ void setup_and_factor(const Params2D& p, const Ctx<N, MODE>& x, int e
       f[i] = p.phi[s * p.nodes + k] * p.src[k];
       sx += xm - x0;
       sy += ym - y0;
+      esc += escaped(xm) + escaped(ym);
     } else {
       f[i] = 0.0;
     }
@@ -271,14 +273,17 @@ __device__ void setup_and_factor(const Params2D& p, const Ctx<N, MODE>& x, int e
   for (int o = 32; o > 0; o >>= 1) {
     sx += __shfl_xor(sx, o, 64);
     sy += __shfl_xor(sy, o, 64);
+    esc += __shfl_xor(esc, o, 64);
   }
   if (lane() == 0) {
     red[wave()] = sx;
     red[4 + wave()] = sy;
+    red[8 + wave()] = (double)esc;
   }
   block_sync();
   const double dbx = (red[0] + red[1] + red[2] + red[3]) / n;
   const double dby = (red[4] + red[5] + red[6] + red[7]) / n;
+  const int escapes = (int)((red[8] + red[9]) + (red[10] + red[11]));
   double* X1 = x.X1();
   double* Y1 = x.Y1();
   for (int i = t; i < n; i += kThreads) {
@@ -379,6 +384,7 @@ __device__ void setup_and_factor(const Params2D& p, const Ctx<N, MODE>& x, int e
       block_sync();
     }
   }
+  return escapes;
 }
 
 __device__ __forceinline__ void fit_index(const Params2D& p, int64_t b, int& e, int64_t& s) {
@@ -397,12 +403,13 @@ __device__ __forceinline__ void phase1_body(const Params2D& p, char* lds_raw, in
   int64_t s;
   fit_index(p, fit, e, s);
   const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)step_counter(p), (uint64_t)s);
-  setup_and_factor<N, MODE>(p, x, e, s, z.a, z.b);
+  const int escapes = setup_and_factor<N, MODE>(p, x, e, s, z.a, z.b);
   double* tv = x.d(L::dT);
   op_C<N, MODE>(x, x.d(L::dC), tv);
   block_sync();
   const int64_t eoff = p.eoff[e];
   for (int q = tid(); q < L::TT; q += kThreads) p.tr[s * p.edges + eoff + q] = tv[q];
+  if (tid() == 0) stat_add(p.stats, kStatEscapes, (unsigned long long)escapes);
 }
 
 template <int N, int MODE>
@@ -599,8 +606,33 @@ __device__ __forceinline__ void phase2_body(const Params2D& p, char* lds_raw, in
       op_CT<N, MODE>(x, e2, v);               // C_r^T dlambda
       block_sync();
       g_solve<N, MODE>(x, v);
-      for (int i = t; i < L::NP; i += kThreads) c[i] += wv[i] - v[i];
+      double dmax = 0.0, cmax = 0.0;
+      for (int i = t; i < L::NP; i += kThreads) {
+        const double d = wv[i] - v[i];
+        c[i] += d;
+        dmax = fmax(dmax, fabs(d));
+        cmax = fmax(cmax, fabs(c[i]));
+      }
       for (int i = t; i < L::RP; i += kThreads) lam[i] += dl[i];
+      if (it == p.refine - 1) {
+        // the relative size of the last correction, max |dc| / max |c|, for the diagnostics
+        double* red = x.d(L::dRed);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+          cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
+        }
+        if (l == 0) {
+          red[8 + w] = dmax;
+          red[12 + w] = cmax;
+        }
+        block_sync();
+        if (t == 0) {
+          const double dm = fmax(fmax(red[8], red[9]), fmax(red[10], red[11]));
+          const double cm = fmax(fmax(red[12], red[13]), fmax(red[14], red[15]));
+          stat_residual(p.stats, cm > 0.0 ? dm / cm : (dm > 0.0 ? __builtin_inf() : 0.0));
+        }
+      }
       block_sync();
     }
   }

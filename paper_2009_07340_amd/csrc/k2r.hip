@@ -431,7 +431,7 @@ __device__ void r_outer_edges(const double* Ev, const double* yv, double* out) {
 // Moves (eq. def_dx), carried values (eq. advection_phi), centred 1-D tables,
 // b = V^T f; returns the mean displacement (dbx, dby) in registers.
 template <int N>
-__device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double za, double zb) {
+__device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double za, double zb) {
   using L = LayR<N>;
   constexpr int n = L::n;
   const int t = tid();
@@ -441,6 +441,7 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double
   double* f = lds + L::oF;
   double* red = lds + L::oRed;
   double sx = 0.0, sy = 0.0;
+  int esc = 0;
   for (int i = t; i < n; i += kThreads) {
     const int64_t k = noff + i;
     const double x0 = p.xi_node[2 * k], y0 = p.xi_node[2 * k + 1];
@@ -451,6 +452,7 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double
     f[i] = p.phi[s * p.nodes + k] * p.src[k];
     sx += xm - x0;
     sy += ym - y0;
+    esc += escaped(xm) + escaped(ym);
   }
   const double* gsrc = p.gxinv + p.gx_off[N];
   double* gxi = lds + L::oGxi;
@@ -459,14 +461,17 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double
   for (int o = 32; o > 0; o >>= 1) {
     sx += __shfl_xor(sx, o, 64);
     sy += __shfl_xor(sy, o, 64);
+    esc += __shfl_xor(esc, o, 64);
   }
   if (lane() == 0) {
     red[wave()] = sx;
     red[4 + wave()] = sy;
+    red[8 + wave()] = (double)esc;
   }
   block_sync();
   const double dbx = (red[0] + red[1] + red[2] + red[3]) / n;
   const double dby = (red[4] + red[5] + red[6] + red[7]) / n;
+  const int escapes = (int)((red[8] + red[9]) + (red[10] + red[11]));
   double* X1 = lds + L::oX1;
   double* Y1 = lds + L::oY1;
   double* Bx = lds + L::oBx;
@@ -500,6 +505,7 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, double
   block_sync();
   r_VT_mc<N>(X1, Y1, f, lds + L::oB);
   block_sync();
+  return escapes;
 }
 
 // The Wiener increments of sample s in this step (eq. def_dx), drawn only by the
@@ -528,15 +534,19 @@ __device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, d
   block_sync();
 }
 
-// Solver statistics of one fit: stats[2 (phase - 1)] += iterations,
-// stats[2 (phase - 1) + 1] += 1 when the tolerance was not reached.
-// Called after the fit's last barrier: a workgroup barrier waits for the
-// memory operations in flight, atomics included.
-__device__ __forceinline__ void count_fit(const Params2D& p, int phase, int iters, bool converged) {
+// Diagnostics of one fit: iterations and whether the tolerance was reached
+// (per phase), moved nodes outside the element (phase 1 counts the moves) and
+// the relative residual left, sqrt(g^T g / x0^T x0).  Called after the fit's
+// last barrier: a workgroup barrier waits for the memory operations in flight,
+// atomics included.
+__device__ __forceinline__ void count_fit(const Params2D& p, int phase, int iters, bool converged, int escapes,
+                                          double gg, double xx) {
   if (tid() == 0 && p.stats) {
-    unsigned long long* c = p.stats + 4 * (blockIdx.x & (kStatSlots - 1)) + 2 * (phase - 1);
+    unsigned long long* c = stat_slot(p.stats) + 2 * (phase - 1);
     atomicAdd(c, (unsigned long long)iters);
     if (!converged) atomicAdd(c + 1, 1ull);
+    stat_add(p.stats, kStatEscapes, (unsigned long long)escapes);
+    stat_residual(p.stats, xx > 0.0 ? sqrt(gg / xx) : (gg > 0.0 ? __builtin_inf() : 0.0));
   }
 }
 
@@ -550,7 +560,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
   const Normal2 z = fit_increments<N>(p, s);
-  r_setup<N>(p, lds, e, s, z.a, z.b);
+  const int escapes = r_setup<N>(p, lds, e, s, z.a, z.b);
   const int t = tid();
   const double* gxi = lds + L::oGxi;
   double* b = lds + L::oB;
@@ -603,7 +613,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   block_sync();
   const int64_t eoff = p.eoff[e];
   for (int qq = t; qq < L::TT; qq += kThreads) p.tr[s * p.edges + eoff + qq] = tv[qq];
-  count_fit(p, 1, it > p.max_iter ? p.max_iter : it, gg <= stop);
+  count_fit(p, 1, it > p.max_iter ? p.max_iter : it, gg <= stop, escapes, gg, xx);
 }
 
 // ---------------------------------------------------------------- phase 2
@@ -1046,7 +1056,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     }
     p.phi[s * p.nodes + noff + i] = v;
   }
-  count_fit(p, 2, it > p.max_iter ? p.max_iter : it, gg <= stop);
+  count_fit(p, 2, it > p.max_iter ? p.max_iter : it, gg <= stop, 0, gg, xx);
 }
 
 template <int N>

@@ -4,39 +4,84 @@
 
 namespace sl {
 
-// Mean over samples at every node (eq. averaged).  A 256-lane workgroup owns
-// 64 consecutive nodes; its 4 wavefronts sum the samples s = w, w+4, ... in
-// order (coalesced 512-byte rows per wavefront), then wavefront 0 adds the
-// four partial sums in fixed order and divides by M.  The result does not
-// depend on the launch, so repeated calls are bitwise identical.
-constexpr int kMeanNodes = 64;
-constexpr int kMeanWaves = 4;
+// Mean over samples at every node (eq. averaged), in two passes with a fixed
+// summation order.  Pass 1: workgroup (x, c) takes 256 consecutive nodes and
+// the samples of chunk c, [c*chunk, min(M, (c+1)*chunk)), and sums them in
+// sample order, one node a lane (coalesced rows).  With one chunk it writes the
+// mean directly; otherwise it writes the partial sum to part[c][node] and pass
+// 2 adds the chunks in order and divides by M.  The chunk count depends only
+// on (M, nodes) (mean_chunks), so every call with the same sizes, whichever
+// entry point makes it and wherever its partial sums live, gives bitwise the
+// same result.  Pass 1 also counts the non-finite values it reads.
+constexpr int kMeanThreads = 256;
 
-__global__ __launch_bounds__(kMeanNodes * kMeanWaves) void mean_kernel(const double* __restrict__ phi,
-                                                                       double* __restrict__ out, int64_t M,
-                                                                       int64_t nodes) {
-  __shared__ double part[kMeanWaves][kMeanNodes];
-  const int l = threadIdx.x % kMeanNodes;
-  const int w = threadIdx.x / kMeanNodes;
-  const int64_t node = (int64_t)blockIdx.x * kMeanNodes + l;
+int64_t mean_chunks(int64_t M, int64_t nodes) {
+  if (M < 1 || nodes < 1) return 1;
+  const int64_t tiles = (nodes + kMeanThreads - 1) / kMeanThreads;
+  int64_t C = (2048 + tiles - 1) / tiles;          // about 8 workgroups a compute unit
+  C = C < M / 32 ? C : M / 32;                     // at least 32 samples a chunk (partials <= 1/32 of the state)
+  const int64_t cap = kMeanScratchDoubles / nodes; // partial sums must fit the scratch bound
+  C = C < cap ? C : cap;
+  if (C < 1) C = 1;
+  const int64_t chunk = (M + C - 1) / C;
+  return (M + chunk - 1) / chunk;
+}
+
+__global__ __launch_bounds__(kMeanThreads) void mean_pass1(const double* __restrict__ phi, double* __restrict__ dst,
+                                                           int64_t M, int64_t nodes, int64_t chunk, int direct,
+                                                           unsigned long long* nonfinite) {
+  const int64_t node = (int64_t)blockIdx.x * kMeanThreads + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  const int64_t s0 = c * chunk;
+  const int64_t s1 = (s0 + chunk) < M ? (s0 + chunk) : M;
   double acc = 0.0;
+  int bad = 0;
   if (node < nodes) {
-    for (int64_t s = w; s < M; s += kMeanWaves) acc += phi[s * nodes + node];
+#pragma unroll 8
+    for (int64_t s = s0; s < s1; ++s) {
+      const double v = phi[s * nodes + node];
+      acc += v;
+      bad += __builtin_isfinite(v) ? 0 : 1;
+    }
+    if (direct) dst[node] = acc / (double)M;
+    else dst[c * nodes + node] = acc;
   }
-  part[w][l] = acc;
-  __syncthreads();
-  if (w == 0 && node < nodes) {
-    double t = part[0][l];
+  if (nonfinite) {
 #pragma unroll
-    for (int k = 1; k < kMeanWaves; ++k) t += part[k][l];
-    out[node] = t / (double)M;
+    for (int o = 32; o > 0; o >>= 1) bad += __shfl_xor(bad, o, 64);
+    if ((threadIdx.x & 63) == 0 && bad > 0) atomicAdd(nonfinite, (unsigned long long)bad);
   }
 }
 
-hipError_t launch_mean(const double* phi, double* out, int64_t M, int64_t nodes, hipStream_t st) {
-  const int64_t blocks = (nodes + kMeanNodes - 1) / kMeanNodes;
-  hipLaunchKernelGGL(mean_kernel, dim3((unsigned)blocks), dim3(kMeanNodes * kMeanWaves), 0, st, phi, out, M,
-                     nodes);
+__global__ __launch_bounds__(kMeanThreads) void mean_pass2(const double* __restrict__ part, double* __restrict__ out,
+                                                           int64_t M, int64_t nodes, int64_t C) {
+  const int64_t node = (int64_t)blockIdx.x * kMeanThreads + threadIdx.x;
+  if (node >= nodes) return;
+  double acc = part[node];
+  for (int64_t c = 1; c < C; ++c) acc += part[c * nodes + node];
+  out[node] = acc / (double)M;
+}
+
+__global__ void clear_u64_kernel(unsigned long long* p) { *p = 0ull; }
+
+hipError_t launch_mean(const double* phi, double* out, double* part, int64_t M, int64_t nodes,
+                       unsigned long long* nonfinite, hipStream_t st) {
+  if (M < 1 || nodes < 1) return hipErrorInvalidValue;
+  const int64_t C = mean_chunks(M, nodes);
+  if (C > 1 && !part) return hipErrorInvalidValue;
+  const int64_t chunk = (M + C - 1) / C;
+  const int64_t tiles = (nodes + kMeanThreads - 1) / kMeanThreads;
+  if (tiles > 0x7fffffff || C > 65535) return hipErrorInvalidValue;
+  if (nonfinite) {
+    hipLaunchKernelGGL(clear_u64_kernel, dim3(1), dim3(1), 0, st, nonfinite);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(mean_pass1, dim3((unsigned)tiles, (unsigned)C), dim3(kMeanThreads), 0, st, phi,
+                     C > 1 ? part : out, M, nodes, chunk, C > 1 ? 0 : 1, nonfinite);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || C == 1) return e;
+  hipLaunchKernelGGL(mean_pass2, dim3((unsigned)tiles), dim3(kMeanThreads), 0, st, part, out, M, nodes, C);
   return hipGetLastError();
 }
 

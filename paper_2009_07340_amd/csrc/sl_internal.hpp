@@ -6,9 +6,34 @@
 
 namespace sl {
 
-// Solver statistics are spread over this many counter slots (by workgroup) so
-// that the per-fit atomics of a launch do not all meet at one address.
+// Per-handle diagnostics are spread over this many counter slots (by
+// workgroup) so that the per-fit atomics of a launch do not all meet at one
+// address.  Slot layout (kStatStride words):
+//   [0], [1] phase 1: solver iterations summed over fits, fits that hit max_iter
+//   [2], [3] phase 2: the same
+//   [4] moved nodes that left their element's reference interval [0, 1]
+//   [5] largest relative solver residual left by a fit (bits of a non-negative
+//       double, so unsigned comparison orders them; NaN sorts above every value)
 constexpr int kStatSlots = 64;
+constexpr int kStatStride = 8;
+constexpr int kStatEscapes = 4;
+constexpr int kStatResidual = 5;
+
+#if defined(__HIPCC__)
+__device__ __forceinline__ unsigned long long* stat_slot(unsigned long long* stats) {
+  return stats + kStatStride * (blockIdx.x & (kStatSlots - 1));
+}
+// Add v to counter idx of this workgroup's slot (nothing when v is 0).
+__device__ __forceinline__ void stat_add(unsigned long long* stats, int idx, unsigned long long v) {
+  if (stats && v) atomicAdd(stat_slot(stats) + idx, v);
+}
+// Raise the recorded largest residual to r (r >= 0 or NaN).
+__device__ __forceinline__ void stat_residual(unsigned long long* stats, double r) {
+  if (stats && !(r <= 0.0)) atomicMax(stat_slot(stats) + kStatResidual, (unsigned long long)__double_as_longlong(r));
+}
+// 1 when a moved reference coordinate lies outside [0, 1].
+__device__ __forceinline__ int escaped(double x) { return (x < 0.0 || x > 1.0) ? 1 : 0; }
+#endif
 
 constexpr int kMaxN = 16;        // largest nodes per direction supported
 constexpr int kMaxAttempts = 64; // polar-method retries before z = 0
@@ -39,6 +64,7 @@ struct Params1D {
   int64_t step0;         // Philox step counter of the first step
   uint64_t seed;
   uint32_t stream;
+  unsigned long long* stats;   // diagnostics slots (kStatSlots x kStatStride), or null
   LegendreRec rec;
   double xi[kMaxN];      // reference nodes
 };
@@ -76,7 +102,7 @@ struct Params2D {
   int64_t gx_off[kMaxN + 1];
   double tol2;             // stop when g^T g <= tol2 * x0^T x0 (g: preconditioned residual)
   int max_iter;
-  unsigned long long* stats;   // [kStatSlots][2 phases][2]: iterations summed over fits, fits that hit max_iter
+  unsigned long long* stats;   // diagnostics slots (kStatSlots x kStatStride, layout above)
   LegendreRec rec;
 };
 
@@ -139,7 +165,13 @@ hipError_t launch_resident_1d_batch(int N, int algo, const Batch1DArgs& a, size_
 size_t resident_1d_lds_bytes(int K, int samples_per_block);
 int resident_1d_samples_per_block(int K);
 
-hipError_t launch_mean(const double* phi, double* out, int64_t M, int64_t nodes, hipStream_t st);
+// Sample mean (two passes, fixed order).  part: partial sums, at least
+// mean_chunks(M, nodes) * nodes doubles when that is above 1 (else unused);
+// nonfinite (may be null): cleared, then receives the count of non-finite values read.
+constexpr int64_t kMeanScratchDoubles = (int64_t)1 << 19;   // bound on the partial sums (4 MiB)
+int64_t mean_chunks(int64_t M, int64_t nodes);
+hipError_t launch_mean(const double* phi, double* out, double* part, int64_t M, int64_t nodes,
+                       unsigned long long* nonfinite, hipStream_t st);
 hipError_t launch_broadcast(double* phi, const double* phi0, int64_t M, int64_t nodes, hipStream_t st);
 hipError_t launch_debug_normals(double* out, uint64_t seed, uint32_t stream, int64_t step,
                                 int64_t s0, int64_t ns, hipStream_t st);

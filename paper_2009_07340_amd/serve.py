@@ -28,6 +28,10 @@ import numpy as np
 
 from . import workloads as W
 
+# status codes of the C ABI (include/sl.h) that argument checks return before
+# anything is enqueued
+_EINVAL, _ESTATE = -1, -5
+
 
 @dataclass
 class Request:
@@ -191,17 +195,20 @@ class Server:
             if active:
                 chunk = min(self.chunk_steps, min(r.remaining for r in active))
                 self.batch_log.append([r.id for r in active])
+                before = [self.B.sl_get_step(r.h) for r in active]
                 try:
                     self.B.sl_step_batch([r.h for r in active], [r.dt for r in active], chunk)
                     launched = True
-                except Exception:
-                    self._isolate(active, chunk)
+                except Exception as err:
+                    launched = self._recover(active, before, chunk, err)
                 for r in active:
                     r.remaining -= chunk
                 self.iterations += 1
             new = self._admit(queue, len(active), self.clock() - t0)
             if launched:
-                self.B.sl_sync(active[0].h)
+                live = [r for r in active if r.h is not None]
+                if live:
+                    self.B.sl_sync(live[0].h)
             now = self.clock() - t0
             still = []
             for r in active:
@@ -222,19 +229,42 @@ class Server:
                 queue.clear()
         return requests
 
-    def _isolate(self, active, chunk):
-        """A failed batch: step each request alone so one bad request cannot poison the rest."""
-        for r in active:
-            try:
-                self.B.sl_step_batch([r.h], [r.dt], chunk)
-            except Exception as e:
-                r.error = f"failed in step: {e}"
+    def _recover(self, active, before, chunk, err):
+        """A batch that raised.  A request whose step counter advanced by the chunk
+        finished it.  When the batch failed its argument checks (SL_EINVAL or
+        SL_ESTATE, raised before anything is enqueued) and no counter moved, no
+        step ran: each request is stepped again alone, so one bad request cannot
+        poison the rest.  Otherwise a request whose counter did not advance may
+        hold a partly advanced state (some of its launches ran) and is failed,
+        never stepped again.  Returns whether any request holds enqueued work."""
+        code = getattr(err, "code", None)
+        steps = [self.B.sl_get_step(r.h) for r in active]
+        nothing_ran = code in (_EINVAL, _ESTATE) and steps == before
+        launched = False
+        for r, b, now_step in zip(active, before, steps):
+            if now_step == b + chunk:
+                launched = True
+                continue
+            if nothing_ran:
                 try:
-                    self.B.sl_destroy(r.h)
-                finally:
-                    r.h = None
-                    self.used -= r.footprint
-                    r.done = self.clock() - self._t0
+                    self.B.sl_step_batch([r.h], [r.dt], chunk)
+                    launched = True
+                    continue
+                except Exception as e:
+                    msg = f"failed in step: {e}"
+            else:
+                msg = f"failed in step: the batch failed ({err}) and this request's state may be partly advanced"
+            self._fail(r, msg)
+        return launched
+
+    def _fail(self, r, msg):
+        r.error = msg
+        try:
+            self.B.sl_destroy(r.h)
+        finally:
+            r.h = None
+            self.used -= r.footprint
+            r.done = self.clock() - self._t0
 
 
 def summarize(requests, makespan=None):

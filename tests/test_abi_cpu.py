@@ -73,3 +73,18 @@ def test_schedule_and_batch_argument_checks_without_a_device():
     B.sl_step_batch([], [], 1)          # an empty batch is a no-op
     with pytest.raises(B.SLError):
         B.sl_step_batch([None], [1e-3], 1)
+
+
+@pytest.mark.parametrize("fault", ["alloc", "host"])
+def test_injected_allocation_failure_returns_enomem(monkeypatch, fault):
+    """SL_FAULT makes the library's own allocations fail: creating a handle that
+    needs them returns SL_ENOMEM and leaves no handle behind (no device call is
+    made before the allocation, so this runs without a GPU)."""
+    from paper_2009_07340_amd import binding as B
+    d = B.make_desc(1, 16, order=8, samples=4)
+    monkeypatch.setenv("SL_FAULT", fault)
+    for _ in range(3):                   # repeated failures leave nothing behind
+        with pytest.raises(B.SLError) as ei:
+            B.sl_init_mesh(d)
+        assert ei.value.code == B.SL_ENOMEM
+        assert "fail" in B.sl_last_error()

@@ -1,0 +1,253 @@
+"""More pins of the oracle, each against something other than the oracle itself:
+
+* the upwind choice under diffusion (Sec. 5.3, eq. bnd_update): with no drift the
+  interface displacement has the sign of the sample's Wiener increment along the
+  edge normal, so the side a boundary value comes from is fixed by the sign of
+  the x draw on W/E edges and of the y draw on S/N edges (Philox draws taken
+  straight from the generator);
+* the exchange between elements of different order, by a pathwise closed form
+  (solid-body rotation with constant D: each step is an affine map, so each
+  sample is the initial field pulled back along its own path);
+* the norms (eqs. l2_error, mass_cons, energy_cons) against closed-form integrals
+  of polynomials;
+* re-seeding (Sec. 5.4, eq. re-seed) against a step-by-step restatement;
+* the stability of the one-step map behind the workloads' time steps (slow).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import rng, sl
+from paper_2009_07340_amd import workloads as W
+
+from helpers import oracle_inputs, oracle_mesh
+
+
+# ---------------------------------------------------------------- upwinding under diffusion
+
+def _jump_field_1d(K, N):
+    mesh = sl.Mesh(dim=1, kx=K, order=N)
+    x = mesh.node_coords()[:, 0]
+    return mesh, np.where(x < 0.5, 1.0 + 0.3 * x, -2.0 + x * x)        # a jump at x = 0.5
+
+
+@pytest.mark.parametrize("u", [0.0, 0.4])
+def test_1d_upwind_side_follows_the_sign_of_the_displacement(u):
+    """Boundary values at an interface come from the element the particles move out of:
+    a positive interface displacement u dt + sqrt(2 D dt) z takes the left (negative-side)
+    element's trace.  With u = 0 that is the sign of z itself."""
+    K, N, dt, D = 4, 6, 1e-3, 0.01
+    mesh, phi0 = _jump_field_1d(K, N)
+    f = sl.Fields(u=np.full((mesh.total_nodes, 1), u), D=np.full(mesh.total_nodes, D),
+                  un=np.full(mesh.total_edge, u), Dn=np.full(mesh.total_edge, D))
+    samples = np.arange(40, dtype=np.uint64)
+    za, _ = rng.normal_pair(5, 3, samples)                    # step 3, seed 5: x uses the first draw
+    z = za[:, None]
+    _, info = sl.step(mesh, f, np.broadcast_to(phi0, (len(samples), mesh.total_nodes)).copy(), dt, z)
+    tr = info["traces"].reshape(len(samples), K, 2)          # [s][e][L, R]
+    g = info["g"].reshape(len(samples), K, 2)
+    h = 1.0 / K
+    moves_right = (u * dt + math.sqrt(2 * D * dt) * za) / h > 0.0
+    if u == 0.0:
+        assert 5 < np.count_nonzero(moves_right) < 35            # both signs occur
+    for s in range(len(samples)):
+        for e in range(K):
+            left, right = (e - 1) % K, (e + 1) % K
+            # left edge of e: moving right brings the left neighbour's right trace
+            want_L = tr[s, left, 1] if moves_right[s] else tr[s, e, 0]
+            # right edge of e: moving right keeps e's own right trace, else the right neighbour's left
+            want_R = tr[s, e, 1] if moves_right[s] else tr[s, right, 0]
+            assert g[s, e, 0] == want_L and g[s, e, 1] == want_R, (s, e)
+    assert np.any(tr[:, 1, 1] != tr[:, 2, 0])                    # the traces differ across the jump
+
+
+def test_2d_upwind_side_uses_the_draw_of_the_edge_normal():
+    """In 2-D the W/E edges follow the x draw and the S/N edges the y draw: with no drift
+    and samples whose two draws have opposite signs, swapping them would pick the other side."""
+    N, kx, ky, dt, D = 4, 3, 3, 1e-3, 0.01
+    mesh = sl.Mesh(dim=2, kx=kx, ky=ky, order=N)
+    xy = mesh.node_coords()
+    phi0 = np.where(xy[:, 0] < 1 / 3, 1.0, 0.0) + np.where(xy[:, 1] < 2 / 3, 0.5, -0.25) + 0.1 * xy[:, 0] * xy[:, 1]
+    f = sl.Fields(u=np.zeros((mesh.total_nodes, 2)), D=np.full(mesh.total_nodes, D),
+                  un=np.zeros(mesh.total_edge), Dn=np.full(mesh.total_edge, D))
+    samples = np.arange(30, dtype=np.uint64)
+    za, zb = rng.normal_pair(9, 2, samples)
+    assert np.any(np.sign(za) != np.sign(zb))
+    _, info = sl.step(mesh, f, np.broadcast_to(phi0, (len(samples), mesh.total_nodes)).copy(), dt,
+                      np.stack([za, zb], 1))
+    tr = info["traces"].reshape(len(samples), mesh.K, 4, N)     # [s][e][W, E, S, N][point]
+    g = info["g"].reshape(len(samples), mesh.K, 4, N)
+    for s in range(len(samples)):
+        right, up = za[s] > 0.0, zb[s] > 0.0                      # D > 0, u = 0: the sign of the draw
+        for e in range(mesh.K):
+            ex, ey = e % kx, e // kx
+            w_, e_ = ey * kx + (ex - 1) % kx, ey * kx + (ex + 1) % kx
+            s_, n_ = ((ey - 1) % ky) * kx + ex, ((ey + 1) % ky) * kx + ex
+            np.testing.assert_array_equal(g[s, e, 0], tr[s, w_, 1] if right else tr[s, e, 0])
+            np.testing.assert_array_equal(g[s, e, 1], tr[s, e, 1] if right else tr[s, e_, 0])
+            np.testing.assert_array_equal(g[s, e, 2], tr[s, s_, 3] if up else tr[s, e, 2])
+            np.testing.assert_array_equal(g[s, e, 3], tr[s, e, 3] if up else tr[s, n_, 2])
+
+
+# ---------------------------------------------------------------- mixed orders, pathwise
+
+def _rotation_pathwise_error(order, kx=6, nsteps=4, samples=(0, 1)):
+    """Max error of the oracle against each sample's exact pull-back under solid-body
+    rotation with constant D (every step the affine map x -> c + R (x - c) + s z)."""
+    dt, D = 2e-4, 0.002
+    c = np.array([0.5, 0.5])
+    R = np.array([[1.0, -2 * np.pi * dt], [2 * np.pi * dt, 1.0]])
+    Ri = np.linalg.inv(R)
+    p0 = lambda x, y: np.exp(-((x - 0.5) ** 2 + (y - 0.62) ** 2) / (2 * 0.07 ** 2))
+    wl = W.c4_2d_rotation(kx=kx, ky=kx, samples=len(samples), steps=nsteps)
+    wl.order, wl.dt, wl.D, wl.phi0 = order, dt, W.const(D), p0
+    mesh, f, phi0, _ = oracle_inputs(wl)
+    samples = np.asarray(samples)
+    phi = sl.run(mesh, f, phi0, dt, nsteps, wl.seed, samples)
+    xy = mesh.node_coords()
+    ex = []
+    for s in samples:
+        y = xy.copy()
+        for k in range(nsteps - 1, -1, -1):
+            z = sl.wiener_normals(mesh, wl.seed, k, np.array([s]))[0]
+            y = c + (y - c - math.sqrt(2 * D * dt) * z) @ Ri.T
+        ex.append(p0(y[:, 0], y[:, 1]))
+    err = np.abs(phi - np.array(ex))
+    return mesh, err
+
+
+def test_mixed_order_exchange_pathwise_rotation():
+    """A mesh mixing N = 6, 8, 10 (neighbours of different order exchange traces by
+    evaluating the neighbour's polynomial at the receiver's own abscissae) reproduces the
+    pathwise solution as well as its coarsest order does on its own, and the elements of
+    each order are as accurate as on a uniform mesh of that order."""
+    kx = 6
+    orders = W.c4_orders(kx, kx, seed=5)
+    assert len(set(orders.tolist())) == 3
+    mesh_m, err_m = _rotation_pathwise_error(orders, kx)
+    errs = {}
+    for N in (6, 8, 10):
+        mesh_u, err_u = _rotation_pathwise_error(N, kx)
+        errs[N] = float(err_u.max())
+    assert errs[10] < errs[8] / 5 < errs[6] / 25, errs                 # spectral in N
+    assert float(err_m.max()) <= 1.5 * errs[6], (float(err_m.max()), errs)
+    # per order: no element of the mixed mesh is much worse than the uniform mesh of its order
+    off = mesh_m.node_offset
+    for N in (8, 10):
+        els = np.nonzero(mesh_m.order == N)[0]
+        worst = max(float(err_m[:, off[e]:off[e + 1]].max()) for e in els)
+        assert worst <= max(10 * errs[N], 2 * errs[6]), (N, worst, errs)
+
+
+# ---------------------------------------------------------------- norms
+
+def test_norms_against_closed_form_integrals_1d():
+    """Eqs. l2_error, mass_cons, energy_cons on [0, 2] with 4 elements (h = 0.5): the
+    integrands are polynomials that Gauss-Legendre quadrature integrates exactly."""
+    K, N = 4, 5
+    mesh = sl.Mesh(dim=1, kx=K, x0=0.0, x1=2.0, order=N)
+    x = mesh.node_coords()[:, 0]
+    exact = 2.0 + x * x
+    phi = exact + (x - 0.25) ** 2              # error (x - 1/4)^2, squared degree 4 <= 2N - 1
+    edges = np.linspace(0.0, 2.0, K + 1)
+    F = lambda b: (b - 0.25) ** 5 / 5.0        # antiderivative of (x - 1/4)^4
+    want_l2 = sum(math.sqrt(F(b) - F(a)) for a, b in zip(edges[:-1], edges[1:]))
+    assert abs(sl.l2_error(mesh, phi, exact) - want_l2) < 1e-13 * want_l2
+    I1 = lambda a, b, f: f(b) - f(a)
+    P = lambda t: 2 * t + t ** 3 / 3 + (t - 0.25) ** 3 / 3          # int of phi
+    Q = lambda t: 2 * t + t ** 3 / 3                                  # int of exact
+    want_mass = sum(I1(a, b, P) / I1(a, b, Q) for a, b in zip(edges[:-1], edges[1:]))
+    assert abs(sl.mass_norm(mesh, phi, exact) - want_mass) < 1e-13 * want_mass
+    # energy: int phi^2 / int exact^2, numerically exact polynomial integrals
+    pp = np.polynomial.Polynomial([2.0, 0.0, 1.0]) + np.polynomial.Polynomial([0.0625, -0.5, 1.0])
+    ee = np.polynomial.Polynomial([2.0, 0.0, 1.0])
+    P2, Q2 = (pp * pp).integ(), (ee * ee).integ()
+    want_en = sum((P2(b) - P2(a)) / (Q2(b) - Q2(a)) for a, b in zip(edges[:-1], edges[1:]))
+    assert abs(sl.energy_norm(mesh, phi, exact) - want_en) < 1e-13 * want_en
+    # the global integral carries the Jacobian h
+    assert abs(sl.integral(mesh, exact) - (Q(2.0) - Q(0.0))) < 1e-13
+
+
+def test_l2_norm_against_closed_form_2d():
+    """2-D: the error x y^2 on [0, 1] x [0, 2] with 2 x 2 elements: per element
+    sqrt(int x^2 y^4) = sqrt((x1^3 - x0^3)/3 (y1^5 - y0^5)/5)."""
+    mesh = sl.Mesh(dim=2, kx=2, ky=2, x0=0.0, x1=1.0, y0=0.0, y1=2.0, order=4)
+    xy = mesh.node_coords()
+    exact = np.cos(xy[:, 0]) + xy[:, 1]
+    phi = exact + xy[:, 0] * xy[:, 1] ** 2
+    want = 0.0
+    for ey in range(2):
+        for ex in range(2):
+            x0, x1, y0, y1 = ex * 0.5, (ex + 1) * 0.5, ey * 1.0, (ey + 1) * 1.0
+            want += math.sqrt((x1 ** 3 - x0 ** 3) / 3 * (y1 ** 5 - y0 ** 5) / 5)
+    assert abs(sl.l2_error(mesh, phi, exact) - want) < 1e-13 * want
+
+
+# ---------------------------------------------------------------- re-seeding
+
+def test_reseeding_sets_every_sample_to_the_mean_after_each_period():
+    """Eq. re-seed: after every `every` steps all samples restart from their mean; restated
+    step by step here (the same Philox counters: step k, global sample index)."""
+    wl = W.c2_1d_sine()
+    wl.kx, wl.order = 8, 6
+    mesh, f, phi0, _ = oracle_inputs(wl)
+    samples = np.arange(5)
+    got = sl.run(mesh, f, phi0, wl.dt * 50, 7, wl.seed, samples, reseed_every=3)
+    phi = np.broadcast_to(phi0, (5, mesh.total_nodes)).copy()
+    for k in range(7):
+        z = sl.wiener_normals(mesh, wl.seed, k, samples)
+        phi, _ = sl.step(mesh, f, phi, wl.dt * 50, z)
+        if k in (2, 5):
+            m = phi.sum(axis=0) / 5.0
+            phi = np.broadcast_to(m, phi.shape).copy()
+    np.testing.assert_allclose(got, phi, rtol=0, atol=1e-15 * np.abs(phi).max())
+    # right after a re-seed (step 6 of 7 follows one) the samples have diverged again by one step,
+    # and without re-seeding the run differs
+    plain = sl.run(mesh, f, phi0, wl.dt * 50, 7, wl.seed, samples)
+    assert np.max(np.abs(plain - got)) > 1e-8
+
+
+# ---------------------------------------------------------------- stability (the time-step finding)
+
+def _one_step_operator_radius(N, delta, K=4):
+    """Spectral radius of the one-step map of a 1-D periodic mesh under a uniform shift of
+    delta element widths (constant u, D = 0, so no draw matters): the map is linear in the
+    samples, built column by column by stepping the unit vectors as samples."""
+    mesh = sl.Mesh(dim=1, kx=K, order=N)
+    n = mesh.total_nodes
+    h = 1.0 / K
+    dt = 1e-3
+    u = delta * h / dt
+    f = sl.Fields(u=np.full((n, 1), u), D=np.zeros(n), un=np.full(mesh.total_edge, u),
+                  Dn=np.zeros(mesh.total_edge))
+    z = np.zeros((n, 1))
+    cols, _ = sl.step(mesh, f, np.eye(n), dt, z)
+    return float(np.max(np.abs(np.linalg.eigvals(cols.T))))
+
+
+@pytest.mark.slow
+def test_one_step_map_radius_grows_with_the_displacement():
+    """The radius stays at 1 for moves of a small fraction of the node spacing and rises
+    quickly beyond it (N = 12: about 1 at 0.005 h, above 1.3 at 0.08 h), which is why long
+    runs need the eq. 1d_timestep displacement well inside one node spacing."""
+    r12 = {d: _one_step_operator_radius(12, d) for d in (0.005, 0.02, 0.08)}
+    r8 = {d: _one_step_operator_radius(8, d) for d in (0.005, 0.08, 0.16)}
+    assert abs(r12[0.005] - 1.0) < 1e-4, r12
+    assert r12[0.08] > 1.3, r12
+    assert r12[0.005] < r12[0.02] < r12[0.08], r12
+    assert abs(r8[0.005] - 1.0) < 1e-4 and 1.0 < r8[0.08] < r8[0.16], r8
+
+
+@pytest.mark.slow
+def test_sinusoidal_1d_workload_is_bounded_at_its_step_and_not_at_the_plan_step():
+    """The 1-D sinusoidal workload: at dt = 1.9e-7 (eq. 1d_timestep with half the node
+    spacing) 1000 steps stay bounded; at the plan's 2e-5 the field blows up within 100 steps."""
+    wl = W.c2_1d_sine()
+    mesh, f, phi0, _ = oracle_inputs(wl)
+    s = np.arange(2)
+    ok = sl.run(mesh, f, phi0, wl.dt, wl.steps, wl.seed, s)
+    assert np.all(np.isfinite(ok)) and np.max(np.abs(ok)) < 1.2 * np.max(np.abs(phi0))
+    with np.errstate(all="ignore"):
+        bad = sl.run(mesh, f, phi0, wl.dt_specified, 100, wl.seed, s)
+    assert not np.all(np.isfinite(bad)) or np.max(np.abs(bad)) > 1e6

@@ -13,15 +13,20 @@ class FakeBackend:
     8 bytes per node value; a step advances a per-handle counter."""
 
     class SLError(RuntimeError):
-        pass
+        def __init__(self, msg, code=-3):
+            super().__init__(msg)
+            self.code = code
 
-    def __init__(self, free=10 ** 9, fail_dims=(), nan_ids=()):
+    def __init__(self, free=10 ** 9, fail_dims=(), nan_ids=(), batch_fault=None):
         self.free = free
         self.live = {}
         self.next = 1
         self.batches = []
         self.fail_dims = fail_dims
         self.nan_ids = set(nan_ids)
+        # batch_fault(call index, handles) -> None, or (code, handles advanced before the error)
+        self.batch_fault = batch_fault
+        self.calls = 0
 
     def make_desc(self, dim, kx, ky, box, order, bc, samples, seed, precision):
         N = int(order) if np.isscalar(order) else int(np.max(order))
@@ -61,9 +66,19 @@ class FakeBackend:
 
     def sl_step_batch(self, hs, dts, n):
         assert len(set(hs)) == len(hs)
+        self.calls += 1
+        fault = self.batch_fault(self.calls, list(hs)) if self.batch_fault else None
+        if fault is not None:
+            code, advanced = fault
+            for h in advanced:              # the part of the batch that ran before the error
+                self.live[h]["steps"] += n
+            raise self.SLError("injected batch failure", code)
         self.batches.append(list(hs))
         for h in hs:
             self.live[h]["steps"] += n
+
+    def sl_get_step(self, h):
+        return self.live[h]["steps"]
 
     def sl_sync(self, h):
         pass
@@ -162,3 +177,35 @@ def test_stream_requests_keep_the_specified_shapes():
         for r, d in zip(reqs, stream):
             assert (r.wl.dim, r.wl.kx, r.wl.ky, r.wl.samples, r.steps) == (d["dim"], d["kx"], d["ky"], d["M"], d["steps"])
             assert r.precision == ("fp64" if d["dim"] == 1 else prec)
+
+
+def test_a_batch_that_fails_midway_never_steps_a_request_twice():
+    """A device error after part of a batch ran: requests whose step counter
+    advanced keep going; the others may hold partly advanced state and fail
+    instead of being stepped again."""
+    def fault(call, hs):
+        return (-3, hs[:2]) if call == 3 and len(hs) >= 4 else None
+    fb, clk = FakeBackend(batch_fault=fault), Clock()
+    reqs = _reqs(5, steps=12, gap=0.0)
+    srv = serve.Server(fb, budget_bytes=10 ** 8, max_active=8, chunk_steps=4, clock=clk, sleep=clk.sleep)
+    srv.run(reqs)
+    ok = [r for r in reqs if r.error is None]
+    bad = [r for r in reqs if r.error is not None]
+    assert len(ok) == 2 and len(bad) == 3
+    for r in ok:                        # exactly the requested steps: none repeated
+        assert np.all(r.mean == r.steps), (r.id, r.mean[0])
+    assert all("partly advanced" in r.error for r in bad)
+    assert not fb.live and srv.used == 0
+
+
+def test_a_batch_rejected_by_its_argument_checks_is_retried_request_by_request():
+    """SL_EINVAL before anything was enqueued: every request is stepped alone once."""
+    def fault(call, hs):
+        return (-1, []) if call == 2 else None
+    fb, clk = FakeBackend(batch_fault=fault), Clock()
+    reqs = _reqs(4, steps=8, gap=0.0)
+    srv = serve.Server(fb, budget_bytes=10 ** 8, max_active=8, chunk_steps=4, clock=clk, sleep=clk.sleep)
+    srv.run(reqs)
+    assert all(r.error is None for r in reqs)
+    for r in reqs:
+        assert np.all(r.mean == r.steps), (r.id, r.mean[0])
