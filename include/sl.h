@@ -288,6 +288,28 @@ int sl_set_stream(sl_handle h, void* hip_stream);
 /* Free and total bytes of the current device (hipMemGetInfo), for admission. */
 int sl_mem_info(size_t* free_bytes, size_t* total_bytes);
 const char* sl_last_error(void);          /* thread-local message of the last failure */
+
+/* Allocation-free sample mean, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc) and hold their own sample arrays: the variant of sl_mean that
+ * needs no handle and allocates nothing.
+ *   phi: device array [samples][nodes] (float64, borrowed, read only);
+ *   out: device array [nodes], receives the mean (same summation order as
+ *     sl_mean, so the two agree bit for bit for the same sizes and values);
+ *   nonfinite: optional device uint64, cleared and then set to the count of
+ *     non-finite values read (NULL: not counted);
+ *   hip_stream: the stream to enqueue on (NULL = the null stream); the call
+ *     returns without waiting.
+ * The partial sums live in one static device array per GPU of the library
+ * (4 MiB, kept until the process ends); the chunk count is chosen so that
+ * they always fit it (for more than 2^19 nodes the mean takes one pass and
+ * uses no scratch), so no size is rejected for lack of scratch.  Calls on one
+ * GPU share that array: calls that overlap in time on one GPU (two streams,
+ * two threads) race and must be serialised by the caller.  Errors: SL_EINVAL
+ * for null pointers or sizes < 1 or above 2^40 (or samples * nodes > 9e15),
+ * SL_EDEVICE when a launch fails. */
+int sl_mean_noalloc(const double* phi, int64_t samples, int64_t nodes, double* out, uint64_t* nonfinite,
+                    void* hip_stream);
 int sl_destroy(sl_handle h);              /* waits, frees what the library allocated */
 
 #ifdef __cplusplus

@@ -94,6 +94,7 @@ _SIGS = {
     "sl_get_schedule": [_P, C.POINTER(sl_schedule_t)],
     "sl_autotune": [_P, C.c_double, C.c_int32, C.c_char_p, C.POINTER(sl_schedule_t)],
     "sl_destroy": [_P],
+    "sl_mean_noalloc": [_P, C.c_int64, C.c_int64, _P, _P, _P],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -304,6 +305,12 @@ def sl_autotune(h, dt, trial_steps=3, cache_path=None):
     path = None if cache_path is None else os.fspath(cache_path).encode()
     _check(_lib.sl_autotune(h, float(dt), int(trial_steps), path, C.byref(s)))
     return _sched_dict(s)
+
+
+def sl_mean_noalloc(phi_dev, samples, nodes, out_dev, nonfinite_dev=None, hip_stream=None):
+    """Allocation-free mean of a device array [samples][nodes] into out_dev (device pointers as ints)."""
+    _check(_lib.sl_mean_noalloc(_ptr(phi_dev), int(samples), int(nodes), _ptr(out_dev), _ptr(nonfinite_dev),
+                                _ptr(hip_stream)))
 
 
 def sl_sync(h):

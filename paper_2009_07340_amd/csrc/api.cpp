@@ -1306,6 +1306,21 @@ int sl_mem_info(size_t* free_bytes, size_t* total_bytes) {
 
 const char* sl_last_error(void) { return g_last_error.c_str(); }
 
+int sl_mean_noalloc(const double* phi, int64_t samples, int64_t nodes, double* out, uint64_t* nonfinite,
+                    void* hip_stream) {
+  if (!phi || !out) return fail(SL_EINVAL, "null sample or output pointer");
+  if (samples < 1 || nodes < 1) return fail(SL_EINVAL, "samples and nodes must be >= 1");
+  if (nodes > ((int64_t)1 << 40) || samples > ((int64_t)1 << 40) || (double)samples * (double)nodes > 9.0e15)
+    return fail(SL_EINVAL, "sizes beyond the supported range (samples, nodes <= 2^40, samples * nodes <= 9e15)");
+  const int64_t C = sl::mean_chunks(samples, nodes);
+  if (C > 1 && C * nodes > sl::kMeanScratchDoubles)
+    return fail(SL_EINVAL, "partial sums exceed the allocation-free scratch bound");
+  double* part = nullptr;
+  if (C > 1) SL_HIP(sl::mean_scratch_device_ptr(&part));
+  SL_HIP(sl::launch_mean(phi, out, part, samples, nodes, (unsigned long long*)nonfinite, (hipStream_t)hip_stream));
+  return SL_OK;
+}
+
 int sl_destroy(sl_handle h) {
   if (!h) return SL_OK;
   (void)hipStreamSynchronize(h->stream);

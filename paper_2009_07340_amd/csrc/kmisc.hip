@@ -2,6 +2,8 @@
 #include "sl_internal.hpp"
 #include "philox.hpp"
 
+#include <mutex>
+
 namespace sl {
 
 // Mean over samples at every node (eq. averaged), in two passes with a fixed
@@ -83,6 +85,35 @@ hipError_t launch_mean(const double* phi, double* out, double* part, int64_t M, 
   if (e != hipSuccess || C == 1) return e;
   hipLaunchKernelGGL(mean_pass2, dim3((unsigned)tiles), dim3(kMeanThreads), 0, st, part, out, M, nodes, C);
   return hipGetLastError();
+}
+
+// Partial sums of the allocation-free mean: one array per device, reserved when
+// the library is loaded and held until the process ends.  Host code never
+// passes `mean_scratch` itself to a kernel (in host code the name stands for a
+// host-side shadow, not a device address): it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) double mean_scratch[kMeanScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+double* g_mean_scratch_ptr[kMaxDevices] = {nullptr};
+std::mutex g_mean_scratch_mu;
+}  // namespace
+
+hipError_t mean_scratch_device_ptr(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_mean_scratch_mu);
+  if (!g_mean_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(mean_scratch));
+    if (e != hipSuccess) return e;
+    g_mean_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_mean_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 __global__ void broadcast_kernel(double* __restrict__ phi, const double* __restrict__ phi0, int64_t total,

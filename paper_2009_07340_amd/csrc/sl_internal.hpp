@@ -172,6 +172,8 @@ constexpr int64_t kMeanScratchDoubles = (int64_t)1 << 19;   // bound on the part
 int64_t mean_chunks(int64_t M, int64_t nodes);
 hipError_t launch_mean(const double* phi, double* out, double* part, int64_t M, int64_t nodes,
                        unsigned long long* nonfinite, hipStream_t st);
+// Device address of this device's allocation-free mean scratch (kMeanScratchDoubles doubles).
+hipError_t mean_scratch_device_ptr(double** out);
 hipError_t launch_broadcast(double* phi, const double* phi0, int64_t M, int64_t nodes, hipStream_t st);
 hipError_t launch_debug_normals(double* out, uint64_t seed, uint32_t stream, int64_t step,
                                 int64_t s0, int64_t ns, hipStream_t st);

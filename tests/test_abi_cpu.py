@@ -88,3 +88,12 @@ def test_injected_allocation_failure_returns_enomem(monkeypatch, fault):
             B.sl_init_mesh(d)
         assert ei.value.code == B.SL_ENOMEM
         assert "fail" in B.sl_last_error()
+
+
+def test_allocation_free_mean_checks_its_arguments_without_a_device():
+    from paper_2009_07340_amd import binding as B
+    for args in [(None, 4, 8, 1), (1, 4, 8, None), (1, 0, 8, 1), (1, 4, 0, 1), (1, 1 << 41, 8, 1),
+                 (1, 1 << 30, 1 << 30, 1)]:
+        with pytest.raises(B.SLError) as ei:
+            B.sl_mean_noalloc(*args)
+        assert ei.value.code == B.SL_EINVAL
