@@ -195,6 +195,13 @@ int sl_ref_nodes(sl_handle h, int32_t N, double* host_xi);
 int sl_set_fields(sl_handle h, const double* u, const double* D, const double* divu,
                   const double* un, const double* Dn, const double* ghost, const double* phi0);
 
+/* Replace the Dirichlet ghost values ([edge points], host, copied; only entries
+ * on the domain boundary are read) for the steps enqueued after this call, for
+ * boundary data that change in time (Sec. 5.3: the boundary is treated as an
+ * interface with a specified ghost solution).  Waits for the handle's stream.
+ * SL_EINVAL for a periodic handle, SL_ENONFINITE for non-finite values. */
+int sl_set_ghost(sl_handle h, const double* ghost);
+
 /* Advance every sample nsteps >= 0 steps of size dt > 0 (Sec. 5).  Enqueued on
  * the handle's stream; returns without waiting.  The step counter advances by
  * nsteps. */
@@ -253,6 +260,28 @@ int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_p
  * on the sizes, the chunks added in order), so repeated calls agree bit for
  * bit.  Uses partial sums in the handle's workspace. */
 int sl_mean(sl_handle h, double* out, int32_t out_is_device);
+
+/* Per-node PDF of the samples by binning (Sec. 5.4: the PDF of the solution at
+ * each grid point from the samples).  counts[nodes][nbins + 2] (uint32):
+ * column 0 counts values below lo, columns 1..nbins the bins of width
+ * w = (hi - lo) / nbins, column nbins + 1 values at or above hi.  A value v in
+ * [lo, hi) goes to bin floor((v - lo) / w), capped at nbins - 1 (float64,
+ * correctly rounded subtraction and division, so the bin of every value is
+ * defined exactly); non-finite values are not counted.  Counts are exact
+ * integers whatever the launch.  1 <= nbins <= 254, finite lo < hi,
+ * samples < 2^32.  out_is_device != 0: counts is a device pointer and the call
+ * is asynchronous; otherwise host memory, a temporary device buffer is
+ * allocated and the call waits. */
+int sl_pdf(sl_handle h, double lo, double hi, int32_t nbins, uint32_t* counts, int32_t out_is_device);
+
+/* Re-seeding (Sec. 5.4, eq. re-seed): every sample is set to the sample mean at
+ * the nodes (the same mean as sl_mean).  Enqueued on the handle's stream; the
+ * step counter is unchanged, so the next step draws the Wiener increments it
+ * would have drawn anyway.  The paper re-seeds every 100 steps of its
+ * Dirichlet cases; the caller chooses when (e.g. sl_step(h, dt, 100) then
+ * sl_reseed(h)).  Non-finite samples met by the mean are counted in
+ * sl_diag().nonfinite. */
+int sl_reseed(sl_handle h);
 
 /* Copy ns samples starting at s0 ([ns][nodes]) out of / into the handle (for
  * checkpoints and subset checks).  Host buffers unless *_is_device != 0. */

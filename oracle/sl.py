@@ -40,6 +40,7 @@ mean displacement dbar of the element's nodes: psi_k(xi - dbar).  This is a
 conditioning choice only: Q_{N-1} is shift invariant, so p is unchanged.
 """
 from dataclasses import dataclass, field
+import math
 
 import numpy as np
 
@@ -420,6 +421,32 @@ def mean(phi):
     for s in range(phi.shape[0]):
         acc = acc + phi[s]
     return acc / phi.shape[0]
+
+
+def pdf_counts(phi, lo, hi, nbins):
+    """Per-node histogram of the samples (Sec. 5.4: the PDF at each grid point by
+    binning the samples): counts (nodes, nbins + 2), column 0 the values below lo,
+    columns 1..nbins the bins of width w = (hi - lo) / nbins, column nbins + 1 the
+    values at or above hi.  A value v in [lo, hi) goes to bin floor((v - lo) / w),
+    capped at nbins - 1 (rounding can reach nbins just below hi).  Non-finite
+    values are not counted.  Plain loops over samples and nodes."""
+    phi = np.asarray(phi, dtype=np.float64)
+    w = (hi - lo) / nbins
+    M, nodes = phi.shape
+    counts = np.zeros((nodes, nbins + 2), dtype=np.int64)
+    for s in range(M):
+        for i in range(nodes):
+            v = phi[s, i]
+            if not np.isfinite(v):
+                continue
+            if v < lo:
+                counts[i, 0] += 1
+            elif v >= hi:
+                counts[i, nbins + 1] += 1
+            else:
+                b = int(math.floor((v - lo) / w))
+                counts[i, 1 + min(b, nbins - 1)] += 1
+    return counts
 
 
 def _quad(mesh):

@@ -76,8 +76,11 @@ _SIGS = {
     "sl_ref_nodes": [_P, C.c_int32, _P],
     "sl_set_fields": [_P, _P, _P, _P, _P, _P, _P, _P],
     "sl_step": [_P, C.c_double, C.c_int32],
+    "sl_set_ghost": [_P, _P],
     "sl_step_batch": [_P, _P, C.c_int32, C.c_int32],
     "sl_mean": [_P, _P, C.c_int32],
+    "sl_reseed": [_P],
+    "sl_pdf": [_P, C.c_double, C.c_double, C.c_int32, _P, C.c_int32],
     "sl_get_samples": [_P, C.c_int64, C.c_int64, _P, C.c_int32],
     "sl_set_samples": [_P, C.c_int64, C.c_int64, _P, C.c_int32],
     "sl_get_step": [_P, C.POINTER(C.c_int64)],
@@ -200,6 +203,11 @@ def sl_set_fields(h, u, D, divu, un, Dn, ghost=None, phi0=None):
     _check(_lib.sl_set_fields(h, *[_ptr(a) for a in arrs]))
 
 
+def sl_set_ghost(h, ghost):
+    _, edges, _ = sl_sizes(h)
+    _check(_lib.sl_set_ghost(h, _ptr(_f64(ghost, edges))))
+
+
 def sl_step(h, dt, nsteps):
     _check(_lib.sl_step(h, float(dt), int(nsteps)))
 
@@ -219,6 +227,21 @@ def sl_mean(h, out=None):
         return res
     _check(_lib.sl_mean(h, _ptr(out), 1))
     return None
+
+
+def sl_pdf(h, lo, hi, nbins, out=None):
+    """Per-node histogram counts (nodes, nbins + 2) as uint32 numpy; or into a device pointer."""
+    if out is None:
+        nodes, _, _ = sl_sizes(h)
+        res = np.empty((nodes, int(nbins) + 2), dtype=np.uint32)
+        _check(_lib.sl_pdf(h, float(lo), float(hi), int(nbins), _ptr(res), 0))
+        return res
+    _check(_lib.sl_pdf(h, float(lo), float(hi), int(nbins), _ptr(out), 1))
+    return None
+
+
+def sl_reseed(h):
+    _check(_lib.sl_reseed(h))
 
 
 def sl_get_samples(h, s0, ns, out=None):

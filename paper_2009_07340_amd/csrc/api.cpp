@@ -999,6 +999,22 @@ int sl_set_fields(sl_handle h, const double* u, const double* D, const double* d
   return SL_OK;
 }
 
+int sl_set_ghost(sl_handle h, const double* ghost) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->fields_set) return fail(SL_ESTATE, "sl_set_fields must come before sl_set_ghost");
+  if (h->desc.bc != SL_BC_DIRICHLET) return fail(SL_EINVAL, "ghost values need Dirichlet boundaries");
+  if (!ghost) return fail(SL_EINVAL, "null ghost values");
+  const Layout& L = h->L;
+  for (int64_t i = 0; i < L.edges; ++i)
+    if (!std::isfinite(ghost[i])) return fail(SL_ENONFINITE, "non-finite ghost values");
+  // the device copy may still be read by enqueued steps: wait before overwriting the staging copy
+  SL_HIP(hipStreamSynchronize(h->stream));
+  h->ghost_h.assign(ghost, ghost + L.edges);
+  SL_HIP(hipMemcpyAsync(h->ghost, h->ghost_h.data(), sizeof(double) * L.edges, hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipStreamSynchronize(h->stream));
+  return SL_OK;
+}
+
 int sl_step(sl_handle h, double dt, int32_t nsteps) {
   if (int rc = check_handle(h)) return rc;
   if (!h->fields_set) return fail(SL_ESTATE, "sl_set_fields must come before sl_step");
@@ -1162,6 +1178,48 @@ int sl_mean(sl_handle h, double* out, int32_t out_is_device) {
     SL_HIP(hipMemcpyAsync(&bad, h->d_nonf, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
     SL_HIP(hipStreamSynchronize(h->stream));
     if (bad) return fail(SL_ENONFINITE, std::to_string(bad) + " non-finite sample values at the nodes");
+  }
+  return SL_OK;
+}
+
+int sl_pdf(sl_handle h, double lo, double hi, int32_t nbins, uint32_t* counts, int32_t out_is_device) {
+  if (int rc = check_handle(h)) return rc;
+  if (!counts) return fail(SL_EINVAL, "null output");
+  if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo)) return fail(SL_EINVAL, "need finite lo < hi");
+  if (!std::isfinite((hi - lo) / (double)std::max(nbins, 1)) || !((hi - lo) / std::max(nbins, 1) > 0.0))
+    return fail(SL_EINVAL, "bin width (hi - lo) / nbins must be a positive finite number");
+  if (nbins < 1 || nbins > sl::kPdfMaxBins) return fail(SL_EINVAL, "nbins must be in [1, 254]");
+  const Layout& L = h->L;
+  if (L.M > 0xffffffffll) return fail(SL_EINVAL, "more samples than a 32-bit count holds");
+  const size_t bytes = sizeof(uint32_t) * (size_t)L.nodes * (nbins + 2);
+  uint32_t* dst = counts;
+  void* tmp = nullptr;
+  if (!out_is_device) {
+    if (dev_malloc(&tmp, bytes) != hipSuccess) return fail(SL_ENOMEM, "no device memory for the histogram");
+    dst = (uint32_t*)tmp;
+  }
+  hipError_t e;
+  {
+    ProfScope ps(h, "pdf");
+    e = sl::launch_pdf(h->phi, dst, L.M, L.nodes, lo, hi, nbins, h->stream);
+  }
+  if (e == hipSuccess && !out_is_device) {
+    e = hipMemcpyAsync(counts, dst, bytes, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  }
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(SL_EDEVICE, std::string("pdf: ") + hipGetErrorString(e));
+  return SL_OK;
+}
+
+int sl_reseed(sl_handle h) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->fields_set) return fail(SL_ESTATE, "sl_set_fields must come before sl_reseed");
+  const Layout& L = h->L;
+  {
+    ProfScope ps(h, "reseed");
+    SL_HIP(sl::launch_mean(h->phi, h->mean, h->d_mpart, L.M, L.nodes, h->d_nonf, h->stream));
+    SL_HIP(sl::launch_broadcast(h->phi, h->mean, L.M, L.nodes, h->stream));
   }
   return SL_OK;
 }

@@ -116,6 +116,81 @@ hipError_t mean_scratch_device_ptr(double** out) {
   return hipSuccess;
 }
 
+// Per-node histogram of the samples (Sec. 5.4: the PDF at each grid point by
+// binning).  counts[node][nbins + 2]: column 0 values below lo, 1..nbins the
+// bins of width w = (hi - lo) / nbins, nbins + 1 values at or above hi; a value
+// v in [lo, hi) goes to bin floor((v - lo) / w) capped at nbins - 1 (a
+// correctly rounded subtraction and division, as the oracle); non-finite values
+// are skipped.  Workgroup (x, c): 64 consecutive nodes (one a lane) and the
+// samples of chunk c, each of the 4 wavefronts taking every fourth sample;
+// counts gather in LDS (atomic adds) and are added to the cleared output with
+// integer atomics, so the result does not depend on the order.
+constexpr int kPdfNodes = 64;
+
+__global__ void clear_u32_kernel(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void pdf_kernel(const double* __restrict__ phi, uint32_t* __restrict__ counts,
+                                                  int64_t M, int64_t nodes, int64_t chunk, double lo, double hi,
+                                                  double w, int nbins) {
+  extern __shared__ uint32_t hist[];     // [kPdfNodes][nbins + 2]
+  const int cols = nbins + 2;
+  for (int i = threadIdx.x; i < kPdfNodes * cols; i += 256) hist[i] = 0u;
+  __syncthreads();
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t node = (int64_t)blockIdx.x * kPdfNodes + l;
+  const int64_t s0 = (int64_t)blockIdx.y * chunk;
+  const int64_t s1 = (s0 + chunk) < M ? (s0 + chunk) : M;
+  if (node < nodes) {
+    for (int64_t s = s0 + wv; s < s1; s += 4) {
+      const double v = phi[s * nodes + node];
+      if (!__builtin_isfinite(v)) continue;
+      int col;
+      if (v < lo) {
+        col = 0;
+      } else if (v >= hi) {
+        col = nbins + 1;
+      } else {
+        const double q = floor((v - lo) / w);
+        col = 1 + (q < (double)(nbins - 1) ? (int)q : nbins - 1);
+      }
+      atomicAdd(&hist[l * cols + col], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kPdfNodes * cols; i += 256) {
+    const int nl = i / cols;
+    const int64_t nd = (int64_t)blockIdx.x * kPdfNodes + nl;
+    const uint32_t c = hist[i];
+    if (nd < nodes && c) atomicAdd(&counts[nd * cols + (i - nl * cols)], c);
+  }
+}
+
+size_t pdf_lds_bytes(int nbins) { return sizeof(uint32_t) * kPdfNodes * (size_t)(nbins + 2); }
+
+hipError_t launch_pdf(const double* phi, uint32_t* counts, int64_t M, int64_t nodes, double lo, double hi,
+                      int nbins, hipStream_t st) {
+  const int64_t total = nodes * (int64_t)(nbins + 2);
+  int64_t cb = (total + 255) / 256;
+  if (cb > 65536) cb = 65536;
+  hipLaunchKernelGGL(clear_u32_kernel, dim3((unsigned)cb), dim3(256), 0, st, counts, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tiles = (nodes + kPdfNodes - 1) / kPdfNodes;
+  int64_t C = (2048 + tiles - 1) / tiles;          // about 8 workgroups a compute unit
+  C = C < M / 64 ? C : M / 64;                     // at least 64 samples a chunk
+  if (C < 1) C = 1;
+  if (C > 65535) C = 65535;
+  const int64_t chunk = (M + C - 1) / C;
+  C = (M + chunk - 1) / chunk;
+  const double w = (hi - lo) / nbins;
+  hipLaunchKernelGGL(pdf_kernel, dim3((unsigned)tiles, (unsigned)C), dim3(256), pdf_lds_bytes(nbins), st, phi, counts,
+                     M, nodes, chunk, lo, hi, w, nbins);
+  return hipGetLastError();
+}
+
 __global__ void broadcast_kernel(double* __restrict__ phi, const double* __restrict__ phi0, int64_t total,
                                  int64_t nodes) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)

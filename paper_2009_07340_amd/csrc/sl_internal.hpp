@@ -175,6 +175,11 @@ hipError_t launch_mean(const double* phi, double* out, double* part, int64_t M, 
 // Device address of this device's allocation-free mean scratch (kMeanScratchDoubles doubles).
 hipError_t mean_scratch_device_ptr(double** out);
 hipError_t launch_broadcast(double* phi, const double* phi0, int64_t M, int64_t nodes, hipStream_t st);
+// Per-node histogram of the samples into counts[nodes][nbins + 2] (cleared first).
+constexpr int kPdfMaxBins = 254;
+size_t pdf_lds_bytes(int nbins);
+hipError_t launch_pdf(const double* phi, uint32_t* counts, int64_t M, int64_t nodes, double lo, double hi,
+                      int nbins, hipStream_t st);
 hipError_t launch_debug_normals(double* out, uint64_t seed, uint32_t stream, int64_t step,
                                 int64_t s0, int64_t ns, hipStream_t st);
 hipError_t launch_debug_positions(double* out, const double* xi_node, const double* A, const double* B,

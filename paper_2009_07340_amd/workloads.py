@@ -213,3 +213,64 @@ def request_workload(r):
         phi0 = lambda x, y: np.exp(-((x - 0.3) ** 2 + (y - 0.3) ** 2) / (2.0 * 0.05 ** 2))
     return Workload(f"req{r['id']}", r["dim"], r["kx"], r["ky"], r["N"], r["M"], r["dt"], r["steps"],
                     r["seed"], u=u, D=D, divu=divu, phi0=phi0)
+
+
+# --- the paper's validation cases (Sec. 6) ---------------------------------------
+#
+# Inputs at the paper's parameters.  `exact(x, y, t)` is the closed-form mean
+# field of each case (a solution of the drift-diffusion equation, not part of
+# the method), used for Dirichlet ghost values and by the validation checks;
+# meta["t0"] is the time of the initial field.
+
+def paper_sine_1d(N, samples=1_000_000, kx=1):
+    """Sec. 6.1: [0, 1] periodic, u = 0, D = 1, phi0 = sin(2 pi x) + 2, dt = 1e-5, 50 steps, H = 1.
+    Mean: exp(-4 pi^2 t) sin(2 pi x) + 2."""
+    ex = lambda x, y, t: np.exp(-4.0 * math.pi ** 2 * t) * np.sin(TWO_PI * x) + 2.0
+    return Workload("paper_6_1_sine", 1, kx, 1, N, samples, 1e-5, 50, 61,
+                    u=lambda x, y: (np.zeros(np.shape(x)), np.zeros(np.shape(x))), D=const(1.0),
+                    divu=const(0.0), phi0=lambda x, y: ex(x, y, 0.0), meta=dict(exact=ex, t0=0.0))
+
+
+def paper_gaussian_1d(N, samples=1_000_000, kx=1):
+    """Sec. 6.4: [-1, 1], u = 0, D = 1, phi = exp(-x^2 / (4 t)) / sqrt(4 pi t) from t0 = 0.05,
+    Dirichlet ghost values from that solution, dt = 1e-5, 100 steps, H = 1."""
+    ex = lambda x, y, t: np.exp(-np.asarray(x) ** 2 / (4.0 * t)) / math.sqrt(4.0 * math.pi * t)
+    t0 = 0.05
+    return Workload("paper_6_4_gaussian", 1, kx, 1, N, samples, 1e-5, 100, 64,
+                    u=lambda x, y: (np.zeros(np.shape(x)), np.zeros(np.shape(x))), D=const(1.0),
+                    divu=const(0.0), phi0=lambda x, y: ex(x, y, t0), box=(-1.0, 1.0, 0.0, 1.0),
+                    bc="dirichlet", ghost=lambda x, y, t: ex(x, y, t0 + t), meta=dict(exact=ex, t0=t0))
+
+
+def paper_ou_1d(N=16, samples=100, dt=1e-4, kx=1):
+    """Sec. 6.5: Ornstein-Uhlenbeck, u = -alpha x (alpha = 1, div u = -1), D = 1, x0 = 2, on
+    [-4, 6], Dirichlet ghost values from the density, from t = 0.25 to t = 1, re-seeded every
+    100 steps, Ns = 100.  The paper runs P = 17; the library's largest order is N = 16 (P = 15).
+    The paper does not give dt; 1e-4 keeps the move a tenth of the smallest node spacing.
+    Density (tau = t, the process started from x0 at t = 0):
+    sqrt(a / (2 pi D (1 - e^{-2 a t}))) exp(-a (x - x0 e^{-a t})^2 / (2 D (1 - e^{-2 a t})))."""
+    a, D, x0, t0 = 1.0, 1.0, 2.0, 0.25
+
+    def ex(x, y, t):
+        v = 1.0 - math.exp(-2.0 * a * t)
+        return math.sqrt(a / (2.0 * math.pi * D * v)) * np.exp(-a * (np.asarray(x) - x0 * math.exp(-a * t)) ** 2
+                                                               / (2.0 * D * v))
+    steps = int(round((1.0 - t0) / dt))
+    return Workload("paper_6_5_ou", 1, kx, 1, N, samples, dt, steps, 65,
+                    u=lambda x, y: (-a * np.asarray(x), np.zeros(np.shape(x))), D=const(D),
+                    divu=const(-a), phi0=lambda x, y: ex(x, y, t0), box=(-4.0, 6.0, 0.0, 1.0),
+                    bc="dirichlet", ghost=lambda x, y, t: ex(x, y, t0 + t),
+                    meta=dict(exact=ex, t0=t0, reseed_every=100))
+
+
+def paper_sine_2d(N, samples=10_000, kx=1):
+    """Sec. 6.7: [0, 1]^2, u = 0, D = 1, phi0 = sin(2 pi x) sin(2 pi y) + 2, Dirichlet ghost
+    values from the solution exp(-8 pi^2 t) sin(2 pi x) sin(2 pi y) + 2, dt = 1e-5, 50 steps, H = 1."""
+    ex = lambda x, y, t: np.exp(-8.0 * math.pi ** 2 * t) * np.sin(TWO_PI * x) * np.sin(TWO_PI * y) + 2.0
+    return Workload("paper_6_7_sine2d", 2, kx, kx, N, samples, 1e-5, 50, 67,
+                    u=lambda x, y: (np.zeros(np.shape(x)), np.zeros(np.shape(x))), D=const(1.0),
+                    divu=const(0.0), phi0=lambda x, y: ex(x, y, 0.0), bc="dirichlet",
+                    ghost=lambda x, y, t: ex(x, y, t), meta=dict(exact=ex, t0=0.0))
+
+
+PAPER_CASES = {"6.1": paper_sine_1d, "6.4": paper_gaussian_1d, "6.5": paper_ou_1d, "6.7": paper_sine_2d}

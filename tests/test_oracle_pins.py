@@ -251,3 +251,32 @@ def test_sinusoidal_1d_workload_is_bounded_at_its_step_and_not_at_the_plan_step(
     with np.errstate(all="ignore"):
         bad = sl.run(mesh, f, phi0, wl.dt_specified, 100, wl.seed, s)
     assert not np.all(np.isfinite(bad)) or np.max(np.abs(bad)) > 1e6
+
+
+# ---------------------------------------------------------------- PDF by binning
+
+def test_pdf_counts_match_numpy_histogram_and_count_every_finite_value():
+    """Per node, the in-range columns equal numpy's histogram over [lo, hi) for values that
+    sit on no bin edge; under- and overflow columns and the total account for every finite
+    value; non-finite values are left out."""
+    g = np.random.default_rng(3)
+    x = g.standard_normal((500, 7)) * 1.5
+    x[3, 2], x[10, 4], x[11, 4] = np.nan, np.inf, -np.inf
+    lo, hi, nb = -2.0, 2.5, 9
+    c = sl.pdf_counts(x, lo, hi, nb)
+    for i in range(7):
+        v = x[:, i][np.isfinite(x[:, i])]
+        h, _ = np.histogram(v[(v >= lo) & (v < hi)], bins=nb, range=(lo, hi))
+        np.testing.assert_array_equal(c[i, 1:nb + 1], h)
+        assert c[i, 0] == np.count_nonzero(v < lo) and c[i, nb + 1] == np.count_nonzero(v >= hi)
+        assert c[i].sum() == v.size
+
+
+def test_pdf_counts_at_the_bin_edges():
+    """lo goes to the first bin, hi to the overflow column, the largest double below hi to
+    the last bin; a value at an interior edge lo + k w to bin k when (v - lo) / w rounds to k."""
+    lo, hi, nb = 0.0, 1.0, 4
+    vals = np.array([[0.0, 1.0, np.nextafter(1.0, 0.0), 0.25, 0.5, 0.75, -0.0, np.nextafter(0.0, -1.0)]])
+    c = sl.pdf_counts(vals.T.copy().reshape(-1, 1), lo, hi, nb)[0]
+    # 0.0 and -0.0: bin 0; 0.25: bin 1; 0.5: bin 2; 0.75 and nextafter(1, 0): bin 3; 1.0: over; -tiny: under
+    np.testing.assert_array_equal(c, [1, 2, 1, 1, 2, 1])
