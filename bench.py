@@ -96,7 +96,7 @@ def kernel_sources_digest(wl):
     import hashlib
     csrc = os.path.join(ROOT, "paper_2009_07340_amd", "csrc")
     names = ["sl_internal.hpp", "philox.hpp", "fit1d.hpp"]
-    names += ["k1d.hip"] if wl.dim == 1 else ["k2d.hip", "k2r.hip", "blocks.hpp"]
+    names += ["k1d.hip"] if wl.dim == 1 else ["k2d.hip", "k2r.hip", "blocks.hpp", "kshared.hip"]
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(csrc, n), "rb") as f:
@@ -140,6 +140,9 @@ def main():
                     help="also run a plain 1 GiB device copy (for scaling HBM counters)")
     ap.add_argument("--schedule", default="perorder", choices=list(SCHEDULES) + ["auto"],
                     help="2-D launch schedule (auto: the library's autotuner picks)")
+    ap.add_argument("--path", default="general", choices=["general", "shared"],
+                    help="2-D: the general path, or the shared-geometry path (constant u and D, one order; "
+                         "reported on its own, never as the general path's figure)")
     ap.add_argument("--serve", action="store_true", help="run the serving stream instead")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=50.0)
@@ -185,7 +188,9 @@ def main():
                    hip_stream=stream.cuda_stream, solver=args.solver)
     prob.set_fields()
     fused = 0
-    if wl.dim == 2:
+    if wl.dim == 2 and args.path == "shared":
+        B.sl_set_schedule(prob.h, 0, 0, 0, 1)
+    elif wl.dim == 2:
         if args.schedule == "auto":
             sched = B.sl_autotune(prob.h, wl.dt, 1)
             print(f"[bench] autotuner: {sched}", file=sys.stderr, flush=True)
@@ -218,12 +223,12 @@ def main():
     prob.step(wl.dt, steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kname = kernel_name(wl, fused, solver)
+    kname = "shared_update" if args.path == "shared" else kernel_name(wl, fused, solver)
     launches, kms = B.sl_kernel_time(prob.h, kname)
     d1 = B.sl_diag(prob.h)
     others = {}
     for other in ("fit2d_phase1", "fit2d_phase2", "fit2r_phase1", "fit2r_phase2", "fit2d_fused_phase1",
-                  "fit2d_fused_phase2", "resident_1d"):
+                  "fit2d_fused_phase2", "resident_1d", "shared_build", "shared_traces", "shared_update"):
         if other != kname:
             n_o, ms_o = B.sl_kernel_time(prob.h, other)
             if n_o:
@@ -249,6 +254,24 @@ def main():
                 "traffic": stored_traffic(wl, kname, args.precision),
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_fit_step": round(fit_flops_1d(N), 1)}
+    elif args.path == "shared":
+        # dense float64 products on the matrix cores: per element-sample 2 n (n + T) for the update
+        # (T = 4N edge points), and 2 T n for the traces (reported beside it)
+        N = int(wl.order)
+        n, T = N * N, 4 * N
+        per_launch = 2.0 * n * (n + T) * wl.K * wl.samples
+        achieved = per_launch * launches / (kms * 1e-3) / 1e12
+        n_t, ms_t = B.sl_kernel_time(prob.h, "shared_traces")
+        n_b, ms_b = B.sl_kernel_time(prob.h, "shared_build")
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": MI355X["fp64_mfma_tflops"],
+                "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_mfma_tflops"], 4),
+                "traffic": stored_traffic(wl, kname, "shared"),
+                "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
+                "flops_per_launch": per_launch, "flops_per_element_sample": 2 * n * (n + T),
+                "traces_kernel": {"ms": round(ms_t, 4), "launches": n_t,
+                                  "tflops": round(2.0 * T * n * wl.K * wl.samples * n_t / (ms_t * 1e-3) / 1e12, 3)
+                                  if ms_t else None},
+                "build_kernel_ms": round(ms_b, 4)}
     elif solver == 2:
         # float64 VALU work of the reference solver with the iteration counts of the timed steps
         fits = wl.K * wl.samples * steps
@@ -303,7 +326,8 @@ def main():
     }
     if wl.dim == 2:
         out["config"]["schedule"] = sched_used
-        out["config"]["solver"] = {1: "factor", 2: "reference"}[solver]
+        out["config"]["solver"] = "shared-geometry path" if args.path == "shared" else {1: "factor", 2: "reference"}[solver]
+        out["config"]["path"] = args.path
     print(json.dumps(out), flush=True)
 
 

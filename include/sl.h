@@ -236,8 +236,22 @@ typedef struct sl_schedule_t {
   int32_t graph;
   int32_t grid;
   float ms_per_step;
+  int32_t shared;   /* 1: the shared-geometry path (below); fused, graph and grid are then unused */
 } sl_schedule_t;
 
+/* Shared-geometry path (schedule.shared = 1; 2-D meshes of one order N <= 12,
+ * at most 65535 samples): when drift, diffusion and div u are the same at every
+ * node, every element of a sample moves by the same displacement (Sec. 5.2,
+ * eq. def_dx), so in the frame centred on it all elements share one
+ * interpolation problem.  Per step and sample one small kernel builds the
+ * remap as two operators, the interpolation Phi to the Gauss nodes and the
+ * boundary correction Mg (range-space multipliers of the constrained least
+ * squares, Sec. 5.3), plus the trace operator C*; the elements of the sample
+ * are then advanced as dense products on the float64 matrix cores:
+ * t = C* f, phi_new = Phi f + Mg (g - t) with g the upwinded traces (eq.
+ * bnd_update).  The result agrees with the general path to rounding.  A step
+ * on this path returns SL_EUNSUPPORTED when the mesh or the fields do not
+ * qualify.  It never replaces the general path on its own. */
 int sl_set_schedule(sl_handle h, const sl_schedule_t* s);
 int sl_get_schedule(sl_handle h, sl_schedule_t* s);
 

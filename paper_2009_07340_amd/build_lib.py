@@ -18,7 +18,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=o
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + SRC, "-I" + os.path.join(os.path.dirname(HERE), "include"), "-Wall", "-Wno-unused-function"]
 
-SOURCES = ["api.cpp", "tables.cpp", "k1d.hip", "k2d.hip", "k2r.hip", "kmisc.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "k1d.hip", "k2d.hip", "k2r.hip", "kmisc.hip", "kshared.hip"]
 
 
 def _compile(src):

@@ -78,7 +78,8 @@ struct Layout {
   // byte offsets in the workspace
   size_t o_phi, o_phi2, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
-  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, total;
+  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_sops, o_bw, total;
+  bool shared_capable = false;      // one order <= kMaxNShared in 2-D: the shared-geometry path can run
   int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
   size_t gx_doubles = 0;
   int max_iter = 32;
@@ -182,6 +183,9 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
     L.o_mpart = take(C > 1 ? sizeof(double) * (size_t)C * L.nodes : 0);
   }
   L.o_gxinv = take(sizeof(double) * (L.gx_doubles + 1));
+  L.shared_capable = L.dim == 2 && L.uniform && L.maxN <= sl::kMaxNShared;
+  L.o_sops = take(L.shared_capable ? sizeof(double) * (size_t)L.M * sl::shared_op_doubles(L.maxN) : 0);
+  L.o_bw = take(sizeof(double) * sl::kMaxN);
   L.total = o;
   return SL_OK;
 }
@@ -228,6 +232,9 @@ struct sl_ctx {
   unsigned long long* d_nonf = nullptr;  // non-finite values seen by the last sample mean
   double* d_mpart = nullptr;             // partial sums of the sample mean
   double* d_gxinv = nullptr;
+  double* d_sops = nullptr;              // shared-geometry path: per-sample operators
+  double* d_bw = nullptr;                // barycentric weights of the (single) order's nodes
+  bool shared_geometry = false;          // the current step coefficients are the same at every node
   hipStream_t cap_stream = nullptr;      // private stream for graph capture
   // measurement
   bool profile = false;
@@ -324,6 +331,12 @@ int update_coefficients(sl_ctx* h, double dt) {
   h->coeff_valid = true;
   h->coeff_dt = dt;
   h->max_disp_ratio = maxratio;
+  // shared geometry: every node moves by the same displacement and carries the same source factor
+  bool same = L.dim == 2 && L.uniform;
+  for (int64_t k = 1; same && k < L.nodes; ++k)
+    same = h->hA[2 * k] == h->hA[0] && h->hA[2 * k + 1] == h->hA[1] && h->hB[2 * k] == h->hB[0] &&
+           h->hB[2 * k + 1] == h->hB[1] && h->hsrc[k] == h->hsrc[0];
+  h->shared_geometry = same;
   return SL_OK;
 }
 
@@ -698,6 +711,46 @@ int step_1d(sl_ctx* h, int32_t nsteps, hipStream_t st) {
   return SL_OK;
 }
 
+// nsteps steps on the shared-geometry path (per-sample operators, then the
+// batched trace and update products), host step counter.
+int step_shared(sl_ctx* h, int32_t nsteps) {
+  const Layout& L = h->L;
+  if (!L.shared_capable)
+    return fail(SL_EUNSUPPORTED, "the shared-geometry path needs a 2-D mesh of one order N <= 12");
+  if (!h->shared_geometry)
+    return fail(SL_EUNSUPPORTED, "the shared-geometry path needs the same drift, diffusion and source factor at every node");
+  if (L.M > 65535) return fail(SL_EUNSUPPORTED, "the shared-geometry path runs at most 65535 samples");
+  const int N = L.order[0];
+  sl::SharedArgs a{};
+  a.A = h->A;
+  a.B = h->B;
+  a.src = h->hsrc[0];
+  a.Af = h->Af;
+  a.Bf = h->Bf;
+  a.ghost = h->ghost;
+  a.nbr = h->d_nbr;
+  a.xi = h->d_xitab + N * sl::kMaxN;
+  a.bw = h->d_bw;
+  a.ur = h->d_ur;   // one order in the mesh: its U_r is the first table
+  a.ops = h->d_sops;
+  a.phi = h->phi;
+  a.tr = h->tr;
+  a.K = L.K;
+  a.step_ptr = nullptr;
+  a.seed = h->desc.seed;
+  a.stream = h->desc.stream_id;
+  static const char* const names[3] = {"shared_build", "shared_traces", "shared_update"};
+  for (int it = 0; it < nsteps; ++it) {
+    a.step = h->step + it;
+    for (int stage = 0; stage < 3; ++stage) {
+      ProfScope ps(h, names[stage]);
+      SL_HIP(sl::launch_shared_step(N, stage, a, L.M, h->stream));
+    }
+  }
+  h->step += nsteps;
+  return SL_OK;
+}
+
 std::string tune_key(const sl_ctx* h) {
   std::ostringstream k;
   const Layout& L = h->L;
@@ -783,6 +836,8 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_nonf = (unsigned long long*)(h->ws + L.o_nonf);
   h->d_mpart = (double*)(h->ws + L.o_mpart);
   h->d_gxinv = (double*)(h->ws + L.o_gxinv);
+  h->d_sops = (double*)(h->ws + L.o_sops);
+  h->d_bw = (double*)(h->ws + L.o_bw);
   // element tables, work list grouped by order, node tables, U_r and trace interpolation
   std::vector<int32_t> nbr(4 * (size_t)L.K, -1), work;
   for (int e = 0; e < L.K; ++e) {
@@ -841,6 +896,11 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       o += G.size();
     }
   }
+  std::vector<double> bw(sl::kMaxN, 0.0);
+  {
+    const auto w = sl::barycentric_weights(h->xi_tab[L.order[0]]);
+    std::copy(w.begin(), w.end(), bw.begin());
+  }
   std::vector<int64_t> noff64(L.noff.begin(), L.noff.end() - 1), eoff64(L.eoff.begin(), L.eoff.end() - 1);
   std::vector<int32_t> order32(L.order.begin(), L.order.end());
   struct Up { void* dst; const void* src; size_t bytes; };
@@ -851,7 +911,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       {h->d_ur, ur.data(), sizeof(double) * ur.size()}, {h->d_uroff, uroff.data(), sizeof(int64_t) * uroff.size()},
       {h->d_interp, interp.data(), sizeof(double) * interp.size()},
       {h->d_interpoff, interpoff.data(), sizeof(int64_t) * interpoff.size()},
-      {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}};
+      {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}, {h->d_bw, bw.data(), sizeof(double) * bw.size()}};
   for (const auto& u : ups) {
     if (hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
       if (h->own_ws) (void)hipFree(h->ws);
@@ -1023,6 +1083,7 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
   if (nsteps == 0) return SL_OK;
   if (int rc = update_coefficients(h, dt)) return rc;
   const Layout& L = h->L;
+  if (h->sched.shared) return step_shared(h, nsteps);
   if (L.dim == 2) return step_2d({h}, nsteps, h->sched.fused, h->sched.graph, h->sched.grid, h->stream);
   return step_1d(h, nsteps, h->stream);
 }
@@ -1055,8 +1116,9 @@ int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t ns
 int sl_set_schedule(sl_handle h, const sl_schedule_t* s) {
   if (int rc = check_handle(h)) return rc;
   if (!s) return fail(SL_EINVAL, "null schedule");
-  if ((s->fused != 0 && s->fused != 1) || (s->graph != 0 && s->graph != 1) || s->grid < 0 || s->grid > (1 << 24))
-    return fail(SL_EINVAL, "schedule: fused and graph are 0 or 1, 0 <= grid <= 2^24");
+  if ((s->fused != 0 && s->fused != 1) || (s->graph != 0 && s->graph != 1) || s->grid < 0 || s->grid > (1 << 24) ||
+      (s->shared != 0 && s->shared != 1))
+    return fail(SL_EINVAL, "schedule: fused, graph and shared are 0 or 1, 0 <= grid <= 2^24");
   h->sched = *s;
   return SL_OK;
 }

@@ -145,6 +145,33 @@ struct Batch1DArgs {
   int nsteps;
 };
 
+// Shared-geometry 2-D step (constant drift, diffusion and source factor, one
+// order): per-sample operators, then batched products over the elements.
+struct SharedArgs {
+  const double* A;       // [nodes][2]: the first node's values are every node's
+  const double* B;       // [nodes][2]
+  double src;            // 1 - dt div u, the same at every node
+  const double* Af;      // [edges]
+  const double* Bf;      // [edges]
+  const double* ghost;   // [edges]
+  const int32_t* nbr;    // [K][4]
+  const double* xi;      // [N] reference nodes
+  const double* bw;      // [N] barycentric weights of the reference nodes
+  const double* ur;      // U_r, column-major 4N x (4N - 4)
+  double* ops;           // [M][shared_op_doubles(N)] per-sample operators
+  double* phi;           // [M][K n]
+  double* tr;            // [M][K 4N]
+  int64_t K;
+  int64_t step;
+  const int64_t* step_ptr;
+  uint64_t seed;
+  uint32_t stream;
+};
+constexpr int kMaxNShared = 12;   // largest order of the shared-geometry path
+size_t shared_op_doubles(int N);
+// stage 0: per-sample operators; 1: traces; 2: update of the samples
+hipError_t launch_shared_step(int N, int stage, const SharedArgs& a, int64_t M, hipStream_t st);
+
 // Host launchers (defined in the .hip files).
 hipError_t launch_fit2d(int phase, int N, int mode, const Params2D& p, int64_t nfits, hipStream_t st);
 size_t fit2d_lds_bytes(int N, int mode, int phase);

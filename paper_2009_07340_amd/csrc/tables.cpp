@@ -100,6 +100,18 @@ static void lagrange_row(const std::vector<double>& from, double x, double* out)
   }
 }
 
+std::vector<double> barycentric_weights(const std::vector<double>& xi) {
+  const int n = (int)xi.size();
+  std::vector<double> w(n);
+  for (int i = 0; i < n; ++i) {
+    long double p = 1.0L;
+    for (int m = 0; m < n; ++m)
+      if (m != i) p *= (long double)xi[i] - (long double)xi[m];
+    w[i] = (double)(1.0L / p);
+  }
+  return w;
+}
+
 std::vector<double> lagrange_matrix(const std::vector<double>& from, const std::vector<double>& to) {
   std::vector<double> L(to.size() * from.size());
   for (size_t i = 0; i < to.size(); ++i) lagrange_row(from, to[i], &L[i * from.size()]);
