@@ -52,7 +52,7 @@ def fit_flops_2d_phase2(N):
         + n * R * (R + 1) + R ** 3 / 3.0 + 2 * R * R + 2 * n * R + 2 * n * n + 2 * n * N
 
 
-def fit_flops_2d_ref(N, phase, iters):
+def fit_flops_2d_ref(N, phase, iters, ncomp=1):
     """Float64 operations of one 2-D fit with the reference-preconditioned solver, as
     the kernel performs them (multiply-add = 2), for `iters` conjugate-gradient
     iterations:  n = N^2, T = 4N, R = 4N - 4, H = N + 2.
@@ -61,22 +61,25 @@ def fit_flops_2d_ref(N, phase, iters):
       C c: 2T(N^2 + N);  C^T v: 6nN;  U_r^T, U_r: 2TR each;  S0^-1 w: 2R^2;
       projection = 2 G0^-1 + C + U_r^T + S0^-1 + U_r + C^T + n;
       phase 2 set-up: H tables 4H^2(N^2 + N), T U_r 3T^2 R, S0 2R^2 T (lower half R^2 T),
-      Cholesky, inverse and X^T X of S0 R^3;  evaluation 2n(N^2 + N)."""
+      Cholesky, inverse and X^T X of S0 R^3;  evaluation 2n(N^2 + N).
+    With ncomp components the moves, tables and the phase-2 set-up are done once per
+    fit and the rest (b, the iterations, traces or evaluation) once per component."""
     n, T, R, H = N * N, 4 * N, 4 * N - 4, N + 2
-    setup = 8 * n + 12 * n * N + 3 * n * n
+    geom = 8 * n + 12 * n * N
+    rhs = 3 * n * n
     g_apply = 2 * n * (N * N + N) + 3 * n * n
     g0 = 4 * N ** 3
     c_op, ct_op, u_op, s_op = 2 * T * (N * N + N), 6 * n * N, 2 * T * R, 2 * R * R
     if phase == 1:
         start = g0 + 2 * n + g_apply + n + g0 + 4 * n
         per_it = g_apply + 2 * n + 4 * n + g0 + 4 * n + 2 * n
-        return setup + start + iters * per_it + c_op
+        return geom + ncomp * (rhs + start + iters * per_it + c_op)
     proj = 2 * g0 + c_op + 2 * u_op + s_op + ct_op + n
     build = 4 * H * H * (N * N + N) + 3 * T * T * R + R * R * T + R ** 3 + u_op
     start = proj + 2 * n + g_apply + n + proj + n + 4 * n
     per_it = g_apply + 2 * n + 4 * n + proj + n + 4 * n + 2 * n
     final = c_op + 2 * u_op + s_op + ct_op + g0 + n
-    return setup + build + start + iters * per_it + final + 2 * n * (N * N + N)
+    return geom + build + ncomp * (rhs + start + iters * per_it + final + 2 * n * (N * N + N))
 
 
 SCHEDULES = {"perorder": (0, 0), "fused": (1, 0), "perorder_graph": (0, 1), "fused_graph": (1, 1)}
@@ -133,6 +136,8 @@ def main():
                     help="samples compared with the oracle (default: one per worker process)")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--samples", type=int, default=None)
+    ap.add_argument("--ncomp", type=int, default=1,
+                    help="components of a vector-valued field sharing the moved points (node-updates count each)")
     ap.add_argument("--solver", default="auto", choices=["auto", "factor", "reference"],
                     help="2-D least-squares solver (auto: reference for fp64, factor for the mixed modes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -182,10 +187,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    nbytes = Problem.required_bytes(wl, args.precision, solver=args.solver)
+    nbytes = Problem.required_bytes(wl, args.precision, solver=args.solver, ncomp=args.ncomp)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)       # device memory from torch
     prob = Problem(wl, precision=args.precision, dev_ws=ws.data_ptr(), ws_bytes=nbytes,
-                   hip_stream=stream.cuda_stream, solver=args.solver)
+                   hip_stream=stream.cuda_stream, solver=args.solver, ncomp=args.ncomp)
     prob.set_fields()
     fused = 0
     if wl.dim == 2 and args.path == "shared":
@@ -203,7 +208,7 @@ def main():
     l2 = None
     if check_steps > 0:
         prob.step(wl.dt, check_steps)             # untimed: compared with the oracle
-        got = prob.samples(0, check_samples)
+        got = prob.samples(0, check_samples)[:, :prob.nodes]     # component 0 (the workload's own field)
         if oracle is not None:
             ref = oracle["ref"]
             dif = np.abs(got - ref)
@@ -237,7 +242,7 @@ def main():
     sched_used = B.sl_get_schedule(prob.h) if wl.dim == 2 else None
     elapsed = t1 - t0
     nodes_per_sample = prob.nodes
-    node_updates = float(nodes_per_sample) * wl.samples * steps
+    node_updates = float(nodes_per_sample) * wl.samples * args.ncomp * steps
     value = node_updates / elapsed
     mean = prob.mean()
     finite = bool(np.all(np.isfinite(mean)))
@@ -247,7 +252,7 @@ def main():
     # roofline of the dominant kernel
     if wl.dim == 1:
         N = int(wl.order)
-        flops = fit_flops_1d(N) * wl.K * wl.samples * steps
+        flops = fit_flops_1d(N) * wl.K * wl.samples * args.ncomp * steps
         achieved = flops / (kms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X["fp64_vector_tflops"],
                 "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_vector_tflops"], 4),
@@ -259,7 +264,7 @@ def main():
         # (T = 4N edge points), and 2 T n for the traces (reported beside it)
         N = int(wl.order)
         n, T = N * N, 4 * N
-        per_launch = 2.0 * n * (n + T) * wl.K * wl.samples
+        per_launch = 2.0 * n * (n + T) * wl.K * wl.samples * args.ncomp
         achieved = per_launch * launches / (kms * 1e-3) / 1e12
         n_t, ms_t = B.sl_kernel_time(prob.h, "shared_traces")
         n_b, ms_b = B.sl_kernel_time(prob.h, "shared_build")
@@ -269,16 +274,16 @@ def main():
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_launch": per_launch, "flops_per_element_sample": 2 * n * (n + T),
                 "traces_kernel": {"ms": round(ms_t, 4), "launches": n_t,
-                                  "tflops": round(2.0 * T * n * wl.K * wl.samples * n_t / (ms_t * 1e-3) / 1e12, 3)
+                                  "tflops": round(2.0 * T * n * wl.K * wl.samples * args.ncomp * n_t / (ms_t * 1e-3) / 1e12, 3)
                                   if ms_t else None},
                 "build_kernel_ms": round(ms_b, 4)}
     elif solver == 2:
         # float64 VALU work of the reference solver with the iteration counts of the timed steps
-        fits = wl.K * wl.samples * steps
+        fits = wl.K * wl.samples * args.ncomp * steps
         it2 = (d1["solver_iterations"][1] - d0["solver_iterations"][1]) / fits
         it1 = (d1["solver_iterations"][0] - d0["solver_iterations"][0]) / fits
         orders = wl.order_array()
-        per_launch = sum(fit_flops_2d_ref(int(N), 2, it2) for N in orders) * wl.samples
+        per_launch = sum(fit_flops_2d_ref(int(N), 2, it2, args.ncomp) for N in orders) * wl.samples
         flops = per_launch * launches
         achieved = flops / (kms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X["fp64_vector_tflops"],
@@ -291,7 +296,7 @@ def main():
                 "other_kernels": others}
     else:
         orders = wl.order_array()
-        per_launch = sum(fit_flops_2d_phase2(int(N)) for N in orders) * wl.samples
+        per_launch = sum(fit_flops_2d_phase2(int(N)) for N in orders) * wl.samples * args.ncomp
         flops = per_launch * launches
         achieved = flops / (kms * 1e-3) / 1e12
         peak = MI355X["fp64_mfma_tflops"] if args.precision == "fp64" else MI355X["fp32_mfma_tflops"]
@@ -318,7 +323,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else args.precision, "data": "synthetic",
         "config": {"workload": wl.name, "dim": wl.dim, "elements": wl.K, "order": int(wl.order) if np.isscalar(wl.order) else "mixed",
                    "samples": wl.samples, "dt": wl.dt, "dt_specified": wl.dt_specified, "precision": args.precision,
-                   "fits_per_step": wl.K * wl.samples, "nodes_per_sample": nodes_per_sample,
+                   "fits_per_step": wl.K * wl.samples * args.ncomp, "nodes_per_sample": nodes_per_sample,
+                   "ncomp": args.ncomp,
                    "element_sample_fits_per_s": wl.K * wl.samples * steps / elapsed},
         "roofline": roof,
         "cpu_baseline": cpu,

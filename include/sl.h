@@ -32,7 +32,9 @@
  *   x = x0 + hx*(ex + xi_ix),  y = y0 + hy*(ey + xi_iy),  hx = (x1-x0)/kx.
  * Per-sample node arrays are ragged: element e occupies entries
  * [off_e, off_e + n_e) with off_e = sum_{e'<e} n_e'; "nodes" below is the
- * total sum_e n_e per sample.
+ * total sum_e n_e per sample.  A vector-valued field (desc.ncomp = C > 1)
+ * stores C such arrays per sample, component-major: [sample][component][node];
+ * the mean is [component][node] and a sample-range copy [ns][component][node].
  *
  * Edges: 1-D element e has edges L (xi = 0) and R (xi = 1), one point each;
  * 2-D element e has edges W (xi = 0), E (xi = 1), S (eta = 0), N (eta = 1),
@@ -69,7 +71,7 @@
 extern "C" {
 #endif
 
-#define SL_ABI_VERSION 2
+#define SL_ABI_VERSION 3
 
 enum sl_status {
   SL_OK = 0,
@@ -124,6 +126,12 @@ typedef struct sl_mesh_desc {
   int32_t max_iter;       /* reference solver: iteration limit per fit, 0 = default (32) */
   double tol;             /* reference solver: stop when the preconditioned residual, relative
                              to the starting iterate, is below tol; 0 = default (1e-13) */
+  int32_t ncomp;          /* components of a vector-valued field phi* (Sec. 5.3, last paragraph:
+                             every component is defined on the same advected points), 1..64;
+                             0 means 1.  Every component of a sample takes the same node moves
+                             (the sample's Wiener increments) and is remapped on its own, with its
+                             own boundary data; the 2-D reference solver shares each fit's
+                             geometry, constraint matrix and its inverse across the components */
 } sl_mesh_desc;
 
 typedef struct sl_diag_t {
@@ -154,6 +162,7 @@ typedef struct sl_diag_t {
                                  last float64 refinement correction, max|dc| / max|c|; 0 where
                                  neither applies (1-D, float64 factorisation); NaN if a fit met one */
   int64_t nonfinite;          /* non-finite sample values met by the last sl_mean (0: all finite) */
+  int32_t ncomp;              /* components of the field */
 } sl_diag_t;
 
 /* Device bytes sl_init_mesh needs for this description (state, traces, fields,
@@ -169,8 +178,9 @@ int sl_required_bytes(const sl_mesh_desc* desc, size_t* bytes);
 int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* hip_stream,
                  sl_handle* out);
 
-/* Per-sample sizes: nodes, edge points, elements. */
-int sl_sizes(sl_handle h, int64_t* nodes, int64_t* edge_points, int64_t* elements);
+/* Per-sample sizes: nodes and edge points (of one component), elements, and the
+ * number of components (any output pointer may be NULL). */
+int sl_sizes(sl_handle h, int64_t* nodes, int64_t* edge_points, int64_t* elements, int32_t* ncomp);
 
 /* Physical coordinates of the nodes ([nodes][dim]) and of the edge points
  * ([edge points][dim]) where the caller samples the fields.  Host buffers.
@@ -189,8 +199,8 @@ int sl_ref_nodes(sl_handle h, int32_t N, double* host_xi);
  *   un [edge points] normal drift; Dn [edge points] diffusion at edge points;
  *   ghost [edge points] Dirichlet ghost values (required iff bc = DIRICHLET;
  *     only entries on the domain boundary are read);
- *   phi0 [nodes] initial field, NULL keeps the current samples; when given,
- *     every sample is set to phi0 and the step counter to 0.
+ *   phi0 [ncomp][nodes] initial field, NULL keeps the current samples; when
+ *     given, every sample is set to phi0 and the step counter to 0.
  * Values must be finite (SL_ENONFINITE otherwise). */
 int sl_set_fields(sl_handle h, const double* u, const double* D, const double* divu,
                   const double* un, const double* Dn, const double* ghost, const double* phi0);

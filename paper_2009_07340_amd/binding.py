@@ -32,7 +32,7 @@ class sl_mesh_desc(C.Structure):
                 ("n_uniform", C.c_int32), ("order", C.POINTER(C.c_int32)), ("nodes", C.c_int32),
                 ("bc", C.c_int32), ("samples", C.c_int64), ("seed", C.c_uint64), ("stream_id", C.c_uint32),
                 ("precision", C.c_int32), ("refine_iters", C.c_int32), ("solver", C.c_int32),
-                ("max_iter", C.c_int32), ("tol", C.c_double)]
+                ("max_iter", C.c_int32), ("tol", C.c_double), ("ncomp", C.c_int32)]
 
 
 class sl_diag_t(C.Structure):
@@ -40,7 +40,7 @@ class sl_diag_t(C.Structure):
                 ("max_disp_ratio", C.c_double), ("precision", C.c_int32), ("refine_iters", C.c_int32),
                 ("device_bytes", C.c_size_t), ("solver", C.c_int32), ("solver_iterations", C.c_int64 * 2),
                 ("solver_unconverged", C.c_int64 * 2), ("escapes", C.c_int64), ("max_residual", C.c_double),
-                ("nonfinite", C.c_int64)]
+                ("nonfinite", C.c_int64), ("ncomp", C.c_int32)]
 
 
 class sl_schedule_t(C.Structure):
@@ -71,7 +71,7 @@ _D = C.POINTER(C.c_double)
 _SIGS = {
     "sl_required_bytes": [C.POINTER(sl_mesh_desc), C.POINTER(C.c_size_t)],
     "sl_init_mesh": [C.POINTER(sl_mesh_desc), _P, C.c_size_t, _P, C.POINTER(_P)],
-    "sl_sizes": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "sl_sizes": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)],
     "sl_node_coords": [_P, _P],
     "sl_edge_coords": [_P, _P, _P],
     "sl_ref_nodes": [_P, C.c_int32, _P],
@@ -133,7 +133,7 @@ def _f64(a, n=None):
 
 
 def make_desc(dim, kx, ky=1, box=(0.0, 1.0, 0.0, 1.0), order=8, nodes="gl", bc="periodic", samples=1,
-              seed=0, stream_id=0, precision="fp64", refine_iters=-1, solver="auto", max_iter=0, tol=0.0):
+              seed=0, stream_id=0, precision="fp64", refine_iters=-1, solver="auto", max_iter=0, tol=0.0, ncomp=1):
     d = sl_mesh_desc()
     d.dim, d.kx, d.ky = dim, kx, ky if dim == 2 else 1
     d.x0, d.x1, d.y0, d.y1 = (float(v) for v in box)
@@ -151,6 +151,7 @@ def make_desc(dim, kx, ky=1, box=(0.0, 1.0, 0.0, 1.0), order=8, nodes="gl", bc="
     d.refine_iters = int(refine_iters)
     d.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     d.max_iter, d.tol = int(max_iter), float(tol)
+    d.ncomp = int(ncomp)
     d._keep = keep
     return d
 
@@ -170,9 +171,22 @@ def sl_init_mesh(desc, dev_ws=None, ws_bytes=0, hip_stream=None):
 
 
 def sl_sizes(h):
-    n, e, k = C.c_int64(), C.c_int64(), C.c_int64()
-    _check(_lib.sl_sizes(h, C.byref(n), C.byref(e), C.byref(k)))
+    """(nodes, edge points, elements) of one component."""
+    n, e, k, c = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+    _check(_lib.sl_sizes(h, C.byref(n), C.byref(e), C.byref(k), C.byref(c)))
     return n.value, e.value, k.value
+
+
+def sl_ncomp(h):
+    c = C.c_int32()
+    _check(_lib.sl_sizes(h, None, None, None, C.byref(c)))
+    return c.value
+
+
+def _row(h):
+    """Values per sample: nodes x components."""
+    nodes, _, _ = sl_sizes(h)
+    return nodes * sl_ncomp(h)
 
 
 def sl_node_coords(h, dim):
@@ -200,7 +214,7 @@ def sl_set_fields(h, u, D, divu, un, Dn, ghost=None, phi0=None):
     nodes, edges, _ = sl_sizes(h)
     arrs = [_f64(u), _f64(D, nodes), None if divu is None else _f64(divu, nodes), _f64(un, edges),
             _f64(Dn, edges), None if ghost is None else _f64(ghost, edges),
-            None if phi0 is None else _f64(phi0, nodes)]
+            None if phi0 is None else _f64(phi0, nodes * sl_ncomp(h))]
     _check(_lib.sl_set_fields(h, *[_ptr(a) for a in arrs]))
 
 
@@ -222,8 +236,7 @@ def sl_step_batch(hs, dts, nsteps):
 def sl_mean(h, out=None):
     """Host mean (numpy) when out is None; else out is a device pointer (int)."""
     if out is None:
-        nodes, _, _ = sl_sizes(h)
-        res = np.empty(nodes)
+        res = np.empty(_row(h))
         _check(_lib.sl_mean(h, _ptr(res), 0))
         return res
     _check(_lib.sl_mean(h, _ptr(out), 1))
@@ -233,8 +246,7 @@ def sl_mean(h, out=None):
 def sl_pdf(h, lo, hi, nbins, out=None):
     """Per-node histogram counts (nodes, nbins + 2) as uint32 numpy; or into a device pointer."""
     if out is None:
-        nodes, _, _ = sl_sizes(h)
-        res = np.empty((nodes, int(nbins) + 2), dtype=np.uint32)
+        res = np.empty((_row(h), int(nbins) + 2), dtype=np.uint32)
         _check(_lib.sl_pdf(h, float(lo), float(hi), int(nbins), _ptr(res), 0))
         return res
     _check(_lib.sl_pdf(h, float(lo), float(hi), int(nbins), _ptr(out), 1))
@@ -246,7 +258,7 @@ def sl_reseed(h):
 
 
 def sl_get_samples(h, s0, ns, out=None):
-    nodes, _, _ = sl_sizes(h)
+    nodes = _row(h)
     if out is None:
         res = np.empty((ns, nodes))
         _check(_lib.sl_get_samples(h, int(s0), int(ns), _ptr(res), 0))
@@ -260,7 +272,7 @@ def sl_set_samples(h, s0, data):
         ptr, ns = data
         _check(_lib.sl_set_samples(h, int(s0), int(ns), _ptr(ptr), 1))
         return
-    nodes, _, _ = sl_sizes(h)
+    nodes = _row(h)
     a = _f64(data)
     ns = a.size // nodes
     _check(_lib.sl_set_samples(h, int(s0), ns, _ptr(a), 0))

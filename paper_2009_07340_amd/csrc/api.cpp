@@ -71,6 +71,8 @@ struct Layout {
   std::vector<int> order;
   std::vector<int64_t> noff, eoff;
   int64_t nodes = 0, edges = 0, M = 0;
+  int nc = 1;                       // components of the field (vector-valued phi*)
+  int64_t MV = 0;                   // rows of `nodes` values in the state: M * nc
   int maxN = 0;
   bool uniform = true;
   std::vector<int> orders;          // distinct orders present, increasing
@@ -133,6 +135,9 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.nodes = L.noff[L.K];
   L.edges = L.eoff[L.K];
   L.M = d->samples;
+  if (d->ncomp < 0 || d->ncomp > 64) return fail(SL_EINVAL, "ncomp must be in [0, 64] (0 means 1)");
+  L.nc = d->ncomp > 1 ? d->ncomp : 1;
+  L.MV = L.M * L.nc;
   for (int N : L.order)
     if (std::find(L.orders.begin(), L.orders.end(), N) == L.orders.end()) L.orders.push_back(N);
   std::sort(L.orders.begin(), L.orders.end());
@@ -143,17 +148,17 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
         if (Nd != Ns) L.interp_doubles += (size_t)Nd * Ns;
     for (int N : L.orders) L.gx_doubles += (size_t)N * N;
   }
-  if ((double)L.M * (double)L.nodes * 8.0 > 250e9) return fail(SL_ENOMEM, "state exceeds device memory");
+  if ((double)L.MV * (double)L.nodes * 8.0 > 250e9) return fail(SL_ENOMEM, "state exceeds device memory");
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
     o += align256(bytes);
     return at;
   };
-  L.o_phi = take(sizeof(double) * (size_t)L.M * L.nodes);
+  L.o_phi = take(sizeof(double) * (size_t)L.MV * L.nodes);
   // 1-D meshes of more than 256 elements step out of place (tiled kernel)
-  L.o_phi2 = take(L.dim == 1 && L.K > 256 ? sizeof(double) * (size_t)L.M * L.nodes : 0);
-  L.o_tr = take(L.dim == 2 ? sizeof(double) * (size_t)L.M * L.edges : 0);
+  L.o_phi2 = take(L.dim == 1 && L.K > 256 ? sizeof(double) * (size_t)L.MV * L.nodes : 0);
+  L.o_tr = take(L.dim == 2 ? sizeof(double) * (size_t)L.MV * L.edges : 0);
   L.o_xi = take(sizeof(double) * L.nodes * L.dim);
   L.o_A = take(sizeof(double) * L.nodes * L.dim);
   L.o_B = take(sizeof(double) * L.nodes * L.dim);
@@ -161,8 +166,8 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_Af = take(sizeof(double) * L.edges);
   L.o_Bf = take(sizeof(double) * L.edges);
   L.o_ghost = take(sizeof(double) * L.edges);
-  L.o_mean = take(sizeof(double) * L.nodes);
-  L.o_phi0 = take(sizeof(double) * L.nodes);
+  L.o_mean = take(sizeof(double) * L.nc * L.nodes);
+  L.o_phi0 = take(sizeof(double) * L.nc * L.nodes);
   L.o_order = take(sizeof(int32_t) * L.K);
   L.o_noff = take(sizeof(int64_t) * L.K);
   L.o_eoff = take(sizeof(int64_t) * L.K);
@@ -179,8 +184,8 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_nonf = take(sizeof(unsigned long long));
   L.o_stats = take(stats_bytes());
   {
-    const int64_t C = sl::mean_chunks(L.M, L.nodes);     // partial sums of the sample mean
-    L.o_mpart = take(C > 1 ? sizeof(double) * (size_t)C * L.nodes : 0);
+    const int64_t C = sl::mean_chunks(L.M, L.nc * L.nodes);     // partial sums of the sample mean
+    L.o_mpart = take(C > 1 ? sizeof(double) * (size_t)C * L.nc * L.nodes : 0);
   }
   L.o_gxinv = take(sizeof(double) * (L.gx_doubles + 1));
   L.shared_capable = L.dim == 2 && L.uniform && L.maxN <= sl::kMaxNShared;
@@ -378,7 +383,10 @@ void build_params(sl_ctx* h) {
     p.interp_off = h->d_interpoff;
     p.phi = h->phi;
     p.tr = h->tr;
-    p.M = L.M;
+    // the reference solver loops over the components inside a fit; the
+    // factorisation kernels take every (sample, component) row as a fit
+    p.M = L.solver == SL_SOLVER_REFERENCE ? L.M : L.MV;
+    p.ncomp = L.nc;
     p.nodes = L.nodes;
     p.edges = L.edges;
     p.block0 = 0;
@@ -408,7 +416,8 @@ void build_params(sl_ctx* h) {
     p.dirichlet = h->desc.bc == SL_BC_DIRICHLET;
     p.nsteps = 0;
     p.algo = h->algo_1d;
-    p.M = L.M;
+    p.M = L.MV;                 // one row per (sample, component), each drawing its sample's increments
+    p.ncomp = L.nc;
     p.step0 = 0;
     p.seed = h->desc.seed;
     p.stream = h->desc.stream_id;
@@ -453,9 +462,9 @@ int enqueue_perorder(sl_ctx* h, int phase, bool devstep, int64_t step, hipStream
     p.work = h->d_work + g.second.first;
     p.block0 = 0;
     if (h->L.solver == SL_SOLVER_REFERENCE)
-      SL_HIP(sl::launch_fit2r(phase, g.first, p, g.second.second * h->L.M, st));
+      SL_HIP(sl::launch_fit2r(phase, g.first, p, g.second.second * h->p2.M, st));
     else
-      SL_HIP(sl::launch_fit2d(phase, g.first, h->desc.precision, p, g.second.second * h->L.M, st));
+      SL_HIP(sl::launch_fit2d(phase, g.first, h->desc.precision, p, g.second.second * h->p2.M, st));
   }
   return SL_OK;
 }
@@ -482,7 +491,7 @@ int enqueue_fused(const std::vector<sl_ctx*>& hs, int phase, int grid_req, hipSt
       for (size_t t = i; t < j; ++t) {
         a.task[t - i] = m[t]->d_p2;
         for (const auto& g : m[t]->groups)
-          segs.push_back({g.first, (int)(t - i), g.second.first * m[t]->L.M, g.second.second * m[t]->L.M});
+          segs.push_back({g.first, (int)(t - i), g.second.first * m[t]->p2.M, g.second.second * m[t]->p2.M});
       }
       std::stable_sort(segs.begin(), segs.end(), [](const S& x, const S& y) { return x.N > y.N; });
       int64_t start = 0;
@@ -527,7 +536,7 @@ int enqueue_multi(const std::vector<sl_ctx*>& hs, int phase, hipStream_t st) {
     for (sl_ctx* h : ref)
       for (const auto& g : h->groups)
         if (g.first == N && g.second.second > 0)
-          segs.push_back({h, {g.second.first * h->L.M, g.second.second * h->L.M}});
+          segs.push_back({h, {g.second.first * h->p2.M, g.second.second * h->p2.M}});
     for (size_t c0 = 0; c0 < segs.size(); c0 += sl::kMaxTasks) {
       sl::Fused2DArgs a{};
       const size_t nc = std::min<size_t>(sl::kMaxTasks, segs.size() - c0);
@@ -675,7 +684,7 @@ int step_1d_batch(const std::vector<sl_ctx*>& hs, int32_t nsteps, hipStream_t st
         const int spb = h->p1.samples_per_block;
         a.task[t] = h->d_p1;
         a.step0[t] = h->step;
-        a.bstart[t + 1] = a.bstart[t] + (h->L.M + spb - 1) / spb;
+        a.bstart[t + 1] = a.bstart[t] + (h->L.MV + spb - 1) / spb;
         lds = std::max(lds, sl::resident_1d_lds_bytes(h->L.K, spb));
       }
       ProfScope ps(v[c0], "resident_1d_batch");
@@ -705,7 +714,7 @@ int step_1d(sl_ctx* h, int32_t nsteps, hipStream_t st) {
       SL_HIP(sl::launch_tiled_1d(N, p, buf[it & 1], buf[(it + 1) & 1], h->step + it, st));
     }
     if (nsteps & 1)
-      SL_HIP(hipMemcpyAsync(h->phi, h->phi2, sizeof(double) * (size_t)L.M * L.nodes, hipMemcpyDeviceToDevice, st));
+      SL_HIP(hipMemcpyAsync(h->phi, h->phi2, sizeof(double) * (size_t)L.MV * L.nodes, hipMemcpyDeviceToDevice, st));
   }
   h->step += nsteps;
   return SL_OK;
@@ -719,7 +728,7 @@ int step_shared(sl_ctx* h, int32_t nsteps) {
     return fail(SL_EUNSUPPORTED, "the shared-geometry path needs a 2-D mesh of one order N <= 12");
   if (!h->shared_geometry)
     return fail(SL_EUNSUPPORTED, "the shared-geometry path needs the same drift, diffusion and source factor at every node");
-  if (L.M > 65535) return fail(SL_EUNSUPPORTED, "the shared-geometry path runs at most 65535 samples");
+  if (L.MV > 65535) return fail(SL_EUNSUPPORTED, "the shared-geometry path runs at most 65535 samples x components");
   const int N = L.order[0];
   sl::SharedArgs a{};
   a.A = h->A;
@@ -736,6 +745,7 @@ int step_shared(sl_ctx* h, int32_t nsteps) {
   a.phi = h->phi;
   a.tr = h->tr;
   a.K = L.K;
+  a.ncomp = L.nc;
   a.step_ptr = nullptr;
   a.seed = h->desc.seed;
   a.stream = h->desc.stream_id;
@@ -756,7 +766,7 @@ std::string tune_key(const sl_ctx* h) {
   const Layout& L = h->L;
   k << "dim=" << L.dim << ";K=" << L.kx << "x" << L.ky << ";orders=";
   for (const auto& g : h->groups) k << g.first << ":" << g.second.second << ",";
-  k << ";M=" << L.M << ";prec=" << h->desc.precision << ";refine=" << h->p2.refine << ";bc=" << h->desc.bc
+  k << ";M=" << L.M << ";nc=" << L.nc << ";prec=" << h->desc.precision << ";refine=" << h->p2.refine << ";bc=" << h->desc.bc
     << ";solver=" << L.solver;
   return k.str();
 }
@@ -936,7 +946,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   }
   build_params(h.get());
   hipError_t e1 = hipMemcpyAsync(h->xi_node, xin.data(), sizeof(double) * xin.size(), hipMemcpyHostToDevice, h->stream);
-  hipError_t e2 = hipMemsetAsync(h->phi, 0, sizeof(double) * (size_t)L.M * L.nodes, h->stream);
+  hipError_t e2 = hipMemsetAsync(h->phi, 0, sizeof(double) * (size_t)L.MV * L.nodes, h->stream);
   hipError_t e4 = L.dim == 2 ? hipMemcpyAsync(h->d_p2, &h->p2, sizeof(sl::Params2D), hipMemcpyHostToDevice, h->stream)
                              : hipMemcpyAsync(h->d_p1, &h->p1, sizeof(sl::Params1D), hipMemcpyHostToDevice, h->stream);
   hipError_t e5 = hipMemsetAsync(h->ws + L.o_dstep, 0, L.o_stats + stats_bytes() - L.o_dstep, h->stream);
@@ -953,11 +963,12 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   return SL_OK;
 }
 
-int sl_sizes(sl_handle h, int64_t* nodes, int64_t* edge_points, int64_t* elements) {
+int sl_sizes(sl_handle h, int64_t* nodes, int64_t* edge_points, int64_t* elements, int32_t* ncomp) {
   if (int rc = check_handle(h)) return rc;
   if (nodes) *nodes = h->L.nodes;
   if (edge_points) *edge_points = h->L.edges;
   if (elements) *elements = h->L.K;
+  if (ncomp) *ncomp = h->L.nc;
   return SL_OK;
 }
 
@@ -1033,7 +1044,7 @@ int sl_set_fields(sl_handle h, const double* u, const double* D, const double* d
   };
   if (!finite(u, L.nodes * L.dim) || !finite(D, L.nodes) || (divu && !finite(divu, L.nodes)) ||
       !finite(un, L.edges) || !finite(Dn, L.edges) || (ghost && !finite(ghost, L.edges)) ||
-      (phi0 && !finite(phi0, L.nodes)))
+      (phi0 && !finite(phi0, L.nc * L.nodes)))
     return fail(SL_ENONFINITE, "non-finite field values");
   for (int64_t i = 0; i < L.nodes; ++i)
     if (D[i] < 0) return fail(SL_EINVAL, "D must be >= 0");
@@ -1049,8 +1060,8 @@ int sl_set_fields(sl_handle h, const double* u, const double* D, const double* d
   if (ghost) h->ghost_h.assign(ghost, ghost + L.edges);
   SL_HIP(hipMemcpyAsync(h->ghost, h->ghost_h.data(), sizeof(double) * L.edges, hipMemcpyHostToDevice, h->stream));
   if (phi0) {
-    SL_HIP(hipMemcpyAsync(h->phi0, phi0, sizeof(double) * L.nodes, hipMemcpyHostToDevice, h->stream));
-    SL_HIP(sl::launch_broadcast(h->phi, h->phi0, L.M, L.nodes, h->stream));
+    SL_HIP(hipMemcpyAsync(h->phi0, phi0, sizeof(double) * L.nc * L.nodes, hipMemcpyHostToDevice, h->stream));
+    SL_HIP(sl::launch_broadcast(h->phi, h->phi0, L.M, L.nc * L.nodes, h->stream));
     h->step = 0;
   }
   SL_HIP(hipStreamSynchronize(h->stream));
@@ -1156,7 +1167,7 @@ int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_p
   }
   if (int rc = update_coefficients(h, dt)) return rc;
   // keep the samples and the step counter; trial steps advance both
-  const size_t bytes = sizeof(double) * (size_t)L.M * L.nodes;
+  const size_t bytes = sizeof(double) * (size_t)L.MV * L.nodes;
   void* snap = nullptr;
   if (dev_malloc(&snap, bytes) != hipSuccess) return fail(SL_ENOMEM, "no device memory for the autotuner's copy of the samples");
   const int64_t step0 = h->step;
@@ -1232,11 +1243,11 @@ int sl_mean(sl_handle h, double* out, int32_t out_is_device) {
   double* dst = out_is_device ? out : h->mean;
   {
     ProfScope ps(h, "mean");
-    SL_HIP(sl::launch_mean(h->phi, dst, h->d_mpart, L.M, L.nodes, h->d_nonf, h->stream));
+    SL_HIP(sl::launch_mean(h->phi, dst, h->d_mpart, L.M, L.nc * L.nodes, h->d_nonf, h->stream));
   }
   if (!out_is_device) {
     unsigned long long bad = 0;
-    SL_HIP(hipMemcpyAsync(out, h->mean, sizeof(double) * L.nodes, hipMemcpyDeviceToHost, h->stream));
+    SL_HIP(hipMemcpyAsync(out, h->mean, sizeof(double) * L.nc * L.nodes, hipMemcpyDeviceToHost, h->stream));
     SL_HIP(hipMemcpyAsync(&bad, h->d_nonf, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
     SL_HIP(hipStreamSynchronize(h->stream));
     if (bad) return fail(SL_ENONFINITE, std::to_string(bad) + " non-finite sample values at the nodes");
@@ -1253,7 +1264,7 @@ int sl_pdf(sl_handle h, double lo, double hi, int32_t nbins, uint32_t* counts, i
   if (nbins < 1 || nbins > sl::kPdfMaxBins) return fail(SL_EINVAL, "nbins must be in [1, 254]");
   const Layout& L = h->L;
   if (L.M > 0xffffffffll) return fail(SL_EINVAL, "more samples than a 32-bit count holds");
-  const size_t bytes = sizeof(uint32_t) * (size_t)L.nodes * (nbins + 2);
+  const size_t bytes = sizeof(uint32_t) * (size_t)L.nc * L.nodes * (nbins + 2);
   uint32_t* dst = counts;
   void* tmp = nullptr;
   if (!out_is_device) {
@@ -1263,7 +1274,7 @@ int sl_pdf(sl_handle h, double lo, double hi, int32_t nbins, uint32_t* counts, i
   hipError_t e;
   {
     ProfScope ps(h, "pdf");
-    e = sl::launch_pdf(h->phi, dst, L.M, L.nodes, lo, hi, nbins, h->stream);
+    e = sl::launch_pdf(h->phi, dst, L.M, L.nc * L.nodes, lo, hi, nbins, h->stream);
   }
   if (e == hipSuccess && !out_is_device) {
     e = hipMemcpyAsync(counts, dst, bytes, hipMemcpyDeviceToHost, h->stream);
@@ -1280,8 +1291,8 @@ int sl_reseed(sl_handle h) {
   const Layout& L = h->L;
   {
     ProfScope ps(h, "reseed");
-    SL_HIP(sl::launch_mean(h->phi, h->mean, h->d_mpart, L.M, L.nodes, h->d_nonf, h->stream));
-    SL_HIP(sl::launch_broadcast(h->phi, h->mean, L.M, L.nodes, h->stream));
+    SL_HIP(sl::launch_mean(h->phi, h->mean, h->d_mpart, L.M, L.nc * L.nodes, h->d_nonf, h->stream));
+    SL_HIP(sl::launch_broadcast(h->phi, h->mean, L.M, L.nc * L.nodes, h->stream));
   }
   return SL_OK;
 }
@@ -1290,7 +1301,7 @@ int sl_get_samples(sl_handle h, int64_t s0, int64_t ns, double* out, int32_t out
   if (int rc = check_handle(h)) return rc;
   const Layout& L = h->L;
   if (!out || s0 < 0 || ns < 0 || s0 + ns > L.M) return fail(SL_EINVAL, "sample range out of bounds");
-  SL_HIP(hipMemcpyAsync(out, h->phi + s0 * L.nodes, sizeof(double) * ns * L.nodes,
+  SL_HIP(hipMemcpyAsync(out, h->phi + s0 * L.nc * L.nodes, sizeof(double) * ns * L.nc * L.nodes,
                         out_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
   if (!out_is_device) SL_HIP(hipStreamSynchronize(h->stream));
   return SL_OK;
@@ -1300,7 +1311,7 @@ int sl_set_samples(sl_handle h, int64_t s0, int64_t ns, const double* in, int32_
   if (int rc = check_handle(h)) return rc;
   const Layout& L = h->L;
   if (!in || s0 < 0 || ns < 0 || s0 + ns > L.M) return fail(SL_EINVAL, "sample range out of bounds");
-  SL_HIP(hipMemcpyAsync(h->phi + s0 * L.nodes, in, sizeof(double) * ns * L.nodes,
+  SL_HIP(hipMemcpyAsync(h->phi + s0 * L.nc * L.nodes, in, sizeof(double) * ns * L.nc * L.nodes,
                         in_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
   SL_HIP(hipStreamSynchronize(h->stream));
   return SL_OK;
@@ -1376,6 +1387,7 @@ int sl_diag(sl_handle h, sl_diag_t* out) {
   std::memset(out, 0, sizeof(*out));
   out->steps = h->step;
   out->samples = h->L.M;
+  out->ncomp = h->L.nc;
   out->nodes = h->L.nodes;
   out->edge_points = h->L.edges;
   out->max_disp_ratio = h->max_disp_ratio;

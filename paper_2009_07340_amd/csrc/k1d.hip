@@ -90,7 +90,7 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
       const int zs = lane / P, zk = lane - zs * P;
       const int64_t sz = block * spb + zs;
       if (zs < spb && sz < p.M && it + zk < nsteps)
-        zbuf[lane] = normal_pair(p.seed, p.stream, (uint64_t)(step0 + it + zk), (uint64_t)sz).a;
+        zbuf[lane] = normal_pair(p.seed, p.stream, (uint64_t)(step0 + it + zk), (uint64_t)(sz / p.ncomp)).a;
       __syncthreads();
     }
     if (active) {
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
     if (p.dirichlet) live = false;            // beyond the boundary: the ghost value is used
     else e = (e + K) % K;                     // periodic image
   }
-  const double z = normal_pair(p.seed, p.stream, (uint64_t)step, (uint64_t)s).a;
+  const double z = normal_pair(p.seed, p.stream, (uint64_t)step, (uint64_t)(s / p.ncomp)).a;
   Fit1DNodal<N> nod;
   Fit1DPre<N> pre;
   double tL = 0.0, tR = 0.0;

@@ -402,7 +402,7 @@ __device__ __forceinline__ void phase1_body(const Params2D& p, char* lds_raw, in
   int e;
   int64_t s;
   fit_index(p, fit, e, s);
-  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)step_counter(p), (uint64_t)s);
+  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)step_counter(p), (uint64_t)(s / p.ncomp));
   const int escapes = setup_and_factor<N, MODE>(p, x, e, s, z.a, z.b);
   double* tv = x.d(L::dT);
   op_C<N, MODE>(x, x.d(L::dC), tv);
@@ -421,7 +421,7 @@ __device__ __forceinline__ void phase2_body(const Params2D& p, char* lds_raw, in
   int e;
   int64_t s;
   fit_index(p, fit, e, s);
-  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)step_counter(p), (uint64_t)s);
+  const Normal2 z = normal_pair(p.seed, p.stream, (uint64_t)step_counter(p), (uint64_t)(s / p.ncomp));
   setup_and_factor<N, MODE>(p, x, e, s, z.a, z.b);
   const int t = tid(), l = lane(), w = wave();
   const int64_t eoff = p.eoff[e];

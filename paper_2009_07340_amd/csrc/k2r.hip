@@ -314,15 +314,67 @@ __device__ void r_CT(const double* Bx, const double* By, const double* Ev, const
   }
 }
 
-// out[c] = (U_r^T v)_c, c < R; U column-major 4N x R, column stride US
+// out[c] = (U_r^T v)_c, c < R; U column-major 4N x R, column stride US (LDS copy) or
+// us (the table in global memory, stride 4N)
 template <int N>
-__device__ void r_UT(const double* U, const double* v, double* out) {
+__device__ void r_UT(const double* U, const double* v, double* out, int us = LayR<N>::US) {
   using L = LayR<N>;
   for (int c = tid(); c < L::R; c += kThreads) {
     double acc = 0.0;
 #pragma unroll 4
-    for (int q = 0; q < L::TT; ++q) acc += U[c * L::US + q] * v[q];
+    for (int q = 0; q < L::TT; ++q) acc += U[c * us + q] * v[q];
     out[c] = acc;
+  }
+}
+
+// Carried values of component c's row of the state (eq. advection_phi) into f
+// and b = V^T f, for the second and later components of a fit (the first one's
+// come with the set-up).  Two barriers.
+template <int N>
+__device__ void r_rhs(const Params2D& p, double* lds, int e, int64_t row) {
+  using L = LayR<N>;
+  const int64_t noff = p.noff[e];
+  double* f = lds + L::oF;
+  for (int i = tid(); i < L::n; i += kThreads) f[i] = p.phi[row * p.nodes + noff + i] * p.src[noff + i];
+  block_sync();
+  r_VT_mc<N>(lds + L::oX1, lds + L::oY1, f, lds + L::oB);
+  block_sync();
+}
+
+// Upwinded boundary data of one component row (eq. bnd_update) into gv: at each
+// own edge point, the element the interface displacement comes from supplies
+// the trace (another order's trace interpolated to this element's abscissae), or
+// the Dirichlet ghost value.  No barrier.
+template <int N>
+__device__ void r_upwind(const Params2D& p, int e, int64_t row, double za, double zb, double* gv) {
+  using L = LayR<N>;
+  const int64_t eoff = p.eoff[e];
+  for (int q = tid(); q < L::TT; q += kThreads) {
+    const int ew = q / N, j = q % N;
+    const double tq = p.tr[row * p.edges + eoff + q];
+    const double zd = (ew < 2) ? za : zb;
+    const double disp = edge_disp(p.Af[eoff + q], p.Bf[eoff + q], zd);
+    const bool pos = disp > 0.0;
+    const bool take_nbr = (ew == 0 || ew == 2) ? pos : !pos;   // W, S: neighbour is the negative side
+    double g = tq;
+    if (take_nbr) {
+      const int nb = p.nbr[4 * e + ew];
+      if (nb < 0) {
+        g = p.ghost[eoff + q];
+      } else {
+        const int Ns = p.order[nb];
+        const double* src = p.tr + row * p.edges + p.eoff[nb] + (ew ^ 1) * Ns;
+        if (Ns == N) {
+          g = src[j];
+        } else {   // trace of another order: Lagrange interpolation to this element's abscissae
+          const double* Lm = p.interp + p.interp_off[N * (kMaxN + 1) + Ns] + j * Ns;
+          double acc = 0.0;
+          for (int m = 0; m < Ns; ++m) acc += Lm[m] * src[m];
+          g = acc;
+        }
+      }
+    }
+    gv[q] = g;
   }
 }
 
@@ -449,7 +501,7 @@ __device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double 
     const double ym = moved_coord(y0, p.A[2 * k + 1], p.B[2 * k + 1], zb);
     xs[i] = xm;
     ys[i] = ym;
-    f[i] = p.phi[s * p.nodes + k] * p.src[k];
+    f[i] = p.phi[s * p.ncomp * p.nodes + k] * p.src[k];   // component 0 of sample s
     sx += xm - x0;
     sy += ym - y0;
     esc += escaped(xm) + escaped(ym);
@@ -539,15 +591,19 @@ __device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, d
 // the relative residual left, sqrt(g^T g / x0^T x0).  Called after the fit's
 // last barrier: a workgroup barrier waits for the memory operations in flight,
 // atomics included.
-__device__ __forceinline__ void count_fit(const Params2D& p, int phase, int iters, bool converged, int escapes,
-                                          double gg, double xx) {
+__device__ __forceinline__ void count_fit(const Params2D& p, int phase, int iters, int unconverged, int escapes,
+                                          double resid) {
   if (tid() == 0 && p.stats) {
     unsigned long long* c = stat_slot(p.stats) + 2 * (phase - 1);
     atomicAdd(c, (unsigned long long)iters);
-    if (!converged) atomicAdd(c + 1, 1ull);
+    if (unconverged) atomicAdd(c + 1, (unsigned long long)unconverged);
     stat_add(p.stats, kStatEscapes, (unsigned long long)escapes);
-    stat_residual(p.stats, xx > 0.0 ? sqrt(gg / xx) : (gg > 0.0 ? __builtin_inf() : 0.0));
+    stat_residual(p.stats, resid);
   }
+}
+
+__device__ __forceinline__ double rel_resid(double gg, double xx) {
+  return xx > 0.0 ? sqrt(gg / xx) : (gg > 0.0 ? __builtin_inf() : 0.0);
 }
 
 // ---------------------------------------------------------------- phase 1
@@ -571,6 +627,13 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   double* q = lds + L::oQ;
   double* t1 = lds + L::oT1;
   double* red = lds + L::oRed;
+  const int64_t eoff = p.eoff[e];
+  int its = 0, unconv = 0;
+  double rmax = 0.0;
+  // the components share the moved nodes and their tables (Sec. 5.3, last paragraph)
+  for (int c = 0; c < p.ncomp; ++c) {
+  const int64_t row = s * p.ncomp + c;
+  if (c > 0) r_rhs<N>(p, lds, e, row);
   // preconditioned conjugate gradients on G c = b from c = G0^-1 b
   r_G0inv<N>(gxi, b, t1, x);
   const double xx = block_dot<N>(x, x, red);
@@ -611,9 +674,12 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   block_sync();
   r_traces_from<N>(lds + L::oBx, lds + L::oBy, uc, tv);
   block_sync();
-  const int64_t eoff = p.eoff[e];
-  for (int qq = t; qq < L::TT; qq += kThreads) p.tr[s * p.edges + eoff + qq] = tv[qq];
-  count_fit(p, 1, it > p.max_iter ? p.max_iter : it, gg <= stop, escapes, gg, xx);
+  for (int qq = t; qq < L::TT; qq += kThreads) p.tr[row * p.edges + eoff + qq] = tv[qq];
+  its += it > p.max_iter ? p.max_iter : it;
+  unconv += gg <= stop ? 0 : 1;
+  rmax = fmax(rmax, rel_resid(gg, xx));
+  }
+  count_fit(p, 1, its, unconv, escapes, rmax);
 }
 
 // ---------------------------------------------------------------- phase 2
@@ -799,35 +865,6 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   const double* Bx = lds + L::oBx;
   const double* By = lds + L::oBy;
   const double* Ev = lds + L::oEv;
-  double* gv = lds + L::oGr;
-  // upwinded boundary data (eq. bnd_update)
-  for (int q = t; q < TT; q += kThreads) {
-    const int ew = q / N, j = q % N;
-    const double tq = p.tr[s * p.edges + eoff + q];
-    const double zd = (ew < 2) ? z.a : z.b;
-    const double disp = edge_disp(p.Af[eoff + q], p.Bf[eoff + q], zd);
-    const bool pos = disp > 0.0;
-    const bool take_nbr = (ew == 0 || ew == 2) ? pos : !pos;   // W, S: neighbour is the negative side
-    double g = tq;
-    if (take_nbr) {
-      const int nb = p.nbr[4 * e + ew];
-      if (nb < 0) {
-        g = p.ghost[eoff + q];
-      } else {
-        const int Ns = p.order[nb];
-        const double* src = p.tr + s * p.edges + p.eoff[nb] + (ew ^ 1) * Ns;
-        if (Ns == N) {
-          g = src[j];
-        } else {   // trace of another order: Lagrange interpolation to this element's abscissae
-          const double* Lm = p.interp + p.interp_off[N * (kMaxN + 1) + Ns] + j * Ns;
-          double acc = 0.0;
-          for (int m = 0; m < Ns; ++m) acc += Lm[m] * src[m];
-          g = acc;
-        }
-      }
-    }
-    gv[q] = g;
-  }
   // 1-D quadratic forms H[a][b] = v_a^T Gx^-1 v_b over {psi(0 - d), psi(1 - d), psi(xi_j - d)}:
   // first W[b] = Gx^-1 v_b (in the space T U_r takes later), then H[a][b] = v_a . W[b]
   double* Hx = lds + L::oHx;
@@ -857,7 +894,6 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   }
   block_sync();
   double* rr = lds + L::oRr;
-  r_UT<N>(U, gv, rr);                    // g_r = U_r^T g
   // TU = (C G0^-1 C^T) U_r, entry (q1, q2) of C G0^-1 C^T = Hx[xa1][xa2] Hy[ya1][ya2];
   // then S0 = U_r^T TU, dense
   double* TU = lds + L::oTU;
@@ -963,6 +999,21 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* q = lds + L::oQ;
   double* t1 = lds + L::oT1;
   double* red = lds + L::oRed;
+  const int64_t noff = p.noff[e];
+  int its = 0, unconv = 0;
+  double rmax = 0.0;
+  // the components share everything above: the tables, S0^-1 and the M tables
+  // (Sec. 5.3, last paragraph); each has its own carried values and boundary data
+  for (int c = 0; c < p.ncomp; ++c) {
+  const int64_t row = s * p.ncomp + c;
+  if (c > 0) r_rhs<N>(p, lds, e, row);
+  {
+    double* gvc = lds + L::oE1;            // free here; the projection's scratch later
+    r_upwind<N>(p, e, row, z.a, z.b, gvc);
+    block_sync();
+    r_UT<N>(p.ur + p.ur_off[N], gvc, rr, L::TT);   // g_r = U_r^T g
+    block_sync();
+  }
   r_Pproj<N>(lds, U, b, rr, x);
   const double xx = block_dot<N>(x, x, red);
   r_G<N>(lds, x, t1, r);
@@ -1040,7 +1091,6 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     block_sync();
   }
   // new values at the Gauss nodes (eq. phi_star)
-  const int64_t noff = p.noff[e];
   for (int i = t; i < n; i += kThreads) {
     const int ix = i % N, iy = i / N;
     double bxr[N];
@@ -1054,9 +1104,13 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       for (int k = 0; k < N; ++k) inner += bxr[k] * x[ly * N + k];
       v += By[iy * N + ly] * inner;
     }
-    p.phi[s * p.nodes + noff + i] = v;
+    p.phi[row * p.nodes + noff + i] = v;
   }
-  count_fit(p, 2, it > p.max_iter ? p.max_iter : it, gg <= stop, 0, gg, xx);
+  its += it > p.max_iter ? p.max_iter : it;
+  unconv += gg <= stop ? 0 : 1;
+  rmax = fmax(rmax, rel_resid(gg, xx));
+  }
+  count_fit(p, 2, its, unconv, 0, rmax);
 }
 
 template <int N>

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void shared_traces(SharedArgs a) {
   typedef Mma<double> M64;
   extern __shared__ __attribute__((aligned(16))) double ls[];
   const int t = tid(), l = lane(), wv = wave();
-  const int64_t s = blockIdx.y;
+  const int64_t s = blockIdx.y;                      // row: (sample, component)
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (a.K - e0) < E ? (int)(a.K - e0) : E;
   double* F = ls;                                    // [E][FS]
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void shared_traces(SharedArgs a) {
     F[e * FS + p] = e < ne ? phi[idx] : 0.0;
   }
   block_sync();
-  const double* Cf = a.ops + (size_t)s * L::op_doubles + L::a_doubles;
+  const double* Cf = a.ops + (size_t)(s / a.ncomp) * L::op_doubles + L::a_doubles;
   constexpr int EB = E / 16, NT = L::TPB * EB;
   M64::acc_t acc[(NT + 3) / 4];
 #pragma unroll
@@ -296,13 +296,13 @@ __global__ __launch_bounds__(kThreads) void shared_update(SharedArgs a) {
   typedef Mma<double> M64;
   extern __shared__ __attribute__((aligned(16))) double ls[];
   const int t = tid(), l = lane(), wv = wave();
-  const int64_t s = blockIdx.y;
+  const int64_t s = blockIdx.y;                      // row: (sample, component)
   const int64_t e0 = (int64_t)blockIdx.x * E;
   const int ne = (a.K - e0) < E ? (int)(a.K - e0) : E;
   double* F = ls;                                    // [E][FS]
   double* G = ls + E * FS;                           // [E][GS]: g - t
   double* phi = a.phi + (size_t)s * a.K * n + (size_t)e0 * n;
-  const double* op = a.ops + (size_t)s * L::op_doubles;
+  const double* op = a.ops + (size_t)(s / a.ncomp) * L::op_doubles;
   const double za = op[L::a_doubles + L::c_doubles], zb = op[L::a_doubles + L::c_doubles + 1];
   for (int idx = t; idx < E * n; idx += kThreads) {
     const int e = idx / n, p = idx - e * n;
@@ -370,16 +370,17 @@ __global__ __launch_bounds__(kThreads) void shared_update(SharedArgs a) {
 template <int N>
 static hipError_t launch_shared_n(int stage, const SharedArgs& a, int64_t M, hipStream_t st) {
   using L = LayS<N>;
-  if (M > 65535 || M < 1) return hipErrorInvalidValue;
+  const int64_t rows = M * a.ncomp;
+  if (rows > 65535 || M < 1 || a.ncomp < 1) return hipErrorInvalidValue;
   const int64_t tiles = (a.K + L::E - 1) / L::E;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   const size_t tb = L::tile_bytes > sizeof(double) * L::E * L::n ? L::tile_bytes : sizeof(double) * L::E * L::n;
   if (stage == 0)
     hipLaunchKernelGGL((shared_build<N>), dim3((unsigned)M), dim3(kThreads), L::build_bytes, st, a);
   else if (stage == 1)
-    hipLaunchKernelGGL((shared_traces<N>), dim3((unsigned)tiles, (unsigned)M), dim3(kThreads), tb, st, a);
+    hipLaunchKernelGGL((shared_traces<N>), dim3((unsigned)tiles, (unsigned)rows), dim3(kThreads), tb, st, a);
   else
-    hipLaunchKernelGGL((shared_update<N>), dim3((unsigned)tiles, (unsigned)M), dim3(kThreads), tb, st, a);
+    hipLaunchKernelGGL((shared_update<N>), dim3((unsigned)tiles, (unsigned)rows), dim3(kThreads), tb, st, a);
   return hipGetLastError();
 }
 

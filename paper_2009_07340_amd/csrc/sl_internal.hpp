@@ -60,7 +60,8 @@ struct Params1D {
   int dirichlet;
   int nsteps;
   int algo;              // 0: nodal (Lagrange) form, 1: Legendre normal equations
-  int64_t M;
+  int ncomp;             // components: row r of the state draws the increments of sample r / ncomp
+  int64_t M;             // rows of K*N values (samples x components)
   int64_t step0;         // Philox step counter of the first step
   uint64_t seed;
   uint32_t stream;
@@ -88,9 +89,11 @@ struct Params2D {
   const int64_t* ur_off;   // [kMaxN+1]
   const double* interp;    // Lagrange matrices between orders (Nd x Ns)
   const int64_t* interp_off;  // [(kMaxN+1)^2], index Nd*(kMaxN+1) + Ns
-  double* phi;             // [M][nodes]
-  double* tr;              // [M][edges]
-  int64_t M, nodes, edges;
+  double* phi;             // [samples][ncomp][nodes]
+  double* tr;              // [samples][ncomp][edges]
+  int64_t M, nodes, edges; // M: fits per element of one launch: samples (reference solver, which
+                           // loops over the components inside a fit) or samples x ncomp (factorisation)
+  int ncomp;
   int64_t block0;          // first fit of this launch within the group
   int64_t step;            // Philox step counter (used when step_ptr is null)
   const int64_t* step_ptr; // device step counter (graph replay), or null
@@ -159,9 +162,10 @@ struct SharedArgs {
   const double* bw;      // [N] barycentric weights of the reference nodes
   const double* ur;      // U_r, column-major 4N x (4N - 4)
   double* ops;           // [M][shared_op_doubles(N)] per-sample operators
-  double* phi;           // [M][K n]
-  double* tr;            // [M][K 4N]
+  double* phi;           // [M][ncomp][K n]
+  double* tr;            // [M][ncomp][K 4N]
   int64_t K;
+  int ncomp;             // row r of phi / tr uses the operators of sample r / ncomp
   int64_t step;
   const int64_t* step_ptr;
   uint64_t seed;

@@ -8,21 +8,22 @@ from . import binding as B
 
 class Problem:
     def __init__(self, wl, precision="fp64", samples=None, seed=None, stream_id=0, dev_ws=None,
-                 ws_bytes=0, hip_stream=None, nodes="gl", refine_iters=-1, solver="auto"):
+                 ws_bytes=0, hip_stream=None, nodes="gl", refine_iters=-1, solver="auto", ncomp=1):
         self.wl = wl
         self.M = int(samples if samples is not None else wl.samples)
         self.desc = B.make_desc(wl.dim, wl.kx, wl.ky, wl.box, wl.order if np.isscalar(wl.order) else wl.order_array(),
                                 nodes=nodes, bc=wl.bc, samples=self.M,
                                 seed=wl.seed if seed is None else seed, stream_id=stream_id,
-                                precision=precision, refine_iters=refine_iters, solver=solver)
+                                precision=precision, refine_iters=refine_iters, solver=solver, ncomp=ncomp)
+        self.ncomp = int(ncomp)
         self.h = B.sl_init_mesh(self.desc, dev_ws, ws_bytes, hip_stream)
         self.nodes, self.edges, self.K = B.sl_sizes(self.h)
 
     @staticmethod
-    def required_bytes(wl, precision="fp64", samples=None, solver="auto"):
+    def required_bytes(wl, precision="fp64", samples=None, solver="auto", ncomp=1):
         d = B.make_desc(wl.dim, wl.kx, wl.ky, wl.box, wl.order if np.isscalar(wl.order) else wl.order_array(),
                         bc=wl.bc, samples=int(samples if samples is not None else wl.samples), precision=precision,
-                        solver=solver)
+                        solver=solver, ncomp=ncomp)
         return B.sl_required_bytes(d)
 
     def coords(self):
@@ -33,8 +34,11 @@ class Problem:
     def set_fields(self, t=0.0, with_phi0=True):
         xy, exy, axis = self.coords()
         a = self.wl.sample_fields(xy, exy, axis, t)
-        B.sl_set_fields(self.h, a["u"], a["D"], a["divu"], a["un"], a["Dn"], a["ghost"],
-                        a["phi0"] if with_phi0 else None)
+        phi0 = None
+        if with_phi0:
+            # component c starts from the workload's field scaled by 1 + c/10 (synthetic components)
+            phi0 = np.concatenate([a["phi0"] * (1.0 + 0.1 * c) for c in range(self.ncomp)])
+        B.sl_set_fields(self.h, a["u"], a["D"], a["divu"], a["un"], a["Dn"], a["ghost"], phi0)
         return a
 
     def step(self, dt, nsteps):
