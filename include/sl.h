@@ -87,6 +87,7 @@ enum sl_status {
 };
 
 enum { SL_BC_PERIODIC = 0, SL_BC_DIRICHLET = 1 };
+enum { SL_CONSTRAIN_BOUNDARY = 0, SL_CONSTRAIN_BOUNDARY_MASS = 1 };
 enum { SL_NODES_GL = 0, SL_NODES_CG = 1 };
 enum {
   SL_PREC_FP64 = 0,          /* every operation of the fit in float64 */
@@ -126,6 +127,15 @@ typedef struct sl_mesh_desc {
   int32_t max_iter;       /* reference solver: iteration limit per fit, 0 = default (32) */
   double tol;             /* reference solver: stop when the preconditioned residual, relative
                              to the starting iterate, is below tol; 0 = default (1e-13) */
+  int32_t constraints;    /* SL_CONSTRAIN_BOUNDARY (0): the remap is constrained by the upwinded
+                             boundary values; SL_CONSTRAIN_BOUNDARY_MASS: also by the element's
+                             mass, the integral of the advected interpolant p0 over the element
+                             (Introduction: a least-squares fit with boundary and mass
+                             conservation constraints), so the boundary correction moves no mass
+                             into or out of an element; for N = 2 the boundary values fix the
+                             polynomial and the mass row is left out.  1-D and the 2-D
+                             shared-geometry path; a 2-D step on the general path returns
+                             SL_EUNSUPPORTED */
   int32_t ncomp;          /* components of a vector-valued field phi* (Sec. 5.3, last paragraph:
                              every component is defined on the same advected points), 1..64;
                              0 means 1.  Every component of a sample takes the same node moves

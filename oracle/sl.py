@@ -63,6 +63,7 @@ class Mesh:
     order: np.ndarray = None
     family: str = "gl"
     bc: str = "periodic"
+    mass: bool = False          # also keep each element's integral of p0 (see constrained_values)
     _cache: dict = field(default_factory=dict, repr=False)
 
     def __post_init__(self):
@@ -300,7 +301,7 @@ def own_edge_points(N, dim, family="gl"):
                            np.stack([eta, zero], 1), np.stack([eta, one], 1)], 0)
 
 
-def constrained_values(N, dim, V, C, f, t, g):
+def constrained_values(N, dim, V, C, f, t, g, m=None):
     """Values a at the moved nodes of the constrained least-squares fit (Sec. 5.3).
 
     The fit minimises sum_i (q(xi*_i) - f_i)^2 over q in Q_{N-1} subject to
@@ -309,13 +310,37 @@ def constrained_values(N, dim, V, C, f, t, g):
     C* = C V^-1, and the minimiser is a = f - pinv(C*) (C* f - g), where
     C* f = t.  pinv is the Moore-Penrose pseudo-inverse of rank
     ``constraint_rank`` (the trailing singular values of C* are zero).
+
+    With the mass constraint (Introduction: a least-squares fit 'with boundary
+    and mass conservation constraints'; the formulation itself is deferred to a
+    reference not available) ``m`` holds, per fit, the coefficients-to-integral
+    row of the element (integral over the element of the polynomial with
+    coefficients c is m . c).  The fit must also keep the integral of p0: one
+    more row m* = m V^-1 with right side m* f, whose residual is zero, so
+    a = f - pinv([C*; m*]) [t - g; 0] with one more unit of rank (for N >= 3;
+    for N = 2 the boundary values fix q and the row is left out).
     """
     r = constraint_rank(N, dim)
+    rhs = t - g
+    if m is not None and N >= 3:
+        C = np.concatenate([C, m[..., None, :]], axis=-2)
+        rhs = np.concatenate([rhs, np.zeros(rhs.shape[:-1] + (1,))], axis=-1)
+        r += 1
     Vt = np.swapaxes(V, -1, -2)
     Cstar = np.swapaxes(np.linalg.solve(Vt, np.swapaxes(C, -1, -2)), -1, -2)
     U, sv, Wt = np.linalg.svd(Cstar, full_matrices=False)
     pinv = np.einsum("...rp,...r,...qr->...pq", Wt[..., :r, :], 1.0 / sv[..., :r], U[..., :, :r])
-    return f - np.einsum("...pq,...q->...p", pinv, t - g)
+    return f - np.einsum("...pq,...q->...p", pinv, rhs)
+
+
+def mass_row(N, dim, dbar, ref, family="gl"):
+    """Row m with m . c = the integral over the (reference) element of the polynomial
+    with coefficients c in the centred basis: the element's own quadrature (weights
+    of its node family, exact on Q_{N-1}) applied to the basis at its Gauss nodes."""
+    E = _basis(np.broadcast_to(ref, dbar.shape[:-1] + ref.shape), dbar, N, dim)     # (..., n, n)
+    w1 = np.asarray(tables.weights(int(N), family))
+    w = w1 if dim == 1 else np.kron(w1, w1)                                          # node i = iy N + ix
+    return np.einsum("i,...ip->...p", w, E)
 
 
 def values_at_nodes(N, dim, V, a, dbar, ref):
@@ -390,7 +415,8 @@ def step(mesh, fields, phi, dt, z):
     for N, g in per.items():
         els = g["els"]
         T = eoff[els][:, None] + np.arange(mesh.n_edge[els[0]])[None, :]   # (K_N, T)
-        a = constrained_values(N, d, g["V"], g["C"], g["f"], g["t"], gvals[:, T])
+        m = mass_row(N, d, g["dbar"], g["ref"], mesh.family) if mesh.mass else None
+        a = constrained_values(N, d, g["V"], g["C"], g["f"], g["t"], gvals[:, T], m)
         new[:, g["idx"]] = values_at_nodes(N, d, g["V"], a, g["dbar"], g["ref"])
     info = dict(positions=xs_all, traces=tvals, g=gvals, f=f_all)
     return new, info

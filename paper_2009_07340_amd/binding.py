@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsl_mi355x.so")
 
 SL_OK, SL_EINVAL, SL_ENOMEM, SL_EDEVICE, SL_ENONFINITE, SL_ESTATE, SL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SL_BC_PERIODIC, SL_BC_DIRICHLET = 0, 1
+SL_CONSTRAIN_BOUNDARY, SL_CONSTRAIN_BOUNDARY_MASS = 0, 1
 SL_NODES_GL, SL_NODES_CG = 0, 1
 SL_PREC_FP64, SL_PREC_FP32_REFINE, SL_PREC_BF16SPLIT_REFINE = 0, 1, 2
 
@@ -32,7 +33,7 @@ class sl_mesh_desc(C.Structure):
                 ("n_uniform", C.c_int32), ("order", C.POINTER(C.c_int32)), ("nodes", C.c_int32),
                 ("bc", C.c_int32), ("samples", C.c_int64), ("seed", C.c_uint64), ("stream_id", C.c_uint32),
                 ("precision", C.c_int32), ("refine_iters", C.c_int32), ("solver", C.c_int32),
-                ("max_iter", C.c_int32), ("tol", C.c_double), ("ncomp", C.c_int32)]
+                ("max_iter", C.c_int32), ("tol", C.c_double), ("constraints", C.c_int32), ("ncomp", C.c_int32)]
 
 
 class sl_diag_t(C.Structure):
@@ -133,7 +134,8 @@ def _f64(a, n=None):
 
 
 def make_desc(dim, kx, ky=1, box=(0.0, 1.0, 0.0, 1.0), order=8, nodes="gl", bc="periodic", samples=1,
-              seed=0, stream_id=0, precision="fp64", refine_iters=-1, solver="auto", max_iter=0, tol=0.0, ncomp=1):
+              seed=0, stream_id=0, precision="fp64", refine_iters=-1, solver="auto", max_iter=0, tol=0.0, ncomp=1,
+              mass=False):
     d = sl_mesh_desc()
     d.dim, d.kx, d.ky = dim, kx, ky if dim == 2 else 1
     d.x0, d.x1, d.y0, d.y1 = (float(v) for v in box)
@@ -152,6 +154,7 @@ def make_desc(dim, kx, ky=1, box=(0.0, 1.0, 0.0, 1.0), order=8, nodes="gl", bc="
     d.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     d.max_iter, d.tol = int(max_iter), float(tol)
     d.ncomp = int(ncomp)
+    d.constraints = 1 if mass else 0
     d._keep = keep
     return d
 

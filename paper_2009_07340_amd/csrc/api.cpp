@@ -72,6 +72,7 @@ struct Layout {
   std::vector<int64_t> noff, eoff;
   int64_t nodes = 0, edges = 0, M = 0;
   int nc = 1;                       // components of the field (vector-valued phi*)
+  bool mass = false;                // mass constraint beside the boundary constraints
   int64_t MV = 0;                   // rows of `nodes` values in the state: M * nc
   int maxN = 0;
   bool uniform = true;
@@ -80,7 +81,7 @@ struct Layout {
   // byte offsets in the workspace
   size_t o_phi, o_phi2, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
-  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_sops, o_bw, total;
+  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_sops, o_bw, o_wqtab, total;
   bool shared_capable = false;      // one order <= kMaxNShared in 2-D: the shared-geometry path can run
   int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
   size_t gx_doubles = 0;
@@ -136,6 +137,9 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.edges = L.eoff[L.K];
   L.M = d->samples;
   if (d->ncomp < 0 || d->ncomp > 64) return fail(SL_EINVAL, "ncomp must be in [0, 64] (0 means 1)");
+  if (d->constraints != SL_CONSTRAIN_BOUNDARY && d->constraints != SL_CONSTRAIN_BOUNDARY_MASS)
+    return fail(SL_EINVAL, "unknown constraint set");
+  L.mass = d->constraints == SL_CONSTRAIN_BOUNDARY_MASS;
   L.nc = d->ncomp > 1 ? d->ncomp : 1;
   L.MV = L.M * L.nc;
   for (int N : L.order)
@@ -188,6 +192,7 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
     L.o_mpart = take(C > 1 ? sizeof(double) * (size_t)C * L.nc * L.nodes : 0);
   }
   L.o_gxinv = take(sizeof(double) * (L.gx_doubles + 1));
+  L.o_wqtab = take(sizeof(double) * (sl::kMaxN + 1) * sl::kMaxN);
   L.shared_capable = L.dim == 2 && L.uniform && L.maxN <= sl::kMaxNShared;
   L.o_sops = take(L.shared_capable ? sizeof(double) * (size_t)L.M * sl::shared_op_doubles(L.maxN) : 0);
   L.o_bw = take(sizeof(double) * sl::kMaxN);
@@ -239,6 +244,7 @@ struct sl_ctx {
   double* d_gxinv = nullptr;
   double* d_sops = nullptr;              // shared-geometry path: per-sample operators
   double* d_bw = nullptr;                // barycentric weights of the (single) order's nodes
+  double* d_wqtab = nullptr;             // [(kMaxN+1)][kMaxN] quadrature weights of each order's nodes
   bool shared_geometry = false;          // the current step coefficients are the same at every node
   hipStream_t cap_stream = nullptr;      // private stream for graph capture
   // measurement
@@ -401,6 +407,8 @@ void build_params(sl_ctx* h) {
     p.max_iter = L.max_iter;
     p.stats = h->d_stats;
     p.rec = h->rec;
+    p.mass = L.mass ? 1 : 0;
+    p.wq_tab = h->d_wqtab;
   } else {
     sl::Params1D& p = h->p1;
     p = sl::Params1D{};
@@ -423,8 +431,11 @@ void build_params(sl_ctx* h) {
     p.stream = h->desc.stream_id;
     p.stats = h->d_stats;
     p.rec = h->rec;
+    p.mass = L.mass ? 1 : 0;
     const auto& xi = h->xi_tab[L.order[0]];
     for (size_t i = 0; i < xi.size(); ++i) p.xi[i] = xi[i];
+    const auto wq = sl::quadrature_weights(xi);
+    for (size_t i = 0; i < wq.size(); ++i) p.wq[i] = wq[i];
   }
 }
 
@@ -667,7 +678,7 @@ int step_1d_batch(const std::vector<sl_ctx*>& hs, int32_t nsteps, hipStream_t st
   std::vector<sl_ctx*> tiled;
   for (sl_ctx* h : hs) {
     if (h->L.K > 256) tiled.push_back(h);
-    else by[{h->L.order[0], h->algo_1d}].push_back(h);
+    else by[{h->L.order[0], h->algo_1d + 2 * h->p1.mass}].push_back(h);
   }
   for (sl_ctx* h : tiled)
     if (int rc = step_1d(h, nsteps, st)) return rc;
@@ -746,6 +757,8 @@ int step_shared(sl_ctx* h, int32_t nsteps) {
   a.tr = h->tr;
   a.K = L.K;
   a.ncomp = L.nc;
+  a.mass = L.mass ? 1 : 0;
+  a.wq = h->d_wqtab + N * sl::kMaxN;
   a.step_ptr = nullptr;
   a.seed = h->desc.seed;
   a.stream = h->desc.stream_id;
@@ -847,6 +860,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_mpart = (double*)(h->ws + L.o_mpart);
   h->d_gxinv = (double*)(h->ws + L.o_gxinv);
   h->d_sops = (double*)(h->ws + L.o_sops);
+  h->d_wqtab = (double*)(h->ws + L.o_wqtab);
   h->d_bw = (double*)(h->ws + L.o_bw);
   // element tables, work list grouped by order, node tables, U_r and trace interpolation
   std::vector<int32_t> nbr(4 * (size_t)L.K, -1), work;
@@ -871,10 +885,14 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       if (L.order[e] == N) work.push_back(e);
     h->groups.push_back({N, {first, (int64_t)work.size() - first}});
   }
-  std::vector<double> xitab((sl::kMaxN + 1) * sl::kMaxN, 0.0);
+  std::vector<double> xitab((sl::kMaxN + 1) * sl::kMaxN, 0.0), wqtab((sl::kMaxN + 1) * sl::kMaxN, 0.0);
   for (int N = 1; N <= sl::kMaxN; ++N) {
     const auto xi = sl::gauss_nodes(N, h->family);
     for (int i = 0; i < N; ++i) xitab[N * sl::kMaxN + i] = xi[i];
+  }
+  for (int N : L.orders) {
+    const auto w = sl::quadrature_weights(h->xi_tab[N]);
+    for (int i = 0; i < N; ++i) wqtab[N * sl::kMaxN + i] = w[i];
   }
   std::vector<double> ur(L.ur_doubles + 1, 0.0), interp(L.interp_doubles + 1, 0.0);
   std::vector<int64_t> uroff(sl::kMaxN + 1, 0), interpoff((sl::kMaxN + 1) * (sl::kMaxN + 1), 0);
@@ -921,7 +939,8 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       {h->d_ur, ur.data(), sizeof(double) * ur.size()}, {h->d_uroff, uroff.data(), sizeof(int64_t) * uroff.size()},
       {h->d_interp, interp.data(), sizeof(double) * interp.size()},
       {h->d_interpoff, interpoff.data(), sizeof(int64_t) * interpoff.size()},
-      {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}, {h->d_bw, bw.data(), sizeof(double) * bw.size()}};
+      {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}, {h->d_bw, bw.data(), sizeof(double) * bw.size()},
+      {h->d_wqtab, wqtab.data(), sizeof(double) * wqtab.size()}};
   for (const auto& u : ups) {
     if (hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
       if (h->own_ws) (void)hipFree(h->ws);
@@ -1095,6 +1114,8 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
   if (int rc = update_coefficients(h, dt)) return rc;
   const Layout& L = h->L;
   if (h->sched.shared) return step_shared(h, nsteps);
+  if (L.dim == 2 && L.mass)
+    return fail(SL_EUNSUPPORTED, "in 2-D the mass constraint runs on the shared-geometry path (schedule.shared = 1)");
   if (L.dim == 2) return step_2d({h}, nsteps, h->sched.fused, h->sched.graph, h->sched.grid, h->stream);
   return step_1d(h, nsteps, h->stream);
 }
@@ -1112,6 +1133,8 @@ int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t ns
     if (!h->fields_set) return fail(SL_ESTATE, "sl_set_fields must come before sl_step_batch");
     if (!(dts[i] > 0) || !std::isfinite(dts[i])) return fail(SL_EINVAL, "dt must be finite and > 0");
     if (h->stream != hs[0]->stream) return fail(SL_EINVAL, "all handles of a batch must share one stream");
+    if (h->L.dim == 2 && (h->L.mass || h->sched.shared))
+      return fail(SL_EUNSUPPORTED, "batches take the general path; a 2-D handle with the mass constraint or the shared-geometry schedule steps alone");
     (h->L.dim == 2 ? two : one).push_back(h);
   }
   for (int i = 0; i < nh; ++i)

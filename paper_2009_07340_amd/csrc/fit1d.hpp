@@ -42,9 +42,22 @@ struct Fit1DPre {
   double phiu[N];   // unconstrained values at the Gauss nodes, E c0
   double wl[N];     // E G^-1 psi(0 - dbar)
   double wr[N];     // E G^-1 psi(1 - dbar)
-  double s00, s01, s11;
+  double wm[N];     // E G^-1 m (mass constraint: m . c = the element integral)
+  double s00, s01, s11, s02, s12, s22;
   double tL, tR;    // traces of p0
 };
+
+// lambda = S^-1 (r0, r1, 0) for the symmetric 3 x 3 system of the boundary and
+// mass constraints (cofactors; S is positive definite).
+__device__ __forceinline__ void solve3_mass(double s00, double s01, double s11, double s02, double s12, double s22,
+                                            double r0, double r1, double& l0, double& l1, double& l2) {
+  const double a00 = s11 * s22 - s12 * s12, a01 = s02 * s12 - s01 * s22, a11 = s00 * s22 - s02 * s02;
+  const double a02 = s01 * s12 - s02 * s11, a12 = s01 * s02 - s00 * s12;
+  const double idet = 1.0 / (s00 * a00 + s01 * a01 + s02 * a02);
+  l0 = (a00 * r0 + a01 * r1) * idet;
+  l1 = (a01 * r0 + a11 * r1) * idet;
+  l2 = (a02 * r0 + a12 * r1) * idet;
+}
 
 // Packed lower-triangular index.
 __device__ __forceinline__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
@@ -68,10 +81,11 @@ __device__ __forceinline__ void chol_solve(const double (&L)[N * (N + 1) / 2], c
   }
 }
 
-// Phase before the exchange.  xs: moved nodes; f: carried values; xi: Gauss nodes.
-template <int N>
+// Phase before the exchange.  xs: moved nodes; f: carried values; xi: Gauss nodes;
+// wq: quadrature weights of the nodes (read with the mass constraint only).
+template <int N, bool MASS = false>
 __device__ __forceinline__ void fit1d_pre(const double (&xs)[N], const double (&f)[N], const double* xi,
-                                          const LegendreRec& rec, Fit1DPre<N>& out) {
+                                          const LegendreRec& rec, Fit1DPre<N>& out, const double* wq = nullptr) {
   double dsum = 0.0;
 #pragma unroll
   for (int i = 0; i < N; ++i) dsum += xs[i] - xi[i];
@@ -121,6 +135,22 @@ __device__ __forceinline__ void fit1d_pre(const double (&xs)[N], const double (&
     wl[k] = pl[k];
     wr[k] = pr[k];
   }
+  // mass row m_k = sum_i wq_i psi_k(xi_i - dbar) (the element's quadrature, exact on Q_{N-1})
+  double mk[N], wm[N];
+  if constexpr (MASS) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) mk[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double psi[N];
+      legendre_eval<N>(xi[i] - dbar, rec, psi);
+#pragma unroll
+      for (int k = 0; k < N; ++k) mk[k] += wq[i] * psi[k];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) wm[k] = mk[k];
+    chol_solve<N>(G, dinv, wm);
+  }
   chol_solve<N>(G, dinv, b);   // b <- c0
   chol_solve<N>(G, dinv, wl);
   chol_solve<N>(G, dinv, wr);
@@ -138,20 +168,34 @@ __device__ __forceinline__ void fit1d_pre(const double (&xs)[N], const double (&
   out.s00 = s00;
   out.s01 = s01;
   out.s11 = s11;
+  if constexpr (MASS) {
+    double s02 = 0.0, s12 = 0.0, s22 = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      s02 += pl[k] * wm[k];
+      s12 += pr[k] * wm[k];
+      s22 += mk[k] * wm[k];
+    }
+    out.s02 = s02;
+    out.s12 = s12;
+    out.s22 = s22;
+  }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     double psi[N];
     legendre_eval<N>(xi[i] - dbar, rec, psi);
-    double u = 0.0, a = 0.0, c = 0.0;
+    double u = 0.0, a = 0.0, c = 0.0, m = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       u += psi[k] * b[k];
       a += psi[k] * wl[k];
       c += psi[k] * wr[k];
+      if constexpr (MASS) m += psi[k] * wm[k];
     }
     out.phiu[i] = u;
     out.wl[i] = a;
     out.wr[i] = c;
+    if constexpr (MASS) out.wm[i] = m;
   }
 }
 
@@ -185,7 +229,8 @@ struct Fit1DNodal {
   double a[N];      // carried values f (becomes the constrained values a)
   double cl[N];     // C*: Lagrange rows of the moved nodes at xi = 0 ...
   double cr[N];     // ... and at xi = 1
-  double s00, s01, s11;
+  double cm[N];     // mass row (mass constraint): integral of each Lagrange basis polynomial
+  double s00, s01, s11, s02, s12, s22;
   double tL, tR;    // traces of p0
 };
 
@@ -228,8 +273,9 @@ __device__ __forceinline__ void reciprocals(const double (&p)[N], double (&w)[N]
   }
 }
 
-template <int N>
-__device__ __forceinline__ void fit1d_nodal_pre(Fit1DNodal<N>& st) {
+template <int N, bool MASS = false>
+__device__ __forceinline__ void fit1d_nodal_pre(Fit1DNodal<N>& st, const double* xi = nullptr,
+                                                const double* wq = nullptr) {
   // p_j = prod_{m != j} (x*_j - x*_m), each difference formed once
   double pj[N];
 #pragma unroll
@@ -260,23 +306,52 @@ __device__ __forceinline__ void fit1d_nodal_pre(Fit1DNodal<N>& st) {
   st.s00 = s00;
   st.s01 = s01;
   st.s11 = s11;
+  if constexpr (MASS) {
+    // cm_j = integral of the j-th Lagrange polynomial of the moved nodes = sum_i wq_i l_j(xi_i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) st.cm[j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double row[N];
+      lagrange_row<N>(st.xs, st.w, xi[i], row);
+#pragma unroll
+      for (int j = 0; j < N; ++j) st.cm[j] += wq[i] * row[j];
+    }
+    double s02 = 0.0, s12 = 0.0, s22 = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      s02 += st.cl[j] * st.cm[j];
+      s12 += st.cr[j] * st.cm[j];
+      s22 += st.cm[j] * st.cm[j];
+    }
+    st.s02 = s02;
+    st.s12 = s12;
+    st.s22 = s22;
+  }
 }
 
 // After the exchange: a = f - C*^T lambda, lambda = S^-1 (t - g); phi = Phi a.
-template <int N>
+template <int N, bool MASS = false>
 __device__ __forceinline__ void fit1d_nodal_post(Fit1DNodal<N>& st, const double* xi, double gL, double gR,
                                                  double (&phi)[N]) {
   const double r0 = st.tL - gL, r1 = st.tR - gR;
-  const double idet = recip(st.s00 * st.s11 - st.s01 * st.s01);
-  const double l0 = (st.s11 * r0 - st.s01 * r1) * idet;
-  const double l1 = (st.s00 * r1 - st.s01 * r0) * idet;
+  double l0, l1, l2 = 0.0;
+  if constexpr (MASS) {
+    // boundary and mass rows: the mass row's residual is zero (the fit keeps p0's integral)
+    solve3_mass(st.s00, st.s01, st.s11, st.s02, st.s12, st.s22, r0, r1, l0, l1, l2);
+  } else {
+    const double idet = recip(st.s00 * st.s11 - st.s01 * st.s01);
+    l0 = (st.s11 * r0 - st.s01 * r1) * idet;
+    l1 = (st.s00 * r1 - st.s01 * r0) * idet;
+  }
   // phi_i = sum_j w_j a_j prod_{m != j} (xi_i - x*_m), with the weights folded
   // into the values once.  With d_m = xi_i - x*_m and P_j = prod_{m < j} d_m the
   // sum is sum_j wa_j P_j prod_{m > j} d_m, a Horner scheme over j:
   // v <- v d_j + wa_j P_j, P <- P d_j (three operations a node pair).
   double wa[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) wa[j] = st.w[j] * (st.a[j] - (st.cl[j] * l0 + st.cr[j] * l1));
+  for (int j = 0; j < N; ++j)
+    wa[j] = st.w[j] * (st.a[j] - (st.cl[j] * l0 + st.cr[j] * l1 + (MASS ? st.cm[j] * l2 : 0.0)));
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     double v = wa[0], dprev = xi[i] - st.xs[0], P = 1.0;
@@ -292,14 +367,21 @@ __device__ __forceinline__ void fit1d_nodal_post(Fit1DNodal<N>& st, const double
 }
 
 // Phase after the exchange: new values from the boundary data gL, gR.
-template <int N>
+template <int N, bool MASS = false>
 __device__ __forceinline__ void fit1d_post(const Fit1DPre<N>& pre, double gL, double gR, double (&phi)[N]) {
   const double r0 = pre.tL - gL, r1 = pre.tR - gR;
-  const double det = pre.s00 * pre.s11 - pre.s01 * pre.s01;
-  const double l0 = (pre.s11 * r0 - pre.s01 * r1) / det;
-  const double l1 = (pre.s00 * r1 - pre.s01 * r0) / det;
+  if constexpr (MASS) {
+    double l0, l1, l2;
+    solve3_mass(pre.s00, pre.s01, pre.s11, pre.s02, pre.s12, pre.s22, r0, r1, l0, l1, l2);
 #pragma unroll
-  for (int i = 0; i < N; ++i) phi[i] = pre.phiu[i] - (pre.wl[i] * l0 + pre.wr[i] * l1);
+    for (int i = 0; i < N; ++i) phi[i] = pre.phiu[i] - (pre.wl[i] * l0 + pre.wr[i] * l1 + pre.wm[i] * l2);
+  } else {
+    const double det = pre.s00 * pre.s11 - pre.s01 * pre.s01;
+    const double l0 = (pre.s11 * r0 - pre.s01 * r1) / det;
+    const double l1 = (pre.s00 * r1 - pre.s01 * r0) / det;
+#pragma unroll
+    for (int i = 0; i < N; ++i) phi[i] = pre.phiu[i] - (pre.wl[i] * l0 + pre.wr[i] * l1);
+  }
 }
 
 // Moved nodes with the contracted-free operation order of the position contract.

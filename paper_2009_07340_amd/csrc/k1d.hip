@@ -32,9 +32,12 @@ size_t resident_1d_lds_bytes(int K, int spb) { return sizeof(double) * 2 * 2 * (
 template <int N, bool kNodal>
 constexpr bool resident_stages_ab() { return kNodal && N >= 9 && N <= 13; }
 
-template <int N, bool kNodal>
+// MASS: the fit also keeps the element integral of p0 (a third constraint row;
+// N = 2 has no room for it: the boundary values fix the linear polynomial).
+template <int N, bool kNodal, bool MASS0>
 __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_tr, double* zbuf, double* abl,
                                                  int64_t block, int64_t step0, int nsteps) {
+  constexpr bool MASS = MASS0 && N >= 3;
   const int K = p.K;
   const int spb = p.samples_per_block;
   const int lane = threadIdx.x;
@@ -107,7 +110,7 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
           nod.a[i] = phi[i] * (kSrcReg ? srcv[i] : src[i]);
           esc += escaped(nod.xs[i]);
         }
-        fit1d_nodal_pre<N>(nod);
+        fit1d_nodal_pre<N, MASS>(nod, p.xi, p.wq);
         tL = nod.tL;
         tR = nod.tR;
       } else {
@@ -118,7 +121,7 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
           f[i] = phi[i] * src[i];
           esc += escaped(xs[i]);
         }
-        fit1d_pre<N>(xs, f, p.xi, p.rec, pre);
+        fit1d_pre<N, MASS>(xs, f, p.xi, p.rec, pre, p.wq);
         tL = pre.tL;
         tR = pre.tR;
       }
@@ -137,8 +140,8 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
       else nbR = p.dirichlet ? ghR : tr[(slot * K) * 2 + 0];
       const double gL = (dL > 0.0) ? nbL : tL;
       const double gR = (dR > 0.0) ? tR : nbR;
-      if constexpr (kNodal) fit1d_nodal_post<N>(nod, p.xi, gL, gR, phi);
-      else fit1d_post<N>(pre, gL, gR, phi);
+      if constexpr (kNodal) fit1d_nodal_post<N, MASS>(nod, p.xi, gL, gR, phi);
+      else fit1d_post<N, MASS>(pre, gL, gR, phi);
     }
   }
   if (active) {
@@ -150,16 +153,16 @@ __device__ __forceinline__ void resident_1d_body(const Params1D& p, double* lds_
   if ((lane & 63) == 0) stat_add(p.stats, kStatEscapes, (unsigned long long)esc);
 }
 
-template <int N, bool kNodal>
+template <int N, bool kNodal, bool MASS>
 __global__ __launch_bounds__(kResidentThreads) void resident_1d_kernel(Params1D p) {
   extern __shared__ double lds_tr[];   // [2 buffers][spb][K][2]
   __shared__ double zbuf[kResidentThreads];
   __shared__ double abl[resident_stages_ab<N, kNodal>() ? 2 * N * kResidentThreads : 1];
-  resident_1d_body<N, kNodal>(p, lds_tr, zbuf, abl, blockIdx.x, p.step0, p.nsteps);
+  resident_1d_body<N, kNodal, MASS>(p, lds_tr, zbuf, abl, blockIdx.x, p.step0, p.nsteps);
 }
 
 // Several problems of one order in one launch; workgroup ranges per problem.
-template <int N, bool kNodal>
+template <int N, bool kNodal, bool MASS>
 __global__ __launch_bounds__(kResidentThreads) void resident_1d_batch_kernel(Batch1DArgs a) {
   extern __shared__ double lds_tr[];
   __shared__ double zbuf[kResidentThreads];
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(kResidentThreads) void resident_1d_batch_kernel(Bat
   const int64_t b = blockIdx.x;
   int t = 0;
   while (t + 1 < a.ntasks && b >= a.bstart[t + 1]) ++t;
-  resident_1d_body<N, kNodal>(*a.task[t], lds_tr, zbuf, abl, b - a.bstart[t], a.step0[t], a.nsteps);
+  resident_1d_body<N, kNodal, MASS>(*a.task[t], lds_tr, zbuf, abl, b - a.bstart[t], a.step0[t], a.nsteps);
 }
 
 // Tiled one-dimensional step for meshes of more than 256 elements: one launch
@@ -181,9 +184,10 @@ constexpr int kTile1D = kResidentThreads - 2;
 
 int tiled_1d_tiles(int K) { return (K + kTile1D - 1) / kTile1D; }
 
-template <int N, bool kNodal>
+template <int N, bool kNodal, bool MASS0>
 __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, const double* phi_in,
                                                                     double* phi_out, int64_t step) {
+  constexpr bool MASS = MASS0 && N >= 3;
   __shared__ double trL[kResidentThreads], trR[kResidentThreads];
   const int K = p.K;
   const int tiles = (K + kTile1D - 1) / kTile1D;
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
         nod.a[i] = ph[i] * src[i];
         esc += owned ? escaped(nod.xs[i]) : 0;
       }
-      fit1d_nodal_pre<N>(nod);
+      fit1d_nodal_pre<N, MASS>(nod, p.xi, p.wq);
       tL = nod.tL;
       tR = nod.tR;
     } else {
@@ -227,7 +231,7 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
         f[i] = ph[i] * src[i];
         esc += owned ? escaped(xs[i]) : 0;
       }
-      fit1d_pre<N>(xs, f, p.xi, p.rec, pre);
+      fit1d_pre<N, MASS>(xs, f, p.xi, p.rec, pre, p.wq);
       tL = pre.tL;
       tR = pre.tR;
     }
@@ -246,8 +250,8 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
     const double gL = (dL > 0.0) ? nbL : tL;
     const double gR = (dR > 0.0) ? tR : nbR;
     double phi[N];
-    if constexpr (kNodal) fit1d_nodal_post<N>(nod, p.xi, gL, gR, phi);
-    else fit1d_post<N>(pre, gL, gR, phi);
+    if constexpr (kNodal) fit1d_nodal_post<N, MASS>(nod, p.xi, gL, gR, phi);
+    else fit1d_post<N, MASS>(pre, gL, gR, phi);
     double* out = phi_out + s * (int64_t)(K * N) + (int64_t)e * N;
 #pragma unroll
     for (int i = 0; i < N; ++i) out[i] = phi[i];
@@ -257,10 +261,11 @@ __global__ __launch_bounds__(kResidentThreads) void tiled_1d_kernel(Params1D p, 
 template <int N>
 static hipError_t launch_tiled_n(const Params1D& p, const double* in, double* out, int64_t step, hipStream_t st) {
   const int64_t blocks = p.M * (int64_t)tiled_1d_tiles(p.K);
-  if (p.algo == 1)
-    hipLaunchKernelGGL((tiled_1d_kernel<N, false>), dim3((unsigned)blocks), dim3(kResidentThreads), 0, st, p, in, out, step);
-  else
-    hipLaunchKernelGGL((tiled_1d_kernel<N, true>), dim3((unsigned)blocks), dim3(kResidentThreads), 0, st, p, in, out, step);
+  const dim3 g((unsigned)blocks), b(kResidentThreads);
+  if (p.algo == 1 && p.mass) hipLaunchKernelGGL((tiled_1d_kernel<N, false, true>), g, b, 0, st, p, in, out, step);
+  else if (p.algo == 1) hipLaunchKernelGGL((tiled_1d_kernel<N, false, false>), g, b, 0, st, p, in, out, step);
+  else if (p.mass) hipLaunchKernelGGL((tiled_1d_kernel<N, true, true>), g, b, 0, st, p, in, out, step);
+  else hipLaunchKernelGGL((tiled_1d_kernel<N, true, false>), g, b, 0, st, p, in, out, step);
   return hipGetLastError();
 }
 
@@ -288,10 +293,12 @@ hipError_t launch_tiled_1d(int N, const Params1D& p, const double* in, double* o
 template <int N>
 static hipError_t launch_batch_n(const Batch1DArgs& a, int algo, size_t lds, hipStream_t st) {
   const int64_t blocks = a.bstart[a.ntasks];
-  if (algo == 1)
-    hipLaunchKernelGGL((resident_1d_batch_kernel<N, false>), dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, a);
-  else
-    hipLaunchKernelGGL((resident_1d_batch_kernel<N, true>), dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, a);
+  const dim3 g((unsigned)blocks), b(kResidentThreads);
+  const bool mass = algo >= 2;        // algo + 2: with the mass constraint
+  if ((algo & 1) == 1 && mass) hipLaunchKernelGGL((resident_1d_batch_kernel<N, false, true>), g, b, lds, st, a);
+  else if ((algo & 1) == 1) hipLaunchKernelGGL((resident_1d_batch_kernel<N, false, false>), g, b, lds, st, a);
+  else if (mass) hipLaunchKernelGGL((resident_1d_batch_kernel<N, true, true>), g, b, lds, st, a);
+  else hipLaunchKernelGGL((resident_1d_batch_kernel<N, true, false>), g, b, lds, st, a);
   return hipGetLastError();
 }
 
@@ -320,10 +327,11 @@ template <int N>
 static hipError_t launch_n(const Params1D& p, hipStream_t st) {
   const int64_t blocks = (p.M + p.samples_per_block - 1) / p.samples_per_block;
   const size_t lds = resident_1d_lds_bytes(p.K, p.samples_per_block);
-  if (p.algo == 1)
-    hipLaunchKernelGGL((resident_1d_kernel<N, false>), dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, p);
-  else
-    hipLaunchKernelGGL((resident_1d_kernel<N, true>), dim3((unsigned)blocks), dim3(kResidentThreads), lds, st, p);
+  const dim3 g((unsigned)blocks), b(kResidentThreads);
+  if (p.algo == 1 && p.mass) hipLaunchKernelGGL((resident_1d_kernel<N, false, true>), g, b, lds, st, p);
+  else if (p.algo == 1) hipLaunchKernelGGL((resident_1d_kernel<N, false, false>), g, b, lds, st, p);
+  else if (p.mass) hipLaunchKernelGGL((resident_1d_kernel<N, true, true>), g, b, lds, st, p);
+  else hipLaunchKernelGGL((resident_1d_kernel<N, true, false>), g, b, lds, st, p);
   return hipGetLastError();
 }
 

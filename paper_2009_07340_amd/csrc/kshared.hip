@@ -56,15 +56,17 @@ struct LayS {
   static constexpr int GS = T + 1;                   // padded row of a tile's boundary data
   static constexpr size_t tile_bytes = sizeof(double) * (size_t)E * (FS + GS);
   // build kernel LDS (doubles): tables, C_r, S, Y = S^-1 U_r^T, W = C_r^T Y; Mg's
-  // first pass reuses the space of C_r and S
-  static constexpr int oPx = 0, oPy = oPx + N * N, oEv = oPy + N * N;
-  static constexpr int CRS = n + 1, SS = R + 1;
-  static constexpr int oCr = oEv + 4 * N;
-  static constexpr int oS = oCr + R * CRS;
-  static constexpr int oY = oS + R * SS;
-  static constexpr int oW = oY + R * T;
+  // first pass reuses the space of C_r and S.  Room for R + 1 constraint rows (the
+  // mass constraint adds one).
+  static constexpr int RX = R + 1;
+  static constexpr int oPx = 0, oPy = oPx + N * N, oEv = oPy + N * N, oMq = oEv + 4 * N;
+  static constexpr int CRS = n + 1, SS = RX + 1;
+  static constexpr int oCr = oMq + 2 * N;
+  static constexpr int oS = oCr + RX * CRS;
+  static constexpr int oY = oS + RX * SS;
+  static constexpr int oW = oY + RX * T;
   static constexpr int oTmp = oCr;                   // n x T, over C_r and S (dead by then)
-  static_assert(n * T <= R * CRS + R * SS + R * T, "the second pass of Mg must fit where C_r, S and Y were");
+  static_assert(n * T <= RX * CRS + RX * SS + RX * T, "the second pass of Mg must fit where C_r, S and Y were");
   static constexpr int bend = oW + n * T;
   static constexpr size_t build_bytes = sizeof(double) * (size_t)(bend + 4);
 };
@@ -89,11 +91,15 @@ __device__ __forceinline__ double cstar(const double* Px, const double* Py, cons
   return Px[j * N + ix] * Ev[3 * N + iy];                 // N: (xi_j, 1)
 }
 
-// One workgroup per sample: the operators of that sample's step.
-template <int N>
+// One workgroup per sample: the operators of that sample's step.  MASS: one more
+// constraint row, the element integral m* (value space) with a zero residual: the
+// remap keeps each element's integral of p0 (left out at N = 2, where the boundary
+// values fix the polynomial).
+template <int N, bool MASS0>
 __global__ __launch_bounds__(kThreads) void shared_build(SharedArgs a) {
   using L = LayS<N>;
-  constexpr int n = L::n, T = L::T, R = L::R;
+  constexpr bool MASS = MASS0 && N >= 3;
+  constexpr int n = L::n, T = L::T, RB = L::R, R = RB + (MASS ? 1 : 0);
   extern __shared__ __attribute__((aligned(16))) double lb[];
   const int t = tid();
   const int64_t s = blockIdx.x;
@@ -101,6 +107,7 @@ __global__ __launch_bounds__(kThreads) void shared_build(SharedArgs a) {
   double* Px = lb + L::oPx;
   double* Py = lb + L::oPy;
   double* Ev = lb + L::oEv;
+  double* Mq = lb + L::oMq;                          // mass row factors: integral of each 1-D Lagrange basis
   double* Cr = lb + L::oCr;
   double* S = lb + L::oS;
   double* Y = lb + L::oY;
@@ -132,6 +139,17 @@ __global__ __launch_bounds__(kThreads) void shared_build(SharedArgs a) {
     }
   }
   block_sync();
+  if constexpr (MASS) {
+    // m*[(iy, ix)] = mx[ix] my[iy], mx[i] = sum_j wq_j Px[j][i]: the element's quadrature of the
+    // interpolant (the element is [0, 1] - delta in the centred frame, its Gauss nodes xi_j - delta)
+    for (int it = t; it < 2 * N; it += kThreads) {
+      const int dir = it >= N, i = it - dir * N;
+      const double* P = dir ? Py : Px;
+      double acc = 0.0;
+      for (int j = 0; j < N; ++j) acc += a.wq[j] * P[j * N + i];
+      Mq[it] = acc;
+    }
+  }
   // C* (traces from the carried values, source factor folded in), fragment order
   double* Cf = op + L::a_doubles;
   for (int idx = t; idx < (int)L::c_doubles; idx += kThreads) {
@@ -139,13 +157,17 @@ __global__ __launch_bounds__(kThreads) void shared_build(SharedArgs a) {
     const int q = 16 * I + (l & 15), p = 4 * kk + (l >> 4);
     Cf[idx] = (q < T && p < n) ? a.src * cstar<N>(Px, Py, Ev, q, p) : 0.0;
   }
-  // C_r = U_r^T C*  (U_r column-major T x R)
-  for (int idx = t; idx < R * n; idx += kThreads) {
+  // C_r = U_r^T C*  (U_r column-major T x R), then the mass row
+  for (int idx = t; idx < RB * n; idx += kThreads) {
     const int c = idx / n, p = idx - c * n;
     const double* U = a.ur + (size_t)c * T;
     double acc = 0.0;
     for (int q = 0; q < T; ++q) acc += U[q] * cstar<N>(Px, Py, Ev, q, p);
     Cr[c * L::CRS + p] = acc;
+  }
+  if constexpr (MASS) {
+    block_sync();
+    for (int p = t; p < n; p += kThreads) Cr[RB * L::CRS + p] = Mq[p % N] * Mq[N + p / N];
   }
   block_sync();
   // S = C_r C_r^T
@@ -185,11 +207,11 @@ __global__ __launch_bounds__(kThreads) void shared_build(SharedArgs a) {
     }
     block_sync();
   }
-  // Y = S^-1 U_r^T  (R x T)
+  // Y = S^-1 [U_r^T; 0]  (R x T; the mass row's right side is zero)
   for (int idx = t; idx < R * T; idx += kThreads) {
     const int c = idx / T, q = idx - c * T;
     double acc = 0.0;
-    for (int c2 = 0; c2 < R; ++c2) acc += S[c * L::SS + c2] * a.ur[(size_t)c2 * T + q];
+    for (int c2 = 0; c2 < RB; ++c2) acc += S[c * L::SS + c2] * a.ur[(size_t)c2 * T + q];
     Y[idx] = acc;
   }
   block_sync();
@@ -375,8 +397,10 @@ static hipError_t launch_shared_n(int stage, const SharedArgs& a, int64_t M, hip
   const int64_t tiles = (a.K + L::E - 1) / L::E;
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   const size_t tb = L::tile_bytes > sizeof(double) * L::E * L::n ? L::tile_bytes : sizeof(double) * L::E * L::n;
-  if (stage == 0)
-    hipLaunchKernelGGL((shared_build<N>), dim3((unsigned)M), dim3(kThreads), L::build_bytes, st, a);
+  if (stage == 0 && a.mass)
+    hipLaunchKernelGGL((shared_build<N, true>), dim3((unsigned)M), dim3(kThreads), L::build_bytes, st, a);
+  else if (stage == 0)
+    hipLaunchKernelGGL((shared_build<N, false>), dim3((unsigned)M), dim3(kThreads), L::build_bytes, st, a);
   else if (stage == 1)
     hipLaunchKernelGGL((shared_traces<N>), dim3((unsigned)tiles, (unsigned)rows), dim3(kThreads), tb, st, a);
   else

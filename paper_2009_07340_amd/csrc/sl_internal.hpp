@@ -66,8 +66,10 @@ struct Params1D {
   uint64_t seed;
   uint32_t stream;
   unsigned long long* stats;   // diagnostics slots (kStatSlots x kStatStride), or null
+  int mass;              // 1: the fit also keeps the element integral of p0
   LegendreRec rec;
   double xi[kMaxN];      // reference nodes
+  double wq[kMaxN];      // quadrature weights of the reference nodes (element integrals)
 };
 
 // Step inputs of one order group for the 2-D phase kernels.
@@ -106,6 +108,8 @@ struct Params2D {
   double tol2;             // stop when g^T g <= tol2 * x0^T x0 (g: preconditioned residual)
   int max_iter;
   unsigned long long* stats;   // diagnostics slots (kStatSlots x kStatStride, layout above)
+  int mass;                // 1: the fit also keeps the element integral of p0 (not on this path)
+  const double* wq_tab;    // [(kMaxN+1)][kMaxN] quadrature weights of each order's nodes
   LegendreRec rec;
 };
 
@@ -166,6 +170,8 @@ struct SharedArgs {
   double* tr;            // [M][ncomp][K 4N]
   int64_t K;
   int ncomp;             // row r of phi / tr uses the operators of sample r / ncomp
+  int mass;              // 1: the remap also keeps each element's integral of p0
+  const double* wq;      // [N] quadrature weights of the reference nodes
   int64_t step;
   const int64_t* step_ptr;
   uint64_t seed;

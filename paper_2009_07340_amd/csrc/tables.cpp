@@ -100,6 +100,35 @@ static void lagrange_row(const std::vector<double>& from, double x, double* out)
   }
 }
 
+std::vector<double> quadrature_weights(const std::vector<double>& xi) {
+  // the interpolatory rule on [0, 1]: sum_i w_i xi_i^k = 1 / (k + 1), k < n, solved in
+  // __float128 by Gaussian elimination with partial pivoting (Gauss weights for GL nodes)
+  const int n = (int)xi.size();
+  std::vector<qd> A((size_t)n * (n + 1));
+  for (int k = 0; k < n; ++k) {
+    for (int i = 0; i < n; ++i) {
+      qd v = 1;
+      for (int e = 0; e < k; ++e) v *= (qd)xi[i];
+      A[(size_t)k * (n + 1) + i] = v;
+    }
+    A[(size_t)k * (n + 1) + n] = (qd)1 / (qd)(k + 1);
+  }
+  for (int c = 0; c < n; ++c) {
+    int pr = c;
+    for (int r = c + 1; r < n; ++r)
+      if (qabs(A[(size_t)r * (n + 1) + c]) > qabs(A[(size_t)pr * (n + 1) + c])) pr = r;
+    for (int j = 0; j <= n; ++j) std::swap(A[(size_t)c * (n + 1) + j], A[(size_t)pr * (n + 1) + j]);
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const qd f = A[(size_t)r * (n + 1) + c] / A[(size_t)c * (n + 1) + c];
+      for (int j = c; j <= n; ++j) A[(size_t)r * (n + 1) + j] -= f * A[(size_t)c * (n + 1) + j];
+    }
+  }
+  std::vector<double> w(n);
+  for (int i = 0; i < n; ++i) w[i] = (double)(A[(size_t)i * (n + 1) + n] / A[(size_t)i * (n + 1) + i]);
+  return w;
+}
+
 std::vector<double> barycentric_weights(const std::vector<double>& xi) {
   const int n = (int)xi.size();
   std::vector<double> w(n);

@@ -14,6 +14,8 @@ double min_node_spacing(const std::vector<double>& xi);
 std::vector<double> lagrange_matrix(const std::vector<double>& from, const std::vector<double>& to);
 // Orthonormal basis of the edge-value vectors of Q_{N-1} (4N x (4N-4)), column-major.
 std::vector<double> edge_range_basis(int N, const std::vector<double>& xi);
+// Weights of the interpolatory quadrature on [0, 1] at the nodes (exact on degree < n).
+std::vector<double> quadrature_weights(const std::vector<double>& xi);
 // Barycentric weights 1 / prod_{m != i} (xi_i - xi_m) of the nodes, in long double.
 std::vector<double> barycentric_weights(const std::vector<double>& xi);
 // Inverse of the reference Gram matrix Gx = Vx^T Vx of the orthonormal Legendre

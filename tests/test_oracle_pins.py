@@ -280,3 +280,85 @@ def test_pdf_counts_at_the_bin_edges():
     c = sl.pdf_counts(vals.T.copy().reshape(-1, 1), lo, hi, nb)[0]
     # 0.0 and -0.0: bin 0; 0.25: bin 1; 0.5: bin 2; 0.75 and nextafter(1, 0): bin 3; 1.0: over; -tiny: under
     np.testing.assert_array_equal(c, [1, 2, 1, 1, 2, 1])
+
+
+# ---------------------------------------------------------------- mass constraint
+
+def _mp_mass_fit(N, dim, xs, f, g):
+    """KKT of the boundary- and mass-constrained least squares in mpmath (60 digits) in the
+    monomial basis (x - 1/2)^k (y - 1/2)^l, with the element integrals of the monomials in
+    closed form: int_0^1 (x - 1/2)^k dx = ((1/2)^(k+1) - (-1/2)^(k+1)) / (k + 1)."""
+    import mpmath
+    from test_oracle_fit import _mp_monomials, _ref_and_edges
+    with mpmath.workdps(60):
+        ref, edges = _ref_and_edges(N, dim)
+        V = _mp_monomials(xs, N, dim)
+        C = _mp_monomials(edges, N, dim)
+        E = _mp_monomials(ref, N, dim)
+        n = V.cols
+        half = mpmath.mpf(1) / 2
+        mu = [(half ** (k + 1) - (-half) ** (k + 1)) / (k + 1) for k in range(N)]
+        m = [mu[k] for k in range(N)] if dim == 1 else [mu[k] * mu[l] for l in range(N) for k in range(N)]
+        r = 2 if dim == 1 else 4 * N - 4
+        U, S, _ = mpmath.svd_r(C)
+        Cr = U[:, :r].T * C
+        gr = U[:, :r].T * mpmath.matrix([mpmath.mpf(float(v)) for v in g])
+        fv = mpmath.matrix([mpmath.mpf(float(v)) for v in f])
+        c0 = mpmath.lu_solve(V, fv)
+        mass0 = sum(m[i] * c0[i] for i in range(n))
+        K = mpmath.zeros(n + r + 1, n + r + 1)
+        G = V.T * V
+        b = V.T * fv
+        rhs = mpmath.matrix(n + r + 1, 1)
+        for i in range(n):
+            rhs[i] = b[i]
+            for j in range(n):
+                K[i, j] = G[i, j]
+            for j in range(r):
+                K[n + j, i] = K[i, n + j] = Cr[j, i]
+            K[n + r, i] = K[i, n + r] = m[i]
+        for j in range(r):
+            rhs[n + j] = gr[j]
+        rhs[n + r] = mass0
+        sol = mpmath.lu_solve(K, rhs)
+        out = E * mpmath.matrix([sol[i] for i in range(n)])
+        return np.array([float(out[i]) for i in range(out.rows)])
+
+
+@pytest.mark.parametrize("dim,N", [(1, 3), (1, 4), (1, 6), (2, 3), (2, 4)])
+def test_mass_constrained_fit_matches_mpmath_kkt(dim, N):
+    """The boundary- and mass-constrained fit against an mpmath KKT solve in an independent
+    basis with exact element integrals; the result keeps the element integral of p0."""
+    from test_oracle_fit import _ref_and_edges
+    g0 = np.random.default_rng(300 + 10 * dim + N)
+    ref, edges = _ref_and_edges(N, dim)
+    for trial in range(3):
+        shift = g0.uniform(-0.3, 0.3, size=dim)
+        xs = ref + shift + g0.uniform(-0.02, 0.02, size=ref.shape)
+        f = np.cos(2.0 * xs[:, 0] + 0.3) + (np.sin(1.5 * xs[:, 1]) if dim == 2 else 0.0)
+        dbar, V, c0, C, t = sl.advected_interpolant(N, dim, xs, f, ref)
+        g = t + 0.05 * g0.normal(size=edges.shape[0])
+        m = sl.mass_row(N, dim, dbar, ref)
+        a = sl.constrained_values(N, dim, V, C, f, t, g, m)
+        ours = sl.values_at_nodes(N, dim, V, a, dbar, ref)
+        want = _mp_mass_fit(N, dim, xs, f, g)
+        assert np.max(np.abs(ours - want)) / max(1.0, np.abs(want).max()) < 1e-12, (trial, ours, want)
+        # the element integral of the remapped polynomial is that of p0
+        c = np.linalg.solve(V, a)
+        assert abs(m @ c - m @ c0) < 1e-13 * max(1.0, abs(m @ c0))
+        # and it differs from the boundary-only fit
+        a_b = sl.constrained_values(N, dim, V, C, f, t, g)
+        assert np.max(np.abs(a_b - a)) > 1e-6
+
+
+def test_mass_constraint_is_left_out_for_two_nodes():
+    """N = 2: the boundary values fix the linear polynomial; the mass row changes nothing."""
+    from test_oracle_fit import _ref_and_edges
+    ref, edges = _ref_and_edges(2, 1)
+    xs = ref + 0.05
+    f = np.array([1.0, 2.0])
+    dbar, V, c0, C, t = sl.advected_interpolant(2, 1, xs, f, ref)
+    g = t + np.array([0.1, -0.2])
+    m = sl.mass_row(2, 1, dbar, ref)
+    np.testing.assert_array_equal(sl.constrained_values(2, 1, V, C, f, t, g, m),
+                                  sl.constrained_values(2, 1, V, C, f, t, g))
