@@ -81,10 +81,10 @@ struct Layout {
   // byte offsets in the workspace
   size_t o_phi, o_phi2, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
-  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_sops, o_bw, o_wqtab, total;
+  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_nsp, o_sops, o_bw, o_wqtab, total;
   bool shared_capable = false;      // one order <= kMaxNShared in 2-D: the shared-geometry path can run
   int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
-  size_t gx_doubles = 0;
+  size_t gx_doubles = 0, nsp_doubles = 0;
   int max_iter = 32;
   double tol = 1e-13;
 };
@@ -151,6 +151,7 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
       for (int Ns : L.orders)
         if (Nd != Ns) L.interp_doubles += (size_t)Nd * Ns;
     for (int N : L.orders) L.gx_doubles += (size_t)N * N;
+    for (int N : L.orders) L.nsp_doubles += (size_t)sl::nsp_doubles(N);
   }
   if ((double)L.MV * (double)L.nodes * 8.0 > 250e9) return fail(SL_ENOMEM, "state exceeds device memory");
   size_t o = 0;
@@ -192,6 +193,7 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
     L.o_mpart = take(C > 1 ? sizeof(double) * (size_t)C * L.nc * L.nodes : 0);
   }
   L.o_gxinv = take(sizeof(double) * (L.gx_doubles + 1));
+  L.o_nsp = take(sizeof(double) * (L.nsp_doubles + 1));
   L.o_wqtab = take(sizeof(double) * (sl::kMaxN + 1) * sl::kMaxN);
   L.shared_capable = L.dim == 2 && L.uniform && L.maxN <= sl::kMaxNShared;
   L.o_sops = take(L.shared_capable ? sizeof(double) * (size_t)L.M * sl::shared_op_doubles(L.maxN) : 0);
@@ -219,6 +221,7 @@ struct sl_ctx {
   std::vector<std::pair<int, std::pair<int64_t, int64_t>>> groups;   // (N, (first work index, count))
   std::map<int, std::vector<double>> xi_tab;    // reference nodes per order
   int64_t gx_off[sl::kMaxN + 1] = {0};          // offsets of the reference Gram inverses
+  int64_t nsp_off[sl::kMaxN + 1] = {0};         // offsets of the null-space tables
   sl::LegendreRec rec{};
   // host copies of the fields
   std::vector<double> u, D, divu, un, Dn, ghost_h;
@@ -242,6 +245,7 @@ struct sl_ctx {
   unsigned long long* d_nonf = nullptr;  // non-finite values seen by the last sample mean
   double* d_mpart = nullptr;             // partial sums of the sample mean
   double* d_gxinv = nullptr;
+  double* d_nsp = nullptr;
   double* d_sops = nullptr;              // shared-geometry path: per-sample operators
   double* d_bw = nullptr;                // barycentric weights of the (single) order's nodes
   double* d_wqtab = nullptr;             // [(kMaxN+1)][kMaxN] quadrature weights of each order's nodes
@@ -403,6 +407,8 @@ void build_params(sl_ctx* h) {
     p.refine = h->desc.refine_iters >= 0 ? h->desc.refine_iters : default_refine(h->desc.precision);
     p.gxinv = h->d_gxinv;
     for (int N = 0; N <= sl::kMaxN; ++N) p.gx_off[N] = h->gx_off[N];
+    p.nsp = h->d_nsp;
+    for (int N = 0; N <= sl::kMaxN; ++N) p.nsp_off[N] = h->nsp_off[N];
     p.tol2 = L.tol * L.tol;
     p.max_iter = L.max_iter;
     p.stats = h->d_stats;
@@ -859,6 +865,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_nonf = (unsigned long long*)(h->ws + L.o_nonf);
   h->d_mpart = (double*)(h->ws + L.o_mpart);
   h->d_gxinv = (double*)(h->ws + L.o_gxinv);
+  h->d_nsp = (double*)(h->ws + L.o_nsp);
   h->d_sops = (double*)(h->ws + L.o_sops);
   h->d_wqtab = (double*)(h->ws + L.o_wqtab);
   h->d_bw = (double*)(h->ws + L.o_bw);
@@ -924,6 +931,16 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       o += G.size();
     }
   }
+  std::vector<double> nsp(L.nsp_doubles + 1, 0.0);
+  if (L.dim == 2) {
+    size_t o = 0;
+    for (int N : L.orders) {
+      const auto T = sl::nullspace_tables(N, h->xi_tab[N]);
+      h->nsp_off[N] = (int64_t)o;
+      std::copy(T.begin(), T.end(), nsp.begin() + o);
+      o += T.size();
+    }
+  }
   std::vector<double> bw(sl::kMaxN, 0.0);
   {
     const auto w = sl::barycentric_weights(h->xi_tab[L.order[0]]);
@@ -939,7 +956,8 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       {h->d_ur, ur.data(), sizeof(double) * ur.size()}, {h->d_uroff, uroff.data(), sizeof(int64_t) * uroff.size()},
       {h->d_interp, interp.data(), sizeof(double) * interp.size()},
       {h->d_interpoff, interpoff.data(), sizeof(int64_t) * interpoff.size()},
-      {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}, {h->d_bw, bw.data(), sizeof(double) * bw.size()},
+      {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}, {h->d_nsp, nsp.data(), sizeof(double) * nsp.size()},
+      {h->d_bw, bw.data(), sizeof(double) * bw.size()},
       {h->d_wqtab, wqtab.data(), sizeof(double) * wqtab.size()}};
   for (const auto& u : ups) {
     if (hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) {

@@ -4,32 +4,23 @@
 // (Sec. 5.3, eqs. phi_stardef, h_star, remap_bnd, bnd_update, phi_star), solved
 // without forming or factoring the Gram matrix G = V^T V of the fit.
 //
-// The basis is centred on the mean node displacement, so a uniform
-// displacement leaves the moved-node basis matrix equal to the reference one,
-// V0 = Vx (x) Vx: the orthonormal Legendre basis at the Gauss nodes.  Its Gram
-// matrix is a Kronecker product, G0 = Gx (x) Gx with Gx = Vx^T Vx, and
-// G0^-1 = Gx^-1 (x) Gx^-1 costs 2 N^3 operations to apply.  Only the
-// non-uniform part of the displacement (velocity and diffusion varying across
-// the element) makes G differ from G0, so G0 is an excellent preconditioner:
+// Phase 1 (unconstrained interpolant p0, its values at the Gauss nodes and its
+// traces at the own edge points): the basis is centred on the mean node
+// displacement, so a uniform displacement leaves the moved-node basis matrix
+// equal to the reference one, V0 = Vx (x) Vx: the orthonormal Legendre basis at
+// the Gauss nodes.  Its Gram matrix is a Kronecker product, G0 = Gx (x) Gx with
+// Gx = Vx^T Vx, and G0^-1 = Gx^-1 (x) Gx^-1 costs 2 N^3 operations to apply.
+// Only the non-uniform part of the displacement (velocity and diffusion
+// varying across the element) makes G differ from G0, so preconditioned
+// conjugate gradients on G c = V^T f with G0^-1 converge in a few iterations,
+// G applied matrix-free as V^T (V p) from the 1-D Legendre tables.
 //
-//   phase 1 (unconstrained interpolant p0, traces at the own edge points):
-//     preconditioned conjugate gradients on G c = V^T f, preconditioner G0^-1,
-//     G applied matrix-free as V^T (V p) from the 1-D Legendre tables;
-//   phase 2 (constrained remap):
-//     projected preconditioned conjugate gradients on the equality-constrained
-//     problem  min |V c - f|^2  s.t.  C_r c = g_r  with the constraint
-//     preconditioner [[G0, C_r^T], [C_r, 0]]^-1, applied by the range-space
-//     formula with S0 = C_r G0^-1 C_r^T.  Every iterate satisfies the
-//     constraints; one final correction restores them to working accuracy.
+// Phase 2 (constrained remap) works in null-space form on the (N-2)^2
+// coefficients of the part of the correction that vanishes on the edges, with
+// a Kronecker preconditioner of the same kind (see the phase-2 section).
 //
-// S0 needs no n x n work either: the edge-point rows of C are tensor products
-// of 1-D basis vectors, so C G0^-1 C^T is assembled from two (N+2) x (N+2)
-// tables of 1-D quadratic forms, and S0 = U_r^T (C G0^-1 C^T) U_r (matrix
-// cores).  S0 is inverted explicitly once per fit (Gauss-Jordan, one barrier
-// per pivot), so each iteration only applies dense matrix-vector products.
-//
-// The iteration count adapts to the fit: zero for a uniform displacement
-// (the preconditioner is then exact), a few for the smooth fields of the
+// The iteration counts adapt to the fit: zero for a uniform displacement (the
+// preconditioners are then exact), a few for the smooth fields of the
 // workloads.  Fits that do not reach the tolerance within the iteration limit
 // are counted in a device statistic.  Everything is float64.  One workgroup
 // (four wavefronts) per fit, all of its data in LDS (N <= 16).
@@ -47,11 +38,10 @@ namespace sl {
 
 using namespace blk;
 
-// LDS layout in doubles.  Phase 1 uses the first part only.
+// LDS layout of phase 1 in doubles.
 template <int N>
 struct LayR {
-  static constexpr int n = N * N, TT = 4 * N, R = 4 * N - 4, RB = (R + 15) / 16, RP = 16 * RB, NH = N + 2;
-  static constexpr int Rs = R + 1;             // row stride of the dense S0 / S0^-1
+  static constexpr int n = N * N, TT = 4 * N;
   // X1, Y1: the 1-D basis at the moved nodes, stored by basis index with an
   // odd row stride (XS = n + 1) so that lanes walking the nodes and lanes
   // walking the basis index both hit distinct LDS banks.
@@ -65,71 +55,51 @@ struct LayR {
   static constexpr int oB = oGxi + N * N;
   static constexpr int oF = oB + n;
   static constexpr int oXv = oF + n;
-  static constexpr int oZ0 = oXv + n;
-  static constexpr int oR = oZ0 + n;
+  static constexpr int oR = oXv + n;
   static constexpr int oGv = oR + n;
   static constexpr int oP = oGv + n;
   static constexpr int oQ = oP + n;
   static constexpr int oT1 = oQ + n;
-  static constexpr int oT2 = oT1 + n;
-  static constexpr int oTr = oT2 + n;          // traces / edge vector
-  static constexpr int oUc = oTr + TT;         // edge contractions (phase 1)
+  static constexpr int oTr = oT1 + n;          // traces
+  static constexpr int oUc = oTr + TT;         // edge contractions
   static constexpr int oXs = oUc + TT;
   static constexpr int oYs = oXs + n;
   static constexpr int oRed = oYs + n;
   static constexpr int end1 = oRed + 16;
-  // Phase 2.  Regions that are dead at the time hold short-lived data:
-  //   [f .. end of phase 1] (f, the iteration vectors, the phase-1 edge vectors,
-  //   the moved coordinates) holds Gx^-1 applied to the 1-D edge vectors while
-  //   the H tables are formed, then T U_r while S0 is assembled, then the
-  //   Gauss-Jordan pivot buffers; the phase-1 edge vectors are the projection's
-  //   edge vectors; S0's own space holds the H tables until S0 is written.
-  static constexpr int TTs = TT + 1;
-  static constexpr int tuMax = TTs * R;
-  static constexpr int oTU = oF;                      // T U_r, column stride US
-  static constexpr int oSd = (end1 > oTU + tuMax ? end1 : oTU + tuMax);   // S0, then S0^-1 (dense, R x Rs)
-  static constexpr int oPiv = oTU;                    // Gauss-Jordan pivot rows, two buffers
-  static_assert(8 * R <= oSd - oTU, "pivot buffers must fit in the aliased region");
-  static constexpr int oE1 = oTr;
-  static constexpr int oE2 = oUc;                     // contraction vectors
-  // The projection's two R-vectors sit in the gap between the phase-1 layout
-  // and S0 when there is one (dead there after S0 is assembled and inverted).
-  static constexpr bool kWinGap = oSd - end1 >= 2 * R;
-  static constexpr int oW1 = kWinGap ? end1 : oSd + R * Rs;
-  static constexpr int oW2 = oW1 + R;
-  static constexpr int oRr = kWinGap ? oSd + R * Rs : oW2 + R;   // g_r = U_r^T g
-  // The H tables and the upwinded boundary data g live in S0's space when they
-  // fit there: both are dead once T U_r and g_r are formed, before S0 is written.
-  static constexpr bool kHinS = 2 * NH * NH + TT <= R * Rs;
-  static constexpr int oHx = kHinS ? oSd : oRr + R;
-  static constexpr int oHy = oHx + NH * NH;
-  static constexpr int oGr = oHy + NH * NH;           // upwinded boundary data g
-  // T U_r and U_r^T (T U_r) run on the matrix cores, the entries of
-  // T = C G0^-1 C^T formed on the fly from the H tables.  U_r is staged in LDS
-  // (column stride TT + 1) when it fits and costs no occupancy (phase-2
-  // workgroups a CU, at most 5); otherwise it is read from the cache.
-  static constexpr int endR = kHinS ? oRr + R : oGr + TT;
-  static constexpr size_t kCU = 160 * 1024, bU = sizeof(double) * (endR + TTs * R), bNoU = sizeof(double) * endR;
-  static constexpr bool kUrLds = bU <= 156 * 1024 && (kCU / bU > 5 ? 5 : kCU / bU) >= (kCU / bNoU > 5 ? 5 : kCU / bNoU);
-  static constexpr int US = kUrLds ? TTs : TT;        // column stride of U_r as used
-  static constexpr int oU = endR;
-  static constexpr int end2 = kUrLds ? endR + TTs * R : endR;
-  // With U_r staged, the edge operators of the projection use the 4 (R x N)
-  // tables M (formed once per fit over the staged U_r, which is not needed
-  // afterwards): C_r z and C_r^T y then take two short stages each.
-  static constexpr bool kM = kUrLds;
-  static_assert(!kM || 4 * R * N <= TTs * R, "M tables replace the staged U_r");
-  static_assert(US * R <= oSd - oTU, "T U_r must fit in the aliased region");
   static constexpr size_t bytes1 = sizeof(double) * end1;
-  static constexpr size_t bytes2 = sizeof(double) * end2;
-  // Workgroups per CU that the LDS admits (one wave per SIMD each): the
-  // register budget is asked to admit as many, phase 2 at most 5 (more would
-  // spill its registers).
+  // Workgroups per CU that the LDS admits (one wave per SIMD each), at most cap:
+  // the register budget is asked to admit as many.
   static constexpr int lds_waves(size_t b, int cap) { return (160 * 1024) / b > (size_t)cap ? cap : (int)((160 * 1024) / b); }
-  static constexpr int waves1 = lds_waves(bytes1, 8), waves2 = lds_waves(bytes2, 5);
+  static constexpr int waves1 = lds_waves(bytes1, 8);
 };
 
 // ---------------------------------------------------------------- helpers
+
+// Lanes per output of a split reduction: as many as the workgroup holds for O
+// outputs (a power of two up to 8, so the lanes of one output share a wavefront).
+constexpr int ksplit(int O) { return O * 8 <= kThreads ? 8 : O * 4 <= kThreads ? 4 : O * 2 <= kThreads ? 2 : 1; }
+
+// out[o] = sum_{j < J} term(o, j) - (sub ? sub[o] : 0) for o < O.  G = ksplit(O)
+// adjacent lanes share an output, each summing j = g, g + G, ..., and the partial
+// sums meet by xor shuffles: the dependent chain is J / G long instead of J, and
+// G times more lanes work.  Every lane takes part in the shuffles.  No barrier.
+template <int O, int J, typename Term>
+__device__ __forceinline__ void splitk(Term term, double* out, const double* sub = nullptr) {
+  constexpr int G = ksplit(O), PER = kThreads / G;
+  const int t = tid(), g = t % G;
+#pragma unroll
+  for (int ob = 0; ob < O; ob += PER) {
+    const int o = ob + t / G;
+    double acc = 0.0;
+    if (o < O) {
+#pragma unroll 4
+      for (int j = g; j < J; j += G) acc += term(o, j);
+    }
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) acc += __shfl_xor(acc, m, 64);
+    if (g == 0 && o < O) out[o] = sub ? acc - sub[o] : acc;
+  }
+}
 
 // Sum over the workgroup of a per-thread value; every thread gets the same
 // result (fixed summation order).  One barrier: the slots in red are read
@@ -158,22 +128,6 @@ __device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) 
   block_sync();
   v0 = (red[0] + red[1]) + (red[2] + red[3]);
   v1 = (red[4] + red[5]) + (red[6] + red[7]);
-}
-
-// r^T g and g^T g of the current iterate.  The stopping test uses g^T g: g is
-// the preconditioned (projected) residual, about the error of the iterate, and
-// its rounding noise enters g^T g only to second order (r^T g carries it to
-// first order once the constraints hold r away from zero).
-template <int N>
-__device__ __forceinline__ void block_rg_gg(const double* r, const double* g, double& rg, double& gg, double* red) {
-  double a = 0.0, c = 0.0;
-  for (int i = tid(); i < N * N; i += kThreads) {
-    a += r[i] * g[i];
-    c += g[i] * g[i];
-  }
-  block_sum2(a, c, red);
-  rg = a;
-  gg = c;
 }
 
 template <int N>
@@ -212,15 +166,21 @@ __device__ void r_VT_mc(const double* X1, const double* Y1, const double* r, dou
   constexpr int n = N * N, XS = LayR<N>::XS;
   const int l = lane(), lr = l & 15, lk = l >> 4;
   const bool col = lr < N;
-  M64::acc_t acc = zacc<double>();
-#pragma unroll 4
-  for (int kk = 0; kk < (n + 3) / 4; ++kk) {
+  // four independent accumulator chains (slices kk = u mod 4), summed at the end,
+  // so that consecutive matrix-core operations do not wait on each other
+  constexpr int KK = (n + 3) / 4;
+  M64::acc_t ac[4] = {zacc<double>(), zacc<double>(), zacc<double>(), zacc<double>()};
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk) {
     const int i = 4 * kk + lk;
     const bool ok = col && i < n;
     const double a = ok ? Y1[lr * XS + i] : 0.0;          // A[ly][i]
     const double b = ok ? r[i] * X1[lr * XS + i] : 0.0;   // B[i][k]
-    acc = M64::mma(a, b, acc);
+    ac[kk & 3] = M64::mma(a, b, ac[kk & 3]);
   }
+  M64::acc_t acc;
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) acc[s4] = (ac[0][s4] + ac[1][s4]) + (ac[2][s4] + ac[3][s4]);
   double d = 0.0;
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
@@ -279,54 +239,6 @@ __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double*
   block_sync();
 }
 
-// out[q] = (C c)_q: the polynomial at own edge point q (W, E, S, N blocks of N)
-template <int N>
-__device__ void r_C(const double* Bx, const double* By, const double* Ev, const double* c, double* out) {
-  for (int q = tid(); q < 4 * N; q += kThreads) {
-    const int w = q / N, j = q % N;
-    double t = 0.0;
-#pragma unroll 1
-    for (int ly = 0; ly < N; ++ly) {
-      double inner = 0.0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const double bx = (w == 0) ? Ev[k] : (w == 1) ? Ev[N + k] : Bx[j * N + k];
-        inner += bx * c[ly * N + k];
-      }
-      const double by = (w < 2) ? By[j * N + ly] : (w == 2) ? Ev[2 * N + ly] : Ev[3 * N + ly];
-      t += by * inner;
-    }
-    out[q] = t;
-  }
-}
-
-// out[p] = (C^T v)_p
-template <int N>
-__device__ void r_CT(const double* Bx, const double* By, const double* Ev, const double* v, double* out) {
-  for (int p = tid(); p < N * N; p += kThreads) {
-    const int k = p % N, ly = p / N;
-    const double e0 = Ev[k], e1 = Ev[N + k], f0 = Ev[2 * N + ly], f1 = Ev[3 * N + ly];
-    double acc = 0.0;
-#pragma unroll 2
-    for (int j = 0; j < N; ++j)
-      acc += By[j * N + ly] * (e0 * v[j] + e1 * v[N + j]) + Bx[j * N + k] * (f0 * v[2 * N + j] + f1 * v[3 * N + j]);
-    out[p] = acc;
-  }
-}
-
-// out[c] = (U_r^T v)_c, c < R; U column-major 4N x R, column stride US (LDS copy) or
-// us (the table in global memory, stride 4N)
-template <int N>
-__device__ void r_UT(const double* U, const double* v, double* out, int us = LayR<N>::US) {
-  using L = LayR<N>;
-  for (int c = tid(); c < L::R; c += kThreads) {
-    double acc = 0.0;
-#pragma unroll 4
-    for (int q = 0; q < L::TT; ++q) acc += U[c * us + q] * v[q];
-    out[c] = acc;
-  }
-}
-
 // Carried values of component c's row of the state (eq. advection_phi) into f
 // and b = V^T f, for the second and later components of a fit (the first one's
 // come with the set-up).  Two barriers.
@@ -341,12 +253,13 @@ __device__ void r_rhs(const Params2D& p, double* lds, int e, int64_t row) {
   block_sync();
 }
 
-// Upwinded boundary data of one component row (eq. bnd_update) into gv: at each
-// own edge point, the element the interface displacement comes from supplies
-// the trace (another order's trace interpolated to this element's abscissae), or
-// the Dirichlet ghost value.  No barrier.
+// t - g at the own edge points of one component row into gv: t the own traces
+// of p0, g the upwinded boundary data (eq. bnd_update): at each own edge point
+// the element the interface displacement comes from supplies the trace
+// (another order's trace interpolated to this element's abscissae), or the
+// Dirichlet ghost value.  No barrier.
 template <int N>
-__device__ void r_upwind(const Params2D& p, int e, int64_t row, double za, double zb, double* gv) {
+__device__ void r_jump_data(const Params2D& p, int e, int64_t row, double za, double zb, double* gv) {
   using L = LayR<N>;
   const int64_t eoff = p.eoff[e];
   for (int q = tid(); q < L::TT; q += kThreads) {
@@ -374,31 +287,7 @@ __device__ void r_upwind(const Params2D& p, int e, int64_t row, double za, doubl
         }
       }
     }
-    gv[q] = g;
-  }
-}
-
-// out[q] = (U_r w)_q
-template <int N>
-__device__ void r_U(const double* U, const double* w, double* out) {
-  using L = LayR<N>;
-  for (int q = tid(); q < L::TT; q += kThreads) {
-    double acc = 0.0;
-#pragma unroll 4
-    for (int c = 0; c < L::R; ++c) acc += U[c * L::US + q] * w[c];
-    out[q] = acc;
-  }
-}
-
-// out = S0^-1 w (dense, row stride Rs)
-template <int N>
-__device__ void r_Sinv(const double* Sd, const double* w, double* out) {
-  using L = LayR<N>;
-  for (int c = tid(); c < L::R; c += kThreads) {
-    double acc = 0.0;
-#pragma unroll 4
-    for (int j = 0; j < L::R; ++j) acc += Sd[c * L::Rs + j] * w[j];
-    out[c] = acc;
+    gv[q] = tq - g;
   }
 }
 
@@ -434,47 +323,6 @@ __device__ void r_traces_from(const double* Bx, const double* By, const double* 
 #pragma unroll
     for (int m = 0; m < N; ++m) acc += B[m] * v[m];
     out[q] = acc;
-  }
-}
-
-// C_r z from the contractions u: w[c] = sum_w sum_m M_w[c][m] u_w[m] - rhs2[c],
-// with M_W[c][ly] = sum_j U_W[j][c] By[j][ly] (and E), M_S[c][k] = sum_j U_S[j][c] Bx[j][k]
-// (and N), stored as Mm[(w R + c) N + m].
-template <int N>
-__device__ void r_M_apply(const double* Mm, const double* u, const double* rhs2, double* out) {
-  using L = LayR<N>;
-  for (int c = tid(); c < L::R; c += kThreads) {
-    double acc = 0.0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const double* Mr = Mm + (w * L::R + c) * N;
-#pragma unroll
-      for (int m = 0; m < N; ++m) acc += Mr[m] * u[w * N + m];
-    }
-    if (rhs2) acc -= rhs2[c];
-    out[c] = acc;
-  }
-}
-
-// y-weighted edge vectors yv[w N + m] = sum_c M_w[c][m] y[c]
-template <int N>
-__device__ void r_MT_apply(const double* Mm, const double* y, double* yv) {
-  using L = LayR<N>;
-  for (int o = tid(); o < 4 * N; o += kThreads) {
-    const int w = o / N, m = o % N;
-    double acc = 0.0;
-#pragma unroll 4
-    for (int c = 0; c < L::R; ++c) acc += Mm[(w * L::R + c) * N + m] * y[c];
-    yv[o] = acc;
-  }
-}
-
-// C_r^T y from yv: out[(ly, k)] = p0x[k] yW[ly] + p1x[k] yE[ly] + p0y[ly] yS[k] + p1y[ly] yN[k]
-template <int N>
-__device__ void r_outer_edges(const double* Ev, const double* yv, double* out) {
-  for (int p = tid(); p < N * N; p += kThreads) {
-    const int k = p % N, ly = p / N;
-    out[p] = Ev[k] * yv[ly] + Ev[N + k] * yv[N + ly] + Ev[2 * N + ly] * yv[2 * N + k] + Ev[3 * N + ly] * yv[3 * N + k];
   }
 }
 
@@ -628,6 +476,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   double* t1 = lds + L::oT1;
   double* red = lds + L::oRed;
   const int64_t eoff = p.eoff[e];
+  const int64_t noff = p.noff[e];
   int its = 0, unconv = 0;
   double rmax = 0.0;
   // the components share the moved nodes and their tables (Sec. 5.3, last paragraph)
@@ -667,6 +516,26 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
       block_sync();
     }
   }
+  // p0 at the Gauss nodes into the state row, where phase 2 starts from it
+  {
+    const double* Bx = lds + L::oBx;
+    const double* By = lds + L::oBy;
+    for (int i = t; i < n; i += kThreads) {
+      const int ix = i % N, iy = i / N;
+      double bxr[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) bxr[k] = Bx[ix * N + k];
+      double v = 0.0;
+#pragma unroll 1
+      for (int ly = 0; ly < N; ++ly) {
+        double inner = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) inner += bxr[k] * x[ly * N + k];
+        v += By[iy * N + ly] * inner;
+      }
+      p.phi[row * p.nodes + noff + i] = v;
+    }
+  }
   // traces of p0 at the own edge points (eq. remap_bnd)
   double* tv = lds + L::oTr;
   double* uc = lds + L::oUc;
@@ -683,432 +552,413 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
 }
 
 // ---------------------------------------------------------------- phase 2
+//
+// Null-space form of the constrained remap.  Phase 1 left p0 at the Gauss nodes
+// in the state; p0 fits the carried values at the moved nodes exactly (up to
+// the solver tolerance), so for q = p0 - delta the misfit at the moved nodes is
+// delta there, and the remap is the delta in Q_{N-1} of least squares at the
+// moved nodes whose edge values are the jump j = P (t - g): t the own traces
+// of p0, g the upwinded data, P the orthogonal projector onto the edge-value
+// vectors of Q_{N-1} (the boundary constraints hold in that range).  Write
+//   delta = lift(j) + sum_{k,l} w_{lk} beta_k(x) beta_l(y),
+// lift(j) the transfinite interpolant of the four edge traces of j (each the
+// degree N-1 interpolant of its N values; it takes the edge values j and lies in
+// Q_{N-1}), beta_k(x) = x (1 - x) psi_k(x - dbar_x), k < N - 2 (psi: orthonormal
+// Legendre, centred on the mean displacement), which vanish on the edges and
+// span, with their y counterparts, the polynomials of Q_{N-1} that vanish
+// there.  w solves the (N-2)^2 normal equations
+//   (Vz^T Vz) w = -Vz^T lift(j)(moved nodes),  Vz[i][(l,k)] = beta_k(x_i) beta_l(y_i),
+// by preconditioned conjugate gradients.  Were the displacement uniform, Vz
+// would be the Kronecker product of the 1-D tables Bx[a][k] = beta_k(xi_a + dbar_x)
+// and By, so (Bx^T Bx)^-1 (x) (By^T By)^-1 (two (N-2)^2 inverses a fit) is the
+// exact inverse there and the preconditioner here.  The new values at the
+// Gauss nodes are p0 - lift(j) - sum w beta beta.  The iteration stops when the
+// nodal size of its estimated error is below tol times that of p0 and lift(j).
 
-// Constraint preconditioner, first block:  out = G0^-1 (r - C_r^T y) with
-// y = S0^-1 (C_r G0^-1 r - rhs2); rhs2 may be null (zero).  Leaves
-// z0 = G0^-1 r, y (in w2) and C_r^T y (in t2) behind.  Scratch: t1, e1, w1.
 template <int N>
-__device__ void r_Pproj(double* lds, const double* U, const double* rin, const double* rhs2, double* out) {
-  using L = LayR<N>;
-  const double* gxi = lds + L::oGxi;
-  double* z0 = lds + L::oZ0;
-  double* t1 = lds + L::oT1;
-  double* t2 = lds + L::oT2;
-  double* e1 = lds + L::oE1;
-  double* w1 = lds + L::oW1;
-  double* w2 = lds + L::oW2;
-  const double* Bx = lds + L::oBx;
-  const double* By = lds + L::oBy;
-  const double* Ev = lds + L::oEv;
-  r_G0inv<N>(gxi, rin, t1, z0);
-  if constexpr (L::kM) {
-    double* u = lds + L::oE2;
-    const double* Mm = lds + L::oU;
-    r_edge_contract<N>(Ev, z0, u);
-    block_sync();
-    r_M_apply<N>(Mm, u, rhs2, w1);
-    block_sync();
-    r_Sinv<N>(lds + L::oSd, w1, w2);
-    block_sync();
-    r_MT_apply<N>(Mm, w2, u);
-    block_sync();
-    r_outer_edges<N>(Ev, u, t2);
-    block_sync();
-  } else {
-    r_C<N>(Bx, By, Ev, z0, e1);
-    block_sync();
-    r_UT<N>(U, e1, w1);
-    block_sync();
-    if (rhs2) {
-      for (int c = tid(); c < L::R; c += kThreads) w1[c] -= rhs2[c];
-      block_sync();
+struct LayZ {
+  static constexpr int n = N * N, m = N - 2, mm = m * m, TT = 4 * N;
+  static constexpr int mA = m > 0 ? m : 1, mmA = mA * mA;
+  static constexpr int ZS = n + 1;            // odd row stride of the bubble tables at the moved nodes
+  static constexpr int oXz = 0;               // Xz[k][i] = beta_k(x_i)
+  static constexpr int oYz = oXz + mA * ZS;   // Yz[l][i] = beta_l(y_i)
+  static constexpr int oZx = oYz + mA * ZS;   // Zx[a][k] = beta_k(xi_a), N x m
+  static constexpr int oZy = oZx + N * mA;
+  static constexpr int oGx = oZy + N * mA;    // (Bx^T Bx)^-1, m x m row-major
+  static constexpr int oGy = oGx + mmA;
+  static constexpr int oB = oGy + mmA;        // right side
+  static constexpr int oW = oB + mmA;         // iterate
+  static constexpr int oR = oW + mmA;         // residual
+  static constexpr int oG = oR + mmA;         // preconditioned residual
+  static constexpr int oP = oG + mmA;         // search direction
+  static constexpr int oQ = oP + mmA;         // (Vz^T Vz) p
+  static constexpr int oT = oQ + mmA;         // Kronecker temporary
+  static constexpr int oL = oT + mmA;         // n values at the moved nodes
+  static constexpr int oD = oL + n;           // t - g at the own edge points
+  static constexpr int oJ = oD + TT;          // the jump and its four corner values
+  static constexpr int oRed = oJ + TT + 4;
+  static constexpr int end = oRed + 16;
+  static constexpr size_t bytes = sizeof(double) * end;
+  static constexpr int waves = LayR<N>::lds_waves(bytes, 4);
+};
+
+// out[i] = (Vz c)_i, i < n
+template <int N>
+__device__ void z_V(const double* Xz, const double* Yz, const double* c, double* out) {
+  using L = LayZ<N>;
+  constexpr int m = L::m;
+  for (int i = tid(); i < L::n; i += kThreads) {
+    double xr[m];
+#pragma unroll
+    for (int k = 0; k < m; ++k) xr[k] = Xz[k * L::ZS + i];
+    double v = 0.0;
+#pragma unroll 1
+    for (int l = 0; l < m; ++l) {
+      double inner = 0.0;
+#pragma unroll
+      for (int k = 0; k < m; ++k) inner += xr[k] * c[l * m + k];
+      v += Yz[l * L::ZS + i] * inner;
     }
-    r_Sinv<N>(lds + L::oSd, w1, w2);
-    block_sync();
-    r_U<N>(U, w2, e1);
-    block_sync();
-    r_CT<N>(Bx, By, Ev, e1, t2);
-    block_sync();
+    out[i] = v;
   }
-  r_G0inv<N>(gxi, t2, t1, out, z0);
 }
 
-// In-place block Gauss-Jordan inversion of the dense SPD matrix S (R x R, row
-// stride Rs; R = 4(N - 1) is a multiple of 4): R / 4 steps, each eliminating a
-// 4 x 4 pivot block K (SPD, so no pivoting):
-//   S_KK <- P^-1,  S_Kj <- P^-1 S_Kj,  S_iK <- -S_iK P^-1,  S_ij <- S_ij - S_iK P^-1 S_Kj.
-// Between steps the working matrix keeps the structure of a partial inverse of
-// an SPD matrix: its eliminated and remaining diagonal blocks are symmetric and
-// the block from eliminated rows to remaining columns is minus the transpose of
-// its mirror, so a row's part of the pivot columns is read from the pivot rows
-// (negated for rows already eliminated).  Each thread keeps a strided piece of
-// one row in registers (TPR threads per row); the pivot rows pass through LDS
-// (two buffers, one barrier a step) and every thread solves with the 4 x 4
-// pivot block itself (Cholesky, two triangular solves).
+// out[(l, k)] = sign (Vz^T r)_(l,k) - (sub ? sub : 0): the m x m matrix Yz diag(r) Xz^T
+// as one 16 x 16 float64 matrix-core tile (K = n in steps of 4), by wavefront 0;
+// with dotw given, <dotw, out> is left in *dot_out.
 template <int N>
-__device__ void r_invert_S(double* Sd, double* piv) {
-  using L = LayR<N>;
-  // two wavefronts hold the matrix up to R = 32 (the per-step pivot solve is
-  // repeated by every wavefront that holds rows), the whole workgroup beyond
-  constexpr int R = L::R, NTH = R <= 32 ? 128 : kThreads, TPR = NTH / R, kE = (R + TPR - 1) / TPR;
-  static_assert(R % 4 == 0, "R is a multiple of 4");
-  const int t = tid();
-  const int i = t / TPR, chunk = t - i * TPR;
-  const bool live = i < R;
-  double a[kE];
-#pragma unroll
-  for (int m = 0; m < kE; ++m) {
-    const int j = chunk + TPR * m;
-    a[m] = (live && j < R) ? Sd[i * L::Rs + j] : 0.0;
+__device__ void z_VT_mc(const double* Xz, const double* Yz, const double* r, double* out, double sign,
+                        const double* sub = nullptr, const double* dotw = nullptr, double* dot_out = nullptr) {
+  typedef Mma<double> M64;
+  if (wave() != 0) return;
+  using L = LayZ<N>;
+  constexpr int n = L::n, m = L::m, ZS = L::ZS;
+  const int l = lane(), lr = l & 15, lk = l >> 4;
+  const bool col = lr < m;
+  constexpr int KK = (n + 3) / 4;
+  M64::acc_t ac[4] = {zacc<double>(), zacc<double>(), zacc<double>(), zacc<double>()};
+#pragma unroll 8
+  for (int kk = 0; kk < KK; ++kk) {
+    const int i = 4 * kk + lk;
+    const bool ok = col && i < n;
+    const double a = ok ? Yz[lr * ZS + i] : 0.0;          // A[l][i]
+    const double b = ok ? r[i] * Xz[lr * ZS + i] : 0.0;   // B[i][k]
+    ac[kk & 3] = M64::mma(a, b, ac[kk & 3]);
   }
-#pragma unroll 1
-  for (int k0 = 0; k0 < R; k0 += 4) {
-    double* prow = piv + ((k0 >> 2) & 1) * 4 * R;   // [4][R] pivot rows, two buffers
-    const bool inK = i >= k0 && i < k0 + 4;
-    if (live && inK) {
+  double d = 0.0;
 #pragma unroll
-      for (int m = 0; m < kE; ++m) {
-        const int j = chunk + TPR * m;
-        if (j < R) prow[(i - k0) * R + j] = a[m];
-      }
-    }
-    block_sync();
-    if (live) {
-      // this row's coefficients x = P^-1 rhs, rhs = S_iK^T (P symmetric) or, for
-      // a row of K, the unit vector (x is then that row of P^-1): Cholesky of
-      // the 4 x 4 pivot block (lower triangle) and two triangular solves
-      double Pl[4][4];
-#pragma unroll
-      for (int pp = 0; pp < 4; ++pp)
-#pragma unroll
-        for (int qq = 0; qq <= pp; ++qq) Pl[pp][qq] = prow[pp * R + k0 + qq];
-      double dinv[4];
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        double d = Pl[jj][jj];
-#pragma unroll
-        for (int kk = 0; kk < jj; ++kk) d -= Pl[jj][kk] * Pl[jj][kk];
-        dinv[jj] = rsqrt_nr(d);
-#pragma unroll
-        for (int ii = jj + 1; ii < 4; ++ii) {
-          double v = Pl[ii][jj];
-#pragma unroll
-          for (int kk = 0; kk < jj; ++kk) v -= Pl[ii][kk] * Pl[jj][kk];
-          Pl[ii][jj] = v * dinv[jj];
-        }
-      }
-      const double sg = (i < k0) ? -1.0 : 1.0;
-      double x[4];
-#pragma unroll
-      for (int pp = 0; pp < 4; ++pp) x[pp] = inK ? (i - k0 == pp ? 1.0 : 0.0) : sg * prow[pp * R + i];
-#pragma unroll
-      for (int ii = 0; ii < 4; ++ii) {
-        double v = x[ii];
-#pragma unroll
-        for (int kk = 0; kk < ii; ++kk) v -= Pl[ii][kk] * x[kk];
-        x[ii] = v * dinv[ii];
-      }
-#pragma unroll
-      for (int ii = 3; ii >= 0; --ii) {
-        double v = x[ii];
-#pragma unroll
-        for (int kk = ii + 1; kk < 4; ++kk) v -= Pl[kk][ii] * x[kk];
-        x[ii] = v * dinv[ii];
-      }
-#pragma unroll
-      for (int m = 0; m < kE; ++m) {
-        const int j = chunk + TPR * m;
-        const int jj = j < R ? j : 0;
-        const bool jK = jj >= k0 && jj < k0 + 4;
-        double v;
-        if (jK) {
-          const int q = jj - k0;
-          const double xq = (q == 0) ? x[0] : (q == 1) ? x[1] : (q == 2) ? x[2] : x[3];
-          v = inK ? xq : -xq;
-        } else {
-          const double r0 = prow[jj], r1 = prow[R + jj], r2 = prow[2 * R + jj], r3 = prow[3 * R + jj];
-          const double xr = x[0] * r0 + x[1] * r1 + x[2] * r2 + x[3] * r3;
-          v = inK ? xr : a[m] - xr;
-        }
-        a[m] = v;
-      }
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const int ly = M64::row(l, s4);
+    if (ly < m && col) {
+      const double v = sign * ((ac[0][s4] + ac[1][s4]) + (ac[2][s4] + ac[3][s4])) - (sub ? sub[ly * m + lr] : 0.0);
+      out[ly * m + lr] = v;
+      if (dotw) d += dotw[ly * m + lr] * v;
     }
   }
-  if (live) {
+  if (dotw) {
 #pragma unroll
-    for (int m = 0; m < kE; ++m) {
-      const int j = chunk + TPR * m;
-      if (j < R) Sd[i * L::Rs + j] = a[m];
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    if (l == 0) *dot_out = d;
+  }
+}
+
+// out = (Gx (x) Gy) v over v[l m + k]: tmp[l][k] = sum_k' Gx[k][k'] v[l][k'], then
+// out[l][k] = sum_l' Gy[l][l'] tmp[l'][k].  Two barriers.  With rr given, the
+// per-wavefront partial sums of rr . out and out . out are left in red2[0..3]
+// and red2[4..7] (readable after the second barrier).
+template <int N>
+__device__ void z_Pinv(const double* Gx, const double* Gy, const double* v, double* tmp, double* out,
+                       const double* rr = nullptr, double* red2 = nullptr) {
+  constexpr int m = LayZ<N>::m;
+  for (int p = tid(); p < m * m; p += kThreads) {
+    const int k = p % m, l = p / m;
+    double acc = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < m; ++kk) acc += Gx[k * m + kk] * v[l * m + kk];
+    tmp[p] = acc;
+  }
+  block_sync();
+  double a = 0.0, c = 0.0;
+  for (int p = tid(); p < m * m; p += kThreads) {
+    const int k = p % m, l = p / m;
+    double acc = 0.0;
+#pragma unroll
+    for (int ll = 0; ll < m; ++ll) acc += Gy[l * m + ll] * tmp[ll * m + k];
+    out[p] = acc;
+    if (rr) {
+      a += rr[p] * acc;
+      c += acc * acc;
+    }
+  }
+  if (rr) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 64);
+      c += __shfl_xor(c, o, 64);
+    }
+    if (lane() == 0) {
+      red2[wave()] = a;
+      red2[4 + wave()] = c;
     }
   }
   block_sync();
+}
+
+// Inverse of the 1-D preconditioner block Bz^T Bz, Bz[a][k] = s(xi_a + d) psi_k(xi_a)
+// with s(x) = x (1 - x) (the bubble table at the Gauss nodes shifted by d, in the
+// basis centred on d).  Called by a whole wavefront (uniform control flow): lane
+// c < m forms column c of the Gram matrix, then Gauss-Jordan elimination without
+// pivoting (the matrix is symmetric positive definite: at most two shifted nodes
+// make s vanish, and N - 2 >= m rows remain) runs in registers, the pivot column
+// broadcast from its lane.  The inverse goes to out, row-major m x m.
+template <int N>
+__device__ void z_gram_inverse(const double* Vx, const double* xi, double d, double* out) {
+  constexpr int m = LayZ<N>::m;
+  const int c = lane();
+  double col[m];
+#pragma unroll
+  for (int k = 0; k < m; ++k) col[k] = 0.0;
+  if (c < m) {
+    double vc[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const double xa = xi[a] + d;
+      const double sa = xa * (1.0 - xa);
+      vc[a] = (sa * sa) * Vx[a * N + c];
+    }
+#pragma unroll
+    for (int k = 0; k < m; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) acc += Vx[a * N + k] * vc[a];
+      col[k] = acc;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < m; ++k) {
+    double ak[m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) ak[i] = bcast(col[i], k);
+    const double pinv = 1.0 / ak[k];
+    if (c == k) {
+#pragma unroll
+      for (int i = 0; i < m; ++i) col[i] = (i == k) ? pinv : -ak[i] * pinv;
+    } else {
+      const double rk = col[k] * pinv;
+#pragma unroll
+      for (int i = 0; i < m; ++i) col[i] = (i == k) ? rk : col[i] - ak[i] * rk;
+    }
+  }
+  if (c < m) {
+#pragma unroll
+    for (int i = 0; i < m; ++i) out[i * m + c] = col[i];
+  }
+}
+
+// s0 = sum_a l_a(x) j0[a] and s1 = sum_a l_a(x) j1[a] for the Lagrange basis of
+// the Gauss abscissae in the first form, l_a(x) = w_a prod_{b != a} (x - xi_b),
+// from prefix products and a running suffix product.
+template <int N>
+__device__ __forceinline__ void lagrange_dots(double x, const double* xi, const double* bw, const double* j0,
+                                              const double* j1, double& s0, double& s1) {
+  double pre[N];
+  double pr = 1.0;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    pre[a] = pr;
+    pr *= x - xi[a];
+  }
+  double suf = 1.0, a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int a = N - 1; a >= 0; --a) {
+    const double la = (pre[a] * suf) * bw[a];
+    a0 += la * j0[a];
+    a1 += la * j1[a];
+    suf *= x - xi[a];
+  }
+  s0 = a0;
+  s1 = a1;
+}
+
+// Transfinite interpolant of the edge traces j (W, E, S, N blocks of N values at
+// the Gauss abscissae, then the corners SW, NW, SE, NE) at (x, y).
+template <int N>
+__device__ __forceinline__ double coons(const double* j, const double* xi, const double* bw, double x, double y) {
+  double tw, te, ts, tn;
+  lagrange_dots<N>(y, xi, bw, j, j + N, tw, te);
+  lagrange_dots<N>(x, xi, bw, j + 2 * N, j + 3 * N, ts, tn);
+  const double* cr = j + 4 * N;
+  const double x1 = 1.0 - x, y1 = 1.0 - y;
+  return (x1 * tw + x * te) + (y1 * ts + y * tn) - (x1 * (y1 * cr[0] + y * cr[1]) + x * (y1 * cr[2] + y * cr[3]));
+}
+
+// The same at the Gauss node (xi_a, xi_b), where the Lagrange values are unit vectors.
+template <int N>
+__device__ __forceinline__ double coons_node(const double* j, int a, int b, double x, double y) {
+  const double* cr = j + 4 * N;
+  const double x1 = 1.0 - x, y1 = 1.0 - y;
+  return (x1 * j[b] + x * j[N + b]) + (y1 * j[2 * N + a] + y * j[3 * N + a]) -
+         (x1 * (y1 * cr[0] + y * cr[1]) + x * (y1 * cr[2] + y * cr[3]));
 }
 
 template <int N>
 __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, int64_t fit) {
-  using L = LayR<N>;
-  constexpr int n = L::n, TT = L::TT, R = L::R, RB = L::RB, NH = L::NH;
+  using L = LayZ<N>;
+  constexpr int n = L::n, m = L::m, mm = L::mm, TT = L::TT;
+  static_assert(n <= kThreads, "one node a thread");
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
   const Normal2 z = fit_increments<N>(p, s);
-  r_setup<N>(p, lds, e, s, z.a, z.b);
-  const int t = tid(), wv = wave();
-  const int64_t eoff = p.eoff[e];
-  const double* U = p.ur + p.ur_off[N];
-  if constexpr (L::kUrLds) {
-    double* Ul = lds + L::oU;
-    for (int i = t; i < TT * R; i += kThreads) Ul[(i / TT) * L::TTs + i % TT] = U[i];
-    U = Ul;   // visible to all threads after the barrier that follows the H tables
-  }
-  const double* gxi = lds + L::oGxi;
-  const double* Bx = lds + L::oBx;
-  const double* By = lds + L::oBy;
-  const double* Ev = lds + L::oEv;
-  // 1-D quadratic forms H[a][b] = v_a^T Gx^-1 v_b over {psi(0 - d), psi(1 - d), psi(xi_j - d)}:
-  // first W[b] = Gx^-1 v_b (in the space T U_r takes later), then H[a][b] = v_a . W[b]
-  double* Hx = lds + L::oHx;
-  double* Hy = lds + L::oHy;
-  double* Wt = lds + L::oTU;   // [dir][b][N]
-  static_assert(2 * NH * N <= L::TTs * R, "W fits where T U_r goes");
-  auto hvec = [&](int dir, int a) -> const double* {
-    return (a == 0) ? Ev + 2 * dir * N : (a == 1) ? Ev + (2 * dir + 1) * N : (dir == 0 ? Bx : By) + (a - 2) * N;
-  };
-  for (int idx = t; idx < 2 * NH * N; idx += kThreads) {
-    const int db = idx / N, k = idx - db * N, dir = db / NH, bb = db - dir * NH;
-    const double* vb = hvec(dir, bb);
-    double acc = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < N; ++kk) acc += gxi[k * N + kk] * vb[kk];
-    Wt[idx] = acc;
-  }
-  block_sync();
-  for (int idx = t; idx < 2 * NH * NH; idx += kThreads) {
-    const int dir = idx / (NH * NH), ab = idx % (NH * NH), a = ab / NH, bb = ab % NH;
-    const double* va = hvec(dir, a);
-    const double* wb = Wt + (dir * NH + bb) * N;
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < N; ++k) acc += va[k] * wb[k];
-    (dir == 0 ? Hx : Hy)[ab] = acc;
-  }
-  block_sync();
-  double* rr = lds + L::oRr;
-  // TU = (C G0^-1 C^T) U_r, entry (q1, q2) of C G0^-1 C^T = Hx[xa1][xa2] Hy[ya1][ya2];
-  // then S0 = U_r^T TU, dense
-  double* TU = lds + L::oTU;
-  double* Sd = lds + L::oSd;
-  constexpr int Rs = L::Rs;
-  typedef Mma<double> M64;
+  const int t = tid();
+  const bool node = t < n;
+  const int ia = t % N, ib = t / N;       // node t sits at (xi_ia, xi_ib)
+  const int64_t noff = p.noff[e];
+  const double* xi = p.xi_tab + N * kMaxN;
+  const double* nsp = p.nsp + p.nsp_off[N];
+  double* red = lds + L::oRed;
+  // the moved nodes (eq. def_dx), one a thread, and their mean displacement
+  double xm = 0.0, ym = 0.0, dbx, dby;
   {
-    constexpr int TTs = L::TTs, US = L::US, QB = (TT + 15) / 16;
-    const int l = lane(), lr = l & 15, lk = l >> 4;
-#pragma unroll 1
-    for (int bidx = wv; bidx < QB * RB; bidx += 4) {
-      const int I = bidx / RB, C = bidx % RB;
-      const int q1 = 16 * I + lr, c = 16 * C + lr;
-      const int w1 = q1 / N, j1 = q1 % N;
-      const int xa1 = (w1 == 0) ? 0 : (w1 == 1) ? 1 : 2 + j1;
-      const int ya1 = (w1 == 2) ? 0 : (w1 == 3) ? 1 : 2 + j1;
-      M64::acc_t acc = zacc<double>();
-#pragma unroll 4
-      for (int kk = 0; kk < TT / 4; ++kk) {
-        const int q = 4 * kk + lk;
-        const int w2 = q / N, j2 = q % N;
-        const int xa2 = (w2 == 0) ? 0 : (w2 == 1) ? 1 : 2 + j2;
-        const int ya2 = (w2 == 2) ? 0 : (w2 == 3) ? 1 : 2 + j2;
-        const double a = q1 < TT ? Hx[xa1 * NH + xa2] * Hy[ya1 * NH + ya2] : 0.0;
-        const double bv = c < R ? U[c * US + q] : 0.0;
-        acc = M64::mma(a, bv, acc);
-      }
+    double sx = 0.0, sy = 0.0;
+    if (node) {
+      const int64_t k = noff + t;
+      const double x0 = p.xi_node[2 * k], y0 = p.xi_node[2 * k + 1];
+      xm = moved_coord(x0, p.A[2 * k], p.B[2 * k], z.a);
+      ym = moved_coord(y0, p.A[2 * k + 1], p.B[2 * k + 1], z.b);
+      sx = xm - x0;
+      sy = ym - y0;
+    }
+    block_sum2(sx, sy, red);
+    dbx = sx / n;
+    dby = sy / n;
+  }
+  double* Xz = lds + L::oXz;
+  double* Yz = lds + L::oYz;
+  double* Zx = lds + L::oZx;
+  double* Zy = lds + L::oZy;
+  double zz = 0.0;   // mean squared nodal value of a bubble function, x times y
+  if constexpr (m > 0) {
+    // bubble tables at the moved nodes (item t < n) and at the Gauss nodes
+    for (int it = t; it < n + 2 * N; it += kThreads) {
+      double q[m];
+      if (it < n) {
+        legendre_eval<m>(xm - dbx, p.rec, q);
+        const double sxm = xm * (1.0 - xm);
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int row = 16 * I + M64::row(l, s4);
-        if (row < TT && c < R) TU[c * TTs + row] = acc[s4];
+        for (int k = 0; k < m; ++k) Xz[k * L::ZS + it] = sxm * q[k];
+        legendre_eval<m>(ym - dby, p.rec, q);
+        const double sym = ym * (1.0 - ym);
+#pragma unroll
+        for (int k = 0; k < m; ++k) Yz[k * L::ZS + it] = sym * q[k];
+      } else {
+        const int u = it - n, dir = u >= N, a = u - dir * N;
+        legendre_eval<m>(xi[a] - (dir ? dby : dbx), p.rec, q);
+        const double sa = xi[a] * (1.0 - xi[a]);
+        double* dst = (dir ? Zy : Zx) + a * m;
+#pragma unroll
+        for (int k = 0; k < m; ++k) dst[k] = sa * q[k];
       }
     }
+    if (wave() < 2) z_gram_inverse<N>(nsp + nsp_vx(N), xi, wave() ? dby : dbx, lds + (wave() ? L::oGy : L::oGx));
     block_sync();
-    // S0 blocks (I, J), J <= I, written to both triangles
-#pragma unroll 1
-    for (int bidx = wv; bidx < RB * (RB + 1) / 2; bidx += 4) {
-      int I = 0;
-      while ((I + 1) * (I + 2) / 2 <= bidx) ++I;
-      const int J = bidx - I * (I + 1) / 2;
-      const int c1 = 16 * I + lr, c2 = 16 * J + lr;
-      M64::acc_t acc = zacc<double>();
-#pragma unroll 4
-      for (int kk = 0; kk < TT / 4; ++kk) {
-        const int q = 4 * kk + lk;
-        const double a = c1 < R ? U[c1 * US + q] : 0.0;
-        const double bv = c2 < R ? TU[c2 * TTs + q] : 0.0;
-        acc = M64::mma(a, bv, acc);
+    double zx = 0.0, zy = 0.0;
+    for (int i = t; i < N * m; i += kThreads) {
+      zx += Zx[i] * Zx[i];
+      zy += Zy[i] * Zy[i];
+    }
+    block_sum2(zx, zy, red);
+    zz = (zx / m) * (zy / m);
+  }
+  const double* Gx = lds + L::oGx;
+  const double* Gy = lds + L::oGy;
+  double* Bv = lds + L::oB;
+  double* Wv = lds + L::oW;
+  double* Rv = lds + L::oR;
+  double* Gv = lds + L::oG;
+  double* Pv = lds + L::oP;
+  double* Qv = lds + L::oQ;
+  double* Tv = lds + L::oT;
+  double* Lv = lds + L::oL;
+  double* D = lds + L::oD;
+  double* J = lds + L::oJ;
+  const double* bw = nsp + nsp_bary(N);
+  int its = 0, unconv = 0;
+  double rmax = 0.0;
+  // the components share the moved nodes and every table above (Sec. 5.3,
+  // last paragraph); each has its own p0, traces and boundary data
+  for (int c = 0; c < p.ncomp; ++c) {
+    const int64_t row = s * p.ncomp + c;
+    r_jump_data<N>(p, e, row, z.a, z.b, D);
+    block_sync();
+    // j = P (t - g) and its corner values
+    splitk<TT + 4, TT>([&](int o, int q) { return nsp[o * TT + q] * D[q]; }, J);
+    block_sync();
+    double p0v = 0.0, lnode = 0.0, sc = 0.0;
+    if (node) {
+      p0v = p.phi[row * p.nodes + noff + t];
+      Lv[t] = coons<N>(J, xi, bw, xm, ym);
+      lnode = coons_node<N>(J, ia, ib, xi[ia], xi[ib]);
+      sc = p0v * p0v + lnode * lnode;
+    }
+    const double scale = block_sum(sc, red);   // also the barrier after Lv
+    double bub = 0.0;
+    if constexpr (m > 0) {
+      z_VT_mc<N>(Xz, Yz, Lv, Bv, -1.0);
+      block_sync();
+      z_Pinv<N>(Gx, Gy, Bv, Tv, Wv);
+      z_V<N>(Xz, Yz, Wv, Lv);
+      block_sync();
+      z_VT_mc<N>(Xz, Yz, Lv, Rv, 1.0, Bv);
+      block_sync();
+      z_Pinv<N>(Gx, Gy, Rv, Tv, Gv, Rv, red + 8);
+      double rg = (red[8] + red[9]) + (red[10] + red[11]);
+      double gg = (red[12] + red[13]) + (red[14] + red[15]);
+      const double xx = zz > 0.0 ? scale / zz : 0.0;
+      const double stop = p.tol2 * xx;
+      int it = 0;
+      if (gg > stop) {
+        for (int i = t; i < mm; i += kThreads) Pv[i] = -Gv[i];
+        block_sync();
+        for (it = 1; it <= p.max_iter; ++it) {
+          z_V<N>(Xz, Yz, Pv, Lv);
+          block_sync();
+          z_VT_mc<N>(Xz, Yz, Lv, Qv, 1.0, nullptr, Pv, red);
+          block_sync();
+          const double alpha = rg / red[0];
+          for (int i = t; i < mm; i += kThreads) {
+            Wv[i] += alpha * Pv[i];
+            Rv[i] += alpha * Qv[i];
+          }
+          block_sync();
+          z_Pinv<N>(Gx, Gy, Rv, Tv, Gv, Rv, red + 8);
+          const double rg1 = (red[8] + red[9]) + (red[10] + red[11]);
+          gg = (red[12] + red[13]) + (red[14] + red[15]);
+          if (gg <= stop) break;
+          const double beta = rg1 / rg;
+          rg = rg1;
+          for (int i = t; i < mm; i += kThreads) Pv[i] = beta * Pv[i] - Gv[i];
+          block_sync();
+        }
       }
+      its += it > p.max_iter ? p.max_iter : it;
+      unconv += gg <= stop ? 0 : 1;
+      rmax = fmax(rmax, rel_resid(gg, xx));
+      if (node) {
+        double zr[m];
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        // lower triangle only, mirrored: the two triangles of a diagonal block
-        // are computed separately and need not agree to the last bit
-        const int row = 16 * I + M64::row(l, s4), col = c2;
-        if (row < R && col < R && row >= col) {
-          Sd[row * Rs + col] = acc[s4];
-          Sd[col * Rs + row] = acc[s4];
+        for (int k = 0; k < m; ++k) zr[k] = Zx[ia * m + k];
+#pragma unroll 1
+        for (int l = 0; l < m; ++l) {
+          double inner = 0.0;
+#pragma unroll
+          for (int k = 0; k < m; ++k) inner += zr[k] * Wv[l * m + k];
+          bub += Zy[ib * m + l] * inner;
         }
       }
     }
-    block_sync();
-  }
-  if constexpr (L::kM) {
-    // M_w = U_w^T B_w (R x N, K = N) on the matrix cores, RB tiles a wavefront,
-    // held in registers until every read of the staged U_r is done, then
-    // written over it
-    const int l = lane(), lr = l & 15, lk = l >> 4;
-    M64::acc_t macc[RB];
-#pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const int tl = wv + 4 * u, w = tl / RB, rt = tl - w * RB;
-      const double* Bw = (w < 2) ? By : Bx;
-      const int c = 16 * rt + lr;
-      M64::acc_t acc = zacc<double>();
-#pragma unroll
-      for (int st = 0; st < (N + 3) / 4; ++st) {
-        const int j = 4 * st + lk;
-        const double av = (c < R && j < N) ? U[c * L::TTs + w * N + j] : 0.0;   // A[c][j]
-        const double bv = (lr < N && j < N) ? Bw[j * N + lr] : 0.0;             // B[j][m]
-        acc = M64::mma(av, bv, acc);
-      }
-      macc[u] = acc;
-    }
-    block_sync();
-    double* Mm = lds + L::oU;
-#pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const int tl = wv + 4 * u, w = tl / RB, rt = tl - w * RB;
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int c = 16 * rt + M64::row(l, s4);
-        if (c < R && lr < N) Mm[(w * R + c) * N + lr] = macc[u][s4];
-      }
-    }
-  }
-  r_invert_S<N>(Sd, lds + L::oPiv);
-  // particular solution x0 = first block of [[G0, C_r^T], [C_r, 0]]^-1 [b; g_r]
-  double* b = lds + L::oB;
-  double* x = lds + L::oXv;
-  double* r = lds + L::oR;
-  double* g = lds + L::oGv;
-  double* pv = lds + L::oP;
-  double* q = lds + L::oQ;
-  double* t1 = lds + L::oT1;
-  double* red = lds + L::oRed;
-  const int64_t noff = p.noff[e];
-  int its = 0, unconv = 0;
-  double rmax = 0.0;
-  // the components share everything above: the tables, S0^-1 and the M tables
-  // (Sec. 5.3, last paragraph); each has its own carried values and boundary data
-  for (int c = 0; c < p.ncomp; ++c) {
-  const int64_t row = s * p.ncomp + c;
-  if (c > 0) r_rhs<N>(p, lds, e, row);
-  {
-    double* gvc = lds + L::oE1;            // free here; the projection's scratch later
-    r_upwind<N>(p, e, row, z.a, z.b, gvc);
-    block_sync();
-    r_UT<N>(p.ur + p.ur_off[N], gvc, rr, L::TT);   // g_r = U_r^T g
-    block_sync();
-  }
-  r_Pproj<N>(lds, U, b, rr, x);
-  const double xx = block_dot<N>(x, x, red);
-  r_G<N>(lds, x, t1, r);
-  for (int i = t; i < n; i += kThreads) r[i] -= b[i];
-  block_sync();
-  r_Pproj<N>(lds, U, r, nullptr, g);
-  // residual update: r -= C_r^T y with the projection's multipliers (left in t2
-  // by r_Pproj), which leaves g unchanged but keeps r, and with it the
-  // rounding noise of the next projections, at the size of the error
-  double* t2 = lds + L::oT2;
-  for (int i = t; i < n; i += kThreads) r[i] -= t2[i];
-  double rg, gg;
-  block_rg_gg<N>(r, g, rg, gg, red + 8);
-  const double stop = p.tol2 * xx;
-  int it = 0;
-  if (gg > stop) {
-    for (int i = t; i < n; i += kThreads) pv[i] = -g[i];
-    block_sync();
-    for (it = 1; it <= p.max_iter; ++it) {
-      r_G<N>(lds, pv, t1, q, red);   // q = G pv and pv^T q
-      const double pq = red[0];
-      const double alpha = rg / pq;
-      for (int i = t; i < n; i += kThreads) {
-        x[i] += alpha * pv[i];
-        r[i] += alpha * q[i];
-      }
-      block_sync();
-      r_Pproj<N>(lds, U, r, nullptr, g);
-      for (int i = t; i < n; i += kThreads) r[i] -= t2[i];
-      double rg1;
-      block_rg_gg<N>(r, g, rg1, gg, red + 8);
-      if (gg <= stop) break;
-      const double beta = rg1 / rg;
-      rg = rg1;
-      for (int i = t; i < n; i += kThreads) pv[i] = beta * pv[i] - g[i];
-      block_sync();
-    }
-  }
-  // restore C_r x = g_r to working accuracy: x -= G0^-1 C_r^T S0^-1 (C_r x - g_r)
-  // (after any iteration; the starting iterate satisfies it already)
-  if (it > 0) {
-    double* zz = lds + L::oZ0;
-    double* e1 = lds + L::oE1;
-    double* w1 = lds + L::oW1;
-    double* w2 = lds + L::oW2;
-    if constexpr (L::kM) {
-      double* u = lds + L::oE2;
-      const double* Mm = lds + L::oU;
-      r_edge_contract<N>(Ev, x, u);
-      block_sync();
-      r_M_apply<N>(Mm, u, rr, w1);
-      block_sync();
-      r_Sinv<N>(lds + L::oSd, w1, w2);
-      block_sync();
-      r_MT_apply<N>(Mm, w2, u);
-      block_sync();
-      r_outer_edges<N>(Ev, u, t2);
-      block_sync();
-    } else {
-      r_C<N>(Bx, By, Ev, x, e1);
-      block_sync();
-      r_UT<N>(U, e1, w1);
-      block_sync();
-      for (int c = t; c < R; c += kThreads) w1[c] -= rr[c];
-      block_sync();
-      r_Sinv<N>(lds + L::oSd, w1, w2);
-      block_sync();
-      r_U<N>(U, w2, e1);
-      block_sync();
-      r_CT<N>(Bx, By, Ev, e1, t2);
-      block_sync();
-    }
-    r_G0inv<N>(gxi, t2, t1, zz);
-    for (int i = t; i < n; i += kThreads) x[i] -= zz[i];
-    block_sync();
-  }
-  // new values at the Gauss nodes (eq. phi_star)
-  for (int i = t; i < n; i += kThreads) {
-    const int ix = i % N, iy = i / N;
-    double bxr[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) bxr[k] = Bx[ix * N + k];
-    double v = 0.0;
-#pragma unroll 1
-    for (int ly = 0; ly < N; ++ly) {
-      double inner = 0.0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) inner += bxr[k] * x[ly * N + k];
-      v += By[iy * N + ly] * inner;
-    }
-    p.phi[row * p.nodes + noff + i] = v;
-  }
-  its += it > p.max_iter ? p.max_iter : it;
-  unconv += gg <= stop ? 0 : 1;
-  rmax = fmax(rmax, rel_resid(gg, xx));
+    // new values at the Gauss nodes (eq. phi_star)
+    if (node) p.phi[row * p.nodes + noff + t] = p0v - (lnode + bub);
   }
   count_fit(p, 2, its, unconv, 0, rmax);
 }
@@ -1120,14 +970,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LayR<N
 }
 
 template <int N>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LayR<N>::waves2))) void fit2r_phase2(Params2D p) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LayZ<N>::waves))) void fit2r_phase2(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r2[];
   r_phase2_body<N>(p, lds_r2, blockIdx.x + p.block0);
 }
 
 template <int N>
 static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStream_t st) {
-  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayR<N>::bytes2;
+  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N>::bytes;
   const int64_t chunk = (int64_t)1 << 30;
   for (int64_t b0 = 0; b0 < nfits; b0 += chunk) {
     Params2D q = p;
@@ -1167,7 +1017,7 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 // One order of several problems in one launch: one workgroup per fit of the
 // segments (problem, order group) of the argument table, all of order N.
 template <int N, int PHASE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::waves1 : LayR<N>::waves2)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::waves1 : LayZ<N>::waves)))
 void fit2r_multi(Fused2DArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds_rm[];
   const int64_t item = blockIdx.x;
@@ -1181,7 +1031,7 @@ void fit2r_multi(Fused2DArgs a) {
 
 template <int N>
 static hipError_t multi_n(int phase, const Fused2DArgs& a, hipStream_t st) {
-  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayR<N>::bytes2;
+  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N>::bytes;
   if (a.total <= 0) return hipSuccess;
   if (phase == 1) hipLaunchKernelGGL((fit2r_multi<N, 1>), dim3((unsigned)a.total), dim3(kThreads), lds, st, a);
   else hipLaunchKernelGGL((fit2r_multi<N, 2>), dim3((unsigned)a.total), dim3(kThreads), lds, st, a);
@@ -1276,7 +1126,7 @@ int fit2r_fused_occupancy(int phase, size_t lds) {
 }
 
 template <int N>
-static size_t lds_r(int phase) { return phase == 1 ? LayR<N>::bytes1 : LayR<N>::bytes2; }
+static size_t lds_r(int phase) { return phase == 1 ? LayR<N>::bytes1 : LayZ<N>::bytes; }
 
 size_t fit2r_lds_bytes(int N, int phase) {
   switch (N) {

@@ -46,6 +46,18 @@ struct LegendreRec {
   double b[kMaxN];
 };
 
+// Tables of one order for the null-space form of the 2-D constrained remap
+// (reference-preconditioned solver), in doubles from the order's offset:
+//   [0, (4N+4) 4N)  rows 0..4N-1: P, the orthogonal projector onto the edge-value
+//                   vectors of Q_{N-1} (row-major, edges W, E, S, N); rows 4N..4N+3:
+//                   the corner values (SW, NW, SE, NE) of the projected vector, each
+//                   the mean of its two edges' extrapolations;
+//   then N          barycentric weights 1 / prod_{b != a} (xi_a - xi_b);
+//   then N x N      psi_k(xi_a) at [a N + k] (orthonormal shifted Legendre).
+constexpr int nsp_bary(int N) { return (4 * N + 4) * 4 * N; }
+constexpr int nsp_vx(int N) { return nsp_bary(N) + N; }
+constexpr int nsp_doubles(int N) { return nsp_vx(N) + N * N; }
+
 // Step inputs of one handle for the 1-D resident kernel.
 struct Params1D {
   const double* A;       // [K][N] (u dt)/h at the nodes
@@ -105,6 +117,8 @@ struct Params2D {
   // reference-preconditioned solver
   const double* gxinv;     // Gx^-1 of each order (N x N, row-major)
   int64_t gx_off[kMaxN + 1];
+  const double* nsp;       // null-space tables of each order (layout: nsp_* below)
+  int64_t nsp_off[kMaxN + 1];
   double tol2;             // stop when g^T g <= tol2 * x0^T x0 (g: preconditioned residual)
   int max_iter;
   unsigned long long* stats;   // diagnostics slots (kStatSlots x kStatStride, layout above)

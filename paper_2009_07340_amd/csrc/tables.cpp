@@ -260,4 +260,54 @@ std::vector<double> reference_gram_inverse(const std::vector<double>& xi) {
   return out;
 }
 
+std::vector<double> nullspace_tables(int N, const std::vector<double>& xi) {
+  const int T = 4 * N, R = T - 4;
+  const auto U = edge_range_basis(N, xi);
+  std::vector<long double> P((size_t)T * T, 0.0L);
+  for (int q = 0; q < T; ++q)
+    for (int q2 = 0; q2 < T; ++q2) {
+      long double acc = 0.0L;
+      for (int c = 0; c < R; ++c) acc += (long double)U[(size_t)c * T + q] * (long double)U[(size_t)c * T + q2];
+      P[(size_t)q * T + q2] = acc;
+    }
+  std::vector<double> l0(N), l1(N);
+  lagrange_row(xi, 0.0, l0.data());
+  lagrange_row(xi, 1.0, l1.data());
+  std::vector<double> out(nsp_doubles(N), 0.0);
+  for (size_t i = 0; i < (size_t)T * T; ++i) out[i] = (double)P[i];
+  // corner rows: SW = (W at eta=0 + S at xi=0) / 2, NW = (W at eta=1 + N at xi=0) / 2,
+  // SE = (E at eta=0 + S at xi=1) / 2, NE = (E at eta=1 + N at xi=1) / 2
+  const int ew[4] = {0, 0, 1, 1}, ns[4] = {2, 3, 2, 3};
+  const std::vector<double>* lw[4] = {&l0, &l1, &l0, &l1};
+  const std::vector<double>* ln[4] = {&l0, &l0, &l1, &l1};
+  for (int c = 0; c < 4; ++c)
+    for (int q2 = 0; q2 < T; ++q2) {
+      long double acc = 0.0L;
+      for (int a = 0; a < N; ++a)
+        acc += (long double)(*lw[c])[a] * P[(size_t)(ew[c] * N + a) * T + q2] +
+               (long double)(*ln[c])[a] * P[(size_t)(ns[c] * N + a) * T + q2];
+      out[(size_t)(T + c) * T + q2] = (double)(0.5L * acc);
+    }
+  const auto bw = barycentric_weights(xi);
+  for (int a = 0; a < N; ++a) out[nsp_bary(N) + a] = bw[a];
+  for (int a = 0; a < N; ++a) {
+    const long double x = 2.0L * xi[a] - 1.0L;
+    long double pm = 1.0L, pc = 0.0L;
+    out[nsp_vx(N) + a * N] = 1.0;
+    if (N > 1) {
+      pc = std::sqrt(3.0L) * x;
+      out[nsp_vx(N) + a * N + 1] = (double)pc;
+    }
+    for (int k = 1; k + 1 < N; ++k) {
+      const long double ak = std::sqrt((2.0L * k + 3.0L) * (2.0L * k + 1.0L)) / (k + 1.0L);
+      const long double bk = k * std::sqrt(2.0L * k + 3.0L) / ((k + 1.0L) * std::sqrt(2.0L * k - 1.0L));
+      const long double pn = ak * x * pc - bk * pm;
+      pm = pc;
+      pc = pn;
+      out[nsp_vx(N) + a * N + k + 1] = (double)pn;
+    }
+  }
+  return out;
+}
+
 }  // namespace sl

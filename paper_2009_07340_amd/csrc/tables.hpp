@@ -21,5 +21,7 @@ std::vector<double> barycentric_weights(const std::vector<double>& xi);
 // Inverse of the reference Gram matrix Gx = Vx^T Vx of the orthonormal Legendre
 // basis at the nodes xi (N x N, row-major), computed in long double.
 std::vector<double> reference_gram_inverse(const std::vector<double>& xi);
+// Null-space tables of order N (nsp_doubles(N) doubles, layout in sl_internal.hpp).
+std::vector<double> nullspace_tables(int N, const std::vector<double>& xi);
 
 }  // namespace sl
