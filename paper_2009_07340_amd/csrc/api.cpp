@@ -150,7 +150,7 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
     for (int Nd : L.orders)
       for (int Ns : L.orders)
         if (Nd != Ns) L.interp_doubles += (size_t)Nd * Ns;
-    for (int N : L.orders) L.gx_doubles += (size_t)N * N;
+    for (int N : L.orders) L.gx_doubles += (size_t)2 * N * N;
     for (int N : L.orders) L.nsp_doubles += (size_t)sl::nsp_doubles(N);
   }
   if ((double)L.MV * (double)L.nodes * 8.0 > 250e9) return fail(SL_ENOMEM, "state exceeds device memory");
@@ -925,7 +925,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   if (L.dim == 2) {
     size_t o = 0;
     for (int N : L.orders) {
-      const auto G = sl::reference_gram_inverse(h->xi_tab[N]);
+      const auto G = sl::reference_inverses(h->xi_tab[N]);
       h->gx_off[N] = (int64_t)o;
       std::copy(G.begin(), G.end(), gx.begin() + o);
       o += G.size();

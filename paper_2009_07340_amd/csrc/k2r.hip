@@ -8,12 +8,13 @@
 // traces at the own edge points): the basis is centred on the mean node
 // displacement, so a uniform displacement leaves the moved-node basis matrix
 // equal to the reference one, V0 = Vx (x) Vx: the orthonormal Legendre basis at
-// the Gauss nodes.  Its Gram matrix is a Kronecker product, G0 = Gx (x) Gx with
-// Gx = Vx^T Vx, and G0^-1 = Gx^-1 (x) Gx^-1 costs 2 N^3 operations to apply.
-// Only the non-uniform part of the displacement (velocity and diffusion
-// varying across the element) makes G differ from G0, so preconditioned
-// conjugate gradients on G c = V^T f with G0^-1 converge in a few iterations,
-// G applied matrix-free as V^T (V p) from the 1-D Legendre tables.
+// the Gauss nodes, whose inverse Vx^-1 (x) Vx^-1 costs 2 N^3 operations to
+// apply.  Only the non-uniform part of the displacement (velocity and diffusion
+// varying across the element) makes V differ from V0, so Richardson iteration
+// on the square system V c = f preconditioned by V0^-1 contracts fast (V c
+// applied matrix-free from the 1-D Legendre tables).  A fit whose correction
+// shrinks by less than half a step continues with conjugate gradients on the
+// normal equations, preconditioned by G0^-1 = Gx^-1 (x) Gx^-1, Gx = Vx^T Vx.
 //
 // Phase 2 (constrained remap) works in null-space form on the (N-2)^2
 // coefficients of the part of the correction that vanishes on the edges, with
@@ -52,7 +53,8 @@ struct LayR {
   static constexpr int oBy = oBx + N * N;
   static constexpr int oEv = oBy + N * N;
   static constexpr int oGxi = oEv + 4 * N;
-  static constexpr int oB = oGxi + N * N;
+  static constexpr int oVxi = oGxi + N * N;
+  static constexpr int oB = oVxi + N * N;
   static constexpr int oF = oB + n;
   static constexpr int oXv = oF + n;
   static constexpr int oR = oXv + n;
@@ -130,13 +132,6 @@ __device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) 
   v1 = (red[4] + red[5]) + (red[6] + red[7]);
 }
 
-template <int N>
-__device__ __forceinline__ double block_dot(const double* a, const double* b, double* red) {
-  double v = 0.0;
-  for (int i = tid(); i < N * N; i += kThreads) v += a[i] * b[i];
-  return block_sum(v, red);
-}
-
 // out[i] = (V c)_i
 template <int N>
 __device__ void r_V(const double* X1, const double* Y1, const double* c, double* out) {
@@ -197,6 +192,54 @@ __device__ void r_VT_mc(const double* X1, const double* Y1, const double* r, dou
   }
 }
 
+// out[i] = f[i] - (V c)_i
+template <int N>
+__device__ void r_resid(const double* X1, const double* Y1, const double* c, const double* f, double* out) {
+  for (int i = tid(); i < N * N; i += kThreads) {
+    double xr[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) xr[k] = X1[k * LayR<N>::XS + i];
+    double v = 0.0;
+#pragma unroll 1
+    for (int ly = 0; ly < N; ++ly) {
+      double inner = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) inner += xr[k] * c[ly * N + k];
+      v += Y1[ly * LayR<N>::XS + i] * inner;
+    }
+    out[i] = f[i] - v;
+  }
+}
+
+// d = V0^-1 r = (Vx^-1 (x) Vx^-1) r for values r at the nodes (r[iy N + ix]):
+// tmp[iy][k] = sum_ix vxi[k][ix] r[iy][ix], then d[ly][k] = sum_iy vxi[ly][iy] tmp[iy][k];
+// x = d, or x += d when add.  Two barriers; the per-wavefront partial sums of
+// d . d are left in red2[0..3] (readable after the second barrier).
+template <int N>
+__device__ void r_V0inv(const double* vxi, const double* r, double* tmp, double* x, bool add, double* red2) {
+  for (int p = tid(); p < N * N; p += kThreads) {
+    const int k = p % N, iy = p / N;
+    double acc = 0.0;
+#pragma unroll
+    for (int ix = 0; ix < N; ++ix) acc += vxi[k * N + ix] * r[iy * N + ix];
+    tmp[p] = acc;
+  }
+  block_sync();
+  double a = 0.0;
+  for (int p = tid(); p < N * N; p += kThreads) {
+    const int k = p % N, ly = p / N;
+    double d = 0.0;
+#pragma unroll
+    for (int iy = 0; iy < N; ++iy) d += vxi[ly * N + iy] * tmp[iy * N + k];
+    x[p] = add ? x[p] + d : d;
+    a += d * d;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if (lane() == 0) red2[wave()] = a;
+  block_sync();
+}
+
 // out = (Gx^-1 (x) Gx^-1) v  (c indexed [ly * N + k]), or minuend - that when
 // minuend is given; tmp n doubles.  Two barriers.  With rr given, the
 // per-wavefront partial sums of rr . out and out . out are left in
@@ -239,17 +282,15 @@ __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double*
   block_sync();
 }
 
-// Carried values of component c's row of the state (eq. advection_phi) into f
-// and b = V^T f, for the second and later components of a fit (the first one's
-// come with the set-up).  Two barriers.
+// Carried values of component c's row of the state (eq. advection_phi) into f,
+// for the second and later components of a fit (the first one's come with the
+// set-up).  One barrier.
 template <int N>
-__device__ void r_rhs(const Params2D& p, double* lds, int e, int64_t row) {
+__device__ void r_carried(const Params2D& p, double* lds, int e, int64_t row) {
   using L = LayR<N>;
   const int64_t noff = p.noff[e];
   double* f = lds + L::oF;
   for (int i = tid(); i < L::n; i += kThreads) f[i] = p.phi[row * p.nodes + noff + i] * p.src[noff + i];
-  block_sync();
-  r_VT_mc<N>(lds + L::oX1, lds + L::oY1, f, lds + L::oB);
   block_sync();
 }
 
@@ -355,8 +396,8 @@ __device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double 
     esc += escaped(xm) + escaped(ym);
   }
   const double* gsrc = p.gxinv + p.gx_off[N];
-  double* gxi = lds + L::oGxi;
-  for (int i = t; i < N * N; i += kThreads) gxi[i] = gsrc[i];
+  double* gxi = lds + L::oGxi;   // Gx^-1 and Vx^-1, adjacent in both places
+  for (int i = t; i < 2 * N * N; i += kThreads) gxi[i] = gsrc[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     sx += __shfl_xor(sx, o, 64);
@@ -402,8 +443,6 @@ __device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double 
 #pragma unroll
     for (int k = 0; k < N; ++k) dst[k * stride] = q[k];
   }
-  block_sync();
-  r_VT_mc<N>(X1, Y1, f, lds + L::oB);
   block_sync();
   return escapes;
 }
@@ -482,38 +521,65 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   // the components share the moved nodes and their tables (Sec. 5.3, last paragraph)
   for (int c = 0; c < p.ncomp; ++c) {
   const int64_t row = s * p.ncomp + c;
-  if (c > 0) r_rhs<N>(p, lds, e, row);
-  // preconditioned conjugate gradients on G c = b from c = G0^-1 b
-  r_G0inv<N>(gxi, b, t1, x);
-  const double xx = block_dot<N>(x, x, red);
-  r_G<N>(lds, x, t1, r);
-  for (int i = t; i < n; i += kThreads) r[i] -= b[i];
-  block_sync();
-  r_G0inv<N>(gxi, r, t1, g, nullptr, r, red + 8);   // with r^T g and g^T g
-  double rg = (red[8] + red[9]) + (red[10] + red[11]);
-  double gg = (red[12] + red[13]) + (red[14] + red[15]);
+  if (c > 0) r_carried<N>(p, lds, e, row);
+  // Richardson iteration on the square system V c = f, preconditioned by the
+  // reference basis matrix: c = V0^-1 f, then c += V0^-1 (f - V c).  Its error
+  // contracts by about the non-uniform part of the displacement each step.
+  const double* vxi = lds + L::oVxi;
+  const double* f = lds + L::oF;
+  r_V0inv<N>(vxi, f, t1, x, false, red + 8);
+  const double xx = (red[8] + red[9]) + (red[10] + red[11]);
   const double stop = p.tol2 * xx;
-  int it = 0;
-  if (gg > stop) {
-    for (int i = t; i < n; i += kThreads) pv[i] = -g[i];
+  double gg = xx;
+  bool slow = false;
+  int it;
+  for (it = 1; it <= p.max_iter; ++it) {
+    r_resid<N>(lds + L::oX1, lds + L::oY1, x, f, r);
     block_sync();
-    for (it = 1; it <= p.max_iter; ++it) {
-      r_G<N>(lds, pv, t1, q, red);   // q = G pv and pv^T q
-      const double pq = red[0];
-      const double alpha = rg / pq;
-      for (int i = t; i < n; i += kThreads) {
-        x[i] += alpha * pv[i];
-        r[i] += alpha * q[i];
+    r_V0inv<N>(vxi, r, t1, x, true, red + 8);
+    const double d1 = (red[8] + red[9]) + (red[10] + red[11]);
+    if (d1 <= stop) {
+      gg = d1;
+      break;
+    }
+    slow = d1 > 0.25 * gg;
+    gg = d1;
+    if (slow) break;
+  }
+  // a correction that shrinks by less than half a step: preconditioned
+  // conjugate gradients on G c = V^T f (preconditioner G0^-1) from the iterate
+  if (slow) {
+    its += it;
+    r_VT_mc<N>(lds + L::oX1, lds + L::oY1, f, b);
+    block_sync();
+    r_G<N>(lds, x, t1, r);
+    for (int i = t; i < n; i += kThreads) r[i] -= b[i];
+    block_sync();
+    r_G0inv<N>(gxi, r, t1, g, nullptr, r, red + 8);   // with r^T g and g^T g
+    double rg = (red[8] + red[9]) + (red[10] + red[11]);
+    gg = (red[12] + red[13]) + (red[14] + red[15]);
+    it = 0;
+    if (gg > stop) {
+      for (int i = t; i < n; i += kThreads) pv[i] = -g[i];
+      block_sync();
+      for (it = 1; it <= p.max_iter; ++it) {
+        r_G<N>(lds, pv, t1, q, red);   // q = G pv and pv^T q
+        const double pq = red[0];
+        const double alpha = rg / pq;
+        for (int i = t; i < n; i += kThreads) {
+          x[i] += alpha * pv[i];
+          r[i] += alpha * q[i];
+        }
+        block_sync();
+        r_G0inv<N>(gxi, r, t1, g, nullptr, r, red + 8);
+        const double rg1 = (red[8] + red[9]) + (red[10] + red[11]);
+        gg = (red[12] + red[13]) + (red[14] + red[15]);
+        if (gg <= stop) break;
+        const double beta = rg1 / rg;
+        rg = rg1;
+        for (int i = t; i < n; i += kThreads) pv[i] = beta * pv[i] - g[i];
+        block_sync();
       }
-      block_sync();
-      r_G0inv<N>(gxi, r, t1, g, nullptr, r, red + 8);
-      const double rg1 = (red[8] + red[9]) + (red[10] + red[11]);
-      gg = (red[12] + red[13]) + (red[14] + red[15]);
-      if (gg <= stop) break;
-      const double beta = rg1 / rg;
-      rg = rg1;
-      for (int i = t; i < n; i += kThreads) pv[i] = beta * pv[i] - g[i];
-      block_sync();
     }
   }
   // p0 at the Gauss nodes into the state row, where phase 2 starts from it

@@ -115,7 +115,7 @@ struct Params2D {
   uint32_t stream;
   int refine;              // float64 refinement sweeps (mixed-precision modes)
   // reference-preconditioned solver
-  const double* gxinv;     // Gx^-1 of each order (N x N, row-major)
+  const double* gxinv;     // Gx^-1, then Vx^-1, of each order (N x N each, row-major)
   int64_t gx_off[kMaxN + 1];
   const double* nsp;       // null-space tables of each order (layout: nsp_* below)
   int64_t nsp_off[kMaxN + 1];

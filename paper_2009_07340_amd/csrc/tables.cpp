@@ -205,31 +205,10 @@ std::vector<double> edge_range_basis(int N, const std::vector<double>& xi) {
   return U;
 }
 
-std::vector<double> reference_gram_inverse(const std::vector<double>& xi) {
-  const int N = (int)xi.size();
-  // Vx[i][k] = psi_k(xi_i), the same three-term recurrence as the device tables
-  std::vector<long double> V(N * N), G(N * N, 0.0L), Inv(N * N, 0.0L);
-  for (int i = 0; i < N; ++i) {
-    const long double x = 2.0L * xi[i] - 1.0L;
-    long double pm = 1.0L, pc = 0.0L;
-    V[i * N + 0] = 1.0L;
-    if (N > 1) {
-      pc = std::sqrt(3.0L) * x;
-      V[i * N + 1] = pc;
-    }
-    for (int k = 1; k + 1 < N; ++k) {
-      const long double a = std::sqrt((2.0L * k + 3.0L) * (2.0L * k + 1.0L)) / (k + 1.0L);
-      const long double b = k * std::sqrt(2.0L * k + 3.0L) / ((k + 1.0L) * std::sqrt(2.0L * k - 1.0L));
-      const long double pn = a * x * pc - b * pm;
-      pm = pc;
-      pc = pn;
-      V[i * N + k + 1] = pn;
-    }
-  }
-  for (int a = 0; a < N; ++a)
-    for (int b = 0; b < N; ++b)
-      for (int i = 0; i < N; ++i) G[a * N + b] += V[i * N + a] * V[i * N + b];
-  // Gauss-Jordan with partial pivoting on [G | I]
+// Inverse of an n x n matrix (row-major) by Gauss-Jordan elimination with
+// partial pivoting, in long double.
+static std::vector<long double> gj_inverse(std::vector<long double> G, int N) {
+  std::vector<long double> Inv((size_t)N * N, 0.0L);
   for (int i = 0; i < N; ++i) Inv[i * N + i] = 1.0L;
   for (int c = 0; c < N; ++c) {
     int piv = c;
@@ -255,8 +234,40 @@ std::vector<double> reference_gram_inverse(const std::vector<double>& xi) {
       }
     }
   }
-  std::vector<double> out(N * N);
-  for (int i = 0; i < N * N; ++i) out[i] = (double)Inv[i];
+  return Inv;
+}
+
+std::vector<double> reference_inverses(const std::vector<double>& xi) {
+  const int N = (int)xi.size();
+  // Vx[i][k] = psi_k(xi_i), the same three-term recurrence as the device tables
+  std::vector<long double> V(N * N), G(N * N, 0.0L);
+  for (int i = 0; i < N; ++i) {
+    const long double x = 2.0L * xi[i] - 1.0L;
+    long double pm = 1.0L, pc = 0.0L;
+    V[i * N + 0] = 1.0L;
+    if (N > 1) {
+      pc = std::sqrt(3.0L) * x;
+      V[i * N + 1] = pc;
+    }
+    for (int k = 1; k + 1 < N; ++k) {
+      const long double a = std::sqrt((2.0L * k + 3.0L) * (2.0L * k + 1.0L)) / (k + 1.0L);
+      const long double b = k * std::sqrt(2.0L * k + 3.0L) / ((k + 1.0L) * std::sqrt(2.0L * k - 1.0L));
+      const long double pn = a * x * pc - b * pm;
+      pm = pc;
+      pc = pn;
+      V[i * N + k + 1] = pn;
+    }
+  }
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b)
+      for (int i = 0; i < N; ++i) G[a * N + b] += V[i * N + a] * V[i * N + b];
+  const auto Gi = gj_inverse(G, N);
+  const auto Vi = gj_inverse(V, N);
+  std::vector<double> out(2 * N * N);
+  for (int i = 0; i < N * N; ++i) {
+    out[i] = (double)Gi[i];
+    out[N * N + i] = (double)Vi[i];
+  }
   return out;
 }
 

@@ -18,9 +18,10 @@ std::vector<double> edge_range_basis(int N, const std::vector<double>& xi);
 std::vector<double> quadrature_weights(const std::vector<double>& xi);
 // Barycentric weights 1 / prod_{m != i} (xi_i - xi_m) of the nodes, in long double.
 std::vector<double> barycentric_weights(const std::vector<double>& xi);
-// Inverse of the reference Gram matrix Gx = Vx^T Vx of the orthonormal Legendre
-// basis at the nodes xi (N x N, row-major), computed in long double.
-std::vector<double> reference_gram_inverse(const std::vector<double>& xi);
+// Inverses of the reference Gram matrix Gx = Vx^T Vx and of the reference basis
+// matrix Vx[i][k] = psi_k(xi_i) of the orthonormal Legendre basis at the nodes
+// xi (each N x N, row-major, Gx^-1 first), computed in long double.
+std::vector<double> reference_inverses(const std::vector<double>& xi);
 // Null-space tables of order N (nsp_doubles(N) doubles, layout in sl_internal.hpp).
 std::vector<double> nullspace_tables(int N, const std::vector<double>& xi);
 
