@@ -54,32 +54,38 @@ def fit_flops_2d_phase2(N):
 
 def fit_flops_2d_ref(N, phase, iters, ncomp=1):
     """Float64 operations of one 2-D fit with the reference-preconditioned solver, as
-    the kernel performs them (multiply-add = 2), for `iters` conjugate-gradient
-    iterations:  n = N^2, T = 4N, R = 4N - 4, H = N + 2.
-      set-up: moves and carried values 8n, 1-D tables 12 n N, b = V^T f 3n^2;
-      G p = V^T (V p): 2n(N^2 + N) + 3n^2;  G0^-1 v (Kronecker): 4N^3;
-      C c: 2T(N^2 + N);  C^T v: 6nN;  U_r^T, U_r: 2TR each;  S0^-1 w: 2R^2;
-      projection = 2 G0^-1 + C + U_r^T + S0^-1 + U_r + C^T + n;
-      phase 2 set-up: H tables 4H^2(N^2 + N), T U_r 3T^2 R, S0 2R^2 T (lower half R^2 T),
-      Cholesky, inverse and X^T X of S0 R^3;  evaluation 2n(N^2 + N).
-    With ncomp components the moves, tables and the phase-2 set-up are done once per
-    fit and the rest (b, the iterations, traces or evaluation) once per component."""
-    n, T, R, H = N * N, 4 * N, 4 * N - 4, N + 2
-    geom = 8 * n + 12 * n * N
-    rhs = 3 * n * n
-    g_apply = 2 * n * (N * N + N) + 3 * n * n
-    g0 = 4 * N ** 3
-    c_op, ct_op, u_op, s_op = 2 * T * (N * N + N), 6 * n * N, 2 * T * R, 2 * R * R
+    the kernels perform them (multiply-add = 2), for `iters` conjugate-gradient
+    iterations:  n = N^2, T = 4N, m = N - 2 (bubble functions per direction).
+    Phase 1 (Richardson iteration on V c = f, each iteration counted): moves and
+      carried values 8n, 1-D tables 12 n N;  V0^-1 v (Kronecker): 4N^3 + 2n;
+      residual f - V c: 2n(N^2 + N) + n;  traces 2T(N^2 + N); p0 at the Gauss
+      nodes 2n(N^2 + N).
+    Phase 2: moves 8n; bubble tables (Legendre recurrence of m terms, times
+      x(1 - x)) 2(n + N)(5m + 4); the two 1-D Gram matrices 4 m^2 N + 12 N and
+      their Gauss-Jordan inverses 4 m^3; jump data T, projected jump 2T(T + 4);
+      transfinite lift at the moved nodes n(20N + 20) and at the Gauss nodes 14n;
+      Vz p: 2n(m^2 + m);  Vz^T r: 2n m^2 + n m;  Kronecker preconditioner 4 m^3;
+      evaluation 2n(m^2 + m) + 3n.
+    With ncomp components the moves, tables and Gram inverses are done once per
+    fit and the rest once per component."""
+    n, T = N * N, 4 * N
     if phase == 1:
-        start = g0 + 2 * n + g_apply + n + g0 + 4 * n
-        per_it = g_apply + 2 * n + 4 * n + g0 + 4 * n + 2 * n
-        return geom + ncomp * (rhs + start + iters * per_it + c_op)
-    proj = 2 * g0 + c_op + 2 * u_op + s_op + ct_op + n
-    build = 4 * H * H * (N * N + N) + 3 * T * T * R + R * R * T + R ** 3 + u_op
-    start = proj + 2 * n + g_apply + n + proj + n + 4 * n
-    per_it = g_apply + 2 * n + 4 * n + proj + n + 4 * n + 2 * n
-    final = c_op + 2 * u_op + s_op + ct_op + g0 + n
-    return geom + build + ncomp * (rhs + start + iters * per_it + final + 2 * n * (N * N + N))
+        geom = 8 * n + 12 * n * N
+        v0 = 4 * N ** 3 + 2 * n
+        per_it = 2 * n * (N * N + N) + n + v0
+        out = 2 * T * (N * N + N) + 2 * n * (N * N + N)
+        return geom + ncomp * (v0 + iters * per_it + out)
+    m = N - 2
+    geom = 8 * n + 2 * (n + N) * (5 * m + 4) + 4 * m * m * N + 12 * N + 4 * m ** 3 + 4 * N * m
+    lift = T + 2 * T * (T + 4) + n * (20 * N + 20) + 14 * n + 3 * n
+    if m == 0:
+        return geom + ncomp * (lift + 3 * n)
+    zv = 2 * n * (m * m + m)
+    zvt = 2 * n * m * m + n * m
+    pinv = 4 * m ** 3
+    start = zvt + pinv + zv + zvt + m * m + pinv + 4 * m * m
+    per_it = zv + zvt + 2 * m * m + 4 * m * m + pinv + 4 * m * m + 2 * m * m
+    return geom + ncomp * (lift + start + iters * per_it + zv + 3 * n)
 
 
 SCHEDULES = {"perorder": (0, 0), "fused": (1, 0), "perorder_graph": (0, 1), "fused_graph": (1, 1)}
@@ -278,14 +284,26 @@ def main():
                                   if ms_t else None},
                 "build_kernel_ms": round(ms_b, 4)}
     elif solver == 2:
-        # float64 VALU work of the reference solver with the iteration counts of the timed steps
+        # float64 VALU work of the reference solver with the iteration counts of the
+        # timed steps; the roofline is the one of the phase that takes longer
         fits = wl.K * wl.samples * args.ncomp * steps
         it2 = (d1["solver_iterations"][1] - d0["solver_iterations"][1]) / fits
         it1 = (d1["solver_iterations"][0] - d0["solver_iterations"][0]) / fits
         orders = wl.order_array()
-        per_launch = sum(fit_flops_2d_ref(int(N), 2, it2, args.ncomp) for N in orders) * wl.samples
-        flops = per_launch * launches
-        achieved = flops / (kms * 1e-3) / 1e12
+        phases = {}
+        for ph, it in ((1, it1), (2, it2)):
+            name = f"fit2r_phase{ph}"
+            n_l, ms_l = (launches, kms) if name == kname else B.sl_kernel_time(prob.h, name)
+            pl = sum(fit_flops_2d_ref(int(N), ph, it, args.ncomp) for N in orders) * wl.samples
+            phases[name] = {"launches": n_l, "ms": round(ms_l, 4), "flops_per_launch": pl,
+                            "tflops": round(pl * n_l / (ms_l * 1e-3) / 1e12, 3) if ms_l else None}
+        kname = max(phases, key=lambda k: phases[k]["ms"])
+        launches, kms, per_launch = phases[kname]["launches"], phases[kname]["ms"], phases[kname]["flops_per_launch"]
+        others = {k: v for k, v in others.items() if k != kname}
+        for k, v in phases.items():
+            if k != kname:
+                others[k] = v
+        achieved = per_launch * launches / (kms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X["fp64_vector_tflops"],
                 "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_vector_tflops"], 4),
                 "traffic": stored_traffic(wl, kname, args.precision),

@@ -32,11 +32,25 @@ def _compile(src):
     return obj, err
 
 
-def build(verbose=False):
+def _stale(src):
+    """True when the object of src is missing or older than src or any header."""
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(SRC, src)] + [os.path.join(SRC, f) for f in os.listdir(SRC) if f.endswith(".hpp")]
+    deps.append(os.path.join(os.path.dirname(HERE), "include", "sl.h"))
+    return any(os.path.getmtime(d) > os.path.getmtime(obj) for d in deps)
+
+
+def build(verbose=False, incremental=False):
+    """Compile every source (or, with incremental, those whose object is out of
+    date) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        results = list(ex.map(_compile, SOURCES))
-    objs = [o for o, _ in results]
+    todo = [s for s in SOURCES if not incremental or _stale(s)]
+    with ThreadPoolExecutor(max_workers=min(8, max(1, len(todo)))) as ex:
+        results = dict(zip(todo, ex.map(_compile, todo)))
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    results = list(results.values())
     if verbose:
         for _, err in results:
             if err.strip():
@@ -51,4 +65,4 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

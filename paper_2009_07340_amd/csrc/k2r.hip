@@ -657,9 +657,9 @@ struct LayZ {
   static constexpr int oR = oW + mmA;         // residual
   static constexpr int oG = oR + mmA;         // preconditioned residual
   static constexpr int oP = oG + mmA;         // search direction
-  static constexpr int oQ = oP + mmA;         // (Vz^T Vz) p
-  static constexpr int oT = oQ + mmA;         // Kronecker temporary
-  static constexpr int oL = oT + mmA;         // n values at the moved nodes
+  static constexpr int oT = oP + mmA;         // Kronecker temporary
+  static constexpr int oPart = oT + mmA;      // four wavefronts' partial Vz^T products
+  static constexpr int oL = oPart + 4 * mmA;  // n values at the moved nodes
   static constexpr int oD = oL + n;           // t - g at the own edge points
   static constexpr int oJ = oD + TT;          // the jump and its four corner values
   static constexpr int oRed = oJ + TT + 4;
@@ -689,85 +689,42 @@ __device__ void z_V(const double* Xz, const double* Yz, const double* c, double*
   }
 }
 
-// out[(l, k)] = sign (Vz^T r)_(l,k) - (sub ? sub : 0): the m x m matrix Yz diag(r) Xz^T
-// as one 16 x 16 float64 matrix-core tile (K = n in steps of 4), by wavefront 0;
-// with dotw given, <dotw, out> is left in *dot_out.
+// Partial products Vz^T r over a quarter of the nodes per wavefront: part[w][(l, k)] =
+// sum_{i in quarter w} Yz[l][i] r[i] Xz[k][i], the m x m matrix Yz diag(r) Xz^T as one
+// 16 x 16 float64 matrix-core tile per wavefront (K in steps of 4).  With dotw
+// given, <dotw, part[w]> goes to dots[w].  No barrier.
 template <int N>
-__device__ void z_VT_mc(const double* Xz, const double* Yz, const double* r, double* out, double sign,
-                        const double* sub = nullptr, const double* dotw = nullptr, double* dot_out = nullptr) {
+__device__ void z_VT_part(const double* Xz, const double* Yz, const double* r, double* part,
+                          const double* dotw = nullptr, double* dots = nullptr) {
   typedef Mma<double> M64;
-  if (wave() != 0) return;
   using L = LayZ<N>;
-  constexpr int n = L::n, m = L::m, ZS = L::ZS;
-  const int l = lane(), lr = l & 15, lk = l >> 4;
+  constexpr int n = L::n, m = L::m, ZS = L::ZS, KK = (n + 3) / 4, KW = (KK + 3) / 4;
+  const int w = wave(), l = lane(), lr = l & 15, lk = l >> 4;
   const bool col = lr < m;
-  constexpr int KK = (n + 3) / 4;
-  M64::acc_t ac[4] = {zacc<double>(), zacc<double>(), zacc<double>(), zacc<double>()};
-#pragma unroll 8
-  for (int kk = 0; kk < KK; ++kk) {
-    const int i = 4 * kk + lk;
+  M64::acc_t ac[2] = {zacc<double>(), zacc<double>()};
+#pragma unroll
+  for (int kq = 0; kq < KW; ++kq) {
+    const int i = 4 * (w * KW + kq) + lk;
     const bool ok = col && i < n;
     const double a = ok ? Yz[lr * ZS + i] : 0.0;          // A[l][i]
     const double b = ok ? r[i] * Xz[lr * ZS + i] : 0.0;   // B[i][k]
-    ac[kk & 3] = M64::mma(a, b, ac[kk & 3]);
+    ac[kq & 1] = M64::mma(a, b, ac[kq & 1]);
   }
   double d = 0.0;
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
     const int ly = M64::row(l, s4);
     if (ly < m && col) {
-      const double v = sign * ((ac[0][s4] + ac[1][s4]) + (ac[2][s4] + ac[3][s4])) - (sub ? sub[ly * m + lr] : 0.0);
-      out[ly * m + lr] = v;
+      const double v = ac[0][s4] + ac[1][s4];
+      part[w * L::mmA + ly * m + lr] = v;
       if (dotw) d += dotw[ly * m + lr] * v;
     }
   }
   if (dotw) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-    if (l == 0) *dot_out = d;
+    if (l == 0) dots[w] = d;
   }
-}
-
-// out = (Gx (x) Gy) v over v[l m + k]: tmp[l][k] = sum_k' Gx[k][k'] v[l][k'], then
-// out[l][k] = sum_l' Gy[l][l'] tmp[l'][k].  Two barriers.  With rr given, the
-// per-wavefront partial sums of rr . out and out . out are left in red2[0..3]
-// and red2[4..7] (readable after the second barrier).
-template <int N>
-__device__ void z_Pinv(const double* Gx, const double* Gy, const double* v, double* tmp, double* out,
-                       const double* rr = nullptr, double* red2 = nullptr) {
-  constexpr int m = LayZ<N>::m;
-  for (int p = tid(); p < m * m; p += kThreads) {
-    const int k = p % m, l = p / m;
-    double acc = 0.0;
-#pragma unroll
-    for (int kk = 0; kk < m; ++kk) acc += Gx[k * m + kk] * v[l * m + kk];
-    tmp[p] = acc;
-  }
-  block_sync();
-  double a = 0.0, c = 0.0;
-  for (int p = tid(); p < m * m; p += kThreads) {
-    const int k = p % m, l = p / m;
-    double acc = 0.0;
-#pragma unroll
-    for (int ll = 0; ll < m; ++ll) acc += Gy[l * m + ll] * tmp[ll * m + k];
-    out[p] = acc;
-    if (rr) {
-      a += rr[p] * acc;
-      c += acc * acc;
-    }
-  }
-  if (rr) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      a += __shfl_xor(a, o, 64);
-      c += __shfl_xor(c, o, 64);
-    }
-    if (lane() == 0) {
-      red2[wave()] = a;
-      red2[4 + wave()] = c;
-    }
-  }
-  block_sync();
 }
 
 // Inverse of the 1-D preconditioner block Bz^T Bz, Bz[a][k] = s(xi_a + d) psi_k(xi_a)
@@ -867,10 +824,55 @@ __device__ __forceinline__ double coons_node(const double* j, int a, int b, doub
          (x1 * (y1 * cr[0] + y * cr[1]) + x * (y1 * cr[2] + y * cr[3]));
 }
 
+// The (N-2)^2-vector work of the bubble iteration runs in wavefront 0 alone,
+// each lane taking the entries p = lane, lane + 64, ...; its LDS traffic is
+// ordered by wave_sync, and its sums are wavefront shuffles.
+
+// Sum over wavefront 0 (every lane gets it).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// out = (Gx (x) Gy) v over v[l m + k] (tmp m^2 doubles), by wavefront 0.  With rr
+// given, returns rr . out in rg and out . out in gg.
+template <int N>
+__device__ __forceinline__ void z_pinv_w0(const double* Gx, const double* Gy, const double* v, double* tmp, double* out,
+                                          const double* rr = nullptr, double* rg = nullptr, double* gg = nullptr) {
+  constexpr int m = LayZ<N>::m;
+  const int l0 = lane();
+  for (int p = l0; p < m * m; p += 64) {
+    const int k = p % m, l = p / m;
+    double acc = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < m; ++kk) acc += Gx[k * m + kk] * v[l * m + kk];
+    tmp[p] = acc;
+  }
+  wave_sync();
+  double a = 0.0, c = 0.0;
+  for (int p = l0; p < m * m; p += 64) {
+    const int k = p % m, l = p / m;
+    double acc = 0.0;
+#pragma unroll
+    for (int ll = 0; ll < m; ++ll) acc += Gy[l * m + ll] * tmp[ll * m + k];
+    out[p] = acc;
+    if (rr) {
+      a += rr[p] * acc;
+      c += acc * acc;
+    }
+  }
+  wave_sync();
+  if (rr) {
+    *rg = wave_sum(a);
+    *gg = wave_sum(c);
+  }
+}
+
 template <int N>
 __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, int64_t fit) {
   using L = LayZ<N>;
-  constexpr int n = L::n, m = L::m, mm = L::mm, TT = L::TT;
+  constexpr int n = L::n, m = L::m, mm = L::mm, TT = L::TT, mmA = L::mmA;
   static_assert(n <= kThreads, "one node a thread");
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
@@ -883,6 +885,9 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   const double* xi = p.xi_tab + N * kMaxN;
   const double* nsp = p.nsp + p.nsp_off[N];
   double* red = lds + L::oRed;
+  double* D = lds + L::oD;
+  // component 0's jump data first: its loads overlap the moves
+  r_jump_data<N>(p, e, s * p.ncomp, z.a, z.b, D);
   // the moved nodes (eq. def_dx), one a thread, and their mean displacement
   double xm = 0.0, ym = 0.0, dbx, dby;
   {
@@ -903,9 +908,9 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* Yz = lds + L::oYz;
   double* Zx = lds + L::oZx;
   double* Zy = lds + L::oZy;
-  double zz = 0.0;   // mean squared nodal value of a bubble function, x times y
   if constexpr (m > 0) {
-    // bubble tables at the moved nodes (item t < n) and at the Gauss nodes
+    // bubble tables at the moved nodes (item t < n) and at the Gauss nodes; the
+    // two Gram inverses by the last two wavefronts
     for (int it = t; it < n + 2 * N; it += kThreads) {
       double q[m];
       if (it < n) {
@@ -926,16 +931,9 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
         for (int k = 0; k < m; ++k) dst[k] = sa * q[k];
       }
     }
-    if (wave() < 2) z_gram_inverse<N>(nsp + nsp_vx(N), xi, wave() ? dby : dbx, lds + (wave() ? L::oGy : L::oGx));
-    block_sync();
-    double zx = 0.0, zy = 0.0;
-    for (int i = t; i < N * m; i += kThreads) {
-      zx += Zx[i] * Zx[i];
-      zy += Zy[i] * Zy[i];
-    }
-    block_sum2(zx, zy, red);
-    zz = (zx / m) * (zy / m);
+    if (wave() >= 2) z_gram_inverse<N>(nsp + nsp_vx(N), xi, wave() == 3 ? dby : dbx, lds + (wave() == 3 ? L::oGy : L::oGx));
   }
+  const double zz = nsp[nsp_zz(N)];
   const double* Gx = lds + L::oGx;
   const double* Gy = lds + L::oGy;
   double* Bv = lds + L::oB;
@@ -943,19 +941,19 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* Rv = lds + L::oR;
   double* Gv = lds + L::oG;
   double* Pv = lds + L::oP;
-  double* Qv = lds + L::oQ;
   double* Tv = lds + L::oT;
+  double* part = lds + L::oPart;
   double* Lv = lds + L::oL;
-  double* D = lds + L::oD;
   double* J = lds + L::oJ;
   const double* bw = nsp + nsp_bary(N);
+  auto qsum = [&](int j) { return ((part[j] + part[mmA + j]) + part[2 * mmA + j]) + part[3 * mmA + j]; };
   int its = 0, unconv = 0;
   double rmax = 0.0;
   // the components share the moved nodes and every table above (Sec. 5.3,
   // last paragraph); each has its own p0, traces and boundary data
   for (int c = 0; c < p.ncomp; ++c) {
     const int64_t row = s * p.ncomp + c;
-    r_jump_data<N>(p, e, row, z.a, z.b, D);
+    if (c > 0) r_jump_data<N>(p, e, row, z.a, z.b, D);
     block_sync();
     // j = P (t - g) and its corner values
     splitk<TT + 4, TT>([&](int o, int q) { return nsp[o * TT + q] * D[q]; }, J);
@@ -970,46 +968,61 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     const double scale = block_sum(sc, red);   // also the barrier after Lv
     double bub = 0.0;
     if constexpr (m > 0) {
-      z_VT_mc<N>(Xz, Yz, Lv, Bv, -1.0);
-      block_sync();
-      z_Pinv<N>(Gx, Gy, Bv, Tv, Wv);
-      z_V<N>(Xz, Yz, Wv, Lv);
-      block_sync();
-      z_VT_mc<N>(Xz, Yz, Lv, Rv, 1.0, Bv);
-      block_sync();
-      z_Pinv<N>(Gx, Gy, Rv, Tv, Gv, Rv, red + 8);
-      double rg = (red[8] + red[9]) + (red[10] + red[11]);
-      double gg = (red[12] + red[13]) + (red[14] + red[15]);
+      // b = -Vz^T lift(j); w = (Gx (x) Gy) b; r = Vz^T Vz w - b; g = (Gx (x) Gy) r;
+      // then conjugate gradients, three workgroup barriers an iteration
       const double xx = zz > 0.0 ? scale / zz : 0.0;
       const double stop = p.tol2 * xx;
+      const bool w0 = wave() == 0;
+      double rg = 0.0, gg = 0.0;      // wavefront 0's
+      z_VT_part<N>(Xz, Yz, Lv, part);
+      block_sync();
+      if (w0) {
+        for (int j = lane(); j < mm; j += 64) Bv[j] = -qsum(j);
+        wave_sync();
+        z_pinv_w0<N>(Gx, Gy, Bv, Tv, Wv);
+      }
+      block_sync();
+      z_V<N>(Xz, Yz, Wv, Lv);
+      block_sync();
+      z_VT_part<N>(Xz, Yz, Lv, part);
+      block_sync();
+      double* flag = red + 12;
+      if (w0) {
+        for (int j = lane(); j < mm; j += 64) Rv[j] = qsum(j) - Bv[j];
+        wave_sync();
+        z_pinv_w0<N>(Gx, Gy, Rv, Tv, Gv, Rv, &rg, &gg);
+        for (int j = lane(); j < mm; j += 64) Pv[j] = -Gv[j];
+        if (lane() == 0) flag[0] = (gg > stop && p.max_iter > 0) ? 1.0 : 0.0;
+      }
+      block_sync();
       int it = 0;
-      if (gg > stop) {
-        for (int i = t; i < mm; i += kThreads) Pv[i] = -Gv[i];
+      while (flag[0] != 0.0) {
+        ++it;
+        z_V<N>(Xz, Yz, Pv, Lv);
         block_sync();
-        for (it = 1; it <= p.max_iter; ++it) {
-          z_V<N>(Xz, Yz, Pv, Lv);
-          block_sync();
-          z_VT_mc<N>(Xz, Yz, Lv, Qv, 1.0, nullptr, Pv, red);
-          block_sync();
-          const double alpha = rg / red[0];
-          for (int i = t; i < mm; i += kThreads) {
-            Wv[i] += alpha * Pv[i];
-            Rv[i] += alpha * Qv[i];
+        z_VT_part<N>(Xz, Yz, Lv, part, Pv, red);   // Vz^T Vz p in parts, <p, .> per part
+        block_sync();
+        if (w0) {
+          const double alpha = rg / ((red[0] + red[1]) + (red[2] + red[3]));
+          for (int j = lane(); j < mm; j += 64) {
+            Rv[j] += alpha * qsum(j);
+            Wv[j] += alpha * Pv[j];
           }
-          block_sync();
-          z_Pinv<N>(Gx, Gy, Rv, Tv, Gv, Rv, red + 8);
-          const double rg1 = (red[8] + red[9]) + (red[10] + red[11]);
-          gg = (red[12] + red[13]) + (red[14] + red[15]);
-          if (gg <= stop) break;
+          wave_sync();
+          double rg1;
+          z_pinv_w0<N>(Gx, Gy, Rv, Tv, Gv, Rv, &rg1, &gg);
           const double beta = rg1 / rg;
           rg = rg1;
-          for (int i = t; i < mm; i += kThreads) Pv[i] = beta * Pv[i] - Gv[i];
-          block_sync();
+          for (int j = lane(); j < mm; j += 64) Pv[j] = beta * Pv[j] - Gv[j];
+          if (lane() == 0) flag[0] = (gg > stop && it < p.max_iter) ? 1.0 : 0.0;
         }
+        block_sync();
       }
-      its += it > p.max_iter ? p.max_iter : it;
-      unconv += gg <= stop ? 0 : 1;
-      rmax = fmax(rmax, rel_resid(gg, xx));
+      if (w0) {
+        its += it;
+        unconv += gg <= stop ? 0 : 1;
+        rmax = fmax(rmax, rel_resid(gg, xx));
+      }
       if (node) {
         double zr[m];
 #pragma unroll

@@ -53,10 +53,14 @@ struct LegendreRec {
 //                   the corner values (SW, NW, SE, NE) of the projected vector, each
 //                   the mean of its two edges' extrapolations;
 //   then N          barycentric weights 1 / prod_{b != a} (xi_a - xi_b);
-//   then N x N      psi_k(xi_a) at [a N + k] (orthonormal shifted Legendre).
+//   then N x N      psi_k(xi_a) at [a N + k] (orthonormal shifted Legendre);
+//   then 1          the squared mean nodal value of the bubble functions,
+//                   ((1/m) sum_{a, k < m} (xi_a (1 - xi_a) psi_k(xi_a))^2)^2, m = N - 2
+//                   (the scale of the remap's stopping test).
 constexpr int nsp_bary(int N) { return (4 * N + 4) * 4 * N; }
 constexpr int nsp_vx(int N) { return nsp_bary(N) + N; }
-constexpr int nsp_doubles(int N) { return nsp_vx(N) + N * N; }
+constexpr int nsp_zz(int N) { return nsp_vx(N) + N * N; }
+constexpr int nsp_doubles(int N) { return nsp_zz(N) + 1; }
 
 // Step inputs of one handle for the 1-D resident kernel.
 struct Params1D {

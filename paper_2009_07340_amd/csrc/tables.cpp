@@ -318,6 +318,19 @@ std::vector<double> nullspace_tables(int N, const std::vector<double>& xi) {
       out[nsp_vx(N) + a * N + k + 1] = (double)pn;
     }
   }
+  const int m = N - 2;
+  if (m > 0) {
+    long double z = 0.0L;
+    for (int a = 0; a < N; ++a) {
+      const long double sa = (long double)xi[a] * (1.0L - (long double)xi[a]);
+      for (int k = 0; k < m; ++k) {
+        const long double v = sa * (long double)out[nsp_vx(N) + a * N + k];
+        z += v * v;
+      }
+    }
+    z /= m;
+    out[nsp_zz(N)] = (double)(z * z);
+  }
   return out;
 }
 
