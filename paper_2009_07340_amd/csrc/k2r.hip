@@ -72,7 +72,9 @@ struct LayR {
   // Workgroups per CU that the LDS admits (one wave per SIMD each), at most cap:
   // the register budget is asked to admit as many.
   static constexpr int lds_waves(size_t b, int cap) { return (160 * 1024) / b > (size_t)cap ? cap : (int)((160 * 1024) / b); }
-  static constexpr int waves1 = lds_waves(bytes1, 8);
+  // at most as many as the registers admit without spilling (by order)
+  static constexpr int reg_cap1 = N <= 3 ? 8 : N == 4 ? 6 : (N <= 6 || N == 8) ? 5 : 4;
+  static constexpr int waves1 = lds_waves(bytes1, reg_cap1);
 };
 
 // ---------------------------------------------------------------- helpers
@@ -300,10 +302,10 @@ __device__ void r_carried(const Params2D& p, double* lds, int e, int64_t row) {
 // (another order's trace interpolated to this element's abscissae), or the
 // Dirichlet ghost value.  No barrier.
 template <int N>
-__device__ void r_jump_data(const Params2D& p, int e, int64_t row, double za, double zb, double* gv) {
+__device__ void r_jump_data(const Params2D& p, int e, int64_t row, double za, double zb, double* gv, int t0) {
   using L = LayR<N>;
   const int64_t eoff = p.eoff[e];
-  for (int q = tid(); q < L::TT; q += kThreads) {
+  for (int q = t0; q < L::TT; q += kThreads) {
     const int ew = q / N, j = q % N;
     const double tq = p.tr[row * p.edges + eoff + q];
     const double zd = (ew < 2) ? za : zb;
@@ -660,12 +662,14 @@ struct LayZ {
   static constexpr int oT = oP + mmA;         // Kronecker temporary
   static constexpr int oPart = oT + mmA;      // four wavefronts' partial Vz^T products
   static constexpr int oL = oPart + 4 * mmA;  // n values at the moved nodes
-  static constexpr int oD = oL + n;           // t - g at the own edge points
+  static constexpr int oXm = oL + n;          // the moved nodes' coordinates (x, then y)
+  static constexpr int oD = oXm + 2 * n;      // t - g at the own edge points
   static constexpr int oJ = oD + TT;          // the jump and its four corner values
   static constexpr int oRed = oJ + TT + 4;
   static constexpr int end = oRed + 16;
   static constexpr size_t bytes = sizeof(double) * end;
-  static constexpr int waves = LayR<N>::lds_waves(bytes, 4);
+  // at most as many as the registers admit without spilling (by order)
+  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 10 ? 4 : 3);
 };
 
 // out[i] = (Vz c)_i, i < n
@@ -880,14 +884,13 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   const Normal2 z = fit_increments<N>(p, s);
   const int t = tid();
   const bool node = t < n;
-  const int ia = t % N, ib = t / N;       // node t sits at (xi_ia, xi_ib)
   const int64_t noff = p.noff[e];
   const double* xi = p.xi_tab + N * kMaxN;
   const double* nsp = p.nsp + p.nsp_off[N];
   double* red = lds + L::oRed;
   double* D = lds + L::oD;
   // component 0's jump data first: its loads overlap the moves
-  r_jump_data<N>(p, e, s * p.ncomp, z.a, z.b, D);
+  r_jump_data<N>(p, e, s * p.ncomp, z.a, z.b, D, t);
   // the moved nodes (eq. def_dx), one a thread, and their mean displacement
   double xm = 0.0, ym = 0.0, dbx, dby;
   {
@@ -908,6 +911,11 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* Yz = lds + L::oYz;
   double* Zx = lds + L::oZx;
   double* Zy = lds + L::oZy;
+  double* XYm = lds + L::oXm;   // the coordinates wait in LDS for every component's lift
+  if (node) {
+    XYm[t] = xm;
+    XYm[n + t] = ym;
+  }
   if constexpr (m > 0) {
     // bubble tables at the moved nodes (item t < n) and at the Gauss nodes; the
     // two Gram inverses by the last two wavefronts
@@ -953,16 +961,23 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   // last paragraph); each has its own p0, traces and boundary data
   for (int c = 0; c < p.ncomp; ++c) {
     const int64_t row = s * p.ncomp + c;
-    if (c > 0) r_jump_data<N>(p, e, row, z.a, z.b, D);
+    // the thread index, opaque to the compiler here, so that the addresses
+    // derived from it are formed again in each pass instead of held (spilled)
+    // in registers across the loop
+    int tl = t;
+    asm volatile("" : "+v"(tl));
+    const bool nodel = tl < n;
+    if (c > 0) r_jump_data<N>(p, e, row, z.a, z.b, D, tl);
     block_sync();
     // j = P (t - g) and its corner values
     splitk<TT + 4, TT>([&](int o, int q) { return nsp[o * TT + q] * D[q]; }, J);
     block_sync();
     double p0v = 0.0, lnode = 0.0, sc = 0.0;
-    if (node) {
-      p0v = p.phi[row * p.nodes + noff + t];
-      Lv[t] = coons<N>(J, xi, bw, xm, ym);
-      lnode = coons_node<N>(J, ia, ib, xi[ia], xi[ib]);
+    if (nodel) {
+      const int ja = tl % N, jb = tl / N;
+      p0v = p.phi[row * p.nodes + noff + tl];
+      Lv[tl] = coons<N>(J, xi, bw, XYm[tl], XYm[n + tl]);
+      lnode = coons_node<N>(J, ja, jb, xi[ja], xi[jb]);
       sc = p0v * p0v + lnode * lnode;
     }
     const double scale = block_sum(sc, red);   // also the barrier after Lv
@@ -1023,21 +1038,22 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
         unconv += gg <= stop ? 0 : 1;
         rmax = fmax(rmax, rel_resid(gg, xx));
       }
-      if (node) {
+      if (nodel) {
+        const int ja = tl % N, jb = tl / N;
         double zr[m];
 #pragma unroll
-        for (int k = 0; k < m; ++k) zr[k] = Zx[ia * m + k];
+        for (int k = 0; k < m; ++k) zr[k] = Zx[ja * m + k];
 #pragma unroll 1
         for (int l = 0; l < m; ++l) {
           double inner = 0.0;
 #pragma unroll
           for (int k = 0; k < m; ++k) inner += zr[k] * Wv[l * m + k];
-          bub += Zy[ib * m + l] * inner;
+          bub += Zy[jb * m + l] * inner;
         }
       }
     }
     // new values at the Gauss nodes (eq. phi_star)
-    if (node) p.phi[row * p.nodes + noff + t] = p0v - (lnode + bub);
+    if (nodel) p.phi[row * p.nodes + noff + tl] = p0v - (lnode + bub);
   }
   count_fit(p, 2, its, unconv, 0, rmax);
 }
