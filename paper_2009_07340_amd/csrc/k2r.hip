@@ -69,27 +69,30 @@ struct LayR {
   static constexpr int oRed = oYs + n;
   static constexpr int end1 = oRed + 16;
   static constexpr size_t bytes1 = sizeof(double) * end1;
-  // Workgroups per CU that the LDS admits (one wave per SIMD each), at most cap:
-  // the register budget is asked to admit as many.
-  static constexpr int lds_waves(size_t b, int cap) { return (160 * 1024) / b > (size_t)cap ? cap : (int)((160 * 1024) / b); }
+  // Waves a SIMD that the LDS admits for fits of b bytes on T threads, at most
+  // cap: the register budget is asked to admit as many.
+  static constexpr int lds_waves(size_t b, int cap, int T = 256) {
+    const int w = (int)(((160 * 1024) / b * (size_t)(T / 64) + 3) / 4);
+    return w > cap ? cap : w;
+  }
   // at most as many as the registers admit without spilling (by order)
   static constexpr int reg_cap1 = N <= 3 ? 8 : N == 4 ? 6 : (N <= 6 || N == 8) ? 5 : 4;
-  static constexpr int waves1 = lds_waves(bytes1, reg_cap1);
+  template <int T> static constexpr int waves1 = lds_waves(bytes1, reg_cap1, T);
 };
 
 // ---------------------------------------------------------------- helpers
 
 // Lanes per output of a split reduction: as many as the workgroup holds for O
 // outputs (a power of two up to 8, so the lanes of one output share a wavefront).
-constexpr int ksplit(int O) { return O * 8 <= kThreads ? 8 : O * 4 <= kThreads ? 4 : O * 2 <= kThreads ? 2 : 1; }
+constexpr int ksplit(int O, int T) { return O * 8 <= T ? 8 : O * 4 <= T ? 4 : O * 2 <= T ? 2 : 1; }
 
 // out[o] = sum_{j < J} term(o, j) - (sub ? sub[o] : 0) for o < O.  G = ksplit(O)
 // adjacent lanes share an output, each summing j = g, g + G, ..., and the partial
 // sums meet by xor shuffles: the dependent chain is J / G long instead of J, and
 // G times more lanes work.  Every lane takes part in the shuffles.  No barrier.
-template <int O, int J, typename Term>
+template <int O, int J, int T, typename Term>
 __device__ __forceinline__ void splitk(Term term, double* out, const double* sub = nullptr) {
-  constexpr int G = ksplit(O), PER = kThreads / G;
+  constexpr int G = ksplit(O, T), PER = T / G;
   const int t = tid(), g = t % G;
 #pragma unroll
   for (int ob = 0; ob < O; ob += PER) {
@@ -105,20 +108,31 @@ __device__ __forceinline__ void splitk(Term term, double* out, const double* sub
   }
 }
 
-// Sum over the workgroup of a per-thread value; every thread gets the same
+// A fit runs on T = 64, 128 or 256 threads (one, two or four wavefronts).
+// Per-wavefront partial sums in r[0 .. T/64) summed in a fixed order.
+template <int T>
+__device__ __forceinline__ double wsum(const double* r) {
+  if constexpr (T == 256) return (r[0] + r[1]) + (r[2] + r[3]);
+  else if constexpr (T == 128) return r[0] + r[1];
+  else return r[0];
+}
+
+// Sum over the fit's threads of a per-thread value; every thread gets the same
 // result (fixed summation order).  One barrier: the slots in red are read
 // after it and written again only by a later sum, which the callers keep
 // behind at least one other barrier (dot products use red, the pair of
 // residual norms red + 8).
+template <int T>
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   if (lane() == 0) red[wave()] = v;
   block_sync();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+  return wsum<T>(red);
 }
 
 // Two sums at once (one barrier, as above).
+template <int T>
 __device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -130,14 +144,14 @@ __device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) 
     red[4 + wave()] = v1;
   }
   block_sync();
-  v0 = (red[0] + red[1]) + (red[2] + red[3]);
-  v1 = (red[4] + red[5]) + (red[6] + red[7]);
+  v0 = wsum<T>(red);
+  v1 = wsum<T>(red + 4);
 }
 
 // out[i] = (V c)_i
-template <int N>
+template <int N, int T>
 __device__ void r_V(const double* X1, const double* Y1, const double* c, double* out) {
-  for (int i = tid(); i < N * N; i += kThreads) {
+  for (int i = tid(); i < N * N; i += T) {
     double xr[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) xr[k] = X1[k * LayR<N>::XS + i];
@@ -195,9 +209,9 @@ __device__ void r_VT_mc(const double* X1, const double* Y1, const double* r, dou
 }
 
 // out[i] = f[i] - (V c)_i
-template <int N>
+template <int N, int T>
 __device__ void r_resid(const double* X1, const double* Y1, const double* c, const double* f, double* out) {
-  for (int i = tid(); i < N * N; i += kThreads) {
+  for (int i = tid(); i < N * N; i += T) {
     double xr[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) xr[k] = X1[k * LayR<N>::XS + i];
@@ -217,9 +231,9 @@ __device__ void r_resid(const double* X1, const double* Y1, const double* c, con
 // tmp[iy][k] = sum_ix vxi[k][ix] r[iy][ix], then d[ly][k] = sum_iy vxi[ly][iy] tmp[iy][k];
 // x = d, or x += d when add.  Two barriers; the per-wavefront partial sums of
 // d . d are left in red2[0..3] (readable after the second barrier).
-template <int N>
+template <int N, int T>
 __device__ void r_V0inv(const double* vxi, const double* r, double* tmp, double* x, bool add, double* red2) {
-  for (int p = tid(); p < N * N; p += kThreads) {
+  for (int p = tid(); p < N * N; p += T) {
     const int k = p % N, iy = p / N;
     double acc = 0.0;
 #pragma unroll
@@ -228,7 +242,7 @@ __device__ void r_V0inv(const double* vxi, const double* r, double* tmp, double*
   }
   block_sync();
   double a = 0.0;
-  for (int p = tid(); p < N * N; p += kThreads) {
+  for (int p = tid(); p < N * N; p += T) {
     const int k = p % N, ly = p / N;
     double d = 0.0;
 #pragma unroll
@@ -246,10 +260,10 @@ __device__ void r_V0inv(const double* vxi, const double* r, double* tmp, double*
 // minuend is given; tmp n doubles.  Two barriers.  With rr given, the
 // per-wavefront partial sums of rr . out and out . out are left in
 // red2[0..3] and red2[4..7] (readable after the second barrier).
-template <int N>
+template <int N, int T>
 __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double* out,
                         const double* minuend = nullptr, const double* rr = nullptr, double* red2 = nullptr) {
-  for (int p = tid(); p < N * N; p += kThreads) {
+  for (int p = tid(); p < N * N; p += T) {
     const int k = p % N, ly = p / N;
     double acc = 0.0;
 #pragma unroll
@@ -258,7 +272,7 @@ __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double*
   }
   block_sync();
   double a = 0.0, c = 0.0;
-  for (int p = tid(); p < N * N; p += kThreads) {
+  for (int p = tid(); p < N * N; p += T) {
     const int k = p % N, ly = p / N;
     double acc = 0.0;
 #pragma unroll
@@ -287,12 +301,12 @@ __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double*
 // Carried values of component c's row of the state (eq. advection_phi) into f,
 // for the second and later components of a fit (the first one's come with the
 // set-up).  One barrier.
-template <int N>
+template <int N, int T>
 __device__ void r_carried(const Params2D& p, double* lds, int e, int64_t row) {
   using L = LayR<N>;
   const int64_t noff = p.noff[e];
   double* f = lds + L::oF;
-  for (int i = tid(); i < L::n; i += kThreads) f[i] = p.phi[row * p.nodes + noff + i] * p.src[noff + i];
+  for (int i = tid(); i < L::n; i += T) f[i] = p.phi[row * p.nodes + noff + i] * p.src[noff + i];
   block_sync();
 }
 
@@ -301,11 +315,11 @@ __device__ void r_carried(const Params2D& p, double* lds, int e, int64_t row) {
 // the element the interface displacement comes from supplies the trace
 // (another order's trace interpolated to this element's abscissae), or the
 // Dirichlet ghost value.  No barrier.
-template <int N>
+template <int N, int T>
 __device__ void r_jump_data(const Params2D& p, int e, int64_t row, double za, double zb, double* gv, int t0) {
   using L = LayR<N>;
   const int64_t eoff = p.eoff[e];
-  for (int q = t0; q < L::TT; q += kThreads) {
+  for (int q = t0; q < L::TT; q += T) {
     const int ew = q / N, j = q % N;
     const double tq = p.tr[row * p.edges + eoff + q];
     const double zd = (ew < 2) ? za : zb;
@@ -337,9 +351,9 @@ __device__ void r_jump_data(const Params2D& p, int e, int64_t row, double za, do
 // One-dimensional contractions of a coefficient array c[ly][k] with the edge
 // basis vectors: out[0..N) = sum_k p0x[k] c[.][k], out[N..2N) with p1x,
 // out[2N..3N) = sum_ly p0y[ly] c[ly][.], out[3N..4N) with p1y.
-template <int N>
+template <int N, int T>
 __device__ void r_edge_contract(const double* Ev, const double* c, double* out) {
-  for (int o = tid(); o < 4 * N; o += kThreads) {
+  for (int o = tid(); o < 4 * N; o += T) {
     const int w = o / N, m = o % N;
     const double* e = Ev + w * N;
     double acc = 0.0;
@@ -356,9 +370,9 @@ __device__ void r_edge_contract(const double* Ev, const double* c, double* out) 
 
 // Traces at the own edge points from the contractions u of r_edge_contract:
 // W, E point j = sum_ly By[j][ly] u_{W,E}[ly]; S, N point j = sum_k Bx[j][k] u_{S,N}[k].
-template <int N>
+template <int N, int T>
 __device__ void r_traces_from(const double* Bx, const double* By, const double* u, double* out) {
-  for (int q = tid(); q < 4 * N; q += kThreads) {
+  for (int q = tid(); q < 4 * N; q += T) {
     const int w = q / N, j = q % N;
     const double* B = (w < 2) ? By + j * N : Bx + j * N;
     const double* v = u + w * N;
@@ -373,7 +387,7 @@ __device__ void r_traces_from(const double* Bx, const double* By, const double* 
 
 // Moves (eq. def_dx), carried values (eq. advection_phi), centred 1-D tables,
 // b = V^T f; returns the mean displacement (dbx, dby) in registers.
-template <int N>
+template <int N, int T>
 __device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double za, double zb) {
   using L = LayR<N>;
   constexpr int n = L::n;
@@ -385,7 +399,7 @@ __device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double 
   double* red = lds + L::oRed;
   double sx = 0.0, sy = 0.0;
   int esc = 0;
-  for (int i = t; i < n; i += kThreads) {
+  for (int i = t; i < n; i += T) {
     const int64_t k = noff + i;
     const double x0 = p.xi_node[2 * k], y0 = p.xi_node[2 * k + 1];
     const double xm = moved_coord(x0, p.A[2 * k], p.B[2 * k], za);
@@ -399,7 +413,7 @@ __device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double 
   }
   const double* gsrc = p.gxinv + p.gx_off[N];
   double* gxi = lds + L::oGxi;   // Gx^-1 and Vx^-1, adjacent in both places
-  for (int i = t; i < 2 * N * N; i += kThreads) gxi[i] = gsrc[i];
+  for (int i = t; i < 2 * N * N; i += T) gxi[i] = gsrc[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     sx += __shfl_xor(sx, o, 64);
@@ -412,9 +426,9 @@ __device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double 
     red[8 + wave()] = (double)esc;
   }
   block_sync();
-  const double dbx = (red[0] + red[1] + red[2] + red[3]) / n;
-  const double dby = (red[4] + red[5] + red[6] + red[7]) / n;
-  const int escapes = (int)((red[8] + red[9]) + (red[10] + red[11]));
+  const double dbx = wsum<T>(red) / n;
+  const double dby = wsum<T>(red + 4) / n;
+  const int escapes = (int)wsum<T>(red + 8);
   double* X1 = lds + L::oX1;
   double* Y1 = lds + L::oY1;
   double* Bx = lds + L::oBx;
@@ -422,7 +436,7 @@ __device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double 
   double* Ev = lds + L::oEv;
   // one basis evaluation an item: the n moved nodes in x, then in y, the N
   // Gauss abscissae of the edges in x and in y, the 4 edge coordinates
-  for (int it = t; it < 2 * n + 2 * N + 4; it += kThreads) {
+  for (int it = t; it < 2 * n + 2 * N + 4; it += T) {
     double arg;
     double* dst;
     int stride = 1;
@@ -466,10 +480,10 @@ __device__ __forceinline__ Normal2 fit_increments(const Params2D& p, int64_t s) 
 
 // G v = V^T (V v) into out (tmp: n doubles).  Two barriers.
 // With dot_out given, <v, G v> is left there too (readable after the return).
-template <int N>
+template <int N, int T>
 __device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, double* out, double* dot_out = nullptr) {
   using L = LayR<N>;
-  r_V<N>(lds + L::oX1, lds + L::oY1, v, tmp);
+  r_V<N, T>(lds + L::oX1, lds + L::oY1, v, tmp);
   block_sync();
   r_VT_mc<N>(lds + L::oX1, lds + L::oY1, tmp, out, dot_out ? v : nullptr, dot_out);
   block_sync();
@@ -497,7 +511,7 @@ __device__ __forceinline__ double rel_resid(double gg, double xx) {
 
 // ---------------------------------------------------------------- phase 1
 
-template <int N>
+template <int N, int T>
 __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, int64_t fit) {
   using L = LayR<N>;
   constexpr int n = L::n;
@@ -505,7 +519,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
   const Normal2 z = fit_increments<N>(p, s);
-  const int escapes = r_setup<N>(p, lds, e, s, z.a, z.b);
+  const int escapes = r_setup<N, T>(p, lds, e, s, z.a, z.b);
   const int t = tid();
   const double* gxi = lds + L::oGxi;
   double* b = lds + L::oB;
@@ -523,23 +537,23 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   // the components share the moved nodes and their tables (Sec. 5.3, last paragraph)
   for (int c = 0; c < p.ncomp; ++c) {
   const int64_t row = s * p.ncomp + c;
-  if (c > 0) r_carried<N>(p, lds, e, row);
+  if (c > 0) r_carried<N, T>(p, lds, e, row);
   // Richardson iteration on the square system V c = f, preconditioned by the
   // reference basis matrix: c = V0^-1 f, then c += V0^-1 (f - V c).  Its error
   // contracts by about the non-uniform part of the displacement each step.
   const double* vxi = lds + L::oVxi;
   const double* f = lds + L::oF;
-  r_V0inv<N>(vxi, f, t1, x, false, red + 8);
-  const double xx = (red[8] + red[9]) + (red[10] + red[11]);
+  r_V0inv<N, T>(vxi, f, t1, x, false, red + 8);
+  const double xx = wsum<T>(red + 8);
   const double stop = p.tol2 * xx;
   double gg = xx;
   bool slow = false;
   int it;
   for (it = 1; it <= p.max_iter; ++it) {
-    r_resid<N>(lds + L::oX1, lds + L::oY1, x, f, r);
+    r_resid<N, T>(lds + L::oX1, lds + L::oY1, x, f, r);
     block_sync();
-    r_V0inv<N>(vxi, r, t1, x, true, red + 8);
-    const double d1 = (red[8] + red[9]) + (red[10] + red[11]);
+    r_V0inv<N, T>(vxi, r, t1, x, true, red + 8);
+    const double d1 = wsum<T>(red + 8);
     if (d1 <= stop) {
       gg = d1;
       break;
@@ -554,32 +568,32 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
     its += it;
     r_VT_mc<N>(lds + L::oX1, lds + L::oY1, f, b);
     block_sync();
-    r_G<N>(lds, x, t1, r);
-    for (int i = t; i < n; i += kThreads) r[i] -= b[i];
+    r_G<N, T>(lds, x, t1, r);
+    for (int i = t; i < n; i += T) r[i] -= b[i];
     block_sync();
-    r_G0inv<N>(gxi, r, t1, g, nullptr, r, red + 8);   // with r^T g and g^T g
-    double rg = (red[8] + red[9]) + (red[10] + red[11]);
-    gg = (red[12] + red[13]) + (red[14] + red[15]);
+    r_G0inv<N, T>(gxi, r, t1, g, nullptr, r, red + 8);   // with r^T g and g^T g
+    double rg = wsum<T>(red + 8);
+    gg = wsum<T>(red + 12);
     it = 0;
     if (gg > stop) {
-      for (int i = t; i < n; i += kThreads) pv[i] = -g[i];
+      for (int i = t; i < n; i += T) pv[i] = -g[i];
       block_sync();
       for (it = 1; it <= p.max_iter; ++it) {
-        r_G<N>(lds, pv, t1, q, red);   // q = G pv and pv^T q
+        r_G<N, T>(lds, pv, t1, q, red);   // q = G pv and pv^T q
         const double pq = red[0];
         const double alpha = rg / pq;
-        for (int i = t; i < n; i += kThreads) {
+        for (int i = t; i < n; i += T) {
           x[i] += alpha * pv[i];
           r[i] += alpha * q[i];
         }
         block_sync();
-        r_G0inv<N>(gxi, r, t1, g, nullptr, r, red + 8);
-        const double rg1 = (red[8] + red[9]) + (red[10] + red[11]);
-        gg = (red[12] + red[13]) + (red[14] + red[15]);
+        r_G0inv<N, T>(gxi, r, t1, g, nullptr, r, red + 8);
+        const double rg1 = wsum<T>(red + 8);
+        gg = wsum<T>(red + 12);
         if (gg <= stop) break;
         const double beta = rg1 / rg;
         rg = rg1;
-        for (int i = t; i < n; i += kThreads) pv[i] = beta * pv[i] - g[i];
+        for (int i = t; i < n; i += T) pv[i] = beta * pv[i] - g[i];
         block_sync();
       }
     }
@@ -588,7 +602,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   {
     const double* Bx = lds + L::oBx;
     const double* By = lds + L::oBy;
-    for (int i = t; i < n; i += kThreads) {
+    for (int i = t; i < n; i += T) {
       const int ix = i % N, iy = i / N;
       double bxr[N];
 #pragma unroll
@@ -607,11 +621,11 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   // traces of p0 at the own edge points (eq. remap_bnd)
   double* tv = lds + L::oTr;
   double* uc = lds + L::oUc;
-  r_edge_contract<N>(lds + L::oEv, x, uc);
+  r_edge_contract<N, T>(lds + L::oEv, x, uc);
   block_sync();
-  r_traces_from<N>(lds + L::oBx, lds + L::oBy, uc, tv);
+  r_traces_from<N, T>(lds + L::oBx, lds + L::oBy, uc, tv);
   block_sync();
-  for (int qq = t; qq < L::TT; qq += kThreads) p.tr[row * p.edges + eoff + qq] = tv[qq];
+  for (int qq = t; qq < L::TT; qq += T) p.tr[row * p.edges + eoff + qq] = tv[qq];
   its += it > p.max_iter ? p.max_iter : it;
   unconv += gg <= stop ? 0 : 1;
   rmax = fmax(rmax, rel_resid(gg, xx));
@@ -669,15 +683,16 @@ struct LayZ {
   static constexpr int end = oRed + 16;
   static constexpr size_t bytes = sizeof(double) * end;
   // at most as many as the registers admit without spilling (by order)
-  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 10 ? 4 : 3);
+  template <int T> static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 10 ? 4 : 3, T);
+  static constexpr int NQ = (n + 3) / 4;   // steps of 4 nodes
 };
 
 // out[i] = (Vz c)_i, i < n
-template <int N>
+template <int N, int T>
 __device__ void z_V(const double* Xz, const double* Yz, const double* c, double* out) {
   using L = LayZ<N>;
   constexpr int m = L::m;
-  for (int i = tid(); i < L::n; i += kThreads) {
+  for (int i = tid(); i < L::n; i += T) {
     double xr[m];
 #pragma unroll
     for (int k = 0; k < m; ++k) xr[k] = Xz[k * L::ZS + i];
@@ -693,16 +708,16 @@ __device__ void z_V(const double* Xz, const double* Yz, const double* c, double*
   }
 }
 
-// Partial products Vz^T r over a quarter of the nodes per wavefront: part[w][(l, k)] =
-// sum_{i in quarter w} Yz[l][i] r[i] Xz[k][i], the m x m matrix Yz diag(r) Xz^T as one
+// Partial products Vz^T r over each wavefront's share of the nodes: part[w][(l, k)] =
+// sum_{i of w} Yz[l][i] r[i] Xz[k][i], the m x m matrix Yz diag(r) Xz^T as one
 // 16 x 16 float64 matrix-core tile per wavefront (K in steps of 4).  With dotw
 // given, <dotw, part[w]> goes to dots[w].  No barrier.
-template <int N>
+template <int N, int T>
 __device__ void z_VT_part(const double* Xz, const double* Yz, const double* r, double* part,
                           const double* dotw = nullptr, double* dots = nullptr) {
   typedef Mma<double> M64;
   using L = LayZ<N>;
-  constexpr int n = L::n, m = L::m, ZS = L::ZS, KK = (n + 3) / 4, KW = (KK + 3) / 4;
+  constexpr int n = L::n, m = L::m, ZS = L::ZS, KW = (L::NQ + T / 64 - 1) / (T / 64);   // steps a wavefront
   const int w = wave(), l = lane(), lr = l & 15, lk = l >> 4;
   const bool col = lr < m;
   M64::acc_t ac[2] = {zacc<double>(), zacc<double>()};
@@ -873,11 +888,12 @@ __device__ __forceinline__ void z_pinv_w0(const double* Gx, const double* Gy, co
   }
 }
 
-template <int N>
+template <int N, int T>
 __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, int64_t fit) {
   using L = LayZ<N>;
   constexpr int n = L::n, m = L::m, mm = L::mm, TT = L::TT, mmA = L::mmA;
-  static_assert(n <= kThreads, "one node a thread");
+  static_assert(n <= T, "one node a thread");
+  constexpr int W = T / 64;
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
@@ -890,7 +906,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* red = lds + L::oRed;
   double* D = lds + L::oD;
   // component 0's jump data first: its loads overlap the moves
-  r_jump_data<N>(p, e, s * p.ncomp, z.a, z.b, D, t);
+  r_jump_data<N, T>(p, e, s * p.ncomp, z.a, z.b, D, t);
   // the moved nodes (eq. def_dx), one a thread, and their mean displacement
   double xm = 0.0, ym = 0.0, dbx, dby;
   {
@@ -903,7 +919,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       sx = xm - x0;
       sy = ym - y0;
     }
-    block_sum2(sx, sy, red);
+    block_sum2<T>(sx, sy, red);
     dbx = sx / n;
     dby = sy / n;
   }
@@ -919,7 +935,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   if constexpr (m > 0) {
     // bubble tables at the moved nodes (item t < n) and at the Gauss nodes; the
     // two Gram inverses by the last two wavefronts
-    for (int it = t; it < n + 2 * N; it += kThreads) {
+    for (int it = t; it < n + 2 * N; it += T) {
       double q[m];
       if (it < n) {
         legendre_eval<m>(xm - dbx, p.rec, q);
@@ -939,7 +955,13 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
         for (int k = 0; k < m; ++k) dst[k] = sa * q[k];
       }
     }
-    if (wave() >= 2) z_gram_inverse<N>(nsp + nsp_vx(N), xi, wave() == 3 ? dby : dbx, lds + (wave() == 3 ? L::oGy : L::oGx));
+    if constexpr (W == 1) {
+      z_gram_inverse<N>(nsp + nsp_vx(N), xi, dbx, lds + L::oGx);
+      z_gram_inverse<N>(nsp + nsp_vx(N), xi, dby, lds + L::oGy);
+    } else {
+      const int wg = wave() - (W - 2);   // the last two wavefronts
+      if (wg >= 0) z_gram_inverse<N>(nsp + nsp_vx(N), xi, wg ? dby : dbx, lds + (wg ? L::oGy : L::oGx));
+    }
   }
   const double zz = nsp[nsp_zz(N)];
   const double* Gx = lds + L::oGx;
@@ -954,7 +976,11 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* Lv = lds + L::oL;
   double* J = lds + L::oJ;
   const double* bw = nsp + nsp_bary(N);
-  auto qsum = [&](int j) { return ((part[j] + part[mmA + j]) + part[2 * mmA + j]) + part[3 * mmA + j]; };
+  auto qsum = [&](int j) {
+    if constexpr (W == 4) return ((part[j] + part[mmA + j]) + part[2 * mmA + j]) + part[3 * mmA + j];
+    else if constexpr (W == 2) return part[j] + part[mmA + j];
+    else return part[j];
+  };
   int its = 0, unconv = 0;
   double rmax = 0.0;
   // the components share the moved nodes and every table above (Sec. 5.3,
@@ -967,10 +993,10 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     int tl = t;
     asm volatile("" : "+v"(tl));
     const bool nodel = tl < n;
-    if (c > 0) r_jump_data<N>(p, e, row, z.a, z.b, D, tl);
+    if (c > 0) r_jump_data<N, T>(p, e, row, z.a, z.b, D, tl);
     block_sync();
     // j = P (t - g) and its corner values
-    splitk<TT + 4, TT>([&](int o, int q) { return nsp[o * TT + q] * D[q]; }, J);
+    splitk<TT + 4, TT, T>([&](int o, int q) { return nsp[o * TT + q] * D[q]; }, J);
     block_sync();
     double p0v = 0.0, lnode = 0.0, sc = 0.0;
     if (nodel) {
@@ -980,7 +1006,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       lnode = coons_node<N>(J, ja, jb, xi[ja], xi[jb]);
       sc = p0v * p0v + lnode * lnode;
     }
-    const double scale = block_sum(sc, red);   // also the barrier after Lv
+    const double scale = block_sum<T>(sc, red);   // also the barrier after Lv
     double bub = 0.0;
     if constexpr (m > 0) {
       // b = -Vz^T lift(j); w = (Gx (x) Gy) b; r = Vz^T Vz w - b; g = (Gx (x) Gy) r;
@@ -989,7 +1015,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       const double stop = p.tol2 * xx;
       const bool w0 = wave() == 0;
       double rg = 0.0, gg = 0.0;      // wavefront 0's
-      z_VT_part<N>(Xz, Yz, Lv, part);
+      z_VT_part<N, T>(Xz, Yz, Lv, part);
       block_sync();
       if (w0) {
         for (int j = lane(); j < mm; j += 64) Bv[j] = -qsum(j);
@@ -997,9 +1023,9 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
         z_pinv_w0<N>(Gx, Gy, Bv, Tv, Wv);
       }
       block_sync();
-      z_V<N>(Xz, Yz, Wv, Lv);
+      z_V<N, T>(Xz, Yz, Wv, Lv);
       block_sync();
-      z_VT_part<N>(Xz, Yz, Lv, part);
+      z_VT_part<N, T>(Xz, Yz, Lv, part);
       block_sync();
       double* flag = red + 12;
       if (w0) {
@@ -1013,12 +1039,12 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       int it = 0;
       while (flag[0] != 0.0) {
         ++it;
-        z_V<N>(Xz, Yz, Pv, Lv);
+        z_V<N, T>(Xz, Yz, Pv, Lv);
         block_sync();
-        z_VT_part<N>(Xz, Yz, Lv, part, Pv, red);   // Vz^T Vz p in parts, <p, .> per part
+        z_VT_part<N, T>(Xz, Yz, Lv, part, Pv, red);   // Vz^T Vz p in parts, <p, .> per part
         block_sync();
         if (w0) {
-          const double alpha = rg / ((red[0] + red[1]) + (red[2] + red[3]));
+          const double alpha = rg / wsum<T>(red);
           for (int j = lane(); j < mm; j += 64) {
             Rv[j] += alpha * qsum(j);
             Wv[j] += alpha * Pv[j];
@@ -1058,16 +1084,23 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   count_fit(p, 2, its, unconv, 0, rmax);
 }
 
+// Threads a fit of the per-order and batched kernels, by phase and order.
+// The persistent fused kernel runs every order on four wavefronts.
+template <int N, int PHASE>
+constexpr int kFitThreads = PHASE == 1 ? (N <= 8 ? 64 : N <= 12 ? 128 : 256) : (N <= 8 ? 64 : N <= 11 ? 128 : 256);
+
 template <int N>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LayR<N>::waves1))) void fit2r_phase1(Params2D p) {
+__global__ __launch_bounds__((kFitThreads<N, 1>)) __attribute__((amdgpu_waves_per_eu(LayR<N>::template waves1<kFitThreads<N, 1>>)))
+void fit2r_phase1(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r1[];
-  r_phase1_body<N>(p, lds_r1, blockIdx.x + p.block0);
+  r_phase1_body<N, kFitThreads<N, 1>>(p, lds_r1, blockIdx.x + p.block0);
 }
 
 template <int N>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(LayZ<N>::waves))) void fit2r_phase2(Params2D p) {
+__global__ __launch_bounds__((kFitThreads<N, 2>)) __attribute__((amdgpu_waves_per_eu(LayZ<N>::template waves<kFitThreads<N, 2>>)))
+void fit2r_phase2(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r2[];
-  r_phase2_body<N>(p, lds_r2, blockIdx.x + p.block0);
+  r_phase2_body<N, kFitThreads<N, 2>>(p, lds_r2, blockIdx.x + p.block0);
 }
 
 template <int N>
@@ -1079,9 +1112,9 @@ static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStrea
     q.block0 = p.block0 + b0;
     const int64_t nb = (nfits - b0) < chunk ? (nfits - b0) : chunk;
     if (phase == 1)
-      hipLaunchKernelGGL((fit2r_phase1<N>), dim3((unsigned)nb), dim3(kThreads), lds, st, q);
+      hipLaunchKernelGGL((fit2r_phase1<N>), dim3((unsigned)nb), dim3(kFitThreads<N, 1>), lds, st, q);
     else
-      hipLaunchKernelGGL((fit2r_phase2<N>), dim3((unsigned)nb), dim3(kThreads), lds, st, q);
+      hipLaunchKernelGGL((fit2r_phase2<N>), dim3((unsigned)nb), dim3(kFitThreads<N, 2>), lds, st, q);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -1112,7 +1145,8 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 // One order of several problems in one launch: one workgroup per fit of the
 // segments (problem, order group) of the argument table, all of order N.
 template <int N, int PHASE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::waves1 : LayZ<N>::waves)))
+__global__ __launch_bounds__((kFitThreads<N, PHASE>))
+__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::template waves1<kFitThreads<N, 1>> : LayZ<N>::template waves<kFitThreads<N, 2>>)))
 void fit2r_multi(Fused2DArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds_rm[];
   const int64_t item = blockIdx.x;
@@ -1120,16 +1154,16 @@ void fit2r_multi(Fused2DArgs a) {
   while (sg + 1 < a.nseg && item >= a.seg[sg + 1].start) ++sg;
   const Params2D& p = *a.task[a.seg[sg].task];
   const int64_t fit = a.seg[sg].fit0 + (item - a.seg[sg].start);
-  if constexpr (PHASE == 1) r_phase1_body<N>(p, lds_rm, fit);
-  else r_phase2_body<N>(p, lds_rm, fit);
+  if constexpr (PHASE == 1) r_phase1_body<N, kFitThreads<N, 1>>(p, lds_rm, fit);
+  else r_phase2_body<N, kFitThreads<N, 2>>(p, lds_rm, fit);
 }
 
 template <int N>
 static hipError_t multi_n(int phase, const Fused2DArgs& a, hipStream_t st) {
   const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N>::bytes;
   if (a.total <= 0) return hipSuccess;
-  if (phase == 1) hipLaunchKernelGGL((fit2r_multi<N, 1>), dim3((unsigned)a.total), dim3(kThreads), lds, st, a);
-  else hipLaunchKernelGGL((fit2r_multi<N, 2>), dim3((unsigned)a.total), dim3(kThreads), lds, st, a);
+  if (phase == 1) hipLaunchKernelGGL((fit2r_multi<N, 1>), dim3((unsigned)a.total), dim3(kFitThreads<N, 1>), lds, st, a);
+  else hipLaunchKernelGGL((fit2r_multi<N, 2>), dim3((unsigned)a.total), dim3(kFitThreads<N, 2>), lds, st, a);
   return hipGetLastError();
 }
 
@@ -1168,8 +1202,8 @@ __device__ __attribute__((noinline)) void fused_fit_r(const Params2D* pp, int64_
   extern __shared__ __attribute__((aligned(16))) double lds_rf[];
   const Params2D& p = *(const Params2D*)(uintptr_t)(uint64_t)uniform64r((int64_t)(uintptr_t)pp);
   fit = uniform64r(fit);
-  if constexpr (PHASE == 1) r_phase1_body<N>(p, lds_rf, fit);
-  else r_phase2_body<N>(p, lds_rf, fit);
+  if constexpr (PHASE == 1) r_phase1_body<N, kThreads>(p, lds_rf, fit);
+  else r_phase2_body<N, kThreads>(p, lds_rf, fit);
 }
 
 template <int PHASE>

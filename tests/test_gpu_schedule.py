@@ -1,7 +1,11 @@
 """Launch schedules of the step: per-order kernels, the persistent fused kernel,
 hipGraph replay, batched steps of several problems and the autotuner.  The
 method fixes the result, not the schedule, so every schedule must reproduce
-the per-order direct launches bit for bit (and those match the oracle)."""
+the per-order direct launches bit for bit (and those match the oracle).  One
+exception: the reference solver's persistent fused kernel runs every order on
+four wavefronts where its per-order and batched kernels run orders up to 12 on
+one or two, so its sums are ordered differently; it must agree to rounding
+(FUSED_TOL)."""
 import numpy as np
 import pytest
 
@@ -13,6 +17,15 @@ from helpers import oracle_inputs, rel_l2
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
+FUSED_TOL = 1e-13
+
+
+def _same(got, want, rounding):
+    """Bitwise, or (rounding) within FUSED_TOL in relative L2 and per node."""
+    if not rounding:
+        return np.array_equal(got, want)
+    scale = np.max(np.abs(want))
+    return rel_l2(got, want) <= FUSED_TOL and np.max(np.abs(got - want)) <= FUSED_TOL * scale
 
 MIXED = np.array([6, 8, 10, 6, 8, 6, 10, 8, 10, 2, 8, 3, 8, 10, 6, 4], dtype=np.int32)
 
@@ -63,7 +76,8 @@ def test_every_schedule_is_bitwise_equal(B, precision):
     for sched in SCHEDULES:
         got = _run(B, wl, sched, [1, 2], precision)
         print(f"{precision} schedule {sched}: max |diff| {np.max(np.abs(got - ref)):.3e}", flush=True)
-        assert np.array_equal(got, ref), (precision, sched)
+        # fp64 runs the reference solver (the automatic choice); the mixed modes the factorisation
+        assert _same(got, ref, precision == "fp64" and sched[0] == 1), (precision, sched)
     if precision == "fp64":
         mesh, f, phi0, a = oracle_inputs(wl)
         want = sl.run(mesh, f, phi0, wl.dt, 3, wl.seed, np.arange(wl.samples))
@@ -87,7 +101,7 @@ def test_graph_follows_step_counter_and_dt(B):
             outs.append(B.sl_get_samples(h, 0, wl.samples))
         finally:
             B.sl_destroy(h)
-    assert np.array_equal(outs[0], outs[1])
+    assert _same(outs[1], outs[0], True)          # fused graph of the reference solver: to rounding
     assert np.array_equal(outs[0], outs[2])
 
 
@@ -133,10 +147,10 @@ def test_batch_equals_each_problem_alone(B, fused, graph):
         dts = [dt for _, _, dt in members]
         B.sl_step_batch(hs, dts, 2)
         B.sl_step_batch(hs, dts, 1)
-        for (wl, _, _), h, want in zip(members, hs, alone):
+        for (wl, prec, _), h, want in zip(members, hs, alone):
             assert B.sl_get_step(h) == 3
             got = B.sl_get_samples(h, 0, wl.samples)
-            assert np.array_equal(got, want), wl.name
+            assert _same(got, want, fused == 1 and wl.dim == 2 and prec == "fp64"), wl.name
     finally:
         for h in hs:
             B.sl_destroy(h)
@@ -167,7 +181,7 @@ def test_batch_of_many_problems_is_chunked(B, fused):
             hs.append(h)
         B.sl_step_batch(hs, [wl.dt for wl in members], 2)
         for wl, h, want in zip(members, hs, alone):
-            assert np.array_equal(B.sl_get_samples(h, 0, wl.samples), want)
+            assert _same(B.sl_get_samples(h, 0, wl.samples), want, fused == 1 and wl.dim == 2)
     finally:
         for h in hs:
             B.sl_destroy(h)
@@ -209,7 +223,7 @@ def test_autotune_restores_state_and_uses_its_cache(B, tmp_path):
         assert len(cache.read_text().splitlines()) == 1
         B.sl_set_schedule(h2, 0, 0, 0)
         B.sl_step(h2, wl.dt, 3)
-        assert np.array_equal(B.sl_get_samples(h2, 0, wl.samples), tuned)
+        assert _same(B.sl_get_samples(h2, 0, wl.samples), tuned, s["fused"] == 1)
     finally:
         B.sl_destroy(h)
         if h2 is not None:
