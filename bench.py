@@ -113,16 +113,17 @@ def kernel_sources_digest(wl):
     return h.hexdigest()[:16]
 
 
-def stored_traffic(wl, kname, precision):
+def stored_traffic(wl, kname, precision, ncomp=1):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or
-    None when none matches this kernel source, workload and step count."""
+    None when none matches this kernel source, workload, precision and number
+    of components."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         table = json.load(f)
-    key = f"{kname}|{wl.name}|{precision}"
+    key = f"{kname}|{wl.name}|{precision}" + (f"|nc{ncomp}" if ncomp > 1 else "")
     e = table.get(key)
     if not e or e.get("source_digest") != kernel_sources_digest(wl):
         return None
@@ -262,7 +263,7 @@ def main():
         achieved = flops / (kms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X["fp64_vector_tflops"],
                 "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_vector_tflops"], 4),
-                "traffic": stored_traffic(wl, kname, args.precision),
+                "traffic": stored_traffic(wl, kname, args.precision, args.ncomp),
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_fit_step": round(fit_flops_1d(N), 1)}
     elif args.path == "shared":
@@ -276,7 +277,7 @@ def main():
         n_b, ms_b = B.sl_kernel_time(prob.h, "shared_build")
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": MI355X["fp64_mfma_tflops"],
                 "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_mfma_tflops"], 4),
-                "traffic": stored_traffic(wl, kname, "shared"),
+                "traffic": stored_traffic(wl, kname, "shared", args.ncomp),
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_launch": per_launch, "flops_per_element_sample": 2 * n * (n + T),
                 "traces_kernel": {"ms": round(ms_t, 4), "launches": n_t,
@@ -306,7 +307,7 @@ def main():
         achieved = per_launch * launches / (kms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": MI355X["fp64_vector_tflops"],
                 "unit": "TFLOP/s", "frac": round(achieved / MI355X["fp64_vector_tflops"], 4),
-                "traffic": stored_traffic(wl, kname, args.precision),
+                "traffic": stored_traffic(wl, kname, args.precision, args.ncomp),
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_launch": per_launch, "mean_iterations": [round(it1, 3), round(it2, 3)],
                 "unconverged": [d1["solver_unconverged"][0] - d0["solver_unconverged"][0],
@@ -320,7 +321,7 @@ def main():
         peak = MI355X["fp64_mfma_tflops"] if args.precision == "fp64" else MI355X["fp32_mfma_tflops"]
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": stored_traffic(wl, kname, args.precision),
+                "traffic": stored_traffic(wl, kname, args.precision, args.ncomp),
                 "kernel": kname, "kernel_ms": round(kms, 4), "launches": launches,
                 "flops_per_launch": per_launch, "other_kernels": others}
 
