@@ -99,9 +99,13 @@ enum {
  * same remap up to rounding:
  *   SL_SOLVER_FACTOR: Gram matrix V^T V on the matrix cores, blocked Cholesky,
  *     range-space constraint elimination (N <= 10; every precision mode);
- *   SL_SOLVER_REFERENCE: conjugate gradients preconditioned by the Gram matrix
- *     of the undisplaced nodes (a Kronecker product), projected onto the
- *     constraints; float64 only; N <= 16;
+ *   SL_SOLVER_REFERENCE: preconditioners built from the undisplaced nodes
+ *     (Kronecker products): the unconstrained interpolant by Richardson
+ *     iteration on the square interpolation system (conjugate gradients on
+ *     the normal equations when that contracts slowly), the constrained remap
+ *     in null-space form (the projected boundary jump lifted by transfinite
+ *     interpolation, plus conjugate gradients over the (N-2)^2 functions that
+ *     vanish on the edges); float64 only; N <= 16;
  *   SL_SOLVER_AUTO: REFERENCE for SL_PREC_FP64, FACTOR for the mixed modes. */
 enum { SL_SOLVER_AUTO = 0, SL_SOLVER_FACTOR = 1, SL_SOLVER_REFERENCE = 2 };
 
@@ -125,8 +129,10 @@ typedef struct sl_mesh_desc {
   int32_t refine_iters;   /* FP64 refinement sweeps for the mixed modes; -1 = default */
   int32_t solver;         /* 2-D least-squares solver, SL_SOLVER_* (0 = automatic) */
   int32_t max_iter;       /* reference solver: iteration limit per fit, 0 = default (32) */
-  double tol;             /* reference solver: stop when the preconditioned residual, relative
-                             to the starting iterate, is below tol; 0 = default (1e-13) */
+  double tol;             /* reference solver: stop an unconstrained fit when its correction, relative
+                             to the starting iterate, is below tol, and the remap when its
+                             estimated nodal error, relative to the nodal values, is below tol;
+                             0 = default (1e-13) */
   int32_t constraints;    /* SL_CONSTRAIN_BOUNDARY (0): the remap is constrained by the upwinded
                              boundary values; SL_CONSTRAIN_BOUNDARY_MASS: also by the element's
                              mass, the integral of the advected interpolant p0 over the element
@@ -141,7 +147,7 @@ typedef struct sl_mesh_desc {
                              0 means 1.  Every component of a sample takes the same node moves
                              (the sample's Wiener increments) and is remapped on its own, with its
                              own boundary data; the 2-D reference solver shares each fit's
-                             geometry, constraint matrix and its inverse across the components */
+                             geometry, tables and preconditioner inverses across the components */
 } sl_mesh_desc;
 
 typedef struct sl_diag_t {
@@ -158,7 +164,9 @@ typedef struct sl_diag_t {
   int32_t refine_iters;
   size_t device_bytes;        /* bytes of device memory the handle uses */
   int32_t solver;             /* SL_SOLVER_FACTOR or SL_SOLVER_REFERENCE (2-D) */
-  int64_t solver_iterations[2];   /* reference solver, per phase: iterations summed over all fits so far */
+  int64_t solver_iterations[2];   /* reference solver, per phase: iterations summed over all fits and
+                                     components so far (phase 1 counts each residual evaluation,
+                                     the one that confirms a start included) */
   int64_t solver_unconverged[2];  /* reference solver, per phase: fits that stopped at max_iter */
   int64_t escapes;            /* moved nodes (per sample, step, node and direction) whose reference
                                  coordinate left [0, 1] since the handle was created: the step
@@ -166,8 +174,10 @@ typedef struct sl_diag_t {
                                  their element; the library allows the move (the interpolant is
                                  extrapolated, never clamped) and counts it here */
   double max_residual;        /* largest relative residual a fit's solver left since the handle was
-                                 created: reference solver sqrt(g^T g / x0^T x0) at its stop (g the
-                                 preconditioned residual, the quantity its tolerance bounds);
+                                 created: reference solver, the relative size its tolerance bounds
+                                 at its stop (unconstrained fit: the last correction over the
+                                 starting iterate; remap: the estimated nodal error over the
+                                 nodal values);
                                  factorisation solver in the mixed modes the relative size of the
                                  last float64 refinement correction, max|dc| / max|c|; 0 where
                                  neither applies (1-D, float64 factorisation); NaN if a fit met one */
@@ -235,14 +245,18 @@ int sl_step(sl_handle h, double dt, int32_t nsteps);
  * mode share one persistent launch per phase (every order in one work list,
  * largest orders first).  The 1-D handles of one order and at most 256
  * elements share one resident launch; larger 1-D meshes step on their own.  Every
- * handle's result is bitwise equal to sl_step on that handle alone.  All
+ * handle's result is bitwise equal to sl_step on that handle alone under the
+ * same schedule (see sl_schedule_t for fused reference-solver handles).  All
  * handles must have been created on the same stream; the batch is enqueued on
  * it and replayed from a cached hipGraph when the first 2-D handle's schedule
  * asks for graphs.  nh = 0 is a no-op; a repeated handle is SL_EINVAL. */
 int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t nsteps);
 
 /* Launch schedule of the 2-D step (Sec. 5 fixes only the result, which is the
- * same bit for bit under every schedule):
+ * same bit for bit under every schedule, with one exception: the persistent
+ * kernel of the reference solver runs every order on four wavefronts a fit,
+ * where its per-order kernels run orders up to 12 on one or two, so its sums
+ * are ordered differently and it agrees with them to rounding):
  *   fused = 0: one kernel per order group and phase, one workgroup per fit;
  *   fused = 1: one persistent kernel per phase over all orders, `grid`
  *              workgroups (0 = as many as fit on the device at once) pulling
