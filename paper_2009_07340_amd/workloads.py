@@ -189,7 +189,8 @@ def serving_requests(n=2000, rate=50.0, seed=2026, kmax=4096, mmax=2048):
             kx = ky = max(1, int(round(math.sqrt(K))))
         h = 1.0 / kx
         umax, Dmax = u0 + ua, D0 * (1.0 + Da)
-        # solve umax dt + sqrt(2 Dmax dt) = 0.05 h for dt (quadratic in sqrt(dt))
+        # solve umax dt + sqrt(2 Dmax dt) = c' 5.9 h / (N + 1/2)^2 for dt (quadratic in sqrt(dt)):
+        # eq. 1d_timestep with the asymptotic smallest node spacing, c' = 1 in 1-D, 1/2 in 2-D
         a, b, c = umax, math.sqrt(2.0 * Dmax), -(1.0 if dim == 1 else 0.5) * 5.9 * h / (N + 0.5) ** 2
         sdt = (-b + math.sqrt(b * b - 4 * a * c)) / (2 * a)
         dt = sdt * sdt
