@@ -139,9 +139,9 @@ typedef struct sl_mesh_desc {
                              (Introduction: a least-squares fit with boundary and mass
                              conservation constraints), so the boundary correction moves no mass
                              into or out of an element; for N = 2 the boundary values fix the
-                             polynomial and the mass row is left out.  1-D and the 2-D
-                             shared-geometry path; a 2-D step on the general path returns
-                             SL_EUNSUPPORTED */
+                             polynomial and the mass row is left out.  1-D, the 2-D
+                             reference solver and the 2-D shared-geometry path; a 2-D step
+                             with the factorisation solver returns SL_EUNSUPPORTED */
   int32_t ncomp;          /* components of a vector-valued field phi* (Sec. 5.3, last paragraph:
                              every component is defined on the same advected points), 1..64;
                              0 means 1.  Every component of a sample takes the same node moves

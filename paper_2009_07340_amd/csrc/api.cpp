@@ -1132,8 +1132,8 @@ int sl_step(sl_handle h, double dt, int32_t nsteps) {
   if (int rc = update_coefficients(h, dt)) return rc;
   const Layout& L = h->L;
   if (h->sched.shared) return step_shared(h, nsteps);
-  if (L.dim == 2 && L.mass)
-    return fail(SL_EUNSUPPORTED, "in 2-D the mass constraint runs on the shared-geometry path (schedule.shared = 1)");
+  if (L.dim == 2 && L.mass && L.solver != SL_SOLVER_REFERENCE)
+    return fail(SL_EUNSUPPORTED, "in 2-D the mass constraint runs with the reference solver or on the shared-geometry path");
   if (L.dim == 2) return step_2d({h}, nsteps, h->sched.fused, h->sched.graph, h->sched.grid, h->stream);
   return step_1d(h, nsteps, h->stream);
 }
@@ -1151,8 +1151,8 @@ int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t ns
     if (!h->fields_set) return fail(SL_ESTATE, "sl_set_fields must come before sl_step_batch");
     if (!(dts[i] > 0) || !std::isfinite(dts[i])) return fail(SL_EINVAL, "dt must be finite and > 0");
     if (h->stream != hs[0]->stream) return fail(SL_EINVAL, "all handles of a batch must share one stream");
-    if (h->L.dim == 2 && (h->L.mass || h->sched.shared))
-      return fail(SL_EUNSUPPORTED, "batches take the general path; a 2-D handle with the mass constraint or the shared-geometry schedule steps alone");
+    if (h->L.dim == 2 && ((h->L.mass && h->L.solver != SL_SOLVER_REFERENCE) || h->sched.shared))
+      return fail(SL_EUNSUPPORTED, "batches take the general path; a 2-D handle of the shared-geometry schedule, or with the mass constraint and the factorisation solver, steps alone");
     (h->L.dim == 2 ? two : one).push_back(h);
   }
   for (int i = 0; i < nh; ++i)

@@ -679,7 +679,8 @@ struct LayZ {
   static constexpr int oXm = oL + n;          // the moved nodes' coordinates (x, then y)
   static constexpr int oD = oXm + 2 * n;      // t - g at the own edge points
   static constexpr int oJ = oD + TT;          // the jump and its four corner values
-  static constexpr int oRed = oJ + TT + 4;
+  static constexpr int oMa = oJ + TT + 4;     // mass constraint: ax, ay, hx, hy (m each), a . h
+  static constexpr int oRed = oMa + 4 * mA + 1;
   static constexpr int end = oRed + 16;
   static constexpr size_t bytes = sizeof(double) * end;
   // at most as many as the registers admit without spilling (by order)
@@ -888,7 +889,8 @@ __device__ __forceinline__ void z_pinv_w0(const double* Gx, const double* Gy, co
   }
 }
 
-template <int N, int T>
+// MC: the mass-constraint code compiled in (it then runs where p.mass is set).
+template <int N, int T, bool MC = true>
 __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, int64_t fit) {
   using L = LayZ<N>;
   constexpr int n = L::n, m = L::m, mm = L::mm, TT = L::TT, mmA = L::mmA;
@@ -976,6 +978,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double* Lv = lds + L::oL;
   double* J = lds + L::oJ;
   const double* bw = nsp + nsp_bary(N);
+  const double* wq = p.wq_tab + N * kMaxN;   // the element's quadrature weights (mass constraint)
   auto qsum = [&](int j) {
     if constexpr (W == 4) return ((part[j] + part[mmA + j]) + part[2 * mmA + j]) + part[3 * mmA + j];
     else if constexpr (W == 2) return part[j] + part[mmA + j];
@@ -998,15 +1001,19 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     // j = P (t - g) and its corner values
     splitk<TT + 4, TT, T>([&](int o, int q) { return nsp[o * TT + q] * D[q]; }, J);
     block_sync();
-    double p0v = 0.0, lnode = 0.0, sc = 0.0;
+    double p0v = 0.0, lnode = 0.0, sc = 0.0, mc = 0.0;
     if (nodel) {
       const int ja = tl % N, jb = tl / N;
       p0v = p.phi[row * p.nodes + noff + tl];
       Lv[tl] = coons<N>(J, xi, bw, XYm[tl], XYm[n + tl]);
       lnode = coons_node<N>(J, ja, jb, xi[ja], xi[jb]);
       sc = p0v * p0v + lnode * lnode;
+      if (MC && p.mass) mc = (wq[ja] * wq[jb]) * lnode;   // the lift's integral over the element
     }
-    const double scale = block_sum<T>(sc, red);   // also the barrier after Lv
+    if constexpr (MC) block_sum2<T>(sc, mc, red);   // also the barrier after Lv
+    else sc = block_sum<T>(sc, red);
+    const double scale = sc;
+    const double cmass = -mc;     // the bubble part must cancel the lift's integral
     double bub = 0.0;
     if constexpr (m > 0) {
       // b = -Vz^T lift(j); w = (Gx (x) Gy) b; r = Vz^T Vz w - b; g = (Gx (x) Gy) r;
@@ -1015,12 +1022,77 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       const double stop = p.tol2 * xx;
       const bool w0 = wave() == 0;
       double rg = 0.0, gg = 0.0;      // wavefront 0's
+      // the mass constraint (G14) is one linear condition a . w = cmass on the
+      // bubble coefficients, a[(l, k)] = ay[l] ax[k] the integrals of the bubble
+      // functions; its projection in the preconditioner's metric uses
+      // h = (Gx (x) Gy) a = hy (x) hx: v -= h (a . v) / (a . h)
+      double* Ma = lds + L::oMa;
+      if (MC && p.mass && c == 0 && w0) {
+        for (int q = lane(); q < 2 * m; q += 64) {
+          const int dir = q >= m, k = q - dir * m;
+          const double* Z = dir ? Zy : Zx;
+          double acc = 0.0;
+          for (int a = 0; a < N; ++a) acc += wq[a] * Z[a * m + k];
+          Ma[q] = acc;
+        }
+        wave_sync();
+        for (int q = lane(); q < 2 * m; q += 64) {
+          const int dir = q >= m, k = q - dir * m;
+          const double* G = dir ? Gy : Gx;
+          double acc = 0.0;
+          for (int kk = 0; kk < m; ++kk) acc += G[k * m + kk] * Ma[dir * m + kk];
+          Ma[2 * m + q] = acc;
+        }
+        wave_sync();
+        if (lane() == 0) {
+          double sx = 0.0, sy = 0.0;
+          for (int k = 0; k < m; ++k) {
+            sx += Ma[k] * Ma[2 * m + k];
+            sy += Ma[m + k] * Ma[3 * m + k];
+          }
+          Ma[4 * m] = sx * sy;
+        }
+        wave_sync();
+      }
+      // wavefront 0: v -= h (a . v - target) / (a . h), which puts v on a . v = target
+      auto mass_project = [&](double* v, double target) {
+        double d = 0.0;
+        for (int j = lane(); j < mm; j += 64) d += (Ma[m + j / m] * Ma[j % m]) * v[j];
+        const double f = (wave_sum(d) - target) / Ma[4 * m];
+        for (int j = lane(); j < mm; j += 64) v[j] -= (Ma[3 * m + j / m] * Ma[2 * m + j % m]) * f;
+        wave_sync();
+      };
+      // wavefront 0: with g = (Gx (x) Gy) r given, g -= mu h and r -= mu a, mu = (a . g) / (a . h):
+      // g becomes the projected preconditioned residual, and r keeps the size of the
+      // error (otherwise its component along a, the constraint's multiplier, grows and
+      // its rounding stalls the iteration)
+      auto mass_resid = [&](double* r, double* g) {
+        double d = 0.0;
+        for (int j = lane(); j < mm; j += 64) d += (Ma[m + j / m] * Ma[j % m]) * g[j];
+        const double mu = wave_sum(d) / Ma[4 * m];
+        for (int j = lane(); j < mm; j += 64) {
+          g[j] -= (Ma[3 * m + j / m] * Ma[2 * m + j % m]) * mu;
+          r[j] -= (Ma[m + j / m] * Ma[j % m]) * mu;
+        }
+        wave_sync();
+      };
+      // wavefront 0: the residual's dot products with the (projected) g
+      auto dots = [&](double& rgo, double& ggo) {
+        double a = 0.0, b = 0.0;
+        for (int j = lane(); j < mm; j += 64) {
+          a += Rv[j] * Gv[j];
+          b += Gv[j] * Gv[j];
+        }
+        rgo = wave_sum(a);
+        ggo = wave_sum(b);
+      };
       z_VT_part<N, T>(Xz, Yz, Lv, part);
       block_sync();
       if (w0) {
         for (int j = lane(); j < mm; j += 64) Bv[j] = -qsum(j);
         wave_sync();
         z_pinv_w0<N>(Gx, Gy, Bv, Tv, Wv);
+        if (MC && p.mass) mass_project(Wv, cmass);
       }
       block_sync();
       z_V<N, T>(Xz, Yz, Wv, Lv);
@@ -1031,7 +1103,13 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       if (w0) {
         for (int j = lane(); j < mm; j += 64) Rv[j] = qsum(j) - Bv[j];
         wave_sync();
-        z_pinv_w0<N>(Gx, Gy, Rv, Tv, Gv, Rv, &rg, &gg);
+        if (MC && p.mass) {
+          z_pinv_w0<N>(Gx, Gy, Rv, Tv, Gv);
+          mass_resid(Rv, Gv);
+          dots(rg, gg);
+        } else {
+          z_pinv_w0<N>(Gx, Gy, Rv, Tv, Gv, Rv, &rg, &gg);
+        }
         for (int j = lane(); j < mm; j += 64) Pv[j] = -Gv[j];
         if (lane() == 0) flag[0] = (gg > stop && p.max_iter > 0) ? 1.0 : 0.0;
       }
@@ -1051,7 +1129,13 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
           }
           wave_sync();
           double rg1;
-          z_pinv_w0<N>(Gx, Gy, Rv, Tv, Gv, Rv, &rg1, &gg);
+          if (MC && p.mass) {
+            z_pinv_w0<N>(Gx, Gy, Rv, Tv, Gv);
+            mass_resid(Rv, Gv);
+            dots(rg1, gg);
+          } else {
+            z_pinv_w0<N>(Gx, Gy, Rv, Tv, Gv, Rv, &rg1, &gg);
+          }
           const double beta = rg1 / rg;
           rg = rg1;
           for (int j = lane(); j < mm; j += 64) Pv[j] = beta * Pv[j] - Gv[j];
@@ -1063,6 +1147,10 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
         its += it;
         unconv += gg <= stop ? 0 : 1;
         rmax = fmax(rmax, rel_resid(gg, xx));
+      }
+      if (MC && p.mass) {   // the constraint to working accuracy
+        if (w0) mass_project(Wv, cmass);
+        block_sync();
       }
       if (nodel) {
         const int ja = tl % N, jb = tl / N;
@@ -1096,11 +1184,11 @@ void fit2r_phase1(Params2D p) {
   r_phase1_body<N, kFitThreads<N, 1>>(p, lds_r1, blockIdx.x + p.block0);
 }
 
-template <int N>
+template <int N, bool MC>
 __global__ __launch_bounds__((kFitThreads<N, 2>)) __attribute__((amdgpu_waves_per_eu(LayZ<N>::template waves<kFitThreads<N, 2>>)))
 void fit2r_phase2(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r2[];
-  r_phase2_body<N, kFitThreads<N, 2>>(p, lds_r2, blockIdx.x + p.block0);
+  r_phase2_body<N, kFitThreads<N, 2>, MC>(p, lds_r2, blockIdx.x + p.block0);
 }
 
 template <int N>
@@ -1113,8 +1201,10 @@ static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStrea
     const int64_t nb = (nfits - b0) < chunk ? (nfits - b0) : chunk;
     if (phase == 1)
       hipLaunchKernelGGL((fit2r_phase1<N>), dim3((unsigned)nb), dim3(kFitThreads<N, 1>), lds, st, q);
+    else if (q.mass)
+      hipLaunchKernelGGL((fit2r_phase2<N, true>), dim3((unsigned)nb), dim3(kFitThreads<N, 2>), lds, st, q);
     else
-      hipLaunchKernelGGL((fit2r_phase2<N>), dim3((unsigned)nb), dim3(kFitThreads<N, 2>), lds, st, q);
+      hipLaunchKernelGGL((fit2r_phase2<N, false>), dim3((unsigned)nb), dim3(kFitThreads<N, 2>), lds, st, q);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
