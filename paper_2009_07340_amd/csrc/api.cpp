@@ -81,7 +81,7 @@ struct Layout {
   // byte offsets in the workspace
   size_t o_phi, o_phi2, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
-  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_nsp, o_sops, o_bw, o_wqtab, total;
+  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_nsp, o_sops, o_bw, o_wqtab, o_z, o_emean, o_nbrtr, total;
   bool shared_capable = false;      // one order <= kMaxNShared in 2-D: the shared-geometry path can run
   int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
   size_t gx_doubles = 0, nsp_doubles = 0;
@@ -198,6 +198,9 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.shared_capable = L.dim == 2 && L.uniform && L.maxN <= sl::kMaxNShared;
   L.o_sops = take(L.shared_capable ? sizeof(double) * (size_t)L.M * sl::shared_op_doubles(L.maxN) : 0);
   L.o_bw = take(sizeof(double) * sl::kMaxN);
+  L.o_z = take(L.dim == 2 ? sizeof(double) * 2 * (size_t)L.M : 0);
+  L.o_emean = take(L.dim == 2 ? sizeof(double) * 4 * (size_t)L.K : 0);
+  L.o_nbrtr = take(L.dim == 2 ? sizeof(int64_t) * 4 * (size_t)L.K : 0);
   L.total = o;
   return SL_OK;
 }
@@ -225,7 +228,7 @@ struct sl_ctx {
   sl::LegendreRec rec{};
   // host copies of the fields
   std::vector<double> u, D, divu, un, Dn, ghost_h;
-  std::vector<double> hA, hB, hsrc, hAf, hBf;
+  std::vector<double> hA, hB, hsrc, hAf, hBf, hemean;
   bool fields_set = false;
   bool coeff_valid = false;
   double coeff_dt = 0.0;
@@ -249,6 +252,9 @@ struct sl_ctx {
   double* d_sops = nullptr;              // shared-geometry path: per-sample operators
   double* d_bw = nullptr;                // barycentric weights of the (single) order's nodes
   double* d_wqtab = nullptr;             // [(kMaxN+1)][kMaxN] quadrature weights of each order's nodes
+  double* d_z = nullptr;                 // [M][2] this step's Wiener normals (reference solver)
+  double* d_emean = nullptr;             // [K][4] element means of the move coefficients
+  int64_t* d_nbrtr = nullptr;            // [K][4] where each side's upwind neighbour trace starts
   bool shared_geometry = false;          // the current step coefficients are the same at every node
   hipStream_t cap_stream = nullptr;      // private stream for graph capture
   // measurement
@@ -342,6 +348,26 @@ int update_coefficients(sl_ctx* h, double dt) {
   SL_HIP(hipMemcpyAsync(h->src, h->hsrc.data(), sizeof(double) * h->hsrc.size(), hipMemcpyHostToDevice, h->stream));
   SL_HIP(hipMemcpyAsync(h->Af, h->hAf.data(), sizeof(double) * h->hAf.size(), hipMemcpyHostToDevice, h->stream));
   SL_HIP(hipMemcpyAsync(h->Bf, h->hBf.data(), sizeof(double) * h->hBf.size(), hipMemcpyHostToDevice, h->stream));
+  if (L.dim == 2) {
+    // element means of A and B per direction: the mean displacement of a
+    // fit's moved nodes is then mean(A) + mean(B) z, up to rounding
+    h->hemean.assign(4 * (size_t)L.K, 0.0);
+    for (int e = 0; e < L.K; ++e) {
+      long double sa[2] = {0, 0}, sb[2] = {0, 0};
+      for (int64_t k = L.noff[e]; k < L.noff[e + 1]; ++k)
+        for (int j = 0; j < 2; ++j) {
+          sa[j] += h->hA[k * 2 + j];
+          sb[j] += h->hB[k * 2 + j];
+        }
+      const long double n = (long double)(L.noff[e + 1] - L.noff[e]);
+      for (int j = 0; j < 2; ++j) {
+        h->hemean[4 * (size_t)e + j] = (double)(sa[j] / n);
+        h->hemean[4 * (size_t)e + 2 + j] = (double)(sb[j] / n);
+      }
+    }
+    SL_HIP(hipMemcpyAsync(h->d_emean, h->hemean.data(), sizeof(double) * h->hemean.size(), hipMemcpyHostToDevice,
+                          h->stream));
+  }
   SL_HIP(hipStreamSynchronize(h->stream));   // host vectors may be reused right after
   h->coeff_valid = true;
   h->coeff_dt = dt;
@@ -415,6 +441,9 @@ void build_params(sl_ctx* h) {
     p.rec = h->rec;
     p.mass = L.mass ? 1 : 0;
     p.wq_tab = h->d_wqtab;
+    p.zdraw = h->d_z;
+    p.emean = h->d_emean;
+    p.nbr_tr = h->d_nbrtr;
   } else {
     sl::Params1D& p = h->p1;
     p = sl::Params1D{};
@@ -465,6 +494,32 @@ int enqueue_counters(const std::vector<sl_ctx*>& hs, int set, hipStream_t st) {
       a.value[i] = hs[c0 + i]->step;
     }
     SL_HIP(sl::launch_step_counters(a, st));
+  }
+  return SL_OK;
+}
+
+// This step's normal pairs of the reference-solver handles among hs, read by
+// both phases.  devstep: the draw reads each handle's device step counter
+// (graph capture), else it takes the host counter plus `ahead`.
+int enqueue_draw(const std::vector<sl_ctx*>& hs, bool devstep, int64_t ahead, hipStream_t st) {
+  std::vector<sl_ctx*> ref;
+  for (sl_ctx* h : hs)
+    if (h->L.solver == SL_SOLVER_REFERENCE) ref.push_back(h);
+  for (size_t c0 = 0; c0 < ref.size(); c0 += sl::kMaxTasks) {
+    sl::DrawArgs a{};
+    a.n = (int)std::min<size_t>(sl::kMaxTasks, ref.size() - c0);
+    int64_t maxM = 0;
+    for (int i = 0; i < a.n; ++i) {
+      sl_ctx* h = ref[c0 + i];
+      a.z[i] = h->d_z;
+      a.step_ptr[i] = devstep ? h->d_step : nullptr;
+      a.step[i] = h->step + ahead;
+      a.M[i] = h->p2.M;
+      a.seed[i] = h->p2.seed;
+      a.stream[i] = h->p2.stream;
+      maxM = std::max<int64_t>(maxM, h->p2.M);
+    }
+    SL_HIP(sl::launch_draw_normals(a, maxM, st));
   }
   return SL_OK;
 }
@@ -574,6 +629,10 @@ int enqueue_multi(const std::vector<sl_ctx*>& hs, int phase, hipStream_t st) {
 
 // One whole step (both phases and the counter advance) on the device step counters.
 int enqueue_device_step(const std::vector<sl_ctx*>& hs, int fused, int grid, hipStream_t st, sl_ctx* prof) {
+  {
+    std::unique_ptr<ProfScope> ps(prof ? new ProfScope(prof, "draw_normals") : nullptr);
+    if (int rc = enqueue_draw(hs, true, 0, st)) return rc;
+  }
   for (int phase = 1; phase <= 2; ++phase) {
     const char* name = fused ? (phase == 1 ? "fit2d_fused_phase1" : "fit2d_fused_phase2")
                        : hs.size() > 1 ? (phase == 1 ? "fit2d_batch_phase1" : "fit2d_batch_phase2")
@@ -655,11 +714,16 @@ int step_2d(const std::vector<sl_ctx*>& hs, int32_t nsteps, int fused, int graph
   sl_ctx* h0 = hs[0];
   if (!fused && !graph && hs.size() == 1) {
     // per-order kernels with the host step counter
-    for (int it = 0; it < nsteps; ++it)
+    for (int it = 0; it < nsteps; ++it) {
+      if (h0->L.solver == SL_SOLVER_REFERENCE) {
+        ProfScope ps(h0, "draw_normals");
+        if (int rc = enqueue_draw(hs, false, it, st)) return rc;
+      }
       for (int phase = 1; phase <= 2; ++phase) {
         ProfScope ps(h0, kernel_label(h0, phase));
         if (int rc = enqueue_perorder(h0, phase, false, h0->step + it, st)) return rc;
       }
+    }
   } else {
     if (int rc = enqueue_counters(hs, 1, st)) return rc;
     if (graph && !h0->profile) {
@@ -869,6 +933,9 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_sops = (double*)(h->ws + L.o_sops);
   h->d_wqtab = (double*)(h->ws + L.o_wqtab);
   h->d_bw = (double*)(h->ws + L.o_bw);
+  h->d_z = (double*)(h->ws + L.o_z);
+  h->d_emean = (double*)(h->ws + L.o_emean);
+  h->d_nbrtr = (int64_t*)(h->ws + L.o_nbrtr);
   // element tables, work list grouped by order, node tables, U_r and trace interpolation
   std::vector<int32_t> nbr(4 * (size_t)L.K, -1), work;
   for (int e = 0; e < L.K; ++e) {
@@ -948,6 +1015,17 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   }
   std::vector<int64_t> noff64(L.noff.begin(), L.noff.end() - 1), eoff64(L.eoff.begin(), L.eoff.end() - 1);
   std::vector<int32_t> order32(L.order.begin(), L.order.end());
+  // per side, the neighbour's facing trace: across W (E, S, N) it is the
+  // neighbour's E (W, N, S) block of Ns values, packed with Ns
+  std::vector<int64_t> nbrtr(L.dim == 2 ? 4 * (size_t)L.K : 1, -1);
+  if (L.dim == 2)
+    for (int e = 0; e < L.K; ++e)
+      for (int w = 0; w < 4; ++w) {
+        const int nb = nbr[4 * (size_t)e + w];
+        if (nb < 0) continue;
+        const int64_t Ns = L.order[nb];
+        nbrtr[4 * (size_t)e + w] = (Ns << 48) | (L.eoff[nb] + (int64_t)(w ^ 1) * Ns);
+      }
   struct Up { void* dst; const void* src; size_t bytes; };
   const Up ups[] = {
       {h->d_order, order32.data(), sizeof(int32_t) * L.K}, {h->d_noff, noff64.data(), sizeof(int64_t) * L.K},
@@ -958,8 +1036,10 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       {h->d_interpoff, interpoff.data(), sizeof(int64_t) * interpoff.size()},
       {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}, {h->d_nsp, nsp.data(), sizeof(double) * nsp.size()},
       {h->d_bw, bw.data(), sizeof(double) * bw.size()},
-      {h->d_wqtab, wqtab.data(), sizeof(double) * wqtab.size()}};
+      {h->d_wqtab, wqtab.data(), sizeof(double) * wqtab.size()},
+      {h->d_nbrtr, nbrtr.data(), L.dim == 2 ? sizeof(int64_t) * nbrtr.size() : 0}};
   for (const auto& u : ups) {
+    if (u.bytes == 0) continue;
     if (hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
       if (h->own_ws) (void)hipFree(h->ws);
       return fail(SL_EDEVICE, "table upload failed");

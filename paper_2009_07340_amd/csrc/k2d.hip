@@ -745,6 +745,25 @@ hipError_t launch_step_counters(const StepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// One step's normal pairs of a batch of problems, one sample a thread
+// (blockIdx.y: the problem), so that the fits of every element read their
+// sample's pair instead of drawing it again.
+__global__ __launch_bounds__(256) void draw_normals_kernel(DrawArgs a) {
+  const int t = blockIdx.y;
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.n || s >= a.M[t]) return;
+  const int64_t step = a.step_ptr[t] ? *a.step_ptr[t] : a.step[t];
+  const Normal2 d = normal_pair(a.seed[t], a.stream[t], (uint64_t)step, (uint64_t)s);
+  a.z[t][2 * s] = d.a;
+  a.z[t][2 * s + 1] = d.b;
+}
+
+hipError_t launch_draw_normals(const DrawArgs& a, int64_t maxM, hipStream_t st) {
+  if (a.n <= 0 || maxM <= 0) return hipSuccess;
+  hipLaunchKernelGGL(draw_normals_kernel, dim3((unsigned)((maxM + 255) / 256), (unsigned)a.n), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 template <int MODE, int PHASE>
 static hipError_t fused_one(const Fused2DArgs& a, int grid, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL((fit2d_fused<MODE, PHASE>), dim3(grid), dim3(kThreads), lds, st, a);

@@ -64,9 +64,7 @@ struct LayR {
   static constexpr int oT1 = oQ + n;
   static constexpr int oTr = oT1 + n;          // traces
   static constexpr int oUc = oTr + TT;         // edge contractions
-  static constexpr int oXs = oUc + TT;
-  static constexpr int oYs = oXs + n;
-  static constexpr int oRed = oYs + n;
+  static constexpr int oRed = oUc + TT;
   static constexpr int end1 = oRed + 16;
   static constexpr size_t bytes1 = sizeof(double) * end1;
   // Waves a SIMD that the LDS admits for fits of b bytes on T threads, at most
@@ -314,37 +312,35 @@ __device__ void r_carried(const Params2D& p, double* lds, int e, int64_t row) {
 // of p0, g the upwinded boundary data (eq. bnd_update): at each own edge point
 // the element the interface displacement comes from supplies the trace
 // (another order's trace interpolated to this element's abscissae), or the
-// Dirichlet ghost value.  No barrier.
+// Dirichlet ghost value.  The outside value is loaded before the side is known,
+// so that no load waits for the draw.  No barrier.
 template <int N, int T>
 __device__ void r_jump_data(const Params2D& p, int e, int64_t row, double za, double zb, double* gv, int t0) {
   using L = LayR<N>;
   const int64_t eoff = p.eoff[e];
   for (int q = t0; q < L::TT; q += T) {
     const int ew = q / N, j = q % N;
+    const int64_t nt = p.nbr_tr[4 * e + ew];
     const double tq = p.tr[row * p.edges + eoff + q];
-    const double zd = (ew < 2) ? za : zb;
-    const double disp = edge_disp(p.Af[eoff + q], p.Bf[eoff + q], zd);
-    const bool pos = disp > 0.0;
-    const bool take_nbr = (ew == 0 || ew == 2) ? pos : !pos;   // W, S: neighbour is the negative side
-    double g = tq;
-    if (take_nbr) {
-      const int nb = p.nbr[4 * e + ew];
-      if (nb < 0) {
-        g = p.ghost[eoff + q];
-      } else {
-        const int Ns = p.order[nb];
-        const double* src = p.tr + row * p.edges + p.eoff[nb] + (ew ^ 1) * Ns;
-        if (Ns == N) {
-          g = src[j];
-        } else {   // trace of another order: Lagrange interpolation to this element's abscissae
-          const double* Lm = p.interp + p.interp_off[N * (kMaxN + 1) + Ns] + j * Ns;
-          double acc = 0.0;
-          for (int m = 0; m < Ns; ++m) acc += Lm[m] * src[m];
-          g = acc;
-        }
+    double out;
+    if (nt < 0) {
+      out = p.ghost[eoff + q];
+    } else {
+      const int Ns = (int)(nt >> 48);
+      const double* src = p.tr + row * p.edges + (nt & 0xffffffffffffll);
+      if (Ns == N) {
+        out = src[j];
+      } else {   // trace of another order: Lagrange interpolation to this element's abscissae
+        const double* Lm = p.interp + p.interp_off[N * (kMaxN + 1) + Ns] + j * Ns;
+        double acc = 0.0;
+        for (int m = 0; m < Ns; ++m) acc += Lm[m] * src[m];
+        out = acc;
       }
     }
-    gv[q] = tq - g;
+    const double zd = (ew < 2) ? za : zb;
+    const bool pos = edge_disp(p.Af[eoff + q], p.Bf[eoff + q], zd) > 0.0;
+    const bool take_nbr = (ew == 0 || ew == 2) ? pos : !pos;   // W, S: neighbour is the negative side
+    gv[q] = tq - (take_nbr ? out : tq);
   }
 }
 
@@ -385,97 +381,83 @@ __device__ void r_traces_from(const double* Bx, const double* By, const double* 
 
 // ---------------------------------------------------------------- per-fit set-up
 
-// Moves (eq. def_dx), carried values (eq. advection_phi), centred 1-D tables,
-// b = V^T f; returns the mean displacement (dbx, dby) in registers.
+// The mean displacement of a fit's moved nodes, (dbx, dby), from the element
+// means of the move coefficients: the same as averaging the moves, up to
+// rounding (it only centres the basis).
+struct Shift2 {
+  double x, y;
+};
+__device__ __forceinline__ Shift2 mean_shift(const Params2D& p, int e, Normal2 z) {
+  const double* em = p.emean + 4 * e;
+  return Shift2{em[0] + em[2] * z.a, em[1] + em[3] * z.b};
+}
+
+// This step's Wiener normals of sample s (eq. def_dx), drawn for every sample
+// before phase 1 and shared by the elements and both phases.
+__device__ __forceinline__ Normal2 fit_increments(const Params2D& p, int64_t s) {
+  return Normal2{p.zdraw[2 * s], p.zdraw[2 * s + 1]};
+}
+
+// Moves (eq. def_dx), carried values (eq. advection_phi) and the centred 1-D
+// tables: item i < n moves node i and evaluates the basis there in x and in y;
+// the next 2N items the N Gauss abscissae of the edges in x and in y, the last
+// 4 the edge coordinates.  Moved nodes outside the element are counted in the
+// statistics.  One barrier.
 template <int N, int T>
-__device__ int r_setup(const Params2D& p, double* lds, int e, int64_t s, double za, double zb) {
+__device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, Normal2 z) {
   using L = LayR<N>;
   constexpr int n = L::n;
   const int t = tid();
   const int64_t noff = p.noff[e];
-  double* xs = lds + L::oXs;
-  double* ys = lds + L::oYs;
+  const Shift2 d = mean_shift(p, e, z);
   double* f = lds + L::oF;
-  double* red = lds + L::oRed;
-  double sx = 0.0, sy = 0.0;
-  int esc = 0;
-  for (int i = t; i < n; i += T) {
-    const int64_t k = noff + i;
-    const double x0 = p.xi_node[2 * k], y0 = p.xi_node[2 * k + 1];
-    const double xm = moved_coord(x0, p.A[2 * k], p.B[2 * k], za);
-    const double ym = moved_coord(y0, p.A[2 * k + 1], p.B[2 * k + 1], zb);
-    xs[i] = xm;
-    ys[i] = ym;
-    f[i] = p.phi[s * p.ncomp * p.nodes + k] * p.src[k];   // component 0 of sample s
-    sx += xm - x0;
-    sy += ym - y0;
-    esc += escaped(xm) + escaped(ym);
-  }
   const double* gsrc = p.gxinv + p.gx_off[N];
   double* gxi = lds + L::oGxi;   // Gx^-1 and Vx^-1, adjacent in both places
   for (int i = t; i < 2 * N * N; i += T) gxi[i] = gsrc[i];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    sx += __shfl_xor(sx, o, 64);
-    sy += __shfl_xor(sy, o, 64);
-    esc += __shfl_xor(esc, o, 64);
-  }
-  if (lane() == 0) {
-    red[wave()] = sx;
-    red[4 + wave()] = sy;
-    red[8 + wave()] = (double)esc;
-  }
-  block_sync();
-  const double dbx = wsum<T>(red) / n;
-  const double dby = wsum<T>(red + 4) / n;
-  const int escapes = (int)wsum<T>(red + 8);
   double* X1 = lds + L::oX1;
   double* Y1 = lds + L::oY1;
   double* Bx = lds + L::oBx;
   double* By = lds + L::oBy;
   double* Ev = lds + L::oEv;
-  // one basis evaluation an item: the n moved nodes in x, then in y, the N
-  // Gauss abscissae of the edges in x and in y, the 4 edge coordinates
-  for (int it = t; it < 2 * n + 2 * N + 4; it += T) {
-    double arg;
-    double* dst;
-    int stride = 1;
-    if (it < 2 * n) {
-      const int dir = it >= n, i = it - dir * n;
-      arg = dir ? ys[i] - dby : xs[i] - dbx;
-      dst = (dir ? Y1 : X1) + i;
-      stride = L::XS;
-    } else if (it < 2 * n + 2 * N) {
-      const int u = it - 2 * n, dir = u >= N, row = u - dir * N;
-      arg = p.xi_tab[N * kMaxN + row] - (dir ? dby : dbx);
-      dst = (dir ? By : Bx) + row * N;
-    } else {
-      const int w = it - 2 * n - 2 * N;
-      arg = (w == 0) ? -dbx : (w == 1) ? 1.0 - dbx : (w == 2) ? -dby : 1.0 - dby;
-      dst = Ev + w * N;
-    }
+  int esc = 0;
+  for (int it = t; it < n + 2 * N + 4; it += T) {
     double q[N];
-    legendre_eval<N>(arg, p.rec, q);
+    if (it < n) {
+      const int64_t k = noff + it;
+      const double x0 = p.xi_node[2 * k], y0 = p.xi_node[2 * k + 1];
+      const double xm = moved_coord(x0, p.A[2 * k], p.B[2 * k], z.a);
+      const double ym = moved_coord(y0, p.A[2 * k + 1], p.B[2 * k + 1], z.b);
+      f[it] = p.phi[s * p.ncomp * p.nodes + k] * p.src[k];   // component 0 of sample s
+      esc += escaped(xm) + escaped(ym);
+      legendre_eval<N>(xm - d.x, p.rec, q);
 #pragma unroll
-    for (int k = 0; k < N; ++k) dst[k * stride] = q[k];
+      for (int j = 0; j < N; ++j) X1[j * L::XS + it] = q[j];
+      legendre_eval<N>(ym - d.y, p.rec, q);
+#pragma unroll
+      for (int j = 0; j < N; ++j) Y1[j * L::XS + it] = q[j];
+    } else {
+      double arg;
+      double* dst;
+      if (it < n + 2 * N) {
+        const int u = it - n, dir = u >= N, row = u - dir * N;
+        arg = p.xi_tab[N * kMaxN + row] - (dir ? d.y : d.x);
+        dst = (dir ? By : Bx) + row * N;
+      } else {
+        const int w = it - n - 2 * N;
+        arg = (w == 0) ? -d.x : (w == 1) ? 1.0 - d.x : (w == 2) ? -d.y : 1.0 - d.y;
+        dst = Ev + w * N;
+      }
+      legendre_eval<N>(arg, p.rec, q);
+#pragma unroll
+      for (int j = 0; j < N; ++j) dst[j] = q[j];
+    }
+  }
+  if (p.stats) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) esc += __shfl_xor(esc, o, 64);
+    if (lane() == 0 && esc) stat_add(p.stats, kStatEscapes, (unsigned long long)esc);
   }
   block_sync();
-  return escapes;
-}
-
-// The Wiener increments of sample s in this step (eq. def_dx), drawn only by the
-// wavefronts that use them (the node moves and the edge displacements: the
-// first max(n, 4N) threads); the others get zeros they never read.
-template <int N>
-__device__ __forceinline__ Normal2 fit_increments(const Params2D& p, int64_t s) {
-  constexpr int kUse = (N * N > 4 * N ? N * N : 4 * N);
-  double za = 0.0, zb = 0.0;
-  if (__builtin_amdgcn_readfirstlane(tid() >> 6) < (kUse + 63) / 64) {
-    const Normal2 d = normal_pair(p.seed, p.stream, (uint64_t)(p.step_ptr ? *p.step_ptr : p.step), (uint64_t)s);
-    za = d.a;
-    zb = d.b;
-  }
-  return Normal2{za, zb};
 }
 
 // G v = V^T (V v) into out (tmp: n doubles).  Two barriers.
@@ -490,17 +472,15 @@ __device__ __forceinline__ void r_G(double* lds, const double* v, double* tmp, d
 }
 
 // Diagnostics of one fit: iterations and whether the tolerance was reached
-// (per phase), moved nodes outside the element (phase 1 counts the moves) and
-// the relative residual left, sqrt(g^T g / x0^T x0).  Called after the fit's
+// (per phase) and the relative residual left, sqrt(g^T g / x0^T x0) (phase 1's
+// set-up counts the moved nodes outside the element).  Called after the fit's
 // last barrier: a workgroup barrier waits for the memory operations in flight,
 // atomics included.
-__device__ __forceinline__ void count_fit(const Params2D& p, int phase, int iters, int unconverged, int escapes,
-                                          double resid) {
+__device__ __forceinline__ void count_fit(const Params2D& p, int phase, int iters, int unconverged, double resid) {
   if (tid() == 0 && p.stats) {
     unsigned long long* c = stat_slot(p.stats) + 2 * (phase - 1);
     atomicAdd(c, (unsigned long long)iters);
     if (unconverged) atomicAdd(c + 1, (unsigned long long)unconverged);
-    stat_add(p.stats, kStatEscapes, (unsigned long long)escapes);
     stat_residual(p.stats, resid);
   }
 }
@@ -518,8 +498,8 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
-  const Normal2 z = fit_increments<N>(p, s);
-  const int escapes = r_setup<N, T>(p, lds, e, s, z.a, z.b);
+  const Normal2 z = fit_increments(p, s);
+  r_setup<N, T>(p, lds, e, s, z);
   const int t = tid();
   const double* gxi = lds + L::oGxi;
   double* b = lds + L::oB;
@@ -630,7 +610,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   unconv += gg <= stop ? 0 : 1;
   rmax = fmax(rmax, rel_resid(gg, xx));
   }
-  count_fit(p, 1, its, unconv, escapes, rmax);
+  count_fit(p, 1, its, unconv, rmax);
 }
 
 // ---------------------------------------------------------------- phase 2
@@ -782,7 +762,11 @@ __device__ void z_gram_inverse(const double* Vx, const double* xi, double d, dou
     double ak[m];
 #pragma unroll
     for (int i = 0; i < m; ++i) ak[i] = bcast(col[i], k);
-    const double pinv = 1.0 / ak[k];
+    // the hardware reciprocal and two Newton steps: the inverse only
+    // preconditions, so the last bit of the pivot's reciprocal does not matter
+    double pinv = __builtin_amdgcn_rcp(ak[k]);
+    pinv = fma(pinv, fma(-ak[k], pinv, 1.0), pinv);
+    pinv = fma(pinv, fma(-ak[k], pinv, 1.0), pinv);
     if (c == k) {
 #pragma unroll
       for (int i = 0; i < m; ++i) col[i] = (i == k) ? pinv : -ak[i] * pinv;
@@ -899,7 +883,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
-  const Normal2 z = fit_increments<N>(p, s);
+  const Normal2 z = fit_increments(p, s);
   const int t = tid();
   const bool node = t < n;
   const int64_t noff = p.noff[e];
@@ -907,23 +891,16 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   const double* nsp = p.nsp + p.nsp_off[N];
   double* red = lds + L::oRed;
   double* D = lds + L::oD;
+  const Shift2 dsh = mean_shift(p, e, z);
+  const double dbx = dsh.x, dby = dsh.y;
   // component 0's jump data first: its loads overlap the moves
   r_jump_data<N, T>(p, e, s * p.ncomp, z.a, z.b, D, t);
-  // the moved nodes (eq. def_dx), one a thread, and their mean displacement
-  double xm = 0.0, ym = 0.0, dbx, dby;
-  {
-    double sx = 0.0, sy = 0.0;
-    if (node) {
-      const int64_t k = noff + t;
-      const double x0 = p.xi_node[2 * k], y0 = p.xi_node[2 * k + 1];
-      xm = moved_coord(x0, p.A[2 * k], p.B[2 * k], z.a);
-      ym = moved_coord(y0, p.A[2 * k + 1], p.B[2 * k + 1], z.b);
-      sx = xm - x0;
-      sy = ym - y0;
-    }
-    block_sum2<T>(sx, sy, red);
-    dbx = sx / n;
-    dby = sy / n;
+  // the moved nodes (eq. def_dx), one a thread
+  double xm = 0.0, ym = 0.0;
+  if (node) {
+    const int64_t k = noff + t;
+    xm = moved_coord(p.xi_node[2 * k], p.A[2 * k], p.B[2 * k], z.a);
+    ym = moved_coord(p.xi_node[2 * k + 1], p.A[2 * k + 1], p.B[2 * k + 1], z.b);
   }
   double* Xz = lds + L::oXz;
   double* Yz = lds + L::oYz;
@@ -1169,7 +1146,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     // new values at the Gauss nodes (eq. phi_star)
     if (nodel) p.phi[row * p.nodes + noff + tl] = p0v - (lnode + bub);
   }
-  count_fit(p, 2, its, unconv, 0, rmax);
+  count_fit(p, 2, its, unconv, rmax);
 }
 
 // Threads a fit of the per-order and batched kernels, by phase and order.

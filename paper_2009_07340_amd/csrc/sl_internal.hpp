@@ -128,6 +128,14 @@ struct Params2D {
   unsigned long long* stats;   // diagnostics slots (kStatSlots x kStatStride, layout above)
   int mass;                // 1: the fit also keeps the element integral of p0 (not on this path)
   const double* wq_tab;    // [(kMaxN+1)][kMaxN] quadrature weights of each order's nodes
+  // reference solver: this step's Wiener normals of each sample ([M][2], written
+  // by the draw kernel before phase 1), the element means of the move
+  // coefficients ([K][4]: mean A in x, in y, mean B in x, in y) and, per element
+  // and side (W, E, S, N), where the neighbour's facing trace starts in a state
+  // row: (order << 48) | edge offset, or -1 on a Dirichlet side
+  const double* zdraw;
+  const double* emean;
+  const int64_t* nbr_tr;
   LegendreRec rec;
 };
 
@@ -152,6 +160,19 @@ struct Fused2DArgs {
 };
 
 // Device step and work counters of up to kMaxTasks problems.
+// One step's Wiener normals of up to kMaxTasks 2-D problems (eq. def_dx: one
+// pair a sample and step): pair s of problem t goes to z[t][2s], z[t][2s+1].
+// The step is *step_ptr[t] when that is set (graph replay), else step[t].
+struct DrawArgs {
+  double* z[kMaxTasks];
+  const int64_t* step_ptr[kMaxTasks];
+  int64_t step[kMaxTasks];
+  int64_t M[kMaxTasks];
+  uint64_t seed[kMaxTasks];
+  uint32_t stream[kMaxTasks];
+  int n;
+};
+
 struct StepArgs {
   int64_t* step[kMaxTasks];
   unsigned long long* counter[kMaxTasks];   // two per problem (phase 1, phase 2)
@@ -206,6 +227,7 @@ size_t fit2d_lds_bytes(int N, int mode, int phase);
 hipError_t launch_fit2d_fused(int phase, int mode, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
 int fit2d_fused_occupancy(int phase, int mode, size_t lds);
 hipError_t launch_step_counters(const StepArgs& a, hipStream_t st);
+hipError_t launch_draw_normals(const DrawArgs& a, int64_t maxM, hipStream_t st);
 hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st);
 size_t fit2r_lds_bytes(int N, int phase);
 hipError_t launch_fit2r_fused(int phase, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
