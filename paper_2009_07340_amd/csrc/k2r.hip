@@ -637,16 +637,15 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
 // Gauss nodes are p0 - lift(j) - sum w beta beta.  The iteration stops when the
 // nodal size of its estimated error is below tol times that of p0 and lift(j).
 
-template <int N>
+// W: wavefronts a fit (the partial products take one m x m block each).
+template <int N, int W = 4>
 struct LayZ {
   static constexpr int n = N * N, m = N - 2, mm = m * m, TT = 4 * N;
   static constexpr int mA = m > 0 ? m : 1, mmA = mA * mA;
   static constexpr int ZS = n + 1;            // odd row stride of the bubble tables at the moved nodes
   static constexpr int oXz = 0;               // Xz[k][i] = beta_k(x_i)
   static constexpr int oYz = oXz + mA * ZS;   // Yz[l][i] = beta_l(y_i)
-  static constexpr int oZx = oYz + mA * ZS;   // Zx[a][k] = beta_k(xi_a), N x m
-  static constexpr int oZy = oZx + N * mA;
-  static constexpr int oGx = oZy + N * mA;    // (Bx^T Bx)^-1, m x m row-major
+  static constexpr int oGx = oYz + mA * ZS;   // (Bx^T Bx)^-1, m x m row-major
   static constexpr int oGy = oGx + mmA;
   static constexpr int oB = oGy + mmA;        // right side
   static constexpr int oW = oB + mmA;         // iterate
@@ -654,17 +653,20 @@ struct LayZ {
   static constexpr int oG = oR + mmA;         // preconditioned residual
   static constexpr int oP = oG + mmA;         // search direction
   static constexpr int oT = oP + mmA;         // Kronecker temporary
-  static constexpr int oPart = oT + mmA;      // four wavefronts' partial Vz^T products
-  static constexpr int oL = oPart + 4 * mmA;  // n values at the moved nodes
-  static constexpr int oXm = oL + n;          // the moved nodes' coordinates (x, then y)
-  static constexpr int oD = oXm + 2 * n;      // t - g at the own edge points
+  static constexpr int oPart = oT + mmA;      // the wavefronts' partial Vz^T products
+  static constexpr int oL = oPart + W * mmA;  // n values at the moved nodes
+  // the moved nodes' coordinates (x, then y) wait for the lift in the space of
+  // R, G, P and T where that holds them: the iteration starts after the lift
+  static constexpr bool kXmShared = 4 * mmA >= 2 * n;
+  static constexpr int oXm = kXmShared ? oR : oL + n;
+  static constexpr int oD = kXmShared ? oL + n : oXm + 2 * n;   // t - g at the own edge points
   static constexpr int oJ = oD + TT;          // the jump and its four corner values
   static constexpr int oMa = oJ + TT + 4;     // mass constraint: ax, ay, hx, hy (m each), a . h
   static constexpr int oRed = oMa + 4 * mA + 1;
   static constexpr int end = oRed + 16;
   static constexpr size_t bytes = sizeof(double) * end;
   // at most as many as the registers admit without spilling (by order)
-  template <int T> static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 10 ? 4 : 3, T);
+  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 9 ? 4 : 3, 64 * W);
   static constexpr int NQ = (n + 3) / 4;   // steps of 4 nodes
 };
 
@@ -876,10 +878,10 @@ __device__ __forceinline__ void z_pinv_w0(const double* Gx, const double* Gy, co
 // MC: the mass-constraint code compiled in (it then runs where p.mass is set).
 template <int N, int T, bool MC = true>
 __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, int64_t fit) {
-  using L = LayZ<N>;
+  constexpr int W = T / 64;
+  using L = LayZ<N, W>;
   constexpr int n = L::n, m = L::m, mm = L::mm, TT = L::TT, mmA = L::mmA;
   static_assert(n <= T, "one node a thread");
-  constexpr int W = T / 64;
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
@@ -904,35 +906,24 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   }
   double* Xz = lds + L::oXz;
   double* Yz = lds + L::oYz;
-  double* Zx = lds + L::oZx;
-  double* Zy = lds + L::oZy;
-  double* XYm = lds + L::oXm;   // the coordinates wait in LDS for every component's lift
+  double* XYm = lds + L::oXm;   // the coordinates wait in LDS for the first component's lift
   if (node) {
     XYm[t] = xm;
     XYm[n + t] = ym;
   }
   if constexpr (m > 0) {
-    // bubble tables at the moved nodes (item t < n) and at the Gauss nodes; the
-    // two Gram inverses by the last two wavefronts
-    for (int it = t; it < n + 2 * N; it += T) {
+    // bubble tables at the moved nodes, one a thread; the two Gram inverses by
+    // the last two wavefronts
+    if (node) {
       double q[m];
-      if (it < n) {
-        legendre_eval<m>(xm - dbx, p.rec, q);
-        const double sxm = xm * (1.0 - xm);
+      legendre_eval<m>(xm - dbx, p.rec, q);
+      const double sxm = xm * (1.0 - xm);
 #pragma unroll
-        for (int k = 0; k < m; ++k) Xz[k * L::ZS + it] = sxm * q[k];
-        legendre_eval<m>(ym - dby, p.rec, q);
-        const double sym = ym * (1.0 - ym);
+      for (int k = 0; k < m; ++k) Xz[k * L::ZS + t] = sxm * q[k];
+      legendre_eval<m>(ym - dby, p.rec, q);
+      const double sym = ym * (1.0 - ym);
 #pragma unroll
-        for (int k = 0; k < m; ++k) Yz[k * L::ZS + it] = sym * q[k];
-      } else {
-        const int u = it - n, dir = u >= N, a = u - dir * N;
-        legendre_eval<m>(xi[a] - (dir ? dby : dbx), p.rec, q);
-        const double sa = xi[a] * (1.0 - xi[a]);
-        double* dst = (dir ? Zy : Zx) + a * m;
-#pragma unroll
-        for (int k = 0; k < m; ++k) dst[k] = sa * q[k];
-      }
+      for (int k = 0; k < m; ++k) Yz[k * L::ZS + t] = sym * q[k];
     }
     if constexpr (W == 1) {
       z_gram_inverse<N>(nsp + nsp_vx(N), xi, dbx, lds + L::oGx);
@@ -973,7 +964,16 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     int tl = t;
     asm volatile("" : "+v"(tl));
     const bool nodel = tl < n;
-    if (c > 0) r_jump_data<N, T>(p, e, row, z.a, z.b, D, tl);
+    if (c > 0) {
+      r_jump_data<N, T>(p, e, row, z.a, z.b, D, tl);
+      if constexpr (L::kXmShared) {   // the iteration has overwritten them
+        if (nodel) {
+          const int64_t k = noff + tl;
+          XYm[tl] = moved_coord(p.xi_node[2 * k], p.A[2 * k], p.B[2 * k], z.a);
+          XYm[n + tl] = moved_coord(p.xi_node[2 * k + 1], p.A[2 * k + 1], p.B[2 * k + 1], z.b);
+        }
+      }
+    }
     block_sync();
     // j = P (t - g) and its corner values
     splitk<TT + 4, TT, T>([&](int o, int q) { return nsp[o * TT + q] * D[q]; }, J);
@@ -1005,12 +1005,21 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       // h = (Gx (x) Gy) a = hy (x) hx: v -= h (a . v) / (a . h)
       double* Ma = lds + L::oMa;
       if (MC && p.mass && c == 0 && w0) {
-        for (int q = lane(); q < 2 * m; q += 64) {
-          const int dir = q >= m, k = q - dir * m;
-          const double* Z = dir ? Zy : Zx;
-          double acc = 0.0;
-          for (int a = 0; a < N; ++a) acc += wq[a] * Z[a * m + k];
-          Ma[q] = acc;
+        // ax[k] = sum_a wq[a] beta_k(xi_a) (shifted by dbx; ay likewise by dby)
+        if (lane() < 2) {
+          const int dir = lane();
+          double acc[m];
+#pragma unroll
+          for (int k = 0; k < m; ++k) acc[k] = 0.0;
+          for (int a = 0; a < N; ++a) {
+            double q[m];
+            legendre_eval<m>(xi[a] - (dir ? dby : dbx), p.rec, q);
+            const double wa = wq[a] * (xi[a] * (1.0 - xi[a]));
+#pragma unroll
+            for (int k = 0; k < m; ++k) acc[k] += wa * q[k];
+          }
+#pragma unroll
+          for (int k = 0; k < m; ++k) Ma[dir * m + k] = acc[k];
         }
         wave_sync();
         for (int q = lane(); q < 2 * m; q += 64) {
@@ -1129,18 +1138,20 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
         if (w0) mass_project(Wv, cmass);
         block_sync();
       }
-      if (nodel) {
+      if (nodel) {   // the bubbles at the Gauss node (xi_ja, xi_jb)
         const int ja = tl % N, jb = tl / N;
-        double zr[m];
+        double zr[m], zc[m];
+        legendre_eval<m>(xi[ja] - dbx, p.rec, zr);
+        legendre_eval<m>(xi[jb] - dby, p.rec, zc);
+        double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < m; ++k) zr[k] = Zx[ja * m + k];
-#pragma unroll 1
         for (int l = 0; l < m; ++l) {
           double inner = 0.0;
 #pragma unroll
           for (int k = 0; k < m; ++k) inner += zr[k] * Wv[l * m + k];
-          bub += Zy[jb * m + l] * inner;
+          acc += zc[l] * inner;
         }
+        bub = ((xi[ja] * (1.0 - xi[ja])) * (xi[jb] * (1.0 - xi[jb]))) * acc;
       }
     }
     // new values at the Gauss nodes (eq. phi_star)
@@ -1162,7 +1173,7 @@ void fit2r_phase1(Params2D p) {
 }
 
 template <int N, bool MC>
-__global__ __launch_bounds__((kFitThreads<N, 2>)) __attribute__((amdgpu_waves_per_eu(LayZ<N>::template waves<kFitThreads<N, 2>>)))
+__global__ __launch_bounds__((kFitThreads<N, 2>)) __attribute__((amdgpu_waves_per_eu(LayZ<N, kFitThreads<N, 2> / 64>::waves)))
 void fit2r_phase2(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r2[];
   r_phase2_body<N, kFitThreads<N, 2>, MC>(p, lds_r2, blockIdx.x + p.block0);
@@ -1170,7 +1181,7 @@ void fit2r_phase2(Params2D p) {
 
 template <int N>
 static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStream_t st) {
-  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N>::bytes;
+  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N, kFitThreads<N, 2> / 64>::bytes;
   const int64_t chunk = (int64_t)1 << 30;
   for (int64_t b0 = 0; b0 < nfits; b0 += chunk) {
     Params2D q = p;
@@ -1213,7 +1224,7 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 // segments (problem, order group) of the argument table, all of order N.
 template <int N, int PHASE>
 __global__ __launch_bounds__((kFitThreads<N, PHASE>))
-__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::template waves1<kFitThreads<N, 1>> : LayZ<N>::template waves<kFitThreads<N, 2>>)))
+__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::template waves1<kFitThreads<N, 1>> : LayZ<N, kFitThreads<N, 2> / 64>::waves)))
 void fit2r_multi(Fused2DArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds_rm[];
   const int64_t item = blockIdx.x;
@@ -1227,7 +1238,7 @@ void fit2r_multi(Fused2DArgs a) {
 
 template <int N>
 static hipError_t multi_n(int phase, const Fused2DArgs& a, hipStream_t st) {
-  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N>::bytes;
+  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N, kFitThreads<N, 2> / 64>::bytes;
   if (a.total <= 0) return hipSuccess;
   if (phase == 1) hipLaunchKernelGGL((fit2r_multi<N, 1>), dim3((unsigned)a.total), dim3(kFitThreads<N, 1>), lds, st, a);
   else hipLaunchKernelGGL((fit2r_multi<N, 2>), dim3((unsigned)a.total), dim3(kFitThreads<N, 2>), lds, st, a);
