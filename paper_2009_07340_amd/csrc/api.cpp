@@ -889,6 +889,9 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   for (int N : L.order)
     if (!h->xi_tab.count(N)) h->xi_tab[N] = sl::gauss_nodes(N, h->family);
   h->rec = sl::legendre_recurrence();
+  for (int k = 0; k < sl::kMaxN; ++k)
+    if (h->rec.a[k] != sl::kLegA[k] || h->rec.b[k] != sl::kLegB[k])
+      return fail(SL_EUNSUPPORTED, "the host's Legendre recurrence differs from the compiled constants");
   if (const char* a = std::getenv("SL_1D_FIT")) h->algo_1d = std::strcmp(a, "normal") == 0 ? 1 : 0;
   if (dev_ws) {
     if (ws_bytes < L.total) return fail(SL_ENOMEM, "workspace smaller than sl_required_bytes");

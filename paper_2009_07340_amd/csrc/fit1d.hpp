@@ -37,6 +37,17 @@ __device__ __forceinline__ void legendre_eval(double t, const LegendreRec& rec, 
   for (int k = 1; k + 1 < N; ++k) psi[k + 1] = rec.a[k] * x * psi[k] - rec.b[k] * psi[k - 1];
 }
 
+// legendre_eval with the compile-time coefficients (the same values, the same
+// rounding).
+template <int N>
+__device__ __forceinline__ void legendre_eval_k(double t, double (&psi)[N]) {
+  const double x = 2.0 * t - 1.0;
+  psi[0] = 1.0;
+  if constexpr (N > 1) psi[1] = kLegA[0] * x;
+#pragma unroll
+  for (int k = 1; k + 1 < N; ++k) psi[k + 1] = kLegA[k] * x * psi[k] - kLegB[k] * psi[k - 1];
+}
+
 template <int N>
 struct Fit1DPre {
   double phiu[N];   // unconstrained values at the Gauss nodes, E c0

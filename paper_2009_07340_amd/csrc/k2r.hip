@@ -429,10 +429,10 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, Normal
       const double ym = moved_coord(y0, p.A[2 * k + 1], p.B[2 * k + 1], z.b);
       f[it] = p.phi[s * p.ncomp * p.nodes + k] * p.src[k];   // component 0 of sample s
       esc += escaped(xm) + escaped(ym);
-      legendre_eval<N>(xm - d.x, p.rec, q);
+      legendre_eval_k<N>(xm - d.x, q);
 #pragma unroll
       for (int j = 0; j < N; ++j) X1[j * L::XS + it] = q[j];
-      legendre_eval<N>(ym - d.y, p.rec, q);
+      legendre_eval_k<N>(ym - d.y, q);
 #pragma unroll
       for (int j = 0; j < N; ++j) Y1[j * L::XS + it] = q[j];
     } else {
@@ -447,7 +447,7 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, Normal
         arg = (w == 0) ? -d.x : (w == 1) ? 1.0 - d.x : (w == 2) ? -d.y : 1.0 - d.y;
         dst = Ev + w * N;
       }
-      legendre_eval<N>(arg, p.rec, q);
+      legendre_eval_k<N>(arg, q);
 #pragma unroll
       for (int j = 0; j < N; ++j) dst[j] = q[j];
     }
@@ -665,8 +665,10 @@ struct LayZ {
   static constexpr int oRed = oMa + 4 * mA + 1;
   static constexpr int end = oRed + 16;
   static constexpr size_t bytes = sizeof(double) * end;
-  // at most as many as the registers admit without spilling (by order)
-  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 9 ? 4 : 3, 64 * W);
+  // at most as many as the registers admit without spilling (by order; the
+  // general form, with the mass constraint and several components, holds more)
+  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 10 ? 4 : 3, 64 * W);
+  static constexpr int waves_general = LayR<N>::lds_waves(bytes, N <= 8 ? 4 : 3, 64 * W);
   static constexpr int NQ = (n + 3) / 4;   // steps of 4 nodes
 };
 
@@ -703,13 +705,19 @@ __device__ void z_VT_part(const double* Xz, const double* Yz, const double* r, d
   constexpr int n = L::n, m = L::m, ZS = L::ZS, KW = (L::NQ + T / 64 - 1) / (T / 64);   // steps a wavefront
   const int w = wave(), l = lane(), lr = l & 15, lk = l >> 4;
   const bool col = lr < m;
+  const int lrc = col ? lr : 0;
   M64::acc_t ac[2] = {zacc<double>(), zacc<double>()};
+  // every lane loads and the products take zeros outside the tables, so that
+  // the loads need no branches and can be issued ahead of the products: past
+  // the last node (at most 4 W + 3 places) the loads read the next row, or the
+  // arrays that follow Yz and r in the workgroup's LDS, and are discarded
 #pragma unroll
   for (int kq = 0; kq < KW; ++kq) {
     const int i = 4 * (w * KW + kq) + lk;
     const bool ok = col && i < n;
-    const double a = ok ? Yz[lr * ZS + i] : 0.0;          // A[l][i]
-    const double b = ok ? r[i] * Xz[lr * ZS + i] : 0.0;   // B[i][k]
+    const double ya = Yz[lrc * ZS + i], xb = Xz[lrc * ZS + i], rb = r[i];
+    const double a = ok ? ya : 0.0;         // A[l][i]
+    const double b = ok ? rb * xb : 0.0;    // B[i][k]
     ac[kq & 1] = M64::mma(a, b, ac[kq & 1]);
   }
   double d = 0.0;
@@ -737,26 +745,21 @@ __device__ void z_VT_part(const double* Xz, const double* Yz, const double* r, d
 // make s vanish, and N - 2 >= m rows remain) runs in registers, the pivot column
 // broadcast from its lane.  The inverse goes to out, row-major m x m.
 template <int N>
-__device__ void z_gram_inverse(const double* Vx, const double* xi, double d, double* out) {
+__device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* xi, double d, double* out) {
   constexpr int m = LayZ<N>::m;
   const int c = lane();
   double col[m];
 #pragma unroll
   for (int k = 0; k < m; ++k) col[k] = 0.0;
   if (c < m) {
-    double vc[N];
-#pragma unroll
+    // one node at a time, so that only one row of Vx is held
+#pragma unroll 1
     for (int a = 0; a < N; ++a) {
       const double xa = xi[a] + d;
       const double sa = xa * (1.0 - xa);
-      vc[a] = (sa * sa) * Vx[a * N + c];
-    }
+      const double va = (sa * sa) * Vx[a * N + c];
 #pragma unroll
-    for (int k = 0; k < m; ++k) {
-      double acc = 0.0;
-#pragma unroll
-      for (int a = 0; a < N; ++a) acc += Vx[a * N + k] * vc[a];
-      col[k] = acc;
+      for (int k = 0; k < m; ++k) col[k] += Vx[a * N + k] * va;
     }
   }
 #pragma unroll
@@ -875,7 +878,9 @@ __device__ __forceinline__ void z_pinv_w0(const double* Gx, const double* Gy, co
   }
 }
 
-// MC: the mass-constraint code compiled in (it then runs where p.mass is set).
+// MC: the general form, with the mass-constraint code (it runs where p.mass
+// is set) and any number of components; without it, one component and no
+// constraint, and fewer values held across the fit.
 template <int N, int T, bool MC = true>
 __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, int64_t fit) {
   constexpr int W = T / 64;
@@ -916,11 +921,11 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     // the last two wavefronts
     if (node) {
       double q[m];
-      legendre_eval<m>(xm - dbx, p.rec, q);
+      legendre_eval_k<m>(xm - dbx, q);
       const double sxm = xm * (1.0 - xm);
 #pragma unroll
       for (int k = 0; k < m; ++k) Xz[k * L::ZS + t] = sxm * q[k];
-      legendre_eval<m>(ym - dby, p.rec, q);
+      legendre_eval_k<m>(ym - dby, q);
       const double sym = ym * (1.0 - ym);
 #pragma unroll
       for (int k = 0; k < m; ++k) Yz[k * L::ZS + t] = sym * q[k];
@@ -956,8 +961,9 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   double rmax = 0.0;
   // the components share the moved nodes and every table above (Sec. 5.3,
   // last paragraph); each has its own p0, traces and boundary data
-  for (int c = 0; c < p.ncomp; ++c) {
-    const int64_t row = s * p.ncomp + c;
+  const int ncomp = MC ? p.ncomp : 1;
+  for (int c = 0; c < ncomp; ++c) {
+    const int64_t row = s * ncomp + c;
     // the thread index, opaque to the compiler here, so that the addresses
     // derived from it are formed again in each pass instead of held (spilled)
     // in registers across the loop
@@ -1013,7 +1019,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
           for (int k = 0; k < m; ++k) acc[k] = 0.0;
           for (int a = 0; a < N; ++a) {
             double q[m];
-            legendre_eval<m>(xi[a] - (dir ? dby : dbx), p.rec, q);
+            legendre_eval_k<m>(xi[a] - (dir ? dby : dbx), q);
             const double wa = wq[a] * (xi[a] * (1.0 - xi[a]));
 #pragma unroll
             for (int k = 0; k < m; ++k) acc[k] += wa * q[k];
@@ -1141,8 +1147,8 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       if (nodel) {   // the bubbles at the Gauss node (xi_ja, xi_jb)
         const int ja = tl % N, jb = tl / N;
         double zr[m], zc[m];
-        legendre_eval<m>(xi[ja] - dbx, p.rec, zr);
-        legendre_eval<m>(xi[jb] - dby, p.rec, zc);
+        legendre_eval_k<m>(xi[ja] - dbx, zr);
+        legendre_eval_k<m>(xi[jb] - dby, zc);
         double acc = 0.0;
 #pragma unroll
         for (int l = 0; l < m; ++l) {
@@ -1173,7 +1179,8 @@ void fit2r_phase1(Params2D p) {
 }
 
 template <int N, bool MC>
-__global__ __launch_bounds__((kFitThreads<N, 2>)) __attribute__((amdgpu_waves_per_eu(LayZ<N, kFitThreads<N, 2> / 64>::waves)))
+__global__ __launch_bounds__((kFitThreads<N, 2>))
+__attribute__((amdgpu_waves_per_eu(MC ? LayZ<N, kFitThreads<N, 2> / 64>::waves_general : LayZ<N, kFitThreads<N, 2> / 64>::waves)))
 void fit2r_phase2(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r2[];
   r_phase2_body<N, kFitThreads<N, 2>, MC>(p, lds_r2, blockIdx.x + p.block0);
@@ -1189,7 +1196,7 @@ static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStrea
     const int64_t nb = (nfits - b0) < chunk ? (nfits - b0) : chunk;
     if (phase == 1)
       hipLaunchKernelGGL((fit2r_phase1<N>), dim3((unsigned)nb), dim3(kFitThreads<N, 1>), lds, st, q);
-    else if (q.mass)
+    else if (q.mass || q.ncomp > 1)
       hipLaunchKernelGGL((fit2r_phase2<N, true>), dim3((unsigned)nb), dim3(kFitThreads<N, 2>), lds, st, q);
     else
       hipLaunchKernelGGL((fit2r_phase2<N, false>), dim3((unsigned)nb), dim3(kFitThreads<N, 2>), lds, st, q);
@@ -1224,7 +1231,7 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 // segments (problem, order group) of the argument table, all of order N.
 template <int N, int PHASE>
 __global__ __launch_bounds__((kFitThreads<N, PHASE>))
-__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::template waves1<kFitThreads<N, 1>> : LayZ<N, kFitThreads<N, 2> / 64>::waves)))
+__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::template waves1<kFitThreads<N, 1>> : LayZ<N, kFitThreads<N, 2> / 64>::waves_general)))
 void fit2r_multi(Fused2DArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds_rm[];
   const int64_t item = blockIdx.x;

@@ -46,6 +46,22 @@ struct LegendreRec {
   double b[kMaxN];
 };
 
+// The same coefficients as compile-time constants, rounded as the host forms
+// them (each square root, product and quotient rounded to nearest in turn);
+// handle creation checks that the two agree bit for bit.  Kernels that use
+// these hold no coefficient in registers: a constant is rematerialised where
+// it is needed.
+constexpr double kLegA[kMaxN] = {
+    0x1.bb67ae8584caap+0, 0x1.efbdeb14f4edap+0, 0x1.f8d6bc21a583cp+0, 0x1.fbfbf7ebc755fp+0,
+    0x1.fd6efe4c9b8a5p+0, 0x1.fe3818941c35bp+0, 0x1.feb1347fa3e26p+0, 0x1.feffbfdfebf1fp+0,
+    0x1.ff359273d543bp+0, 0x1.ff5c0eb678cbep+0, 0x1.ff78866842d89p+0, 0x1.ff8e2c3c65c25p+0,
+    0x1.ff9f0472ace9ep+0, 0x1.ffac61a95fbd2p+0, 0x1.ffb72977c57adp+0, 0x1.ffbffbff7fec0p+0};
+constexpr double kLegB[kMaxN] = {
+    0x0.0p+0,             0x1.1e3779b97f4a8p+0, 0x1.04b298812c5ccp+0, 0x1.019853f3bf5cap+0,
+    0x1.00bafa9e8fc3dp+0, 0x1.00650ed19a3c0p+0, 0x1.003cc41178a0fp+0, 0x1.00275f6f0badep+0,
+    0x1.001af6c8b98f3p+0, 0x1.001345bff6204p+0, 0x1.000e40691ddabp+0, 0x1.000ad5c8026d6p+0,
+    0x1.00086dfae5feep+0, 0x1.0006afdf9c67ap+0, 0x1.000564c8b46bap+0, 0x1.000469e49acd9p+0};
+
 // Tables of one order for the null-space form of the 2-D constrained remap
 // (reference-preconditioned solver), in doubles from the order's offset:
 //   [0, (4N+4) 4N)  rows 0..4N-1: P, the orthogonal projector onto the edge-value
