@@ -520,7 +520,11 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   if (c > 0) r_carried<N, T>(p, lds, e, row);
   // Richardson iteration on the square system V c = f, preconditioned by the
   // reference basis matrix: c = V0^-1 f, then c += V0^-1 (f - V c).  Its error
-  // contracts by about the non-uniform part of the displacement each step.
+  // contracts by about the non-uniform part of the displacement each step, so
+  // the error left after a correction dc is about rho |dc| / (1 - rho), rho the
+  // ratio of the last two corrections (of the first correction to c0 at the
+  // start): the iteration stops when that estimate, or the correction itself,
+  // is below tol |c0|.
   const double* vxi = lds + L::oVxi;
   const double* f = lds + L::oF;
   r_V0inv<N, T>(vxi, f, t1, x, false, red + 8);
@@ -539,6 +543,14 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
       break;
     }
     slow = d1 > 0.25 * gg;
+    if (!slow) {
+      const double q = d1 / gg, rq = sqrt(q);
+      const double e2 = (d1 * q) / ((1.0 - rq) * (1.0 - rq));   // the estimated error, squared
+      if (e2 <= stop) {
+        gg = e2;
+        break;
+      }
+    }
     gg = d1;
     if (slow) break;
   }
