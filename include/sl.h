@@ -183,6 +183,10 @@ typedef struct sl_diag_t {
                                  neither applies (1-D, float64 factorisation); NaN if a fit met one */
   int64_t nonfinite;          /* non-finite sample values met by the last sl_mean (0: all finite) */
   int32_t ncomp;              /* components of the field */
+  int64_t solver_fallbacks;   /* reference solver: unconstrained fits (per component) whose
+                                 fixed-point iteration contracted by less than half a step and
+                                 turned to preconditioned conjugate gradients, since the handle
+                                 was created */
 } sl_diag_t;
 
 /* Device bytes sl_init_mesh needs for this description (state, traces, fields,

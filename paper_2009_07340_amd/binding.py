@@ -41,7 +41,7 @@ class sl_diag_t(C.Structure):
                 ("max_disp_ratio", C.c_double), ("precision", C.c_int32), ("refine_iters", C.c_int32),
                 ("device_bytes", C.c_size_t), ("solver", C.c_int32), ("solver_iterations", C.c_int64 * 2),
                 ("solver_unconverged", C.c_int64 * 2), ("escapes", C.c_int64), ("max_residual", C.c_double),
-                ("nonfinite", C.c_int64), ("ncomp", C.c_int32)]
+                ("nonfinite", C.c_int64), ("ncomp", C.c_int32), ("solver_fallbacks", C.c_int64)]
 
 
 class sl_schedule_t(C.Structure):

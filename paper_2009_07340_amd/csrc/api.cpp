@@ -81,7 +81,7 @@ struct Layout {
   // byte offsets in the workspace
   size_t o_phi, o_phi2, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
-  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_nsp, o_sops, o_bw, o_wqtab, o_z, o_emean, o_nbrtr, total;
+  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_nsp, o_sops, o_bw, o_wqtab, o_z, o_emean, o_nbrtr, o_rlist, o_rcount, total;
   bool shared_capable = false;      // one order <= kMaxNShared in 2-D: the shared-geometry path can run
   int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
   size_t gx_doubles = 0, nsp_doubles = 0;
@@ -201,6 +201,10 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_z = take(L.dim == 2 ? sizeof(double) * 2 * (size_t)L.M : 0);
   L.o_emean = take(L.dim == 2 ? sizeof(double) * 4 * (size_t)L.K : 0);
   L.o_nbrtr = take(L.dim == 2 ? sizeof(int64_t) * 4 * (size_t)L.K : 0);
+  // phase-1 fits to redo (reference solver, one component): one slot a fit
+  const bool lean = L.dim == 2 && L.solver == SL_SOLVER_REFERENCE && L.nc == 1;
+  L.o_rlist = take(lean ? sizeof(uint32_t) * (size_t)L.K * (size_t)L.M : 0);
+  L.o_rcount = take(lean ? sizeof(unsigned int) * (sl::kMaxN + 1) : 0);
   L.total = o;
   return SL_OK;
 }
@@ -255,6 +259,8 @@ struct sl_ctx {
   double* d_z = nullptr;                 // [M][2] this step's Wiener normals (reference solver)
   double* d_emean = nullptr;             // [K][4] element means of the move coefficients
   int64_t* d_nbrtr = nullptr;            // [K][4] where each side's upwind neighbour trace starts
+  uint32_t* d_rlist = nullptr;           // phase-1 fits to redo, by order group (null: none)
+  unsigned int* d_rcount = nullptr;      // [kMaxN + 1] their counts, by order
   bool shared_geometry = false;          // the current step coefficients are the same at every node
   hipStream_t cap_stream = nullptr;      // private stream for graph capture
   // measurement
@@ -512,6 +518,7 @@ int enqueue_draw(const std::vector<sl_ctx*>& hs, bool devstep, int64_t ahead, hi
     for (int i = 0; i < a.n; ++i) {
       sl_ctx* h = ref[c0 + i];
       a.z[i] = h->d_z;
+      a.rescue_count[i] = h->d_rcount;
       a.step_ptr[i] = devstep ? h->d_step : nullptr;
       a.step[i] = h->step + ahead;
       a.M[i] = h->p2.M;
@@ -533,6 +540,9 @@ int enqueue_perorder(sl_ctx* h, int phase, bool devstep, int64_t step, hipStream
   for (const auto& g : h->groups) {
     p.work = h->d_work + g.second.first;
     p.block0 = 0;
+    // the group's slots of the phase-1 redo list
+    p.rescue_list = h->d_rlist ? h->d_rlist + g.second.first * h->p2.M : nullptr;
+    p.rescue_count = h->d_rcount ? h->d_rcount + g.first : nullptr;
     if (h->L.solver == SL_SOLVER_REFERENCE)
       SL_HIP(sl::launch_fit2r(phase, g.first, p, g.second.second * h->p2.M, st));
     else
@@ -939,6 +949,9 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_z = (double*)(h->ws + L.o_z);
   h->d_emean = (double*)(h->ws + L.o_emean);
   h->d_nbrtr = (int64_t*)(h->ws + L.o_nbrtr);
+  const bool lean = L.dim == 2 && L.solver == SL_SOLVER_REFERENCE && L.nc == 1;
+  h->d_rlist = lean ? (uint32_t*)(h->ws + L.o_rlist) : nullptr;
+  h->d_rcount = lean ? (unsigned int*)(h->ws + L.o_rcount) : nullptr;
   // element tables, work list grouped by order, node tables, U_r and trace interpolation
   std::vector<int32_t> nbr(4 * (size_t)L.K, -1), work;
   for (int e = 0; e < L.K; ++e) {
@@ -1533,6 +1546,7 @@ int sl_diag(sl_handle h, sl_diag_t* out) {
       out->solver_unconverged[ph] += (int64_t)c[2 * ph + 1];
     }
     out->escapes += (int64_t)c[sl::kStatEscapes];
+    out->solver_fallbacks += (int64_t)c[sl::kStatFallbacks];
     rmax = std::max(rmax, c[sl::kStatResidual]);
   }
   std::memcpy(&out->max_residual, &rmax, sizeof(double));

@@ -747,10 +747,12 @@ hipError_t launch_step_counters(const StepArgs& a, hipStream_t st) {
 
 // One step's normal pairs of a batch of problems, one sample a thread
 // (blockIdx.y: the problem), so that the fits of every element read their
-// sample's pair instead of drawing it again.
+// sample's pair instead of drawing it again; also clears each problem's
+// counters of phase-1 fits to redo.
 __global__ __launch_bounds__(256) void draw_normals_kernel(DrawArgs a) {
   const int t = blockIdx.y;
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < a.n && blockIdx.x == 0 && threadIdx.x <= kMaxN && a.rescue_count[t]) a.rescue_count[t][threadIdx.x] = 0u;
   if (t >= a.n || s >= a.M[t]) return;
   const int64_t step = a.step_ptr[t] ? *a.step_ptr[t] : a.step[t];
   const Normal2 d = normal_pair(a.seed[t], a.stream[t], (uint64_t)step, (uint64_t)s);

@@ -402,9 +402,9 @@ __device__ __forceinline__ Normal2 fit_increments(const Params2D& p, int64_t s) 
 // tables: item i < n moves node i and evaluates the basis there in x and in y;
 // the next 2N items the N Gauss abscissae of the edges in x and in y, the last
 // 4 the edge coordinates.  Moved nodes outside the element are counted in the
-// statistics.  One barrier.
+// statistics (unless the fit is being redone).  One barrier.
 template <int N, int T>
-__device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, Normal2 z) {
+__device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, Normal2 z, bool count = true) {
   using L = LayR<N>;
   constexpr int n = L::n;
   const int t = tid();
@@ -452,7 +452,7 @@ __device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, Normal
       for (int j = 0; j < N; ++j) dst[j] = q[j];
     }
   }
-  if (p.stats) {
+  if (p.stats && count) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) esc += __shfl_xor(esc, o, 64);
     if (lane() == 0 && esc) stat_add(p.stats, kStatEscapes, (unsigned long long)esc);
@@ -491,15 +491,36 @@ __device__ __forceinline__ double rel_resid(double gg, double xx) {
 
 // ---------------------------------------------------------------- phase 1
 
+// p0 = By C Bx^T at the Gauss nodes (C = c[ly][k]) into dst[i], i < n.
 template <int N, int T>
-__device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, int64_t fit) {
+__device__ __forceinline__ void r_p0_out(const double* Bx, const double* By, const double* c, double* dst) {
+  for (int i = tid(); i < N * N; i += T) {
+    const int ix = i % N, iy = i / N;
+    double bxr[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) bxr[k] = Bx[ix * N + k];
+    double v = 0.0;
+#pragma unroll 1
+    for (int ly = 0; ly < N; ++ly) {
+      double inner = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) inner += bxr[k] * c[ly * N + k];
+      v += By[iy * N + ly] * inner;
+    }
+    dst[i] = v;
+  }
+}
+
+// redo: the fit is one the lean kernel listed (its moved nodes were counted there).
+template <int N, int T>
+__device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, int64_t fit, bool redo = false) {
   using L = LayR<N>;
   constexpr int n = L::n;
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
   const int e = p.work[w];
   const Normal2 z = fit_increments(p, s);
-  r_setup<N, T>(p, lds, e, s, z);
+  r_setup<N, T>(p, lds, e, s, z, !redo);
   const int t = tid();
   const double* gxi = lds + L::oGxi;
   double* b = lds + L::oB;
@@ -558,6 +579,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   // conjugate gradients on G c = V^T f (preconditioner G0^-1) from the iterate
   if (slow) {
     its += it;
+    if (tid() == 0) stat_add(p.stats, kStatFallbacks, 1ull);
     r_VT_mc<N>(lds + L::oX1, lds + L::oY1, f, b);
     block_sync();
     r_G<N, T>(lds, x, t1, r);
@@ -591,25 +613,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
     }
   }
   // p0 at the Gauss nodes into the state row, where phase 2 starts from it
-  {
-    const double* Bx = lds + L::oBx;
-    const double* By = lds + L::oBy;
-    for (int i = t; i < n; i += T) {
-      const int ix = i % N, iy = i / N;
-      double bxr[N];
-#pragma unroll
-      for (int k = 0; k < N; ++k) bxr[k] = Bx[ix * N + k];
-      double v = 0.0;
-#pragma unroll 1
-      for (int ly = 0; ly < N; ++ly) {
-        double inner = 0.0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) inner += bxr[k] * x[ly * N + k];
-        v += By[iy * N + ly] * inner;
-      }
-      p.phi[row * p.nodes + noff + i] = v;
-    }
-  }
+  r_p0_out<N, T>(lds + L::oBx, lds + L::oBy, x, p.phi + row * p.nodes + noff);
   // traces of p0 at the own edge points (eq. remap_bnd)
   double* tv = lds + L::oTr;
   double* uc = lds + L::oUc;
@@ -623,6 +627,182 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   rmax = fmax(rmax, rel_resid(gg, xx));
   }
   count_fit(p, 1, its, unconv, rmax);
+}
+
+// ---------------------------------------------------------------- phase 1, lean form
+//
+// The same fit for one component without the basis tables at the moved nodes:
+// the residual evaluates the basis at each node as it goes, so a fit needs
+// about a third of the LDS of the full form and more fits share a compute
+// unit.  A fit whose iteration contracts too slowly (where the full form
+// turns to conjugate gradients) is listed, and the full form redoes it.
+
+template <int N>
+struct LayL {
+  static constexpr int n = N * N, TT = 4 * N;
+  static constexpr int oXY = 0;              // moved nodes, x then y
+  static constexpr int oBx = oXY + 2 * n;
+  static constexpr int oBy = oBx + N * N;
+  static constexpr int oEv = oBy + N * N;
+  static constexpr int oVxi = oEv + 4 * N;
+  static constexpr int oF = oVxi + N * N;
+  static constexpr int oXv = oF + n;
+  static constexpr int oR = oXv + n;
+  static constexpr int oT1 = oR + n;
+  static constexpr int oTr = oT1 + n;
+  static constexpr int oUc = oTr + TT;
+  static constexpr int oRed = oUc + TT;
+  static constexpr int end = oRed + 16;
+  static constexpr size_t bytes = sizeof(double) * end;
+  static constexpr int reg_cap = N <= 6 ? 8 : N <= 8 ? 6 : N <= 10 ? 5 : 4;
+  template <int T> static constexpr int waves = LayR<N>::lds_waves(bytes, reg_cap, T);
+};
+
+// Set-up of the lean form: moves, carried values, Vx^-1 and the tables at the
+// Gauss abscissae and edge coordinates.  One barrier.
+template <int N, int T>
+__device__ void r_setup_lean(const Params2D& p, double* lds, int e, int64_t s, Normal2 z, Shift2 d) {
+  using L = LayL<N>;
+  constexpr int n = L::n;
+  const int t = tid();
+  const int64_t noff = p.noff[e];
+  double* f = lds + L::oF;
+  double* XY = lds + L::oXY;
+  const double* vsrc = p.gxinv + p.gx_off[N] + N * N;
+  double* vxi = lds + L::oVxi;
+  for (int i = t; i < N * N; i += T) vxi[i] = vsrc[i];
+  int esc = 0;
+  for (int it = t; it < n + 2 * N + 4; it += T) {
+    if (it < n) {
+      const int64_t k = noff + it;
+      const double xm = moved_coord(p.xi_node[2 * k], p.A[2 * k], p.B[2 * k], z.a);
+      const double ym = moved_coord(p.xi_node[2 * k + 1], p.A[2 * k + 1], p.B[2 * k + 1], z.b);
+      XY[it] = xm;
+      XY[n + it] = ym;
+      f[it] = p.phi[s * p.nodes + k] * p.src[k];
+      esc += escaped(xm) + escaped(ym);
+    } else {
+      double arg;
+      double* dst;
+      if (it < n + 2 * N) {
+        const int u = it - n, dir = u >= N, row = u - dir * N;
+        arg = p.xi_tab[N * kMaxN + row] - (dir ? d.y : d.x);
+        dst = (dir ? lds + L::oBy : lds + L::oBx) + row * N;
+      } else {
+        const int w = it - n - 2 * N;
+        arg = (w == 0) ? -d.x : (w == 1) ? 1.0 - d.x : (w == 2) ? -d.y : 1.0 - d.y;
+        dst = lds + L::oEv + w * N;
+      }
+      double q[N];
+      legendre_eval_k<N>(arg, q);
+#pragma unroll
+      for (int j = 0; j < N; ++j) dst[j] = q[j];
+    }
+  }
+  if (p.stats) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) esc += __shfl_xor(esc, o, 64);
+    if (lane() == 0 && esc) stat_add(p.stats, kStatEscapes, (unsigned long long)esc);
+  }
+  block_sync();
+}
+
+// out[i] = f[i] - (V c)_i with the basis evaluated at the moved node i
+// (centred on d) as it goes.
+template <int N, int T>
+__device__ void r_resid_fly(const double* XY, Shift2 d, const double* c, const double* f, double* out) {
+  constexpr int n = N * N;
+  for (int i = tid(); i < n; i += T) {
+    double px[N];
+    legendre_eval_k<N>(XY[i] - d.x, px);
+    double v = 0.0;
+    if constexpr (N <= 10) {   // unrolled: the whole of C is read once
+      double py[N];
+      legendre_eval_k<N>(XY[n + i] - d.y, py);
+#pragma unroll
+      for (int ly = 0; ly < N; ++ly) {
+        double inner = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) inner += px[k] * c[ly * N + k];
+        v += py[ly] * inner;
+      }
+    } else {   // a row of C at a time, the y basis advanced by its recurrence
+      const double yv = 2.0 * (XY[n + i] - d.y) - 1.0;
+      double pm = 0.0, pc = 1.0;
+#pragma unroll 1
+      for (int ly = 0; ly < N; ++ly) {
+        double inner = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) inner += px[k] * c[ly * N + k];
+        v += pc * inner;
+        const double pn = kLegA[ly] * yv * pc - kLegB[ly] * pm;
+        pm = pc;
+        pc = pn;
+      }
+    }
+    out[i] = f[i] - v;
+  }
+}
+
+// One fit of one component: the Richardson iteration of the full form; a fit
+// that it does not settle is listed for the full form and writes nothing.
+template <int N, int T>
+__device__ __forceinline__ void r_phase1_lean(const Params2D& p, double* lds, int64_t fit) {
+  using L = LayL<N>;
+  const int64_t w = fit / p.M;
+  const int64_t s = fit - w * p.M;
+  const int e = p.work[w];
+  const Normal2 z = fit_increments(p, s);
+  const Shift2 d = mean_shift(p, e, z);
+  r_setup_lean<N, T>(p, lds, e, s, z, d);
+  const double* vxi = lds + L::oVxi;
+  const double* f = lds + L::oF;
+  double* x = lds + L::oXv;
+  double* r = lds + L::oR;
+  double* t1 = lds + L::oT1;
+  double* red = lds + L::oRed;
+  r_V0inv<N, T>(vxi, f, t1, x, false, red + 8);
+  const double xx = wsum<T>(red + 8);
+  const double stop = p.tol2 * xx;
+  double gg = xx;
+  bool slow = false;
+  int it;
+  for (it = 1; it <= p.max_iter; ++it) {
+    r_resid_fly<N, T>(lds + L::oXY, d, x, f, r);
+    block_sync();
+    r_V0inv<N, T>(vxi, r, t1, x, true, red + 8);
+    const double d1 = wsum<T>(red + 8);
+    if (d1 <= stop) {
+      gg = d1;
+      break;
+    }
+    slow = d1 > 0.25 * gg;
+    if (!slow) {
+      const double q = d1 / gg, rq = sqrt(q);
+      const double e2 = (d1 * q) / ((1.0 - rq) * (1.0 - rq));
+      if (e2 <= stop) {
+        gg = e2;
+        break;
+      }
+    }
+    gg = d1;
+    if (slow) break;
+  }
+  if (slow) {
+    if (tid() == 0) p.rescue_list[atomicAdd(p.rescue_count, 1u)] = (uint32_t)fit;
+    return;
+  }
+  const int64_t noff = p.noff[e];
+  const int64_t eoff = p.eoff[e];
+  r_p0_out<N, T>(lds + L::oBx, lds + L::oBy, x, p.phi + s * p.nodes + noff);
+  double* tv = lds + L::oTr;
+  double* uc = lds + L::oUc;
+  r_edge_contract<N, T>(lds + L::oEv, x, uc);
+  block_sync();
+  r_traces_from<N, T>(lds + L::oBx, lds + L::oBy, uc, tv);
+  block_sync();
+  for (int qq = tid(); qq < L::TT; qq += T) p.tr[s * p.edges + eoff + qq] = tv[qq];
+  count_fit(p, 1, it > p.max_iter ? p.max_iter : it, gg <= stop ? 0 : 1, rel_resid(gg, xx));
 }
 
 // ---------------------------------------------------------------- phase 2
@@ -1190,6 +1370,26 @@ void fit2r_phase1(Params2D p) {
   r_phase1_body<N, kFitThreads<N, 1>>(p, lds_r1, blockIdx.x + p.block0);
 }
 
+template <int N>
+__global__ __launch_bounds__((kFitThreads<N, 1>)) __attribute__((amdgpu_waves_per_eu(LayL<N>::template waves<kFitThreads<N, 1>>)))
+void fit2r_phase1_lean(Params2D p) {
+  extern __shared__ __attribute__((aligned(16))) double lds_l1[];
+  r_phase1_lean<N, kFitThreads<N, 1>>(p, lds_l1, blockIdx.x + p.block0);
+}
+
+// The listed fits of the lean kernel, redone by the full form: a persistent
+// grid that walks the list (usually empty).
+template <int N>
+__global__ __launch_bounds__((kFitThreads<N, 1>)) __attribute__((amdgpu_waves_per_eu(N >= 15 ? 1 : 2)))
+void fit2r_phase1_redo(Params2D p) {
+  extern __shared__ __attribute__((aligned(16))) double lds_d1[];
+  const unsigned int cnt = *p.rescue_count;
+  for (unsigned int j = blockIdx.x; j < cnt; j += gridDim.x) {
+    r_phase1_body<N, kFitThreads<N, 1>>(p, lds_d1, (int64_t)p.rescue_list[j], true);
+    __syncthreads();
+  }
+}
+
 template <int N, bool MC>
 __global__ __launch_bounds__((kFitThreads<N, 2>))
 __attribute__((amdgpu_waves_per_eu(MC ? LayZ<N, kFitThreads<N, 2> / 64>::waves_general : LayZ<N, kFitThreads<N, 2> / 64>::waves)))
@@ -1201,6 +1401,22 @@ void fit2r_phase2(Params2D p) {
 template <int N>
 static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStream_t st) {
   const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N, kFitThreads<N, 2> / 64>::bytes;
+  if (phase == 1 && p.rescue_list && p.ncomp == 1 && p.block0 + nfits <= (int64_t)0xffffffff) {
+    // lean form, then the full form over the fits it listed
+    if (nfits <= 0) return hipSuccess;
+    const int64_t chunk = (int64_t)1 << 30;
+    for (int64_t b0 = 0; b0 < nfits; b0 += chunk) {
+      Params2D q = p;
+      q.block0 = p.block0 + b0;
+      const int64_t nb = (nfits - b0) < chunk ? (nfits - b0) : chunk;
+      hipLaunchKernelGGL((fit2r_phase1_lean<N>), dim3((unsigned)nb), dim3(kFitThreads<N, 1>), LayL<N>::bytes, st, q);
+      hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+    }
+    const unsigned grid = (unsigned)(nfits < 2048 ? (nfits > 0 ? nfits : 1) : 2048);
+    hipLaunchKernelGGL((fit2r_phase1_redo<N>), dim3(grid), dim3(kFitThreads<N, 1>), lds, st, p);
+    return hipGetLastError();
+  }
   const int64_t chunk = (int64_t)1 << 30;
   for (int64_t b0 = 0; b0 < nfits; b0 += chunk) {
     Params2D q = p;

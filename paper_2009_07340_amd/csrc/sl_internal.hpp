@@ -14,10 +14,13 @@ namespace sl {
 //   [4] moved nodes that left their element's reference interval [0, 1]
 //   [5] largest relative solver residual left by a fit (bits of a non-negative
 //       double, so unsigned comparison orders them; NaN sorts above every value)
+//   [6] phase-1 fits (per component) whose fixed-point iteration turned to
+//       conjugate gradients
 constexpr int kStatSlots = 64;
 constexpr int kStatStride = 8;
 constexpr int kStatEscapes = 4;
 constexpr int kStatResidual = 5;
+constexpr int kStatFallbacks = 6;
 
 #if defined(__HIPCC__)
 __device__ __forceinline__ unsigned long long* stat_slot(unsigned long long* stats) {
@@ -152,6 +155,12 @@ struct Params2D {
   const double* zdraw;
   const double* emean;
   const int64_t* nbr_tr;
+  // reference solver, phase 1 of a per-order launch of one-component fits:
+  // fits whose fixed-point iteration contracts too slowly are listed here (by
+  // fit index within the launch's group) and redone by a second kernel that
+  // holds the full basis tables; null: every fit takes the full kernel
+  uint32_t* rescue_list;
+  unsigned int* rescue_count;
   LegendreRec rec;
 };
 
@@ -181,6 +190,7 @@ struct Fused2DArgs {
 // The step is *step_ptr[t] when that is set (graph replay), else step[t].
 struct DrawArgs {
   double* z[kMaxTasks];
+  unsigned int* rescue_count[kMaxTasks];   // kMaxN + 1 counters each, cleared (or null)
   const int64_t* step_ptr[kMaxTasks];
   int64_t step[kMaxTasks];
   int64_t M[kMaxTasks];

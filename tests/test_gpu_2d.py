@@ -80,6 +80,38 @@ def test_small_periodic_parity_every_order(B, N, solver):
     assert err < TOL, (N, solver, err)
 
 
+def test_slowly_contracting_fits_are_redone_by_the_full_form(B):
+    """A rotation step long enough that many element fits' fixed-point
+    iteration contracts by less than half a step: the per-order kernels list
+    those fits and the full form (with conjugate gradients) redoes them.  The
+    result matches the oracle, every fit converges, the fallbacks are counted,
+    and the batched launch (the full form for every fit) agrees to rounding.
+    Orders 4 and 6 on one mesh, so that two order groups keep their own lists."""
+    wl = W.c4_2d_rotation(kx=3, ky=3, samples=6, steps=1)
+    wl.order = np.where(np.arange(wl.K) % 2 == 0, 6, 4).astype(np.int32)
+    wl.dt = 0.01
+    mesh, f, phi0, a = oracle_inputs(wl)
+    hs = [_handle(B, wl, a, solver="reference") for _ in range(3)]
+    try:
+        B.sl_step(hs[0], wl.dt, 1)
+        B.sl_step_batch(hs[1:], [wl.dt, wl.dt], 1)
+        got = B.sl_get_samples(hs[0], 0, wl.samples)
+        batch = B.sl_get_samples(hs[1], 0, wl.samples)
+        d = B.sl_diag(hs[0])
+        db = B.sl_diag(hs[1])
+    finally:
+        for h in hs:
+            B.sl_destroy(h)
+    ref = sl.run(mesh, f, phi0, wl.dt, 1, wl.seed, np.arange(4))
+    err = rel_l2(got[:4], ref)
+    print(f"fallbacks {d['solver_fallbacks']} (batched {db['solver_fallbacks']}), iterations {d['solver_iterations']}, "
+          f"unconverged {d['solver_unconverged']}, rel L2 {err:.3e}, vs batched {rel_l2(got, batch):.3e}", flush=True)
+    assert d["solver_fallbacks"] > 0 and d["solver_fallbacks"] == db["solver_fallbacks"]
+    assert d["solver_unconverged"] == [0, 0]
+    assert err < TOL
+    assert rel_l2(got, batch) < 1e-13
+
+
 @pytest.mark.parametrize("solver", ["factor", "reference"])
 def test_rectangular_mesh_and_rotation(B, solver):
     wl = _small(6, kx=4, ky=2, samples=4, rot=True)
