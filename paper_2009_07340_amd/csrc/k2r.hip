@@ -931,21 +931,27 @@ __device__ void z_VT_part(const double* Xz, const double* Yz, const double* r, d
 
 // Inverse of the 1-D preconditioner block Bz^T Bz, Bz[a][k] = s(xi_a + d) psi_k(xi_a)
 // with s(x) = x (1 - x) (the bubble table at the Gauss nodes shifted by d, in the
-// basis centred on d).  Called by a whole wavefront (uniform control flow): lane
-// c < m forms column c of the Gram matrix, then Gauss-Jordan elimination without
-// pivoting (the matrix is symmetric positive definite: at most two shifted nodes
-// make s vanish, and N - 2 >= m rows remain) runs in registers, the pivot column
-// broadcast from its lane.  The inverse goes to out, row-major m x m.
-template <int N>
-__device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* xi, double d, double* out) {
+// basis centred on d); Vx: psi_k(xi_a) at [a N + k] (in LDS).  Called by a whole
+// wavefront (uniform control flow): lane c < m forms column c of the Gram
+// matrix, then Gauss-Jordan elimination without pivoting (the matrix is
+// symmetric positive definite: at most two shifted nodes make s vanish, and
+// N - 2 >= m rows remain) runs in registers, the pivot column broadcast from its
+// lane.  The inverse goes to out0, row-major m x m.  TWO: the upper half of the
+// wavefront (lanes 32 + c) forms the block at d1 into out1 at the same time.
+template <int N, bool TWO = false>
+__device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* xi, double d0, double* out0,
+                                               double d1 = 0.0, double* out1 = nullptr) {
   constexpr int m = LayZ<N>::m;
-  const int c = lane();
+  static_assert(!TWO || m <= 32, "two blocks a wavefront");
+  const int h = TWO ? lane() >> 5 : 0;
+  const int c = TWO ? lane() & 31 : lane();
+  const double d = h ? d1 : d0;
   double col[m];
 #pragma unroll
   for (int k = 0; k < m; ++k) col[k] = 0.0;
   if (c < m) {
-    // one node at a time, so that only one row of Vx is held
-#pragma unroll 1
+    // two nodes at a time, so that only two rows of Vx are held
+#pragma unroll 2
     for (int a = 0; a < N; ++a) {
       const double xa = xi[a] + d;
       const double sa = xa * (1.0 - xa);
@@ -958,7 +964,7 @@ __device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* x
   for (int k = 0; k < m; ++k) {
     double ak[m];
 #pragma unroll
-    for (int i = 0; i < m; ++i) ak[i] = bcast(col[i], k);
+    for (int i = 0; i < m; ++i) ak[i] = TWO ? (h ? bcast(col[i], 32 + k) : bcast(col[i], k)) : bcast(col[i], k);
     // the hardware reciprocal and two Newton steps: the inverse only
     // preconditions, so the last bit of the pivot's reciprocal does not matter
     double pinv = __builtin_amdgcn_rcp(ak[k]);
@@ -974,6 +980,7 @@ __device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* x
     }
   }
   if (c < m) {
+    double* out = h ? out1 : out0;
 #pragma unroll
     for (int i = 0; i < m; ++i) out[i * m + c] = col[i];
   }
@@ -1094,6 +1101,10 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   const double dbx = dsh.x, dby = dsh.y;
   // component 0's jump data first: its loads overlap the moves
   r_jump_data<N, T>(p, e, s * p.ncomp, z.a, z.b, D, t);
+  // psi_k(xi_a) for the Gram inverses, in the space of the lift values (free
+  // until the lift)
+  if constexpr (m > 0)
+    for (int i = t; i < N * N; i += T) lds[L::oL + i] = nsp[nsp_vx(N) + i];
   // the moved nodes (eq. def_dx), one a thread
   double xm = 0.0, ym = 0.0;
   if (node) {
@@ -1122,12 +1133,12 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
 #pragma unroll
       for (int k = 0; k < m; ++k) Yz[k * L::ZS + t] = sym * q[k];
     }
-    if constexpr (W == 1) {
-      z_gram_inverse<N>(nsp + nsp_vx(N), xi, dbx, lds + L::oGx);
-      z_gram_inverse<N>(nsp + nsp_vx(N), xi, dby, lds + L::oGy);
+    block_sync();
+    if constexpr (W == 1) {   // both blocks at once, one a half-wavefront
+      z_gram_inverse<N, true>(lds + L::oL, xi, dbx, lds + L::oGx, dby, lds + L::oGy);
     } else {
       const int wg = wave() - (W - 2);   // the last two wavefronts
-      if (wg >= 0) z_gram_inverse<N>(nsp + nsp_vx(N), xi, wg ? dby : dbx, lds + (wg ? L::oGy : L::oGx));
+      if (wg >= 0) z_gram_inverse<N>(lds + L::oL, xi, wg ? dby : dbx, lds + (wg ? L::oGy : L::oGx));
     }
   }
   const double zz = nsp[nsp_zz(N)];
