@@ -861,6 +861,7 @@ struct LayZ {
   // general form, with the mass constraint and several components, holds more)
   static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 10 ? 4 : 3, 64 * W);
   static constexpr int waves_general = LayR<N>::lds_waves(bytes, N <= 8 ? 4 : 3, 64 * W);
+  static constexpr int waves_multi = LayR<N>::lds_waves(bytes, N <= 6 ? 4 : 3, 64 * W);   // batched launches
   static constexpr int NQ = (n + 3) / 4;   // steps of 4 nodes
 };
 
@@ -983,6 +984,55 @@ __device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* x
     double* out = h ? out1 : out0;
 #pragma unroll
     for (int i = 0; i < m; ++i) out[i * m + c] = col[i];
+  }
+}
+
+// j = P d (d: the 4N edge data t - g, edges W, E, S, N) and the corner values
+// of j (SW, NW, SE, NE) into J[0..4N+4), by one wavefront.  P projects onto the
+// edge values of Q_{N-1}: the vectors whose edges' polynomials agree at the
+// four corners, the null space of C^T with C's columns the corner
+// differences; P = I - C (C^T C)^-1 C^T.  C^T d takes the eight end values
+// l_s . d_e (lanes 0..7), then lambda = (C^T C)^-1 C^T d, j = d - C lambda, and
+// a corner value is the mean of its two edges' end values (equal after the
+// projection).  No barrier.
+template <int N>
+__device__ void z_project(const double* tab, const double* D, double* J) {
+  const double* l0 = tab + nsp_ends(N);
+  const double* l1 = l0 + N;
+  const double* Ci = tab + nsp_cinv(N);
+  const double* Ls = tab + nsp_ll(N);
+  const int l = lane();
+  double a = 0.0;
+  if (l < 8) {   // end value s = l & 1 of edge e = l >> 1
+    const double* ls = (l & 1) ? l1 : l0;
+    const double* de = D + (l >> 1) * N;
+#pragma unroll
+    for (int k = 0; k < N; ++k) a += ls[k] * de[k];
+  }
+  const double aW0 = bcast(a, 0), aW1 = bcast(a, 1), aE0 = bcast(a, 2), aE1 = bcast(a, 3);
+  const double aS0 = bcast(a, 4), aS1 = bcast(a, 5), aN0 = bcast(a, 6), aN1 = bcast(a, 7);
+  const double y[4] = {aW0 - aS0, aW1 - aN0, aE0 - aS1, aE1 - aN1};   // C^T d
+  double lam[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) lam[i] = ((Ci[4 * i] * y[0] + Ci[4 * i + 1] * y[1]) + Ci[4 * i + 2] * y[2]) + Ci[4 * i + 3] * y[3];
+  const double sw = lam[0], nw = lam[1], se = lam[2], ne = lam[3];
+  for (int q = l; q < 4 * N; q += 64) {
+    const int e = q / N, k = q % N;
+    double c;   // (C lambda)_q
+    if (e == 0) c = l0[k] * sw + l1[k] * nw;
+    else if (e == 1) c = l0[k] * se + l1[k] * ne;
+    else if (e == 2) c = -(l0[k] * sw + l1[k] * se);
+    else c = -(l0[k] * nw + l1[k] * ne);
+    J[q] = D[q] - c;
+  }
+  if (l < 4) {   // the corner values from the end values of j
+    const double L00 = Ls[0], L01 = Ls[1], L11 = Ls[2];
+    double v;
+    if (l == 0) v = (aW0 - (L00 * sw + L01 * nw)) + (aS0 + (L00 * sw + L01 * se));
+    else if (l == 1) v = (aW1 - (L01 * sw + L11 * nw)) + (aN0 + (L00 * nw + L01 * ne));
+    else if (l == 2) v = (aE0 - (L00 * se + L01 * ne)) + (aS1 + (L01 * sw + L11 * se));
+    else v = (aE1 - (L01 * se + L11 * ne)) + (aN1 + (L01 * nw + L11 * ne));
+    J[4 * N + l] = 0.5 * v;
   }
 }
 
@@ -1185,7 +1235,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     }
     block_sync();
     // j = P (t - g) and its corner values
-    splitk<TT + 4, TT, T>([&](int o, int q) { return nsp[o * TT + q] * D[q]; }, J);
+    if (wave() == 0) z_project<N>(nsp, D, J);
     block_sync();
     double p0v = 0.0, lnode = 0.0, sc = 0.0, mc = 0.0;
     if (nodel) {
@@ -1470,7 +1520,7 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 // segments (problem, order group) of the argument table, all of order N.
 template <int N, int PHASE>
 __global__ __launch_bounds__((kFitThreads<N, PHASE>))
-__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::template waves1<kFitThreads<N, 1>> : LayZ<N, kFitThreads<N, 2> / 64>::waves_general)))
+__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::template waves1<kFitThreads<N, 1>> : LayZ<N, kFitThreads<N, 2> / 64>::waves_multi)))
 void fit2r_multi(Fused2DArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds_rm[];
   const int64_t item = blockIdx.x;

@@ -67,19 +67,26 @@ constexpr double kLegB[kMaxN] = {
 
 // Tables of one order for the null-space form of the 2-D constrained remap
 // (reference-preconditioned solver), in doubles from the order's offset:
-//   [0, (4N+4) 4N)  rows 0..4N-1: P, the orthogonal projector onto the edge-value
-//                   vectors of Q_{N-1} (row-major, edges W, E, S, N); rows 4N..4N+3:
-//                   the corner values (SW, NW, SE, NE) of the projected vector, each
-//                   the mean of its two edges' extrapolations;
-//   then N          barycentric weights 1 / prod_{b != a} (xi_a - xi_b);
+//   [0, N)          barycentric weights 1 / prod_{b != a} (xi_a - xi_b);
 //   then N x N      psi_k(xi_a) at [a N + k] (orthonormal shifted Legendre);
 //   then 1          the squared mean nodal value of the bubble functions,
 //                   ((1/m) sum_{a, k < m} (xi_a (1 - xi_a) psi_k(xi_a))^2)^2, m = N - 2
-//                   (the scale of the remap's stopping test).
-constexpr int nsp_bary(int N) { return (4 * N + 4) * 4 * N; }
-constexpr int nsp_vx(int N) { return nsp_bary(N) + N; }
+//                   (the scale of the remap's stopping test);
+//   then N, N       l0, l1: the Lagrange weights of the Gauss abscissae at 0 and at 1
+//                   (the value at an edge's ends of the polynomial through its data);
+//   then 4 x 4      (C^T C)^-1, C the four corner-consistency rows over the edge
+//                   points (SW: l0 on W minus l0 on S; NW: l1 on W minus l0 on N;
+//                   SE: l0 on E minus l1 on S; NE: l1 on E minus l1 on N), whose null
+//                   space is the edge values of Q_{N-1}: the orthogonal projector onto
+//                   them is I - C (C^T C)^-1 C^T;
+//   then 3          l0.l0, l0.l1, l1.l1.
+constexpr int nsp_bary(int N) { return 0; }
+constexpr int nsp_vx(int N) { return N; }
 constexpr int nsp_zz(int N) { return nsp_vx(N) + N * N; }
-constexpr int nsp_doubles(int N) { return nsp_zz(N) + 1; }
+constexpr int nsp_ends(int N) { return nsp_zz(N) + 1; }
+constexpr int nsp_cinv(int N) { return nsp_ends(N) + 2 * N; }
+constexpr int nsp_ll(int N) { return nsp_cinv(N) + 16; }
+constexpr int nsp_doubles(int N) { return nsp_ll(N) + 3; }
 
 // Step inputs of one handle for the 1-D resident kernel.
 struct Params1D {

@@ -272,33 +272,31 @@ std::vector<double> reference_inverses(const std::vector<double>& xi) {
 }
 
 std::vector<double> nullspace_tables(int N, const std::vector<double>& xi) {
-  const int T = 4 * N, R = T - 4;
-  const auto U = edge_range_basis(N, xi);
-  std::vector<long double> P((size_t)T * T, 0.0L);
-  for (int q = 0; q < T; ++q)
-    for (int q2 = 0; q2 < T; ++q2) {
-      long double acc = 0.0L;
-      for (int c = 0; c < R; ++c) acc += (long double)U[(size_t)c * T + q] * (long double)U[(size_t)c * T + q2];
-      P[(size_t)q * T + q2] = acc;
-    }
   std::vector<double> l0(N), l1(N);
   lagrange_row(xi, 0.0, l0.data());
   lagrange_row(xi, 1.0, l1.data());
   std::vector<double> out(nsp_doubles(N), 0.0);
-  for (size_t i = 0; i < (size_t)T * T; ++i) out[i] = (double)P[i];
-  // corner rows: SW = (W at eta=0 + S at xi=0) / 2, NW = (W at eta=1 + N at xi=0) / 2,
-  // SE = (E at eta=0 + S at xi=1) / 2, NE = (E at eta=1 + N at xi=1) / 2
-  const int ew[4] = {0, 0, 1, 1}, ns[4] = {2, 3, 2, 3};
-  const std::vector<double>* lw[4] = {&l0, &l1, &l0, &l1};
-  const std::vector<double>* ln[4] = {&l0, &l0, &l1, &l1};
-  for (int c = 0; c < 4; ++c)
-    for (int q2 = 0; q2 < T; ++q2) {
-      long double acc = 0.0L;
-      for (int a = 0; a < N; ++a)
-        acc += (long double)(*lw[c])[a] * P[(size_t)(ew[c] * N + a) * T + q2] +
-               (long double)(*ln[c])[a] * P[(size_t)(ns[c] * N + a) * T + q2];
-      out[(size_t)(T + c) * T + q2] = (double)(0.5L * acc);
-    }
+  for (int a = 0; a < N; ++a) {
+    out[nsp_ends(N) + a] = l0[a];
+    out[nsp_ends(N) + N + a] = l1[a];
+  }
+  // C^T C for the corner rows (SW, NW, SE, NE): each row has l_s on one edge and
+  // -l_s' on the other, and two rows share an edge only through one end weight
+  long double L00 = 0.0L, L01 = 0.0L, L11 = 0.0L;
+  for (int a = 0; a < N; ++a) {
+    L00 += (long double)l0[a] * l0[a];
+    L01 += (long double)l0[a] * l1[a];
+    L11 += (long double)l1[a] * l1[a];
+  }
+  const std::vector<long double> CtC = {2 * L00, L01,       L01,       0.0L,   //
+                                        L01,     L00 + L11, 0.0L,      L01,    //
+                                        L01,     0.0L,      L00 + L11, L01,    //
+                                        0.0L,    L01,       L01,       2 * L11};
+  const auto Ci = gj_inverse(CtC, 4);
+  for (int i = 0; i < 16; ++i) out[nsp_cinv(N) + i] = (double)Ci[i];
+  out[nsp_ll(N)] = (double)L00;
+  out[nsp_ll(N) + 1] = (double)L01;
+  out[nsp_ll(N) + 2] = (double)L11;
   const auto bw = barycentric_weights(xi);
   for (int a = 0; a < N; ++a) out[nsp_bary(N) + a] = bw[a];
   for (int a = 0; a < N; ++a) {
