@@ -654,7 +654,7 @@ struct LayL {
   static constexpr int oRed = oUc + TT;
   static constexpr int end = oRed + 16;
   static constexpr size_t bytes = sizeof(double) * end;
-  static constexpr int reg_cap = N <= 6 ? 8 : N <= 8 ? 6 : N <= 10 ? 5 : 4;
+  static constexpr int reg_cap = N <= 6 ? 8 : N <= 10 ? 6 : 4;
   template <int T> static constexpr int waves = LayR<N>::lds_waves(bytes, reg_cap, T);
 };
 
