@@ -448,6 +448,9 @@ void build_params(sl_ctx* h) {
     p.mass = L.mass ? 1 : 0;
     p.wq_tab = h->d_wqtab;
     p.zdraw = h->d_z;
+    p.rescue_list = h->d_rlist;
+    p.rescue_count = h->d_rcount;
+    for (const auto& g : h->groups) p.rescue_off[g.first] = g.second.first * p.M;
     p.emean = h->d_emean;
     p.nbr_tr = h->d_nbrtr;
   } else {
@@ -631,7 +634,9 @@ int enqueue_multi(const std::vector<sl_ctx*>& hs, int phase, hipStream_t st) {
       a.nseg = (int)nc;
       a.total = start;
       if (start > 0x7fffffff) return fail(SL_EUNSUPPORTED, "too many fits of one order in one batch");
-      SL_HIP(sl::launch_fit2r_multi(phase, N, a, st));
+      bool fast = true;
+      for (size_t i = 0; i < nc; ++i) fast = fast && segs[c0 + i].first->d_rlist && !segs[c0 + i].first->L.mass;
+      SL_HIP(sl::launch_fit2r_multi(phase, N, a, fast, st));
     }
   }
   return SL_OK;

@@ -745,9 +745,11 @@ __device__ void r_resid_fly(const double* XY, Shift2 d, const double* c, const d
 }
 
 // One fit of one component: the Richardson iteration of the full form; a fit
-// that it does not settle is listed for the full form and writes nothing.
+// that it does not settle is listed (list[atomicAdd(count)]) for the full form
+// and writes nothing.
 template <int N, int T>
-__device__ __forceinline__ void r_phase1_lean(const Params2D& p, double* lds, int64_t fit) {
+__device__ __forceinline__ void r_phase1_lean(const Params2D& p, double* lds, int64_t fit, uint32_t* list,
+                                              unsigned int* count) {
   using L = LayL<N>;
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
@@ -789,7 +791,7 @@ __device__ __forceinline__ void r_phase1_lean(const Params2D& p, double* lds, in
     if (slow) break;
   }
   if (slow) {
-    if (tid() == 0) p.rescue_list[atomicAdd(p.rescue_count, 1u)] = (uint32_t)fit;
+    if (tid() == 0) list[atomicAdd(count, 1u)] = (uint32_t)fit;
     return;
   }
   const int64_t noff = p.noff[e];
@@ -1435,7 +1437,7 @@ template <int N>
 __global__ __launch_bounds__((kFitThreads<N, 1>)) __attribute__((amdgpu_waves_per_eu(LayL<N>::template waves<kFitThreads<N, 1>>)))
 void fit2r_phase1_lean(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_l1[];
-  r_phase1_lean<N, kFitThreads<N, 1>>(p, lds_l1, blockIdx.x + p.block0);
+  r_phase1_lean<N, kFitThreads<N, 1>>(p, lds_l1, blockIdx.x + p.block0, p.rescue_list, p.rescue_count);
 }
 
 // The listed fits of the lean kernel, redone by the full form: a persistent
@@ -1518,9 +1520,13 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 
 // One order of several problems in one launch: one workgroup per fit of the
 // segments (problem, order group) of the argument table, all of order N.
-template <int N, int PHASE>
+// FAST: every problem has one component and no mass constraint (phase 1 the
+// lean form, listing slow fits in each problem's own list; phase 2 without
+// the general form).
+template <int N, int PHASE, bool FAST>
 __global__ __launch_bounds__((kFitThreads<N, PHASE>))
-__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? LayR<N>::template waves1<kFitThreads<N, 1>> : LayZ<N, kFitThreads<N, 2> / 64>::waves_multi)))
+__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? (FAST ? LayL<N>::template waves<kFitThreads<N, 1>> : LayR<N>::template waves1<kFitThreads<N, 1>>)
+                                              : (FAST ? LayZ<N, kFitThreads<N, 2> / 64>::waves : LayZ<N, kFitThreads<N, 2> / 64>::waves_multi))))
 void fit2r_multi(Fused2DArgs a) {
   extern __shared__ __attribute__((aligned(16))) double lds_rm[];
   const int64_t item = blockIdx.x;
@@ -1528,36 +1534,64 @@ void fit2r_multi(Fused2DArgs a) {
   while (sg + 1 < a.nseg && item >= a.seg[sg + 1].start) ++sg;
   const Params2D& p = *a.task[a.seg[sg].task];
   const int64_t fit = a.seg[sg].fit0 + (item - a.seg[sg].start);
-  if constexpr (PHASE == 1) r_phase1_body<N, kFitThreads<N, 1>>(p, lds_rm, fit);
-  else r_phase2_body<N, kFitThreads<N, 2>>(p, lds_rm, fit);
+  if constexpr (PHASE == 1 && FAST) r_phase1_lean<N, kFitThreads<N, 1>>(p, lds_rm, fit, p.rescue_list + p.rescue_off[N], p.rescue_count + N);
+  else if constexpr (PHASE == 1) r_phase1_body<N, kFitThreads<N, 1>>(p, lds_rm, fit);
+  else r_phase2_body<N, kFitThreads<N, 2>, !FAST>(p, lds_rm, fit);
+}
+
+// The fits that the lean batched kernel listed, problem by problem, redone by
+// the full form (a persistent grid; the lists are usually empty).
+template <int N>
+__global__ __launch_bounds__((kFitThreads<N, 1>)) __attribute__((amdgpu_waves_per_eu(N >= 15 ? 1 : 2)))
+void fit2r_multi_redo(Fused2DArgs a) {
+  extern __shared__ __attribute__((aligned(16))) double lds_rr[];
+  for (int sg = 0; sg < a.nseg; ++sg) {
+    const Params2D& p = *a.task[a.seg[sg].task];
+    const unsigned int cnt = p.rescue_count[N];
+    const uint32_t* list = p.rescue_list + p.rescue_off[N];
+    for (unsigned int j = blockIdx.x; j < cnt; j += gridDim.x) {
+      r_phase1_body<N, kFitThreads<N, 1>>(p, lds_rr, (int64_t)list[j], true);
+      __syncthreads();
+    }
+  }
 }
 
 template <int N>
-static hipError_t multi_n(int phase, const Fused2DArgs& a, hipStream_t st) {
-  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N, kFitThreads<N, 2> / 64>::bytes;
+static hipError_t multi_n(int phase, const Fused2DArgs& a, bool fast, hipStream_t st) {
   if (a.total <= 0) return hipSuccess;
-  if (phase == 1) hipLaunchKernelGGL((fit2r_multi<N, 1>), dim3((unsigned)a.total), dim3(kFitThreads<N, 1>), lds, st, a);
-  else hipLaunchKernelGGL((fit2r_multi<N, 2>), dim3((unsigned)a.total), dim3(kFitThreads<N, 2>), lds, st, a);
+  if (phase == 1 && fast) {
+    hipLaunchKernelGGL((fit2r_multi<N, 1, true>), dim3((unsigned)a.total), dim3(kFitThreads<N, 1>), LayL<N>::bytes, st, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const unsigned grid = (unsigned)(a.total < 2048 ? a.total : 2048);
+    hipLaunchKernelGGL((fit2r_multi_redo<N>), dim3(grid), dim3(kFitThreads<N, 1>), LayR<N>::bytes1, st, a);
+  } else if (phase == 1) {
+    hipLaunchKernelGGL((fit2r_multi<N, 1, false>), dim3((unsigned)a.total), dim3(kFitThreads<N, 1>), LayR<N>::bytes1, st, a);
+  } else {
+    constexpr size_t lds2 = LayZ<N, kFitThreads<N, 2> / 64>::bytes;
+    if (fast) hipLaunchKernelGGL((fit2r_multi<N, 2, true>), dim3((unsigned)a.total), dim3(kFitThreads<N, 2>), lds2, st, a);
+    else hipLaunchKernelGGL((fit2r_multi<N, 2, false>), dim3((unsigned)a.total), dim3(kFitThreads<N, 2>), lds2, st, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_fit2r_multi(int phase, int N, const Fused2DArgs& a, hipStream_t st) {
+hipError_t launch_fit2r_multi(int phase, int N, const Fused2DArgs& a, bool fast, hipStream_t st) {
   switch (N) {
-    case 2: return multi_n<2>(phase, a, st);
-    case 3: return multi_n<3>(phase, a, st);
-    case 4: return multi_n<4>(phase, a, st);
-    case 5: return multi_n<5>(phase, a, st);
-    case 6: return multi_n<6>(phase, a, st);
-    case 7: return multi_n<7>(phase, a, st);
-    case 8: return multi_n<8>(phase, a, st);
-    case 9: return multi_n<9>(phase, a, st);
-    case 10: return multi_n<10>(phase, a, st);
-    case 11: return multi_n<11>(phase, a, st);
-    case 12: return multi_n<12>(phase, a, st);
-    case 13: return multi_n<13>(phase, a, st);
-    case 14: return multi_n<14>(phase, a, st);
-    case 15: return multi_n<15>(phase, a, st);
-    case 16: return multi_n<16>(phase, a, st);
+    case 2: return multi_n<2>(phase, a, fast, st);
+    case 3: return multi_n<3>(phase, a, fast, st);
+    case 4: return multi_n<4>(phase, a, fast, st);
+    case 5: return multi_n<5>(phase, a, fast, st);
+    case 6: return multi_n<6>(phase, a, fast, st);
+    case 7: return multi_n<7>(phase, a, fast, st);
+    case 8: return multi_n<8>(phase, a, fast, st);
+    case 9: return multi_n<9>(phase, a, fast, st);
+    case 10: return multi_n<10>(phase, a, fast, st);
+    case 11: return multi_n<11>(phase, a, fast, st);
+    case 12: return multi_n<12>(phase, a, fast, st);
+    case 13: return multi_n<13>(phase, a, fast, st);
+    case 14: return multi_n<14>(phase, a, fast, st);
+    case 15: return multi_n<15>(phase, a, fast, st);
+    case 16: return multi_n<16>(phase, a, fast, st);
     default: return hipErrorInvalidValue;
   }
 }

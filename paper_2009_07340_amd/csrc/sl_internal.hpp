@@ -162,12 +162,16 @@ struct Params2D {
   const double* zdraw;
   const double* emean;
   const int64_t* nbr_tr;
-  // reference solver, phase 1 of a per-order launch of one-component fits:
-  // fits whose fixed-point iteration contracts too slowly are listed here (by
-  // fit index within the launch's group) and redone by a second kernel that
-  // holds the full basis tables; null: every fit takes the full kernel
+  // reference solver, phase 1 of one-component fits: fits whose fixed-point
+  // iteration contracts too slowly are listed and redone by a second kernel
+  // that holds the full basis tables.  A per-order launch passes its group's
+  // slots (fit index within the group) and its order's counter; the device
+  // copy holds the handle's whole list and counters (kMaxN + 1), the slots of
+  // order N starting at rescue_off[N] (fit index within the handle).  Null:
+  // every fit takes the full kernel.
   uint32_t* rescue_list;
   unsigned int* rescue_count;
+  int64_t rescue_off[kMaxN + 1];
   LegendreRec rec;
 };
 
@@ -265,7 +269,10 @@ hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipS
 size_t fit2r_lds_bytes(int N, int phase);
 hipError_t launch_fit2r_fused(int phase, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
 int fit2r_fused_occupancy(int phase, size_t lds);
-hipError_t launch_fit2r_multi(int phase, int N, const Fused2DArgs& a, hipStream_t st);
+// fast: every problem of the table has one component and no mass constraint
+// (the lean phase-1 kernel with its redo pass; the phase-2 kernel without the
+// general form).
+hipError_t launch_fit2r_multi(int phase, int N, const Fused2DArgs& a, bool fast, hipStream_t st);
 constexpr int kMaxNRef = 16;  // largest order of the reference-preconditioned 2-D solver
 constexpr int kMaxN2D = 10;   // largest order of the 2-D LDS-resident fit
 hipError_t launch_resident_1d(int N, const Params1D& p, hipStream_t st);
