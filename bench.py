@@ -62,7 +62,9 @@ def fit_flops_2d_ref(N, phase, iters, ncomp=1):
       nodes 2n(N^2 + N).
     Phase 2: moves 8n; bubble tables (Legendre recurrence of m terms, times
       x(1 - x)) 2(n + N)(5m + 4); the two 1-D Gram matrices 4 m^2 N + 12 N and
-      their Gauss-Jordan inverses 4 m^3; jump data T, projected jump 2T(T + 4);
+      their Gauss-Jordan inverses 4 m^3; jump data T, the jump projected through
+      the four corner conditions 16N + 32 + 4T + 40 (eight end values, a 4 x 4
+      solve, the correction, the corner values);
       transfinite lift at the moved nodes n(20N + 20) and at the Gauss nodes 14n;
       Vz p: 2n(m^2 + m);  Vz^T r: 2n m^2 + n m;  Kronecker preconditioner 4 m^3;
       evaluation 2n(m^2 + m) + 3n.
@@ -77,7 +79,7 @@ def fit_flops_2d_ref(N, phase, iters, ncomp=1):
         return geom + ncomp * (v0 + iters * per_it + out)
     m = N - 2
     geom = 8 * n + 2 * (n + N) * (5 * m + 4) + 4 * m * m * N + 12 * N + 4 * m ** 3 + 4 * N * m
-    lift = T + 2 * T * (T + 4) + n * (20 * N + 20) + 14 * n + 3 * n
+    lift = T + (16 * N + 32 + 4 * T + 40) + n * (20 * N + 20) + 14 * n + 3 * n
     if m == 0:
         return geom + ncomp * (lift + 3 * n)
     zv = 2 * n * (m * m + m)
@@ -100,16 +102,21 @@ def kernel_name(wl, fused=0, solver=1):
 
 
 def kernel_sources_digest(wl):
-    """Digest of the sources the dominant kernel is built from (a stored HBM
-    traffic measurement is only valid for the kernel it was taken on)."""
+    """Digest of the sources the dominant kernel is built from, comments and
+    blank lines left out (a stored HBM traffic measurement is only valid for
+    the kernel it was taken on; a comment does not change the kernel)."""
     import hashlib
+    import re
     csrc = os.path.join(ROOT, "paper_2009_07340_amd", "csrc")
     names = ["sl_internal.hpp", "philox.hpp", "fit1d.hpp"]
     names += ["k1d.hip"] if wl.dim == 1 else ["k2d.hip", "k2r.hip", "blocks.hpp", "kshared.hip"]
     h = hashlib.sha256()
     for n in names:
-        with open(os.path.join(csrc, n), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(csrc, n)) as f:
+            for line in f:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -129,10 +129,12 @@ typedef struct sl_mesh_desc {
   int32_t refine_iters;   /* FP64 refinement sweeps for the mixed modes; -1 = default */
   int32_t solver;         /* 2-D least-squares solver, SL_SOLVER_* (0 = automatic) */
   int32_t max_iter;       /* reference solver: iteration limit per fit, 0 = default (32) */
-  double tol;             /* reference solver: stop an unconstrained fit when its correction, relative
-                             to the starting iterate, is below tol, and the remap when its
-                             estimated nodal error, relative to the nodal values, is below tol;
-                             0 = default (1e-13) */
+  double tol;             /* reference solver: stop an unconstrained fit when the error its last
+                             correction leaves (estimated as that correction times r / (1 - r),
+                             r the ratio of the last two corrections), or the correction itself,
+                             relative to the starting iterate, is below tol, and the remap when
+                             its estimated nodal error, relative to the nodal values, is below
+                             tol; 0 = default (1e-13) */
   int32_t constraints;    /* SL_CONSTRAIN_BOUNDARY (0): the remap is constrained by the upwinded
                              boundary values; SL_CONSTRAIN_BOUNDARY_MASS: also by the element's
                              mass, the integral of the advected interpolant p0 over the element
@@ -175,9 +177,9 @@ typedef struct sl_diag_t {
                                  extrapolated, never clamped) and counts it here */
   double max_residual;        /* largest relative residual a fit's solver left since the handle was
                                  created: reference solver, the relative size its tolerance bounds
-                                 at its stop (unconstrained fit: the last correction over the
-                                 starting iterate; remap: the estimated nodal error over the
-                                 nodal values);
+                                 at its stop (unconstrained fit: the estimated error left, or the
+                                 last correction, over the starting iterate; remap: the estimated
+                                 nodal error over the nodal values);
                                  factorisation solver in the mixed modes the relative size of the
                                  last float64 refinement correction, max|dc| / max|c|; 0 where
                                  neither applies (1-D, float64 factorisation); NaN if a fit met one */

@@ -15,6 +15,8 @@
 // applied matrix-free from the 1-D Legendre tables).  A fit whose correction
 // shrinks by less than half a step continues with conjugate gradients on the
 // normal equations, preconditioned by G0^-1 = Gx^-1 (x) Gx^-1, Gx = Vx^T Vx.
+// One-component fits take a lean form without the basis tables at the moved
+// nodes and leave the fits that need conjugate gradients to the full form.
 //
 // Phase 2 (constrained remap) works in null-space form on the (N-2)^2
 // coefficients of the part of the correction that vanishes on the edges, with
@@ -24,7 +26,8 @@
 // preconditioners are then exact), a few for the smooth fields of the
 // workloads.  Fits that do not reach the tolerance within the iteration limit
 // are counted in a device statistic.  Everything is float64.  One workgroup
-// (four wavefronts) per fit, all of its data in LDS (N <= 16).
+// per fit (one to four wavefronts by order), all of its data in LDS
+// (N <= 16).
 #include "sl_internal.hpp"
 #include "philox.hpp"
 #include "fit1d.hpp"
