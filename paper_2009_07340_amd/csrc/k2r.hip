@@ -905,17 +905,24 @@ __device__ void z_VT_part(const double* Xz, const double* Yz, const double* r, d
   const bool col = lr < m;
   const int lrc = col ? lr : 0;
   M64::acc_t ac[2] = {zacc<double>(), zacc<double>()};
-  // every lane loads and the products take zeros outside the tables, so that
-  // the loads need no branches and can be issued ahead of the products: past
-  // the last node (at most 4 W + 3 places) the loads read the next row, or the
-  // arrays that follow Yz and r in the workgroup's LDS, and are discarded
+  // every lane loads, so that the loads need no branches and can be issued
+  // ahead of the products.  Lanes past the m rows (columns) read row 0: they
+  // only feed the tile's rows (columns) beyond m, which are not kept.  Past
+  // the last node (at most 4 W + 3 places, only in the last SAFE.. steps) the
+  // loads read the next row, or the arrays that follow Yz and r in the
+  // workgroup's LDS, and the products take zeros there.
+  constexpr int SAFE0 = (n - 3) / 4 - (T / 64 - 1) * KW;   // steps in range for every wavefront
+  constexpr int SAFE = SAFE0 < 0 ? 0 : SAFE0 > KW ? KW : SAFE0;
 #pragma unroll
   for (int kq = 0; kq < KW; ++kq) {
     const int i = 4 * (w * KW + kq) + lk;
-    const bool ok = col && i < n;
     const double ya = Yz[lrc * ZS + i], xb = Xz[lrc * ZS + i], rb = r[i];
-    const double a = ok ? ya : 0.0;         // A[l][i]
-    const double b = ok ? rb * xb : 0.0;    // B[i][k]
+    double a = ya, b = rb * xb;   // A[l][i], B[i][k]
+    if (kq >= SAFE) {
+      const bool ok = i < n;
+      a = ok ? a : 0.0;
+      b = ok ? b : 0.0;
+    }
     ac[kq & 1] = M64::mma(a, b, ac[kq & 1]);
   }
   double d = 0.0;
