@@ -118,6 +118,30 @@ __device__ __forceinline__ double wsum(const double* r) {
   else return r[0];
 }
 
+// One DPP lane move of a double (both halves), lanes outside the move or in
+// the rows left out of ROWS taking 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_take(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of v over the wavefront, in every lane (fixed order): quad sums by two
+// quad permutations, row sums by row shifts of 4 and 8 (the row's total lands
+// in its lanes 12..15), then lane 15 of rows 0 and 2 into rows 1 and 3 and
+// lane 31 into rows 2 and 3, so lane 63 holds the total; its value is read
+// from there.  The lane moves go through the DPP network, not the LDS.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_take<0xB1, 0xF>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_take<0x4E, 0xF>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_take<0x114, 0xF>(v);   // row_shr:4
+  v += dpp_take<0x118, 0xF>(v);   // row_shr:8
+  v += dpp_take<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_take<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return bcast(v, 63);
+}
+
 // Sum over the fit's threads of a per-thread value; every thread gets the same
 // result (fixed summation order).  One barrier: the slots in red are read
 // after it and written again only by a later sum, which the callers keep
@@ -125,8 +149,7 @@ __device__ __forceinline__ double wsum(const double* r) {
 // residual norms red + 8).
 template <int T>
 __device__ __forceinline__ double block_sum(double v, double* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_total(v);
   if (lane() == 0) red[wave()] = v;
   block_sync();
   return wsum<T>(red);
@@ -135,11 +158,8 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Two sums at once (one barrier, as above).
 template <int T>
 __device__ __forceinline__ void block_sum2(double& v0, double& v1, double* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    v0 += __shfl_xor(v0, o, 64);
-    v1 += __shfl_xor(v1, o, 64);
-  }
+  v0 = wave_total(v0);
+  v1 = wave_total(v1);
   if (lane() == 0) {
     red[wave()] = v0;
     red[4 + wave()] = v1;
@@ -203,8 +223,7 @@ __device__ void r_VT_mc(const double* X1, const double* Y1, const double* r, dou
     }
   }
   if (dotw) {   // <dotw, out> from the accumulators, summed across the wavefront
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    d = wave_total(d);
     if (l == 0) *dot_out = d;
   }
 }
@@ -251,8 +270,7 @@ __device__ void r_V0inv(const double* vxi, const double* r, double* tmp, double*
     x[p] = add ? x[p] + d : d;
     a += d * d;
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  a = wave_total(a);
   if (lane() == 0) red2[wave()] = a;
   block_sync();
 }
@@ -286,11 +304,8 @@ __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double*
     }
   }
   if (rr) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      a += __shfl_xor(a, o, 64);
-      c += __shfl_xor(c, o, 64);
-    }
+    a = wave_total(a);
+    c = wave_total(c);
     if (lane() == 0) {
       red2[wave()] = a;
       red2[4 + wave()] = c;
@@ -936,8 +951,7 @@ __device__ void z_VT_part(const double* Xz, const double* Yz, const double* r, d
     }
   }
   if (dotw) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+    d = wave_total(d);
     if (l == 0) dots[w] = d;
   }
 }
@@ -1099,11 +1113,7 @@ __device__ __forceinline__ double coons_node(const double* j, int a, int b, doub
 // ordered by wave_sync, and its sums are wavefront shuffles.
 
 // Sum over wavefront 0 (every lane gets it).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_total(v); }
 
 // out = (Gx (x) Gy) v over v[l m + k] (tmp m^2 doubles), by wavefront 0.  With rr
 // given, returns rr . out in rg and out . out in gg.
