@@ -83,32 +83,6 @@ struct LayR {
 
 // ---------------------------------------------------------------- helpers
 
-// Lanes per output of a split reduction: as many as the workgroup holds for O
-// outputs (a power of two up to 8, so the lanes of one output share a wavefront).
-constexpr int ksplit(int O, int T) { return O * 8 <= T ? 8 : O * 4 <= T ? 4 : O * 2 <= T ? 2 : 1; }
-
-// out[o] = sum_{j < J} term(o, j) - (sub ? sub[o] : 0) for o < O.  G = ksplit(O)
-// adjacent lanes share an output, each summing j = g, g + G, ..., and the partial
-// sums meet by xor shuffles: the dependent chain is J / G long instead of J, and
-// G times more lanes work.  Every lane takes part in the shuffles.  No barrier.
-template <int O, int J, int T, typename Term>
-__device__ __forceinline__ void splitk(Term term, double* out, const double* sub = nullptr) {
-  constexpr int G = ksplit(O, T), PER = T / G;
-  const int t = tid(), g = t % G;
-#pragma unroll
-  for (int ob = 0; ob < O; ob += PER) {
-    const int o = ob + t / G;
-    double acc = 0.0;
-    if (o < O) {
-#pragma unroll 4
-      for (int j = g; j < J; j += G) acc += term(o, j);
-    }
-#pragma unroll
-    for (int m = 1; m < G; m <<= 1) acc += __shfl_xor(acc, m, 64);
-    if (g == 0 && o < O) out[o] = sub ? acc - sub[o] : acc;
-  }
-}
-
 // A fit runs on T = 64, 128 or 256 threads (one, two or four wavefronts).
 // Per-wavefront partial sums in r[0 .. T/64) summed in a fixed order.
 template <int T>
