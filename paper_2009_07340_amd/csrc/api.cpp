@@ -81,7 +81,7 @@ struct Layout {
   // byte offsets in the workspace
   size_t o_phi, o_phi2, o_tr, o_xi, o_A, o_B, o_src, o_Af, o_Bf, o_ghost, o_mean, o_phi0;
   size_t o_order, o_noff, o_eoff, o_nbr, o_work, o_xitab, o_ur, o_uroff, o_interp, o_interpoff;
-  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_nsp, o_sops, o_bw, o_wqtab, o_z, o_emean, o_nbrtr, o_rlist, o_rcount, total;
+  size_t o_params, o_dstep, o_ctr, o_nonf, o_stats, o_mpart, o_gxinv, o_nsp, o_sops, o_bw, o_wqtab, o_z, o_wrec, o_rlist, o_rcount, total;
   bool shared_capable = false;      // one order <= kMaxNShared in 2-D: the shared-geometry path can run
   int solver = SL_SOLVER_FACTOR;    // effective 2-D solver
   size_t gx_doubles = 0, nsp_doubles = 0;
@@ -199,8 +199,7 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_sops = take(L.shared_capable ? sizeof(double) * (size_t)L.M * sl::shared_op_doubles(L.maxN) : 0);
   L.o_bw = take(sizeof(double) * sl::kMaxN);
   L.o_z = take(L.dim == 2 ? sizeof(double) * 2 * (size_t)L.M : 0);
-  L.o_emean = take(L.dim == 2 ? sizeof(double) * 4 * (size_t)L.K : 0);
-  L.o_nbrtr = take(L.dim == 2 ? sizeof(int64_t) * 4 * (size_t)L.K : 0);
+  L.o_wrec = take(L.dim == 2 ? sizeof(sl::WorkRec) * (size_t)L.K : 0);
   // phase-1 fits to redo (reference solver, one component): one slot a fit
   const bool lean = L.dim == 2 && L.solver == SL_SOLVER_REFERENCE && L.nc == 1;
   L.o_rlist = take(lean ? sizeof(uint32_t) * (size_t)L.K * (size_t)L.M : 0);
@@ -232,7 +231,9 @@ struct sl_ctx {
   sl::LegendreRec rec{};
   // host copies of the fields
   std::vector<double> u, D, divu, un, Dn, ghost_h;
-  std::vector<double> hA, hB, hsrc, hAf, hBf, hemean;
+  std::vector<double> hA, hB, hsrc, hAf, hBf;
+  std::vector<int32_t> work_h;           // the work list (elements grouped by order)
+  std::vector<sl::WorkRec> hwrec;        // host copy of the work records
   bool fields_set = false;
   bool coeff_valid = false;
   double coeff_dt = 0.0;
@@ -257,8 +258,7 @@ struct sl_ctx {
   double* d_bw = nullptr;                // barycentric weights of the (single) order's nodes
   double* d_wqtab = nullptr;             // [(kMaxN+1)][kMaxN] quadrature weights of each order's nodes
   double* d_z = nullptr;                 // [M][2] this step's Wiener normals (reference solver)
-  double* d_emean = nullptr;             // [K][4] element means of the move coefficients
-  int64_t* d_nbrtr = nullptr;            // [K][4] where each side's upwind neighbour trace starts
+  sl::WorkRec* d_wrec = nullptr;         // [K] element data of each work item (reference solver)
   uint32_t* d_rlist = nullptr;           // phase-1 fits to redo, by order group (null: none)
   unsigned int* d_rcount = nullptr;      // [kMaxN + 1] their counts, by order
   bool shared_geometry = false;          // the current step coefficients are the same at every node
@@ -355,10 +355,11 @@ int update_coefficients(sl_ctx* h, double dt) {
   SL_HIP(hipMemcpyAsync(h->Af, h->hAf.data(), sizeof(double) * h->hAf.size(), hipMemcpyHostToDevice, h->stream));
   SL_HIP(hipMemcpyAsync(h->Bf, h->hBf.data(), sizeof(double) * h->hBf.size(), hipMemcpyHostToDevice, h->stream));
   if (L.dim == 2) {
-    // element means of A and B per direction: the mean displacement of a
-    // fit's moved nodes is then mean(A) + mean(B) z, up to rounding
-    h->hemean.assign(4 * (size_t)L.K, 0.0);
-    for (int e = 0; e < L.K; ++e) {
+    // element means of A and B per direction into the work records: the mean
+    // displacement of a fit's moved nodes is then mean(A) + mean(B) z, up to
+    // rounding
+    for (size_t w = 0; w < h->work_h.size(); ++w) {
+      const int e = h->work_h[w];
       long double sa[2] = {0, 0}, sb[2] = {0, 0};
       for (int64_t k = L.noff[e]; k < L.noff[e + 1]; ++k)
         for (int j = 0; j < 2; ++j) {
@@ -367,11 +368,11 @@ int update_coefficients(sl_ctx* h, double dt) {
         }
       const long double n = (long double)(L.noff[e + 1] - L.noff[e]);
       for (int j = 0; j < 2; ++j) {
-        h->hemean[4 * (size_t)e + j] = (double)(sa[j] / n);
-        h->hemean[4 * (size_t)e + 2 + j] = (double)(sb[j] / n);
+        h->hwrec[w].emean[j] = (double)(sa[j] / n);
+        h->hwrec[w].emean[2 + j] = (double)(sb[j] / n);
       }
     }
-    SL_HIP(hipMemcpyAsync(h->d_emean, h->hemean.data(), sizeof(double) * h->hemean.size(), hipMemcpyHostToDevice,
+    SL_HIP(hipMemcpyAsync(h->d_wrec, h->hwrec.data(), sizeof(sl::WorkRec) * h->hwrec.size(), hipMemcpyHostToDevice,
                           h->stream));
   }
   SL_HIP(hipStreamSynchronize(h->stream));   // host vectors may be reused right after
@@ -451,8 +452,7 @@ void build_params(sl_ctx* h) {
     p.rescue_list = h->d_rlist;
     p.rescue_count = h->d_rcount;
     for (const auto& g : h->groups) p.rescue_off[g.first] = g.second.first * p.M;
-    p.emean = h->d_emean;
-    p.nbr_tr = h->d_nbrtr;
+    p.wrec = h->d_wrec;
   } else {
     sl::Params1D& p = h->p1;
     p = sl::Params1D{};
@@ -542,6 +542,7 @@ int enqueue_perorder(sl_ctx* h, int phase, bool devstep, int64_t step, hipStream
   p.step = step;
   for (const auto& g : h->groups) {
     p.work = h->d_work + g.second.first;
+    p.wrec = h->d_wrec ? h->d_wrec + g.second.first : nullptr;
     p.block0 = 0;
     // the group's slots of the phase-1 redo list
     p.rescue_list = h->d_rlist ? h->d_rlist + g.second.first * h->p2.M : nullptr;
@@ -952,8 +953,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   h->d_wqtab = (double*)(h->ws + L.o_wqtab);
   h->d_bw = (double*)(h->ws + L.o_bw);
   h->d_z = (double*)(h->ws + L.o_z);
-  h->d_emean = (double*)(h->ws + L.o_emean);
-  h->d_nbrtr = (int64_t*)(h->ws + L.o_nbrtr);
+  h->d_wrec = (sl::WorkRec*)(h->ws + L.o_wrec);
   const bool lean = L.dim == 2 && L.solver == SL_SOLVER_REFERENCE && L.nc == 1;
   h->d_rlist = lean ? (uint32_t*)(h->ws + L.o_rlist) : nullptr;
   h->d_rcount = lean ? (unsigned int*)(h->ws + L.o_rcount) : nullptr;
@@ -1036,17 +1036,23 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
   }
   std::vector<int64_t> noff64(L.noff.begin(), L.noff.end() - 1), eoff64(L.eoff.begin(), L.eoff.end() - 1);
   std::vector<int32_t> order32(L.order.begin(), L.order.end());
-  // per side, the neighbour's facing trace: across W (E, S, N) it is the
-  // neighbour's E (W, N, S) block of Ns values, packed with Ns
-  std::vector<int64_t> nbrtr(L.dim == 2 ? 4 * (size_t)L.K : 1, -1);
-  if (L.dim == 2)
-    for (int e = 0; e < L.K; ++e)
-      for (int w = 0; w < 4; ++w) {
-        const int nb = nbr[4 * (size_t)e + w];
-        if (nb < 0) continue;
-        const int64_t Ns = L.order[nb];
-        nbrtr[4 * (size_t)e + w] = (Ns << 48) | (L.eoff[nb] + (int64_t)(w ^ 1) * Ns);
-      }
+  // work records (2-D): the element's offsets and, per side, the neighbour's
+  // facing trace (across W (E, S, N) the neighbour's E (W, N, S) block of Ns
+  // values, packed with Ns); the move-coefficient means come with the step
+  // coefficients
+  h->work_h = work;
+  h->hwrec.assign(L.dim == 2 ? work.size() : 0, sl::WorkRec{});
+  for (size_t w = 0; w < h->hwrec.size(); ++w) {
+    const int e = work[w];
+    sl::WorkRec& r = h->hwrec[w];
+    r.noff = L.noff[e];
+    r.eoff = L.eoff[e];
+    for (int sd = 0; sd < 4; ++sd) {
+      const int nb = nbr[4 * (size_t)e + sd];
+      const int64_t Ns = nb < 0 ? 0 : L.order[nb];
+      r.nbr_tr[sd] = nb < 0 ? -1 : (Ns << 48) | (L.eoff[nb] + (int64_t)(sd ^ 1) * Ns);
+    }
+  }
   struct Up { void* dst; const void* src; size_t bytes; };
   const Up ups[] = {
       {h->d_order, order32.data(), sizeof(int32_t) * L.K}, {h->d_noff, noff64.data(), sizeof(int64_t) * L.K},
@@ -1058,7 +1064,7 @@ int sl_init_mesh(const sl_mesh_desc* desc, void* dev_ws, size_t ws_bytes, void* 
       {h->d_gxinv, gx.data(), sizeof(double) * gx.size()}, {h->d_nsp, nsp.data(), sizeof(double) * nsp.size()},
       {h->d_bw, bw.data(), sizeof(double) * bw.size()},
       {h->d_wqtab, wqtab.data(), sizeof(double) * wqtab.size()},
-      {h->d_nbrtr, nbrtr.data(), L.dim == 2 ? sizeof(int64_t) * nbrtr.size() : 0}};
+      {h->d_wrec, h->hwrec.data(), sizeof(sl::WorkRec) * h->hwrec.size()}};
   for (const auto& u : ups) {
     if (u.bytes == 0) continue;
     if (hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, h->stream) != hipSuccess) {

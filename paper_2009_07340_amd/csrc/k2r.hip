@@ -292,9 +292,9 @@ __device__ void r_G0inv(const double* gxi, const double* v, double* tmp, double*
 // for the second and later components of a fit (the first one's come with the
 // set-up).  One barrier.
 template <int N, int T>
-__device__ void r_carried(const Params2D& p, double* lds, int e, int64_t row) {
+__device__ void r_carried(const Params2D& p, double* lds, const WorkRec* e, int64_t row) {
   using L = LayR<N>;
-  const int64_t noff = p.noff[e];
+  const int64_t noff = e->noff;
   double* f = lds + L::oF;
   for (int i = tid(); i < L::n; i += T) f[i] = p.phi[row * p.nodes + noff + i] * p.src[noff + i];
   block_sync();
@@ -307,12 +307,12 @@ __device__ void r_carried(const Params2D& p, double* lds, int e, int64_t row) {
 // Dirichlet ghost value.  The outside value is loaded before the side is known,
 // so that no load waits for the draw.  No barrier.
 template <int N, int T>
-__device__ void r_jump_data(const Params2D& p, int e, int64_t row, double za, double zb, double* gv, int t0) {
+__device__ void r_jump_data(const Params2D& p, const WorkRec* e, int64_t row, double za, double zb, double* gv, int t0) {
   using L = LayR<N>;
-  const int64_t eoff = p.eoff[e];
+  const int64_t eoff = e->eoff;
   for (int q = t0; q < L::TT; q += T) {
     const int ew = q / N, j = q % N;
-    const int64_t nt = p.nbr_tr[4 * e + ew];
+    const int64_t nt = e->nbr_tr[ew];
     const double tq = p.tr[row * p.edges + eoff + q];
     double out;
     if (nt < 0) {
@@ -379,8 +379,8 @@ __device__ void r_traces_from(const double* Bx, const double* By, const double* 
 struct Shift2 {
   double x, y;
 };
-__device__ __forceinline__ Shift2 mean_shift(const Params2D& p, int e, Normal2 z) {
-  const double* em = p.emean + 4 * e;
+__device__ __forceinline__ Shift2 mean_shift(const WorkRec* e, Normal2 z) {
+  const double* em = e->emean;
   return Shift2{em[0] + em[2] * z.a, em[1] + em[3] * z.b};
 }
 
@@ -396,12 +396,12 @@ __device__ __forceinline__ Normal2 fit_increments(const Params2D& p, int64_t s) 
 // 4 the edge coordinates.  Moved nodes outside the element are counted in the
 // statistics (unless the fit is being redone).  One barrier.
 template <int N, int T>
-__device__ void r_setup(const Params2D& p, double* lds, int e, int64_t s, Normal2 z, bool count = true) {
+__device__ void r_setup(const Params2D& p, double* lds, const WorkRec* e, int64_t s, Normal2 z, bool count = true) {
   using L = LayR<N>;
   constexpr int n = L::n;
   const int t = tid();
-  const int64_t noff = p.noff[e];
-  const Shift2 d = mean_shift(p, e, z);
+  const int64_t noff = e->noff;
+  const Shift2 d = mean_shift(e, z);
   double* f = lds + L::oF;
   const double* gsrc = p.gxinv + p.gx_off[N];
   double* gxi = lds + L::oGxi;   // Gx^-1 and Vx^-1, adjacent in both places
@@ -510,7 +510,7 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   constexpr int n = L::n;
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
-  const int e = p.work[w];
+  const WorkRec* e = p.wrec + w;
   const Normal2 z = fit_increments(p, s);
   r_setup<N, T>(p, lds, e, s, z, !redo);
   const int t = tid();
@@ -523,8 +523,8 @@ __device__ __forceinline__ void r_phase1_body(const Params2D& p, double* lds, in
   double* q = lds + L::oQ;
   double* t1 = lds + L::oT1;
   double* red = lds + L::oRed;
-  const int64_t eoff = p.eoff[e];
-  const int64_t noff = p.noff[e];
+  const int64_t eoff = e->eoff;
+  const int64_t noff = e->noff;
   int its = 0, unconv = 0;
   double rmax = 0.0;
   // the components share the moved nodes and their tables (Sec. 5.3, last paragraph)
@@ -653,11 +653,11 @@ struct LayL {
 // Set-up of the lean form: moves, carried values, Vx^-1 and the tables at the
 // Gauss abscissae and edge coordinates.  One barrier.
 template <int N, int T>
-__device__ void r_setup_lean(const Params2D& p, double* lds, int e, int64_t s, Normal2 z, Shift2 d) {
+__device__ void r_setup_lean(const Params2D& p, double* lds, const WorkRec* e, int64_t s, Normal2 z, Shift2 d) {
   using L = LayL<N>;
   constexpr int n = L::n;
   const int t = tid();
-  const int64_t noff = p.noff[e];
+  const int64_t noff = e->noff;
   double* f = lds + L::oF;
   double* XY = lds + L::oXY;
   const double* vsrc = p.gxinv + p.gx_off[N] + N * N;
@@ -745,9 +745,9 @@ __device__ __forceinline__ void r_phase1_lean(const Params2D& p, double* lds, in
   using L = LayL<N>;
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
-  const int e = p.work[w];
+  const WorkRec* e = p.wrec + w;
   const Normal2 z = fit_increments(p, s);
-  const Shift2 d = mean_shift(p, e, z);
+  const Shift2 d = mean_shift(e, z);
   r_setup_lean<N, T>(p, lds, e, s, z, d);
   const double* vxi = lds + L::oVxi;
   const double* f = lds + L::oF;
@@ -786,8 +786,8 @@ __device__ __forceinline__ void r_phase1_lean(const Params2D& p, double* lds, in
     if (tid() == 0) list[atomicAdd(count, 1u)] = (uint32_t)fit;
     return;
   }
-  const int64_t noff = p.noff[e];
-  const int64_t eoff = p.eoff[e];
+  const int64_t noff = e->noff;
+  const int64_t eoff = e->eoff;
   r_p0_out<N, T>(lds + L::oBx, lds + L::oBy, x, p.phi + s * p.nodes + noff);
   double* tv = lds + L::oTr;
   double* uc = lds + L::oUc;
@@ -849,7 +849,13 @@ struct LayZ {
   static constexpr int oJ = oD + TT;          // the jump and its four corner values
   static constexpr int oMa = oJ + TT + 4;     // mass constraint: ax, ay, hx, hy (m each), a . h
   static constexpr int oRed = oMa + 4 * mA + 1;
-  static constexpr int end = oRed + 16;
+  // the projection's edge tables (l0, l1, (C^T C)^-1, l0.l0, l0.l1, l1.l1): in
+  // the space of the partial products (free until the first Vz^T product,
+  // which follows the projection) where that holds them, else after the rest
+  static constexpr int kEdge = 2 * N + 19;
+  static constexpr bool kEdgeShared = W * mmA >= kEdge;
+  static constexpr int oEdge = kEdgeShared ? oPart : oRed + 16;
+  static constexpr int end = oRed + 16 + (kEdgeShared ? 0 : kEdge);
   static constexpr size_t bytes = sizeof(double) * end;
   // at most as many as the registers admit without spilling (by order; the
   // general form, with the mass constraint and several components, holds more)
@@ -988,7 +994,8 @@ __device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* x
 }
 
 // j = P d (d: the 4N edge data t - g, edges W, E, S, N) and the corner values
-// of j (SW, NW, SE, NE) into J[0..4N+4), by one wavefront.  P projects onto the
+// of j (SW, NW, SE, NE) into J[0..4N+4), by one wavefront; tab: the edge
+// tables l0 (N), l1 (N), (C^T C)^-1 (16), l0.l0, l0.l1, l1.l1.  P projects onto the
 // edge values of Q_{N-1}: the vectors whose edges' polynomials agree at the
 // four corners, the null space of C^T with C's columns the corner
 // differences; P = I - C (C^T C)^-1 C^T.  C^T d takes the eight end values
@@ -997,10 +1004,10 @@ __device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* x
 // projection).  No barrier.
 template <int N>
 __device__ void z_project(const double* tab, const double* D, double* J) {
-  const double* l0 = tab + nsp_ends(N);
-  const double* l1 = l0 + N;
-  const double* Ci = tab + nsp_cinv(N);
-  const double* Ls = tab + nsp_ll(N);
+  const double* l0 = tab;
+  const double* l1 = tab + N;
+  const double* Ci = tab + 2 * N;
+  const double* Ls = tab + 2 * N + 16;
   const int l = lane();
   double a = 0.0;
   if (l < 8) {   // end value s = l & 1 of edge e = l >> 1
@@ -1134,23 +1141,24 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
   static_assert(n <= T, "one node a thread");
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
-  const int e = p.work[w];
+  const WorkRec* e = p.wrec + w;
   const Normal2 z = fit_increments(p, s);
   const int t = tid();
   const bool node = t < n;
-  const int64_t noff = p.noff[e];
+  const int64_t noff = e->noff;
   const double* xi = p.xi_tab + N * kMaxN;
   const double* nsp = p.nsp + p.nsp_off[N];
   double* red = lds + L::oRed;
   double* D = lds + L::oD;
-  const Shift2 dsh = mean_shift(p, e, z);
+  const Shift2 dsh = mean_shift(e, z);
   const double dbx = dsh.x, dby = dsh.y;
   // component 0's jump data first: its loads overlap the moves
   r_jump_data<N, T>(p, e, s * p.ncomp, z.a, z.b, D, t);
   // psi_k(xi_a) for the Gram inverses, in the space of the lift values (free
-  // until the lift)
+  // until the lift), and the projection's edge tables
   if constexpr (m > 0)
     for (int i = t; i < N * N; i += T) lds[L::oL + i] = nsp[nsp_vx(N) + i];
+  for (int i = t; i < L::kEdge; i += T) lds[L::oEdge + i] = nsp[nsp_ends(N) + i];
   // the moved nodes (eq. def_dx), one a thread
   double xm = 0.0, ym = 0.0;
   if (node) {
@@ -1221,6 +1229,8 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     const bool nodel = tl < n;
     if (c > 0) {
       r_jump_data<N, T>(p, e, row, z.a, z.b, D, tl);
+      if constexpr (L::kEdgeShared)   // the iteration has overwritten them
+        for (int i = tl; i < L::kEdge; i += T) lds[L::oEdge + i] = nsp[nsp_ends(N) + i];
       if constexpr (L::kXmShared) {   // the iteration has overwritten them
         if (nodel) {
           const int64_t k = noff + tl;
@@ -1231,7 +1241,7 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
     }
     block_sync();
     // j = P (t - g) and its corner values
-    if (wave() == 0) z_project<N>(nsp, D, J);
+    if (wave() == 0) z_project<N>(lds + L::oEdge, D, J);
     block_sync();
     double p0v = 0.0, lnode = 0.0, sc = 0.0, mc = 0.0;
     if (nodel) {

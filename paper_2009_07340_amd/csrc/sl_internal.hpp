@@ -115,6 +115,18 @@ struct Params1D {
 };
 
 // Step inputs of one order group for the 2-D phase kernels.
+// What a reference-solver fit needs of its element, in work-list order, so
+// that a fit reaches it with one load: the element's first node and first edge
+// point, per side (W, E, S, N) where the neighbour's facing trace starts in a
+// state row, (order << 48) | edge offset, or -1 on a Dirichlet side, and the
+// element means of the move coefficients (mean A in x, in y, mean B in x, in y).
+struct WorkRec {
+  int64_t noff;
+  int64_t eoff;
+  int64_t nbr_tr[4];
+  double emean[4];
+};
+
 struct Params2D {
   const double* xi_node;   // [nodes][2] reference coordinates
   const double* A;         // [nodes][2]
@@ -155,13 +167,10 @@ struct Params2D {
   int mass;                // 1: the fit also keeps the element integral of p0 (not on this path)
   const double* wq_tab;    // [(kMaxN+1)][kMaxN] quadrature weights of each order's nodes
   // reference solver: this step's Wiener normals of each sample ([M][2], written
-  // by the draw kernel before phase 1), the element means of the move
-  // coefficients ([K][4]: mean A in x, in y, mean B in x, in y) and, per element
-  // and side (W, E, S, N), where the neighbour's facing trace starts in a state
-  // row: (order << 48) | edge offset, or -1 on a Dirichlet side
+  // by the draw kernel before phase 1) and the element data of each work item
+  // (indexed like work)
   const double* zdraw;
-  const double* emean;
-  const int64_t* nbr_tr;
+  const struct WorkRec* wrec;
   // reference solver, phase 1 of one-component fits: fits whose fixed-point
   // iteration contracts too slowly are listed and redone by a second kernel
   // that holds the full basis tables.  A per-order launch passes its group's
