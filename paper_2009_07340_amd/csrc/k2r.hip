@@ -993,6 +993,51 @@ __device__ __forceinline__ void z_gram_inverse(const double* Vx, const double* x
   }
 }
 
+// The same inverse with one matrix element a lane, for m^2 <= 64: lane
+// (r, c) = (l / m, l % m) forms G[r][c] (the same sums in the same order as
+// the column form), then each Gauss-Jordan step takes the pivot by a lane
+// read and the pivot row's and column's entries by two lane permutations, so
+// a step is one exchange instead of 2m lane reads.  The arithmetic is that of
+// the column form, term for term.  TWO: lanes 32 + (r, c) form the block at
+// d1 into out1 at the same time (m^2 <= 32).
+template <int N, bool TWO = false>
+__device__ __forceinline__ void z_gram_inverse_ep(const double* Vx, const double* xi, double d0, double* out0,
+                                                  double d1 = 0.0, double* out1 = nullptr) {
+  constexpr int m = LayZ<N>::m, mm = m * m;
+  static_assert(mm <= 64 && (!TWO || mm <= 32), "one element a lane");
+  const int l = lane();
+  const int h = TWO ? l >> 5 : 0;
+  const int le = TWO ? l & 31 : l;
+  const bool live = le < mm;
+  const int r = live ? le / m : 0, c = live ? le % m : 0;
+  const double d = h ? d1 : d0;
+  double a = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double xa = xi[j] + d;
+    const double sa = xa * (1.0 - xa);
+    a += Vx[j * N + r] * ((sa * sa) * Vx[j * N + c]);
+  }
+  const int base = h << 5;
+#pragma unroll
+  for (int k = 0; k < m; ++k) {
+    // the pivot of each half, the entry (k, c) of the lane's column and (r, k) of its row
+    const double pk0 = bcast(a, k * m + k);
+    const double pk = TWO ? (h ? bcast(a, 32 + k * m + k) : pk0) : pk0;
+    const int srow = (base + k * m + c) << 2, scol = (base + r * m + k) << 2;
+    const double arow = __hiloint2double(__builtin_amdgcn_ds_bpermute(srow, __double2hiint(a)),
+                                         __builtin_amdgcn_ds_bpermute(srow, __double2loint(a)));
+    const double acol = __hiloint2double(__builtin_amdgcn_ds_bpermute(scol, __double2hiint(a)),
+                                         __builtin_amdgcn_ds_bpermute(scol, __double2loint(a)));
+    double pinv = __builtin_amdgcn_rcp(pk);
+    pinv = fma(pinv, fma(-pk, pinv, 1.0), pinv);
+    pinv = fma(pinv, fma(-pk, pinv, 1.0), pinv);
+    if (c == k) a = (r == k) ? pinv : -acol * pinv;
+    else a = (r == k) ? arow * pinv : a - acol * (arow * pinv);
+  }
+  if (live) (h ? out1 : out0)[r * m + c] = a;
+}
+
 // j = P d (d: the 4N edge data t - g, edges W, E, S, N) and the corner values
 // of j (SW, NW, SE, NE) into J[0..4N+4), by one wavefront; tab: the edge
 // tables l0 (N), l1 (N), (C^T C)^-1 (16), l0.l0, l0.l1, l1.l1.  P projects onto the
@@ -1188,7 +1233,15 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
       for (int k = 0; k < m; ++k) Yz[k * L::ZS + t] = sym * q[k];
     }
     block_sync();
-    if constexpr (W == 1) {   // both blocks at once, one a half-wavefront
+    if constexpr (m * m <= 32 && W == 1) {   // both blocks at once, one a half-wavefront
+      z_gram_inverse_ep<N, true>(lds + L::oL, xi, dbx, lds + L::oGx, dby, lds + L::oGy);
+    } else if constexpr (m * m <= 64 && W == 1) {
+      z_gram_inverse_ep<N>(lds + L::oL, xi, dbx, lds + L::oGx);
+      z_gram_inverse_ep<N>(lds + L::oL, xi, dby, lds + L::oGy);
+    } else if constexpr (m * m <= 64) {
+      const int wg = wave() - (W - 2);   // the last two wavefronts
+      if (wg >= 0) z_gram_inverse_ep<N>(lds + L::oL, xi, wg ? dby : dbx, lds + (wg ? L::oGy : L::oGx));
+    } else if constexpr (W == 1) {
       z_gram_inverse<N, true>(lds + L::oL, xi, dbx, lds + L::oGx, dby, lds + L::oGy);
     } else {
       const int wg = wave() - (W - 2);   // the last two wavefronts
