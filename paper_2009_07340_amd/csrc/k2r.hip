@@ -859,7 +859,7 @@ struct LayZ {
   static constexpr size_t bytes = sizeof(double) * end;
   // at most as many as the registers admit without spilling (by order; the
   // general form, with the mass constraint and several components, holds more)
-  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 10 ? 4 : 3, 64 * W);
+  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 6 ? 6 : N <= 10 ? 4 : 3, 64 * W);
   static constexpr int waves_general = LayR<N>::lds_waves(bytes, N <= 8 ? 4 : 3, 64 * W);
   static constexpr int waves_multi = LayR<N>::lds_waves(bytes, N <= 6 ? 4 : 3, 64 * W);   // batched launches
   static constexpr int NQ = (n + 3) / 4;   // steps of 4 nodes
