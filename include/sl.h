@@ -268,7 +268,14 @@ int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t ns
  *              workgroups (0 = as many as fit on the device at once) pulling
  *              fits from a device work counter;
  *   graph = 1: the step is captured once as a hipGraph (device step counter,
- *              counters cleared by a kernel) and replayed nsteps times.
+ *              counters cleared by a kernel) and replayed nsteps times;
+ *   wide = 1:  fit shape of the reference solver's per-order kernels (fused = 0,
+ *              a handle stepped alone): every fit of order <= 12 runs on
+ *              twice the default wavefronts (orders <= 8: two instead of one;
+ *              9..12: four instead of two), which shortens a fit where there are
+ *              too few fits to fill the device.  The sums are ordered
+ *              differently, so the result agrees with the default shape to
+ *              rounding.  Other solvers, schedules and batches ignore it.
  * ms_per_step is what sl_autotune measured (0 if set by hand).  The 1-D step
  * is one resident launch for all steps whatever the schedule. */
 typedef struct sl_schedule_t {
@@ -276,7 +283,8 @@ typedef struct sl_schedule_t {
   int32_t graph;
   int32_t grid;
   float ms_per_step;
-  int32_t shared;   /* 1: the shared-geometry path (below); fused, graph and grid are then unused */
+  int32_t shared;   /* 1: the shared-geometry path (below); fused, graph, grid and wide are then unused */
+  int32_t wide;     /* 1: the wide fit shape (above) */
 } sl_schedule_t;
 
 /* Shared-geometry path (schedule.shared = 1; 2-D meshes of one order N <= 12,
@@ -295,8 +303,9 @@ typedef struct sl_schedule_t {
 int sl_set_schedule(sl_handle h, const sl_schedule_t* s);
 int sl_get_schedule(sl_handle h, sl_schedule_t* s);
 
-/* Autotuner: time every candidate schedule (per-order / fused with several
- * grid sizes, each direct and as a graph) over trial_steps steps of size dt
+/* Autotuner: time every candidate schedule (per-order in both fit shapes for
+ * the reference solver / fused with several grid sizes, each direct and as a
+ * graph) over trial_steps steps of size dt
  * and keep the fastest.  The samples and the step counter are restored
  * afterwards (a temporary device copy of the samples is allocated for that).
  * cache_path (may be NULL) names a text file of earlier choices keyed by

@@ -46,7 +46,7 @@ class sl_diag_t(C.Structure):
 
 class sl_schedule_t(C.Structure):
     _fields_ = [("fused", C.c_int32), ("graph", C.c_int32), ("grid", C.c_int32), ("ms_per_step", C.c_float),
-                ("shared", C.c_int32)]
+                ("shared", C.c_int32), ("wide", C.c_int32)]
 
 
 class SLError(RuntimeError):
@@ -325,11 +325,12 @@ def sl_diag(h):
 
 
 def _sched_dict(s):
-    return {"fused": s.fused, "graph": s.graph, "grid": s.grid, "ms_per_step": s.ms_per_step, "shared": s.shared}
+    return {"fused": s.fused, "graph": s.graph, "grid": s.grid, "ms_per_step": s.ms_per_step, "shared": s.shared,
+            "wide": s.wide}
 
 
-def sl_set_schedule(h, fused=0, graph=0, grid=0, shared=0):
-    s = sl_schedule_t(int(fused), int(graph), int(grid), 0.0, int(shared))
+def sl_set_schedule(h, fused=0, graph=0, grid=0, shared=0, wide=0):
+    s = sl_schedule_t(int(fused), int(graph), int(grid), 0.0, int(shared), int(wide))
     _check(_lib.sl_set_schedule(h, C.byref(s)))
 
 

@@ -548,7 +548,7 @@ int enqueue_perorder(sl_ctx* h, int phase, bool devstep, int64_t step, hipStream
     p.rescue_list = h->d_rlist ? h->d_rlist + g.second.first * h->p2.M : nullptr;
     p.rescue_count = h->d_rcount ? h->d_rcount + g.first : nullptr;
     if (h->L.solver == SL_SOLVER_REFERENCE)
-      SL_HIP(sl::launch_fit2r(phase, g.first, p, g.second.second * h->p2.M, st));
+      SL_HIP(sl::launch_fit2r(phase, g.first, p, g.second.second * h->p2.M, st, h->sched.wide != 0));
     else
       SL_HIP(sl::launch_fit2d(phase, g.first, h->desc.precision, p, g.second.second * h->p2.M, st));
   }
@@ -668,7 +668,7 @@ int enqueue_device_step(const std::vector<sl_ctx*>& hs, int fused, int grid, hip
 // Graph cache: one captured step per (handles, schedule), least recently used first out.
 struct GraphEntry {
   std::vector<uint64_t> ids;
-  int fused, grid;
+  int fused, grid, wide;
   hipGraphExec_t exec;
 };
 std::mutex g_graph_mu;
@@ -691,10 +691,12 @@ void purge_graphs(uint64_t id) {
 int get_graph(const std::vector<sl_ctx*>& hs, int fused, int grid, hipGraphExec_t* out) {
   std::vector<uint64_t> ids;
   for (sl_ctx* h : hs) ids.push_back(h->id);
+  // the fit shape of a handle that runs its per-order kernels alone
+  const int wide = !fused && hs.size() == 1 ? hs[0]->sched.wide : 0;
   {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
-      if (it->ids == ids && it->fused == fused && it->grid == grid) {
+      if (it->ids == ids && it->fused == fused && it->grid == grid && it->wide == wide) {
         g_graphs.splice(g_graphs.begin(), g_graphs, it);
         *out = it->exec;
         return SL_OK;
@@ -716,7 +718,7 @@ int get_graph(const std::vector<sl_ctx*>& hs, int fused, int grid, hipGraphExec_
   (void)hipGraphDestroy(graph);
   if (ei != hipSuccess) return fail(SL_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
   std::lock_guard<std::mutex> lk(g_graph_mu);
-  g_graphs.push_front(GraphEntry{ids, fused, grid, exec});
+  g_graphs.push_front(GraphEntry{ids, fused, grid, wide, exec});
   while (g_graphs.size() > kMaxGraphs) {
     (void)hipGraphExecDestroy(g_graphs.back().exec);
     g_graphs.pop_back();
@@ -1276,8 +1278,8 @@ int sl_set_schedule(sl_handle h, const sl_schedule_t* s) {
   if (int rc = check_handle(h)) return rc;
   if (!s) return fail(SL_EINVAL, "null schedule");
   if ((s->fused != 0 && s->fused != 1) || (s->graph != 0 && s->graph != 1) || s->grid < 0 || s->grid > (1 << 24) ||
-      (s->shared != 0 && s->shared != 1))
-    return fail(SL_EINVAL, "schedule: fused, graph and shared are 0 or 1, 0 <= grid <= 2^24");
+      (s->shared != 0 && s->shared != 1) || (s->wide != 0 && s->wide != 1))
+    return fail(SL_EINVAL, "schedule: fused, graph, shared and wide are 0 or 1, 0 <= grid <= 2^24");
   h->sched = *s;
   return SL_OK;
 }
@@ -1307,6 +1309,7 @@ int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_p
       std::string k;
       sl_schedule_t c{};
       if (ls >> k >> c.fused >> c.graph >> c.grid >> c.ms_per_step && k == key) {
+        if (!(ls >> c.wide)) c.wide = 0;   // lines written before the fit shape was a choice
         if (int rc = sl_set_schedule(h, &c)) return rc;
         if (out) *out = h->sched;
         return SL_OK;
@@ -1325,10 +1328,18 @@ int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_p
   int rc = SL_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   std::vector<sl_schedule_t> cand;
+  // the wide fit shape changes the per-order reference-solver kernels of
+  // orders up to 12 only
+  bool shape = L.solver == SL_SOLVER_REFERENCE;
+  if (shape) {
+    shape = false;
+    for (const auto& g : h->groups) shape = shape || (g.first <= 12 && g.second.second > 0);
+  }
   for (int fused = 0; fused <= 1; ++fused)
     for (int graph = 0; graph <= 1; ++graph) {
       if (!fused) {
-        cand.push_back({0, graph, 0, 0.f});
+        cand.push_back({0, graph, 0, 0.f, 0, 0});
+        if (shape) cand.push_back({0, graph, 0, 0.f, 0, 1});
       } else {
         cand.push_back({1, graph, 0, 0.f});                    // every resident workgroup
         cand.push_back({1, graph, device_cus(), 0.f});         // one per compute unit
@@ -1378,7 +1389,7 @@ int sl_autotune(sl_handle h, double dt, int32_t trial_steps, const char* cache_p
   h->sched = best;
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << key << " " << best.fused << " " << best.graph << " " << best.grid << " " << best.ms_per_step << "\n";
+    o << key << " " << best.fused << " " << best.graph << " " << best.grid << " " << best.ms_per_step << " " << best.wide << "\n";
   }
   if (out) *out = best;
   return SL_OK;

@@ -857,9 +857,10 @@ struct LayZ {
   static constexpr int oEdge = kEdgeShared ? oPart : oRed + 16;
   static constexpr int end = oRed + 16 + (kEdgeShared ? 0 : kEdge);
   static constexpr size_t bytes = sizeof(double) * end;
-  // at most as many as the registers admit without spilling (by order; the
-  // general form, with the mass constraint and several components, holds more)
-  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 6 ? 6 : N <= 10 ? 4 : 3, 64 * W);
+  // at most as many as the registers admit without spilling (by order and fit
+  // shape; the general form, with the mass constraint and several components,
+  // holds more)
+  static constexpr int waves = LayR<N>::lds_waves(bytes, N <= 6 ? (W == 1 ? 6 : 5) : N <= 10 ? 4 : 3, 64 * W);
   static constexpr int waves_general = LayR<N>::lds_waves(bytes, N <= 8 ? 4 : 3, 64 * W);
   static constexpr int waves_multi = LayR<N>::lds_waves(bytes, N <= 6 ? 4 : 3, 64 * W);   // batched launches
   static constexpr int NQ = (n + 3) / 4;   // steps of 4 nodes
@@ -1482,19 +1483,23 @@ __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, in
 // The persistent fused kernel runs every order on four wavefronts.
 template <int N, int PHASE>
 constexpr int kFitThreads = PHASE == 1 ? (N <= 8 ? 64 : N <= 12 ? 128 : 256) : (N <= 8 ? 64 : N <= 11 ? 128 : 256);
+// The wide fit shape of the per-order kernels: twice the wavefronts a fit, at
+// most four (it shortens a fit where there are too few fits to fill the device).
+template <int N, int PHASE>
+constexpr int kWideThreads = kFitThreads<N, PHASE> < 256 ? 2 * kFitThreads<N, PHASE> : 256;
 
-template <int N>
-__global__ __launch_bounds__((kFitThreads<N, 1>)) __attribute__((amdgpu_waves_per_eu(LayR<N>::template waves1<kFitThreads<N, 1>>)))
+template <int N, int T>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(LayR<N>::template waves1<T>)))
 void fit2r_phase1(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r1[];
-  r_phase1_body<N, kFitThreads<N, 1>>(p, lds_r1, blockIdx.x + p.block0);
+  r_phase1_body<N, T>(p, lds_r1, blockIdx.x + p.block0);
 }
 
-template <int N>
-__global__ __launch_bounds__((kFitThreads<N, 1>)) __attribute__((amdgpu_waves_per_eu(LayL<N>::template waves<kFitThreads<N, 1>>)))
+template <int N, int T>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(LayL<N>::template waves<T>)))
 void fit2r_phase1_lean(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_l1[];
-  r_phase1_lean<N, kFitThreads<N, 1>>(p, lds_l1, blockIdx.x + p.block0, p.rescue_list, p.rescue_count);
+  r_phase1_lean<N, T>(p, lds_l1, blockIdx.x + p.block0, p.rescue_list, p.rescue_count);
 }
 
 // The listed fits of the lean kernel, redone by the full form: a persistent
@@ -1510,17 +1515,19 @@ void fit2r_phase1_redo(Params2D p) {
   }
 }
 
-template <int N, bool MC>
-__global__ __launch_bounds__((kFitThreads<N, 2>))
-__attribute__((amdgpu_waves_per_eu(MC ? LayZ<N, kFitThreads<N, 2> / 64>::waves_general : LayZ<N, kFitThreads<N, 2> / 64>::waves)))
+template <int N, bool MC, int T>
+__global__ __launch_bounds__(T)
+__attribute__((amdgpu_waves_per_eu(MC ? LayZ<N, T / 64>::waves_general : LayZ<N, T / 64>::waves)))
 void fit2r_phase2(Params2D p) {
   extern __shared__ __attribute__((aligned(16))) double lds_r2[];
-  r_phase2_body<N, kFitThreads<N, 2>, MC>(p, lds_r2, blockIdx.x + p.block0);
+  r_phase2_body<N, T, MC>(p, lds_r2, blockIdx.x + p.block0);
 }
 
-template <int N>
-static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStream_t st) {
-  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N, kFitThreads<N, 2> / 64>::bytes;
+// T1, T2: threads a fit in phase 1 and 2.  The redo kernel keeps the default
+// shape whatever T1 is.
+template <int N, int T1, int T2>
+static hipError_t launch_r_shape(int phase, const Params2D& p, int64_t nfits, hipStream_t st) {
+  const size_t lds = phase == 1 ? LayR<N>::bytes1 : LayZ<N, T2 / 64>::bytes;
   if (phase == 1 && p.rescue_list && p.ncomp == 1 && p.block0 + nfits <= (int64_t)0xffffffff) {
     // lean form, then the full form over the fits it listed
     if (nfits <= 0) return hipSuccess;
@@ -1529,12 +1536,12 @@ static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStrea
       Params2D q = p;
       q.block0 = p.block0 + b0;
       const int64_t nb = (nfits - b0) < chunk ? (nfits - b0) : chunk;
-      hipLaunchKernelGGL((fit2r_phase1_lean<N>), dim3((unsigned)nb), dim3(kFitThreads<N, 1>), LayL<N>::bytes, st, q);
+      hipLaunchKernelGGL((fit2r_phase1_lean<N, T1>), dim3((unsigned)nb), dim3(T1), LayL<N>::bytes, st, q);
       hipError_t err = hipGetLastError();
       if (err != hipSuccess) return err;
     }
     const unsigned grid = (unsigned)(nfits < 2048 ? (nfits > 0 ? nfits : 1) : 2048);
-    hipLaunchKernelGGL((fit2r_phase1_redo<N>), dim3(grid), dim3(kFitThreads<N, 1>), lds, st, p);
+    hipLaunchKernelGGL((fit2r_phase1_redo<N>), dim3(grid), dim3(kFitThreads<N, 1>), LayR<N>::bytes1, st, p);
     return hipGetLastError();
   }
   const int64_t chunk = (int64_t)1 << 30;
@@ -1543,34 +1550,40 @@ static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStrea
     q.block0 = p.block0 + b0;
     const int64_t nb = (nfits - b0) < chunk ? (nfits - b0) : chunk;
     if (phase == 1)
-      hipLaunchKernelGGL((fit2r_phase1<N>), dim3((unsigned)nb), dim3(kFitThreads<N, 1>), lds, st, q);
+      hipLaunchKernelGGL((fit2r_phase1<N, T1>), dim3((unsigned)nb), dim3(T1), lds, st, q);
     else if (q.mass || q.ncomp > 1)
-      hipLaunchKernelGGL((fit2r_phase2<N, true>), dim3((unsigned)nb), dim3(kFitThreads<N, 2>), lds, st, q);
+      hipLaunchKernelGGL((fit2r_phase2<N, true, T2>), dim3((unsigned)nb), dim3(T2), lds, st, q);
     else
-      hipLaunchKernelGGL((fit2r_phase2<N, false>), dim3((unsigned)nb), dim3(kFitThreads<N, 2>), lds, st, q);
+      hipLaunchKernelGGL((fit2r_phase2<N, false, T2>), dim3((unsigned)nb), dim3(T2), lds, st, q);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
   return hipSuccess;
 }
 
-hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st) {
+template <int N>
+static hipError_t launch_r(int phase, const Params2D& p, int64_t nfits, hipStream_t st, bool wide) {
+  if (wide) return launch_r_shape<N, kWideThreads<N, 1>, kWideThreads<N, 2>>(phase, p, nfits, st);
+  return launch_r_shape<N, kFitThreads<N, 1>, kFitThreads<N, 2>>(phase, p, nfits, st);
+}
+
+hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st, bool wide) {
   switch (N) {
-    case 2: return launch_r<2>(phase, p, nfits, st);
-    case 3: return launch_r<3>(phase, p, nfits, st);
-    case 4: return launch_r<4>(phase, p, nfits, st);
-    case 5: return launch_r<5>(phase, p, nfits, st);
-    case 6: return launch_r<6>(phase, p, nfits, st);
-    case 7: return launch_r<7>(phase, p, nfits, st);
-    case 8: return launch_r<8>(phase, p, nfits, st);
-    case 9: return launch_r<9>(phase, p, nfits, st);
-    case 10: return launch_r<10>(phase, p, nfits, st);
-    case 11: return launch_r<11>(phase, p, nfits, st);
-    case 12: return launch_r<12>(phase, p, nfits, st);
-    case 13: return launch_r<13>(phase, p, nfits, st);
-    case 14: return launch_r<14>(phase, p, nfits, st);
-    case 15: return launch_r<15>(phase, p, nfits, st);
-    case 16: return launch_r<16>(phase, p, nfits, st);
+    case 2: return launch_r<2>(phase, p, nfits, st, wide);
+    case 3: return launch_r<3>(phase, p, nfits, st, wide);
+    case 4: return launch_r<4>(phase, p, nfits, st, wide);
+    case 5: return launch_r<5>(phase, p, nfits, st, wide);
+    case 6: return launch_r<6>(phase, p, nfits, st, wide);
+    case 7: return launch_r<7>(phase, p, nfits, st, wide);
+    case 8: return launch_r<8>(phase, p, nfits, st, wide);
+    case 9: return launch_r<9>(phase, p, nfits, st, wide);
+    case 10: return launch_r<10>(phase, p, nfits, st, wide);
+    case 11: return launch_r<11>(phase, p, nfits, st, wide);
+    case 12: return launch_r<12>(phase, p, nfits, st, wide);
+    case 13: return launch_r<13>(phase, p, nfits, st, wide);
+    case 14: return launch_r<14>(phase, p, nfits, st, wide);
+    case 15: return launch_r<15>(phase, p, nfits, st, wide);
+    case 16: return launch_r<16>(phase, p, nfits, st, wide);
     default: return hipErrorInvalidValue;
   }
 }

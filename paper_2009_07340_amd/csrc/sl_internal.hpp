@@ -274,7 +274,7 @@ hipError_t launch_fit2d_fused(int phase, int mode, const Fused2DArgs& a, int gri
 int fit2d_fused_occupancy(int phase, int mode, size_t lds);
 hipError_t launch_step_counters(const StepArgs& a, hipStream_t st);
 hipError_t launch_draw_normals(const DrawArgs& a, int64_t maxM, hipStream_t st);
-hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st);
+hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st, bool wide);
 size_t fit2r_lds_bytes(int N, int phase);
 hipError_t launch_fit2r_fused(int phase, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
 int fit2r_fused_occupancy(int phase, size_t lds);

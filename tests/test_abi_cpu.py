@@ -25,6 +25,37 @@ def test_library_exports_every_declared_symbol():
     assert sorted(B.EXPORTED) == names
 
 
+_C_SIZES = {"int32_t": 4, "uint32_t": 4, "int64_t": 8, "uint64_t": 8, "double": 8, "float": 4, "size_t": 8}
+
+
+def _header_fields(name):
+    """(field, bytes) of `typedef struct name {...} name;` in include/sl.h, in order."""
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "sl.h")).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), src, re.S).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = " ".join(decl.split())
+        if not decl:
+            continue
+        m = re.match(r"(?:const )?(\w+)\s*(\*?)\s*(.*)$", decl)
+        assert m, decl
+        base, ptr, names = m.groups()
+        for d in names.split(","):        # several declarators share the type
+            f = re.fullmatch(r"\s*(\w+)(?:\[(\d+)\])?\s*", d)
+            assert f, decl
+            out.append((f.group(1), 8 if ptr else _C_SIZES[base] * int(f.group(2) or 1)))
+    return out
+
+
+@pytest.mark.parametrize("name", ["sl_mesh_desc", "sl_diag_t", "sl_schedule_t"])
+def test_binding_structs_follow_the_header(name):
+    """Field order and sizes of the ctypes mirrors equal the C declarations."""
+    from paper_2009_07340_amd import binding as B
+    py = getattr(B, name)
+    got = [(f, ctypes.sizeof(t)) for f, t in py._fields_]
+    assert got == _header_fields(name)
+
+
 def test_required_bytes_counts_state_and_tables():
     from paper_2009_07340_amd import binding as B
     d = B.make_desc(1, 256, order=12, samples=1024)

@@ -5,7 +5,8 @@ the per-order direct launches bit for bit (and those match the oracle).  One
 exception: the reference solver's persistent fused kernel runs every order on
 four wavefronts where its per-order and batched kernels run orders up to 12 on
 one or two, so its sums are ordered differently; it must agree to rounding
-(FUSED_TOL)."""
+(FUSED_TOL).  So must the wide fit shape of the per-order kernels (twice the
+wavefronts a fit up to order 12)."""
 import numpy as np
 import pytest
 
@@ -29,7 +30,9 @@ def _same(got, want, rounding):
 
 MIXED = np.array([6, 8, 10, 6, 8, 6, 10, 8, 10, 2, 8, 3, 8, 10, 6, 4], dtype=np.int32)
 
-SCHEDULES = [(0, 1, 0), (1, 0, 0), (1, 0, 5), (1, 1, 0), (1, 1, 7)]
+# (fused, graph, grid, shared, wide)
+SCHEDULES = [(0, 1, 0, 0, 0), (1, 0, 0, 0, 0), (1, 0, 5, 0, 0), (1, 1, 0, 0, 0), (1, 1, 7, 0, 0), (0, 0, 0, 0, 1),
+             (0, 1, 0, 0, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -45,18 +48,19 @@ def _mixed_wl(samples=3):
     return wl
 
 
-def _make(B, wl, precision="fp64", samples=None):
+def _make(B, wl, precision="fp64", samples=None, ncomp=1, mass=False):
     mesh, f, phi0, a = oracle_inputs(wl)
     order = wl.order if np.isscalar(wl.order) else wl.order_array()
     desc = B.make_desc(wl.dim, wl.kx, wl.ky, wl.box, order, bc=wl.bc, samples=samples or wl.samples,
-                       seed=wl.seed, precision=precision)
+                       seed=wl.seed, precision=precision, ncomp=ncomp, mass=mass)
     h = B.sl_init_mesh(desc)
-    B.sl_set_fields(h, a["u"], a["D"], a["divu"], a["un"], a["Dn"], a["ghost"], a["phi0"])
+    p0 = np.concatenate([a["phi0"] * (1.0 + 0.1 * c) for c in range(ncomp)])
+    B.sl_set_fields(h, a["u"], a["D"], a["divu"], a["un"], a["Dn"], a["ghost"], p0)
     return h, (mesh, f, phi0)
 
 
-def _run(B, wl, sched, steps, precision="fp64"):
-    h, _ = _make(B, wl, precision)
+def _run(B, wl, sched, steps, precision="fp64", **kw):
+    h, _ = _make(B, wl, precision, **kw)
     try:
         if sched is not None:
             B.sl_set_schedule(h, *sched)
@@ -76,12 +80,41 @@ def test_every_schedule_is_bitwise_equal(B, precision):
     for sched in SCHEDULES:
         got = _run(B, wl, sched, [1, 2], precision)
         print(f"{precision} schedule {sched}: max |diff| {np.max(np.abs(got - ref)):.3e}", flush=True)
-        # fp64 runs the reference solver (the automatic choice); the mixed modes the factorisation
-        assert _same(got, ref, precision == "fp64" and sched[0] == 1), (precision, sched)
+        # fp64 runs the reference solver (the automatic choice); the mixed modes the
+        # factorisation, whose kernels have one fit shape
+        assert _same(got, ref, precision == "fp64" and (sched[0] == 1 or sched[4] == 1)), (precision, sched)
     if precision == "fp64":
         mesh, f, phi0, a = oracle_inputs(wl)
         want = sl.run(mesh, f, phi0, wl.dt, 3, wl.seed, np.arange(wl.samples))
         assert rel_l2(ref, want) < TOL
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_wide_fit_shape_matches_the_default_and_the_oracle(B, graph):
+    """Every order the wide shape changes (2..12: one wavefront a fit becomes two, two
+    become four) and some it leaves alone (13, 16), direct and as a graph."""
+    wl = W.c4_2d_rotation(kx=3, ky=3, samples=2, steps=3)
+    wl.order = np.array([9, 11, 12, 13, 5, 7, 2, 16, 10], dtype=np.int32)
+    wl.dt = 2e-4
+    ref = _run(B, wl, None, [2])
+    got = _run(B, wl, (0, graph, 0, 0, 1), [1, 1])
+    print(f"wide graph={graph}: max |diff| {np.max(np.abs(got - ref)):.3e}", flush=True)
+    assert _same(got, ref, True)
+    mesh, f, phi0, a = oracle_inputs(wl)
+    want = sl.run(mesh, f, phi0, wl.dt, 2, wl.seed, np.arange(wl.samples))
+    assert rel_l2(got, want) < TOL
+    assert np.max(np.abs(got - want)) <= TOL * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("kw", [{"ncomp": 2}, {"mass": True}])
+def test_wide_fit_shape_of_the_general_form(B, kw):
+    """Several components, or the mass constraint: the full phase-1 form and the
+    general phase-2 form in the wide shape agree with the default shape."""
+    wl = _mixed_wl(samples=2)
+    ref = _run(B, wl, None, [2], **kw)
+    got = _run(B, wl, (0, 0, 0, 0, 1), [2], **kw)
+    print(f"wide {kw}: max |diff| {np.max(np.abs(got - ref)):.3e}", flush=True)
+    assert _same(got, ref, True)
 
 
 def test_graph_follows_step_counter_and_dt(B):
@@ -211,7 +244,8 @@ def test_autotune_restores_state_and_uses_its_cache(B, tmp_path):
         B.sl_step(h, wl.dt, 1)
         before = B.sl_get_samples(h, 0, wl.samples)
         s = B.sl_autotune(h, wl.dt, 2, cache)
-        assert s["fused"] in (0, 1) and s["graph"] in (0, 1) and s["ms_per_step"] > 0
+        assert s["fused"] in (0, 1) and s["graph"] in (0, 1) and s["wide"] in (0, 1) and s["ms_per_step"] > 0
+        assert not (s["fused"] and s["wide"])
         assert B.sl_get_step(h) == 1
         assert np.array_equal(B.sl_get_samples(h, 0, wl.samples), before)
         assert len(cache.read_text().splitlines()) == 1
@@ -219,11 +253,11 @@ def test_autotune_restores_state_and_uses_its_cache(B, tmp_path):
         tuned = B.sl_get_samples(h, 0, wl.samples)
         h2, _ = _make(B, wl)
         s2 = B.sl_autotune(h2, wl.dt, 2, cache)       # cache hit: no timing, same choice
-        assert (s2["fused"], s2["graph"], s2["grid"]) == (s["fused"], s["graph"], s["grid"])
+        assert (s2["fused"], s2["graph"], s2["grid"], s2["wide"]) == (s["fused"], s["graph"], s["grid"], s["wide"])
         assert len(cache.read_text().splitlines()) == 1
         B.sl_set_schedule(h2, 0, 0, 0)
         B.sl_step(h2, wl.dt, 3)
-        assert _same(B.sl_get_samples(h2, 0, wl.samples), tuned, s["fused"] == 1)
+        assert _same(B.sl_get_samples(h2, 0, wl.samples), tuned, s["fused"] == 1 or s["wide"] == 1)
     finally:
         B.sl_destroy(h)
         if h2 is not None:
