@@ -300,7 +300,7 @@ def main():
         orders = wl.order_array()
         phases = {}
         for ph, it in ((1, it1), (2, it2)):
-            name = f"fit2r_phase{ph}"
+            name = f"fit2d_fused_phase{ph}" if fused else f"fit2r_phase{ph}"   # the persistent kernel's label
             n_l, ms_l = (launches, kms) if name == kname else B.sl_kernel_time(prob.h, name)
             pl = sum(fit_flops_2d_ref(int(N), ph, it, args.ncomp) for N in orders) * wl.samples
             phases[name] = {"launches": n_l, "ms": round(ms_l, 4), "flops_per_launch": pl,
