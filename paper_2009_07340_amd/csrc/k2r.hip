@@ -1183,7 +1183,7 @@ template <int N, int T, bool MC = true>
 __device__ __forceinline__ void r_phase2_body(const Params2D& p, double* lds, int64_t fit) {
   constexpr int W = T / 64;
   using L = LayZ<N, W>;
-  constexpr int n = L::n, m = L::m, mm = L::mm, TT = L::TT, mmA = L::mmA;
+  constexpr int n = L::n, m = L::m, mm = L::mm, mmA = L::mmA;
   static_assert(n <= T, "one node a thread");
   const int64_t w = fit / p.M;
   const int64_t s = fit - w * p.M;
