@@ -235,6 +235,28 @@ def test_batch_argument_errors(B):
         B.sl_destroy(h)
 
 
+def test_autotune_reads_cache_lines_without_a_fit_shape(B, tmp_path):
+    """A cache line written before the fit shape was a choice (five fields) is a hit
+    with the default shape."""
+    wl = _mixed_wl(samples=2)
+    cache = tmp_path / "tune.txt"
+    h, _ = _make(B, wl)
+    h2 = None
+    try:
+        B.sl_autotune(h, wl.dt, 1, cache)
+        fields = cache.read_text().split()
+        assert len(fields) == 6
+        cache.write_text(" ".join(fields[:1] + ["0", "1", "0", "1.5"]) + "\n")   # per-order graph, no shape field
+        h2, _ = _make(B, wl)
+        s = B.sl_autotune(h2, wl.dt, 1, cache)
+        assert (s["fused"], s["graph"], s["grid"], s["wide"]) == (0, 1, 0, 0)
+        assert len(cache.read_text().splitlines()) == 1
+    finally:
+        B.sl_destroy(h)
+        if h2 is not None:
+            B.sl_destroy(h2)
+
+
 def test_autotune_restores_state_and_uses_its_cache(B, tmp_path):
     wl = _mixed_wl(samples=4)
     cache = tmp_path / "tune.txt"
