@@ -259,14 +259,15 @@ int sl_step(sl_handle h, double dt, int32_t nsteps);
 int sl_step_batch(const sl_handle* hs, const double* dts, int32_t nh, int32_t nsteps);
 
 /* Launch schedule of the 2-D step (Sec. 5 fixes only the result, which is the
- * same bit for bit under every schedule, with one exception: the persistent
- * kernel of the reference solver runs every order on four wavefronts a fit,
- * where its per-order kernels run orders up to 12 on one or two, so its sums
- * are ordered differently and it agrees with them to rounding):
+ * same bit for bit under every schedule, with one exception: the wide fit
+ * shape below orders its sums differently and agrees with the others to
+ * rounding):
  *   fused = 0: one kernel per order group and phase, one workgroup per fit;
- *   fused = 1: one persistent kernel per phase over all orders, `grid`
- *              workgroups (0 = as many as fit on the device at once) pulling
- *              fits from a device work counter;
+ *   fused = 1: persistent kernels, `grid` workgroups each (0 = as many as fit
+ *              on the device at once) pulling fits from device work counters:
+ *              factorisation solver one kernel per phase over all orders;
+ *              reference solver one kernel per phase and order present, with
+ *              that order's per-order fit shape and body;
  *   graph = 1: the step is captured once as a hipGraph (device step counter,
  *              counters cleared by a kernel) and replayed nsteps times;
  *   wide = 1:  fit shape of the reference solver's per-order kernels (fused = 0,

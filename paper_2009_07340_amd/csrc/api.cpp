@@ -185,7 +185,7 @@ int make_layout(const sl_mesh_desc* d, Layout& L) {
   L.o_interpoff = take(sizeof(int64_t) * (sl::kMaxN + 1) * (sl::kMaxN + 1));
   L.o_params = take(std::max(sizeof(sl::Params1D), sizeof(sl::Params2D)));
   L.o_dstep = take(sizeof(int64_t));
-  L.o_ctr = take(2 * sizeof(unsigned long long));
+  L.o_ctr = take(sl::kWorkCounters * sizeof(unsigned long long));
   L.o_nonf = take(sizeof(unsigned long long));
   L.o_stats = take(stats_bytes());
   {
@@ -248,7 +248,7 @@ struct sl_ctx {
   sl::Params1D* d_p1 = nullptr;
   sl::Params2D* d_p2 = nullptr;
   int64_t* d_step = nullptr;             // device step counter (fused / graph schedules)
-  unsigned long long* d_ctr = nullptr;   // work counters of the two phases
+  unsigned long long* d_ctr = nullptr;   // work counters of the persistent launches (phase, order)
   unsigned long long* d_stats = nullptr; // diagnostics slots (solver statistics, escapes, residuals)
   unsigned long long* d_nonf = nullptr;  // non-finite values seen by the last sample mean
   double* d_mpart = nullptr;             // partial sums of the sample mean
@@ -555,16 +555,54 @@ int enqueue_perorder(sl_ctx* h, int phase, bool devstep, int64_t step, hipStream
   return SL_OK;
 }
 
-// Persistent fused launches of one phase over a batch of 2-D handles: one
+// Persistent launches of one phase of the reference solver over a batch of
+// handles, per chunk of kMaxTasks handles / kMaxSegs order segments: one
+// launch per order present, largest first, each pulling the chunk's fits of
+// that order from its own counter of the chunk's first handle.
+int enqueue_fused_ref(const std::vector<sl_ctx*>& m, int phase, int grid_req, hipStream_t st) {
+  size_t i = 0;
+  while (i < m.size()) {
+    size_t j = i, nseg = 0;
+    while (j < m.size() && j - i < (size_t)sl::kMaxTasks && nseg + m[j]->groups.size() <= (size_t)sl::kMaxSegs)
+      nseg += m[j++]->groups.size();
+    bool fast = true;   // every handle takes the lean phase 1 and the one-component phase 2
+    for (size_t t = i; t < j; ++t) fast = fast && m[t]->d_rlist && !m[t]->L.mass;
+    for (int N = sl::kMaxNRef; N >= 2; --N) {
+      sl::Fused2DArgs a{};
+      int64_t start = 0;
+      for (size_t t = i; t < j; ++t) {
+        a.task[t - i] = m[t]->d_p2;
+        for (const auto& g : m[t]->groups)
+          if (g.first == N && g.second.second > 0) {
+            a.seg[a.nseg++] = sl::FusedSeg{start, g.second.first * m[t]->p2.M, (int32_t)(t - i), N};
+            start += g.second.second * m[t]->p2.M;
+          }
+      }
+      a.total = start;
+      if (start <= 0) continue;
+      a.counter = m[i]->d_ctr + 2 * N + (phase - 1);
+      SL_HIP(sl::launch_fit2r_persist(phase, N, a, fast, grid_req, device_cus(), st));
+    }
+    i = j;
+  }
+  return SL_OK;
+}
+
+// Persistent fused launches of one phase over a batch of 2-D handles: the
+// reference solver's by enqueue_fused_ref; for the factorisation solver one
 // launch per precision mode (and per chunk of kMaxTasks handles / kMaxSegs
 // order segments), each chunk pulling work from its first handle's counter.
 int enqueue_fused(const std::vector<sl_ctx*>& hs, int phase, int grid_req, hipStream_t st) {
-  for (int kind = 0; kind <= 3; ++kind) {
-    const int mode = kind == 3 ? 0 : kind;
+  {
+    std::vector<sl_ctx*> ref;
+    for (sl_ctx* h : hs)
+      if (h->L.solver == SL_SOLVER_REFERENCE) ref.push_back(h);
+    if (int rc = enqueue_fused_ref(ref, phase, grid_req, st)) return rc;
+  }
+  for (int mode = 0; mode <= 2; ++mode) {
     std::vector<sl_ctx*> m;
     for (sl_ctx* h : hs)
-      if ((h->L.solver == SL_SOLVER_REFERENCE) == (kind == 3) && (kind == 3 || h->desc.precision == mode))
-        m.push_back(h);
+      if (h->L.solver != SL_SOLVER_REFERENCE && h->desc.precision == mode) m.push_back(h);
     size_t i = 0;
     while (i < m.size()) {
       // take handles while the chunk's segments fit
@@ -588,19 +626,16 @@ int enqueue_fused(const std::vector<sl_ctx*>& hs, int phase, int grid_req, hipSt
         a.seg[a.nseg] = sl::FusedSeg{start, g.fit0, g.task, g.N};
         ++a.nseg;
         start += g.count;
-        lds = std::max(lds, kind == 3 ? sl::fit2r_lds_bytes(g.N, phase) : sl::fit2d_lds_bytes(g.N, mode, phase));
+        lds = std::max(lds, sl::fit2d_lds_bytes(g.N, mode, phase));
       }
       a.total = start;
       a.counter = m[i]->d_ctr + (phase - 1);
       if (a.total > 0) {
-        const int occ = kind == 3 ? sl::fit2r_fused_occupancy(phase, lds) : sl::fit2d_fused_occupancy(phase, mode, lds);
+        const int occ = sl::fit2d_fused_occupancy(phase, mode, lds);
         if (occ <= 0) return fail(SL_EDEVICE, "fused kernel does not fit on a compute unit");
         int64_t grid = grid_req > 0 ? grid_req : (int64_t)occ * device_cus();
         grid = std::min<int64_t>(grid, a.total);
-        if (kind == 3)
-          SL_HIP(sl::launch_fit2r_fused(phase, a, (int)grid, lds, st));
-        else
-          SL_HIP(sl::launch_fit2d_fused(phase, mode, a, (int)grid, lds, st));
+        SL_HIP(sl::launch_fit2d_fused(phase, mode, a, (int)grid, lds, st));
       }
       i = j;
     }

@@ -735,8 +735,7 @@ __global__ void step_counters_kernel(StepArgs a) {
   if (i < a.n) {
     if (a.set) *a.step[i] = a.value[i];
     else *a.step[i] += 1;
-    a.counter[i][0] = 0ull;
-    a.counter[i][1] = 0ull;
+    for (int c = 0; c < kWorkCounters; ++c) a.counter[i][c] = 0ull;
   }
 }
 

@@ -28,6 +28,8 @@
 // are counted in a device statistic.  Everything is float64.  One workgroup
 // per fit (one to four wavefronts by order), all of its data in LDS
 // (N <= 16).
+#include <atomic>
+
 #include "sl_internal.hpp"
 #include "philox.hpp"
 #include "fit1d.hpp"
@@ -1666,93 +1668,136 @@ hipError_t launch_fit2r_multi(int phase, int N, const Fused2DArgs& a, bool fast,
   }
 }
 
-// Persistent fused kernel over every order (2..16) of several problems, as
-// the factorisation kernels' fused form: segments largest order first, a
-// device work counter, each order outlined with its own registers.
+// Persistent form of the reference solver: one kernel per order present, each
+// with the grid that fits on the device at once, pulling the fits of that
+// order of several problems (segments) from its own device counter and
+// running each with the body, fit shape, LDS layout and register budget of the
+// batched kernel of that order, so its results are those of the per-order and
+// batched kernels bit for bit.  (One kernel over every order would have to
+// hold registers for all the orders' bodies at once.)  FAST as for the batched
+// kernels; after a FAST phase 1 the batched redo kernel of each order walks the
+// fits that the lean form listed.
 __device__ __forceinline__ int64_t uniform64r(int64_t v) {
   const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
   const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-template <int N, int PHASE>
-__device__ __attribute__((noinline)) void fused_fit_r(const Params2D* pp, int64_t fit) {
-  extern __shared__ __attribute__((aligned(16))) double lds_rf[];
-  const Params2D& p = *(const Params2D*)(uintptr_t)(uint64_t)uniform64r((int64_t)(uintptr_t)pp);
-  fit = uniform64r(fit);
-  if constexpr (PHASE == 1) r_phase1_body<N, kThreads>(p, lds_rf, fit);
-  else r_phase2_body<N, kThreads>(p, lds_rf, fit);
-}
+constexpr int kPersistChunk = 16;   // most items a workgroup claims at once
 
-template <int PHASE>
-__global__ __launch_bounds__(kThreads) void fit2r_fused(Fused2DArgs a) {
+template <int N, int PHASE, bool FAST>
+__global__ __launch_bounds__((kFitThreads<N, PHASE>))
+__attribute__((amdgpu_waves_per_eu(PHASE == 1 ? (FAST ? LayL<N>::template waves<kFitThreads<N, 1>> : LayR<N>::template waves1<kFitThreads<N, 1>>)
+                                              : (FAST ? LayZ<N, kFitThreads<N, 2> / 64>::waves : LayZ<N, kFitThreads<N, 2> / 64>::waves_multi))))
+void fit2r_persist(Fused2DArgs a) {
+  constexpr int T = kFitThreads<N, PHASE>;
+  extern __shared__ __attribute__((aligned(16))) double lds_rp[];
   __shared__ int64_t item_sh;
   for (;;) {
-    if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(a.counter, 1ull);
-    __syncthreads();
-    const int64_t item = uniform64r(item_sh);
-    __syncthreads();
-    if (item >= a.total) break;
-    int sg = 0;
-    while (sg + 1 < a.nseg && item >= a.seg[sg + 1].start) ++sg;
-    const Params2D* p = a.task[a.seg[sg].task];
-    const int64_t fit = a.seg[sg].fit0 + (item - a.seg[sg].start);
-    switch (a.seg[sg].N) {
-      case 2: fused_fit_r<2, PHASE>(p, fit); break;
-      case 3: fused_fit_r<3, PHASE>(p, fit); break;
-      case 4: fused_fit_r<4, PHASE>(p, fit); break;
-      case 5: fused_fit_r<5, PHASE>(p, fit); break;
-      case 6: fused_fit_r<6, PHASE>(p, fit); break;
-      case 7: fused_fit_r<7, PHASE>(p, fit); break;
-      case 8: fused_fit_r<8, PHASE>(p, fit); break;
-      case 9: fused_fit_r<9, PHASE>(p, fit); break;
-      case 10: fused_fit_r<10, PHASE>(p, fit); break;
-      case 11: fused_fit_r<11, PHASE>(p, fit); break;
-      case 12: fused_fit_r<12, PHASE>(p, fit); break;
-      case 13: fused_fit_r<13, PHASE>(p, fit); break;
-      case 14: fused_fit_r<14, PHASE>(p, fit); break;
-      case 15: fused_fit_r<15, PHASE>(p, fit); break;
-      case 16: fused_fit_r<16, PHASE>(p, fit); break;
-      default: break;
+    // a workgroup claims a.chunk consecutive items at a time (one atomic per
+    // chunk, not per fit: millions of fits a launch would otherwise queue on
+    // one address); every wavefront takes the same chunk and leaves on the
+    // same one, so the grid drains once the counter has passed the last item
+    int64_t item0;
+    if constexpr (T == 64) {
+      unsigned long long v = 0ull;
+      if (threadIdx.x == 0) v = atomicAdd(a.counter, (unsigned long long)a.chunk);
+      item0 = uniform64r((int64_t)v);
+    } else {
+      if (threadIdx.x == 0) item_sh = (int64_t)atomicAdd(a.counter, (unsigned long long)a.chunk);
+      __syncthreads();
+      item0 = uniform64r(item_sh);
+      __syncthreads();
     }
-    __syncthreads();
+    if (item0 >= a.total) break;
+    const int64_t item1 = item0 + a.chunk < a.total ? item0 + a.chunk : a.total;
+    int sg = 0;
+#pragma unroll 1
+    for (int64_t item = item0; item < item1; ++item) {
+      while (sg + 1 < a.nseg && item >= a.seg[sg + 1].start) ++sg;
+      const Params2D& p = *a.task[a.seg[sg].task];
+      const int64_t fit = a.seg[sg].fit0 + (item - a.seg[sg].start);
+      if constexpr (PHASE == 1 && FAST) r_phase1_lean<N, T>(p, lds_rp, fit, p.rescue_list + p.rescue_off[N], p.rescue_count + N);
+      else if constexpr (PHASE == 1) r_phase1_body<N, T>(p, lds_rp, fit);
+      else r_phase2_body<N, T, !FAST>(p, lds_rp, fit);
+      __syncthreads();   // the next item reuses the LDS
+    }
   }
 }
 
-hipError_t launch_fit2r_fused(int phase, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st) {
-  if (phase == 1) hipLaunchKernelGGL((fit2r_fused<1>), dim3(grid), dim3(kThreads), lds, st, a);
-  else hipLaunchKernelGGL((fit2r_fused<2>), dim3(grid), dim3(kThreads), lds, st, a);
-  return hipGetLastError();
-}
-
-int fit2r_fused_occupancy(int phase, size_t lds) {
-  int nb = 0;
-  hipError_t e = phase == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2r_fused<1>, kThreads, lds)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2r_fused<2>, kThreads, lds);
-  return e == hipSuccess ? nb : 0;
+template <int N>
+static size_t lds_persist(int phase, bool fast) {
+  return phase == 1 ? (fast ? LayL<N>::bytes : LayR<N>::bytes1) : LayZ<N, kFitThreads<N, 2> / 64>::bytes;
 }
 
 template <int N>
-static size_t lds_r(int phase) { return phase == 1 ? LayR<N>::bytes1 : LayZ<N>::bytes; }
+static int persist_occ(int phase, bool fast) {
+  // a property of the kernel and the device model: asked once a process
+  static std::atomic<int> known[2][2];
+  std::atomic<int>& slot = known[phase - 1][fast ? 1 : 0];
+  if (const int v = slot.load(std::memory_order_relaxed)) return v;
+  const size_t lds = lds_persist<N>(phase, fast);
+  const int T = phase == 1 ? kFitThreads<N, 1> : kFitThreads<N, 2>;
+  int nb = 0;
+  hipError_t e;
+  if (phase == 1) e = fast ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2r_persist<N, 1, true>, T, lds)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2r_persist<N, 1, false>, T, lds);
+  else e = fast ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2r_persist<N, 2, true>, T, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit2r_persist<N, 2, false>, T, lds);
+  if (e != hipSuccess) return 0;
+  slot.store(nb, std::memory_order_relaxed);
+  return nb;
+}
 
-size_t fit2r_lds_bytes(int N, int phase) {
+// grid_req > 0: that many workgroups, else as many as are resident at once
+// (occupancy x compute units); never more than the items.
+template <int N>
+static hipError_t persist_n(int phase, const Fused2DArgs& a, bool fast, int grid_req, int cus, hipStream_t st) {
+  if (a.total <= 0) return hipSuccess;
+  const size_t lds = lds_persist<N>(phase, fast);
+  int64_t grid = grid_req;
+  if (grid <= 0) {
+    const int occ = persist_occ<N>(phase, fast);
+    if (occ <= 0) return hipErrorInvalidConfiguration;
+    grid = (int64_t)occ * cus;
+  }
+  grid = grid < a.total ? grid : a.total;
+  // chunks small enough that every workgroup gets about four of them (one
+  // item each where there are few), at most kPersistChunk
+  Fused2DArgs c = a;
+  const int64_t ck = a.total / (4 * grid);
+  c.chunk = (int)(ck < 1 ? 1 : ck > kPersistChunk ? kPersistChunk : ck);
+  const dim3 g((unsigned)grid), b((unsigned)(phase == 1 ? kFitThreads<N, 1> : kFitThreads<N, 2>));
+  if (phase == 1 && fast) hipLaunchKernelGGL((fit2r_persist<N, 1, true>), g, b, lds, st, c);
+  else if (phase == 1) hipLaunchKernelGGL((fit2r_persist<N, 1, false>), g, b, lds, st, c);
+  else if (fast) hipLaunchKernelGGL((fit2r_persist<N, 2, true>), g, b, lds, st, c);
+  else hipLaunchKernelGGL((fit2r_persist<N, 2, false>), g, b, lds, st, c);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || phase != 1 || !fast) return err;
+  // the fits that the lean form listed, by the full form
+  const unsigned rg = (unsigned)(a.total < 2048 ? a.total : 2048);
+  hipLaunchKernelGGL((fit2r_multi_redo<N>), dim3(rg), dim3(kFitThreads<N, 1>), LayR<N>::bytes1, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit2r_persist(int phase, int N, const Fused2DArgs& a, bool fast, int grid, int cus, hipStream_t st) {
   switch (N) {
-    case 2: return lds_r<2>(phase);
-    case 3: return lds_r<3>(phase);
-    case 4: return lds_r<4>(phase);
-    case 5: return lds_r<5>(phase);
-    case 6: return lds_r<6>(phase);
-    case 7: return lds_r<7>(phase);
-    case 8: return lds_r<8>(phase);
-    case 9: return lds_r<9>(phase);
-    case 10: return lds_r<10>(phase);
-    case 11: return lds_r<11>(phase);
-    case 12: return lds_r<12>(phase);
-    case 13: return lds_r<13>(phase);
-    case 14: return lds_r<14>(phase);
-    case 15: return lds_r<15>(phase);
-    case 16: return lds_r<16>(phase);
-    default: return 0;
+    case 2: return persist_n<2>(phase, a, fast, grid, cus, st);
+    case 3: return persist_n<3>(phase, a, fast, grid, cus, st);
+    case 4: return persist_n<4>(phase, a, fast, grid, cus, st);
+    case 5: return persist_n<5>(phase, a, fast, grid, cus, st);
+    case 6: return persist_n<6>(phase, a, fast, grid, cus, st);
+    case 7: return persist_n<7>(phase, a, fast, grid, cus, st);
+    case 8: return persist_n<8>(phase, a, fast, grid, cus, st);
+    case 9: return persist_n<9>(phase, a, fast, grid, cus, st);
+    case 10: return persist_n<10>(phase, a, fast, grid, cus, st);
+    case 11: return persist_n<11>(phase, a, fast, grid, cus, st);
+    case 12: return persist_n<12>(phase, a, fast, grid, cus, st);
+    case 13: return persist_n<13>(phase, a, fast, grid, cus, st);
+    case 14: return persist_n<14>(phase, a, fast, grid, cus, st);
+    case 15: return persist_n<15>(phase, a, fast, grid, cus, st);
+    case 16: return persist_n<16>(phase, a, fast, grid, cus, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

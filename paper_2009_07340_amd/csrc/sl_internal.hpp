@@ -202,6 +202,7 @@ struct Fused2DArgs {
   int nseg;
   int64_t total;
   unsigned long long* counter;
+  int chunk;   // items a workgroup of a persistent reference-solver kernel claims at once
 };
 
 // Device step and work counters of up to kMaxTasks problems.
@@ -219,9 +220,14 @@ struct DrawArgs {
   int n;
 };
 
+// Work counters of a problem's persistent launches: index 2 N + (phase - 1)
+// (the reference solver, one launch per order N; the factorisation kernels'
+// single launch uses N = 0).
+constexpr int kWorkCounters = 2 * (kMaxN + 1);
+
 struct StepArgs {
   int64_t* step[kMaxTasks];
-  unsigned long long* counter[kMaxTasks];   // two per problem (phase 1, phase 2)
+  unsigned long long* counter[kMaxTasks];   // kWorkCounters per problem
   int64_t value[kMaxTasks];
   int n;
   int set;
@@ -275,9 +281,10 @@ int fit2d_fused_occupancy(int phase, int mode, size_t lds);
 hipError_t launch_step_counters(const StepArgs& a, hipStream_t st);
 hipError_t launch_draw_normals(const DrawArgs& a, int64_t maxM, hipStream_t st);
 hipError_t launch_fit2r(int phase, int N, const Params2D& p, int64_t nfits, hipStream_t st, bool wide);
-size_t fit2r_lds_bytes(int N, int phase);
-hipError_t launch_fit2r_fused(int phase, const Fused2DArgs& a, int grid, size_t lds, hipStream_t st);
-int fit2r_fused_occupancy(int phase, size_t lds);
+// reference solver, persistent form: the fits of order N of the segments in a,
+// grid workgroups (0: as many as are resident at once on `cus` compute units)
+// pulling them from a.counter; after a FAST phase 1 also the redo kernel
+hipError_t launch_fit2r_persist(int phase, int N, const Fused2DArgs& a, bool fast, int grid, int cus, hipStream_t st);
 // fast: every problem of the table has one component and no mass constraint
 // (the lean phase-1 kernel with its redo pass; the phase-2 kernel without the
 // general form).
